@@ -1,0 +1,239 @@
+"""CPU oracle for the level-blocked matrix power kernel.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product path never
+does, and this package imports nothing from the product package.
+
+Contents (each function names the passage of Lacey et al., "Cache Blocking of
+Distributed-Memory Parallel Matrix Power Kernels", that it follows):
+
+* :func:`powers`  -- y_k = A^k x, k = 1..p, as p back-to-back FP64 SpMVs
+  (Sec. "RACE Applied to the Matrix Power Kernel"; Alg. 1 without halo
+  exchange).  Implemented in plain C (``mpk_oracle.c``), sequential in-row
+  accumulation, no fused multiply-add.
+* :func:`recur`   -- the three-term recurrence of the Chebyshev application,
+  Eq. (anderson_spmv), with general coefficients.
+* :func:`bfs_levels` -- the level sets of Sec. "RACE Applied to the Matrix
+  Power Kernel" (the case equation for L(i)), computed literally with set
+  operations on the symmetrised graph G(A).
+* :func:`lp_diagonal_order` -- the LB-MPK traversal of the Lp diagram: the
+  diagonals i + p = const in increasing order, each walked from bottom-right
+  (largest level) to top-left (Fig. lp_basic).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mpk_oracle.c")
+_LIB = os.path.join(_HERE, "libmpk_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (gcc, -O2 -ffp-contract=off, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_powers.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int, P,
+                                      ctypes.c_int, P, ctypes.c_int]
+        lib.oracle_powers.restype = ctypes.c_int
+        lib.oracle_recur.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int, P,
+                                     ctypes.c_int, P, P, P, P, ctypes.c_int]
+        lib.oracle_recur.restype = ctypes.c_int
+        lib.oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _prep(A, x, value_bits):
+    rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    if value_bits == 32:
+        val = np.ascontiguousarray(A.val, dtype=np.float32)
+    elif value_bits == 64:
+        val = np.ascontiguousarray(A.val, dtype=np.float64)
+    else:
+        raise ValueError("value_bits must be 32 or 64")
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x.reshape(-1, 1)
+    if x.shape[0] != A.n:
+        raise ValueError("x has the wrong number of rows")
+    return rowptr, col, val, x
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def powers(A, x: np.ndarray, p: int, value_bits: int = 64, nthreads: int = 0) -> np.ndarray:
+    """All powers y_k = A^k x, k = 1..p; returns Y of shape (p, n, R).
+
+    Each y_k is one SpMV of y_{k-1} (MPK definition, Sec. "RACE Applied to the
+    Matrix Power Kernel"; the SpMV loop of Alg. 1).  ``value_bits=32`` rounds
+    the stored values to float and promotes them before each product (the
+    FP32-storage reading: vectors and sums stay FP64).
+    """
+    rowptr, col, val, x = _prep(A, x, value_bits)
+    R = x.shape[1]
+    Y = np.empty((p, A.n, R), dtype=np.float64)
+    rc = _load().oracle_powers(A.n, _ptr(rowptr), _ptr(col), _ptr(val), value_bits, R, _ptr(x),
+                               p, _ptr(Y), nthreads)
+    if rc:
+        raise ValueError(f"oracle_powers failed ({rc})")
+    return Y
+
+
+def recur(A, x: np.ndarray, alpha, beta, gamma, value_bits: int = 64,
+          nthreads: int = 0) -> np.ndarray:
+    """Three-term recurrence y_{j+1} = alpha_j A y_j + beta_j y_j + gamma_j y_{j-1}.
+
+    j = 0..p-1 with y_0 = x and no gamma term at j = 0; returns (p, n, R).
+    The Chebyshev recurrence of Eq. (anderson_spmv) is alpha = (1, 2, 2, ...),
+    beta = 0, gamma = (0, -1, -1, ...).
+    """
+    rowptr, col, val, x = _prep(A, x, value_bits)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    p = alpha.size
+    if beta.size != p or gamma.size != p or p < 1:
+        raise ValueError("coefficient arrays must have the same length p >= 1")
+    R = x.shape[1]
+    Y = np.empty((p, A.n, R), dtype=np.float64)
+    rc = _load().oracle_recur(A.n, _ptr(rowptr), _ptr(col), _ptr(val), value_bits, R, _ptr(x),
+                              p, _ptr(alpha), _ptr(beta), _ptr(gamma), _ptr(Y), nthreads)
+    if rc:
+        raise ValueError(f"oracle_recur failed ({rc})")
+    return Y
+
+
+def chebyshev_coefficients(p: int):
+    """alpha, beta, gamma of the Chebyshev recurrence (v_1 = H v_0, then 2H v_k - v_{k-1})."""
+    alpha = np.full(p, 2.0)
+    alpha[0] = 1.0
+    beta = np.zeros(p)
+    gamma = np.full(p, -1.0)
+    gamma[0] = 0.0
+    return alpha, beta, gamma
+
+
+# ------------------------------------------------------------ graph side
+
+def neighbour_sets(n: int, rowptr, col):
+    """N(u) on G(A): an edge joins v and j for every stored entry (v, j).
+
+    Values play no role, self-loops are dropped and the pattern is taken as
+    symmetric (the paper's note on non-symmetric matrices: missing mirror
+    entries are filled in for the level construction only).
+    """
+    N = [set() for _ in range(n)]
+    for v in range(n):
+        for e in range(int(rowptr[v]), int(rowptr[v + 1])):
+            j = int(col[e])
+            if j != v:
+                N[v].add(j)
+                N[j].add(v)
+    return N
+
+
+def bfs_levels(n: int, rowptr, col, root: int = 0):
+    """Level sets L(0), L(1), ... of G(A) by the paper's case equation.
+
+    L(0) = {root}; L(1) = N(L(0)); L(i) = N(L(i-1)) minus N(L(i-2)) minus
+    L(i-2) for i >= 2.  When a level comes out empty while vertices remain
+    (a disconnected graph), the next level restarts at the lowest unvisited
+    vertex.  Inside a level, vertices are listed in ascending original index.
+    Returns (levels, perm, iperm) with perm[new] = old and iperm[old] = new.
+    """
+    N = neighbour_sets(n, rowptr, col)
+
+    def nb(S):
+        out = set()
+        for u in S:
+            out |= N[u]
+        return out
+
+    levels = []
+    seen = set()
+    if n and not 0 <= root < n:
+        raise ValueError("root out of range")
+    if n == 0:
+        return levels, np.zeros(0, np.int64), np.zeros(0, np.int64)
+    prev2, prev1 = None, None
+    while len(seen) < n:
+        if prev1 is None:
+            start = root if not levels else min(set(range(n)) - seen)
+            cur = {start}
+        elif prev2 is None:
+            cur = nb(prev1) - prev1
+        else:
+            cur = nb(prev1) - nb(prev2) - prev2
+        # the case equation never yields an already-levelled vertex
+        assert not (cur & seen), "level equation revisited a vertex"
+        if not cur:
+            prev2, prev1 = None, None
+            continue
+        levels.append(sorted(cur))
+        seen |= cur
+        prev2, prev1 = prev1, cur
+    perm = np.array([v for L in levels for v in L], dtype=np.int64)
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[perm] = np.arange(n)
+    return levels, perm, iperm
+
+
+def lp_diagonal_order(n_levels: int, p_m: int):
+    """Execution order of the Lp diagram (Fig. lp_basic).
+
+    The diagonals i + p = const are taken for const = 1, 2, ...; on each,
+    cells go from the largest level (bottom-right, p small) to the smallest
+    level (top-left, p large).  Returns the list of (level, power).
+    """
+    order = []
+    for const in range(1, n_levels + p_m):
+        for i in range(n_levels - 1, -1, -1):
+            p = const - i
+            if 1 <= p <= p_m:
+                order.append((i, p))
+    return order
+
+
+def permute_csr(A, perm):
+    """Symmetric permutation P A P^T with perm[new] = old, in-row order kept (Sec.
+    "RACE Applied to the Matrix Power Kernel", BFS reordering)."""
+    n = A.n
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[np.asarray(perm)] = np.arange(n)
+    counts = np.diff(A.rowptr.astype(np.int64))[perm]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    col = np.empty(A.nnz, dtype=np.int32)
+    val = np.empty(A.nnz, dtype=np.float64)
+    for new in range(n):
+        old = int(perm[new])
+        s, e = int(A.rowptr[old]), int(A.rowptr[old + 1])
+        col[rowptr[new]:rowptr[new + 1]] = iperm[A.col[s:e]]
+        val[rowptr[new]:rowptr[new + 1]] = A.val[s:e]
+    return type(A)(n, rowptr.astype(np.int32), col, val, A.name + "_perm")

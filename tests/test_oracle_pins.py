@@ -1,0 +1,232 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's formula: every expected value comes from a
+closed form, an exact-integer or exact-rational brute force, a library routine
+of a different kind (dense matrix power, graph distances), or a worked example
+printed in the paper (tests/golden/).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+import oracle
+import workloads as w
+from tests._util import read_golden, rel_err_per_power
+
+
+# ------------------------------------------------------------------ exact results
+
+def test_identity_powers_are_exact():
+    A = w.identity(37)
+    x = w.uniform_vectors(37, 3, 7)
+    Y = oracle.powers(A, x, 5)
+    for k in range(5):
+        assert np.array_equal(Y[k], x)
+
+
+def test_permutation_powers_are_exact_and_not_transposed():
+    # (P x)[i] = x[sigma[i]]; P^k composes the index map k times.
+    P, sigma = w.permutation_matrix(50, 11)
+    x = w.uniform_vectors(50, 2, 3)
+    Y = oracle.powers(P, x, 6)
+    idx = np.arange(50)
+    for k in range(6):
+        idx = sigma[idx]
+        assert np.array_equal(Y[k], x[idx])
+    # the transpose would apply sigma^{-1}: make sure that differs here
+    inv = np.argsort(sigma)
+    assert not np.array_equal(Y[0], x[inv])
+
+
+def test_laplacian_1d_delta_binomials():
+    # tridiag(-1, 2, -1) applied k times to a delta gives (-1)^j C(2k, k+j)
+    n, c = 121, 60
+    A = w.tridiag_1d(n)
+    x = np.zeros((n, 1))
+    x[c, 0] = 1.0
+    p = 24
+    Y = oracle.powers(A, x, p)
+    for k in range(1, p + 1):
+        expect = np.zeros(n)
+        for j in range(-k, k + 1):
+            expect[c + j] = (-1) ** j * math.comb(2 * k, k + j)
+        assert np.array_equal(Y[k - 1, :, 0], expect), k
+
+
+def _exact_int_powers(A, xi, p):
+    """A^k x in exact integer arithmetic through a dense int64 matrix."""
+    D = A.to_dense()
+    Di = D.astype(np.int64)
+    assert np.array_equal(Di.astype(np.float64), D)
+    out, y = [], xi.astype(np.int64)
+    for _ in range(p):
+        y = Di @ y
+        out.append(y.copy())
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("A,p", [(w.stencil_2d5(12), 7), (w.stencil_3d27(6), 6),
+                                 (w.random_sparse(40, 0.1, 5, values="int"), 6)])
+def test_integer_inputs_exact(A, p):
+    x = w.integer_vectors(A.n, 2, 99)
+    Y = oracle.powers(A, x, p)
+    E = _exact_int_powers(A, x, p)
+    assert np.abs(E).max() < 2 ** 53
+    assert np.array_equal(Y, E.astype(np.float64))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_dense_brute_force_nonsymmetric(seed):
+    A = w.random_sparse(48, 0.12, seed)
+    x = w.uniform_vectors(48, 3, seed + 100)
+    p = 6
+    D = A.to_dense()
+    ref = np.stack([np.linalg.matrix_power(D, k) @ x for k in range(1, p + 1)])
+    assert rel_err_per_power(oracle.powers(A, x, p), ref).max() < 1e-12
+    # a transposed operand would be caught here
+    refT = np.stack([np.linalg.matrix_power(D.T, k) @ x for k in range(1, p + 1)])
+    assert rel_err_per_power(refT, ref).max() > 1e-3
+
+
+def test_fp32_values_round_then_promote():
+    A = w.random_sparse(60, 0.1, 4)
+    x = w.uniform_vectors(60, 2, 5)
+    Y32 = oracle.powers(A, x, 5, value_bits=32)
+    A2 = w.CSR(A.n, A.rowptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    assert np.array_equal(Y32, oracle.powers(A2, x, 5))
+    assert rel_err_per_power(Y32, oracle.powers(A, x, 5)).max() < 1e-5
+
+
+# ------------------------------------------------------------------ recurrence
+
+def test_chebyshev_on_diagonal_is_cos_k_theta():
+    th = np.linspace(0.05, 3.1, 30)
+    n = th.size
+    A = w.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.cos(th))
+    x = w.uniform_vectors(n, 1, 8)
+    p = 16
+    Y = oracle.recur(A, x, *oracle.chebyshev_coefficients(p))
+    for k in range(1, p + 1):
+        np.testing.assert_allclose(Y[k - 1, :, 0], np.cos(k * th) * x[:, 0], rtol=0, atol=1e-13)
+
+
+def test_chebyshev_fourier_mode_periodic_hopping():
+    # H = (S + S^-1)/2 on a ring: v_j = cos(theta_m j) has eigenvalue cos(theta_m)
+    n, m = 64, 5
+    A = w.tridiag_1d(n, diag=0.0, off=0.5, periodic=True)
+    th = 2 * math.pi * m / n
+    v = np.cos(th * np.arange(n)).reshape(n, 1)
+    p = 12
+    Yc = oracle.recur(A, v, *oracle.chebyshev_coefficients(p))
+    Yp = oracle.powers(A, v, p)
+    for k in range(1, p + 1):
+        np.testing.assert_allclose(Yc[k - 1], math.cos(k * th) * v, atol=1e-13)
+        np.testing.assert_allclose(Yp[k - 1], math.cos(th) ** k * v, atol=1e-13)
+
+
+def test_general_recurrence_exact_rationals():
+    # dyadic data keeps every intermediate exactly representable; the
+    # expected values come from a Fraction brute force over a dense matrix.
+    D = np.array([[0.5, -1.0, 0.0, 0.25],
+                  [0.0, 1.0, 0.5, 0.0],
+                  [-0.25, 0.0, -0.5, 1.0],
+                  [1.0, 0.0, 0.0, 0.5]])
+    A = w.from_dense(D)
+    x = np.array([[1.0, -2.0], [0.5, 1.0], [-1.0, 0.0], [2.0, 0.25]])
+    alpha = np.array([1.0, 2.0, -0.5, 1.0, 2.0, 0.5])
+    beta = np.array([0.5, 0.0, 1.0, -1.0, 0.25, 0.0])
+    gamma = np.array([0.0, -1.0, 0.5, 0.25, -1.0, 2.0])
+    Y = oracle.recur(A, x, alpha, beta, gamma)
+    F = [[Fraction(v) for v in row] for row in D]
+    X = [[Fraction(v) for v in row] for row in x]
+    prev, cur, out = None, X, []
+    for j in range(alpha.size):
+        t = [[sum(F[i][c] * cur[c][r] for c in range(4)) for r in range(2)] for i in range(4)]
+        nxt = [[Fraction(alpha[j]) * t[i][r] + Fraction(beta[j]) * cur[i][r]
+                + (Fraction(gamma[j]) * prev[i][r] if prev is not None else 0)
+                for r in range(2)] for i in range(4)]
+        out.append(nxt)
+        prev, cur = cur, nxt
+    assert np.array_equal(Y, np.array(out, dtype=np.float64))
+
+
+# ------------------------------------------------------------------ invariants
+
+def test_split_and_block_invariants():
+    A = w.stencil_2d5(20)
+    x = w.uniform_vectors(A.n, 4, 21)
+    Y = oracle.powers(A, x, 7)
+    Ya = oracle.powers(A, x, 3)
+    Yb = oracle.powers(A, Ya[-1], 4)
+    assert np.array_equal(Y[:3], Ya) and np.array_equal(Y[3:], Yb)
+    for r in range(4):
+        assert np.array_equal(Y[:, :, r:r + 1], oracle.powers(A, x[:, r:r + 1], 7))
+    # linearity
+    Z = oracle.powers(A, 2.0 * x[:, :1] - 3.0 * x[:, 1:2], 7)
+    assert rel_err_per_power(Z, 2.0 * Y[:, :, :1] - 3.0 * Y[:, :, 1:2]).max() < 1e-13
+
+
+def test_empty_matrix():
+    A = w.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert oracle.powers(A, np.zeros((0, 1)), 3).shape == (3, 0, 1)
+
+
+# ------------------------------------------------------------------ levels and order
+
+def _golden_graph():
+    rows = read_golden("stencil20_graph.txt")
+    n = int(rows[0][1])
+    D = np.eye(n)
+    for u, v in rows[1:]:
+        D[int(u), int(v)] = D[int(v), int(u)] = -1.0
+    return w.from_dense(D, "stencil20")
+
+
+def test_paper_stencil_levels_and_permutation():
+    A = _golden_graph()
+    g = read_golden("stencil20_bfs.txt")
+    new_label = [int(v) for v in g[0][1:]]
+    levels = [[int(v) for v in r[1:]] for r in g if r[0] == "level"]
+    row8 = [int(v) for v in g[-1][1:]]
+    assert list(A.col[A.rowptr[8]:A.rowptr[9]]) == row8
+    lv, perm, iperm = oracle.bfs_levels(A.n, A.rowptr, A.col, root=0)
+    assert lv == levels
+    assert list(iperm) == new_label
+
+
+def test_lp_diagram_order_matches_figure():
+    grid = [[int(v) for v in r[1:]] for r in read_golden("lp_order_10x5.txt")]
+    order = oracle.lp_diagonal_order(10, 5)
+    assert len(order) == 50
+    for step, (i, p) in enumerate(order):
+        assert grid[p - 1][i] == step
+    assert grid[0][5] == 15 and grid[1][5] == 21  # stated next to the figure
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_levels_are_graph_distances(seed):
+    A = w.random_sparse(300, 0.008, seed, symmetric_pattern=False)
+    lv, perm, iperm = oracle.bfs_levels(A.n, A.rowptr, A.col, root=0)
+    M = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n, A.n))
+    dist = csg.shortest_path(M, unweighted=True, directed=False, indices=0)
+    comp0 = [v for v in range(A.n) if np.isfinite(dist[v])]
+    lev_of = {v: i for i, L in enumerate(lv) for v in L}
+    for v in comp0:
+        assert lev_of[v] == dist[v]
+    # every vertex appears exactly once; neighbours are at most one level apart
+    assert sorted(perm.tolist()) == list(range(A.n))
+    for v in range(A.n):
+        for e in range(A.rowptr[v], A.rowptr[v + 1]):
+            assert abs(lev_of[v] - lev_of[int(A.col[e])]) <= 1
+
+
+def test_permute_csr_symmetric():
+    A = w.random_sparse(30, 0.2, 9)
+    perm = w.rng(1).permutation(30)
+    B = oracle.permute_csr(A, perm)
+    D, E = A.to_dense(), B.to_dense()
+    assert np.array_equal(E, D[np.ix_(perm, perm)])
