@@ -1,0 +1,231 @@
+/*
+ * mpk.h -- C ABI of the MI355X level-blocked matrix power kernel.
+ *
+ * The operation (Lacey et al., "Cache Blocking of Distributed-Memory Parallel
+ * Matrix Power Kernels", Sec. "RACE Applied to the Matrix Power Kernel"):
+ * for a square sparse matrix A in CSR and a dense block x, compute every power
+ * y_k = A^k x, k = 1..p, and store all p results.  The level-blocked variant
+ * (LB-MPK, executed inside Alg. 2 as localLBMPK) returns exactly the same
+ * products as p back-to-back SpMVs (Alg. 1 without halo exchange); it only
+ * reorders them in time so that matrix rows are reused from cache across
+ * powers.  A three-term-recurrence form covers Chebyshev polynomial filters,
+ * Eq. (anderson_spmv).
+ *
+ * Conventions shared by every call:
+ *   - Indices are 0-based; row pointers and column indices are int32.
+ *   - Dense blocks are row-major with the right-hand side fastest:
+ *       x[i*nrhs + r],   Y[(k-1)*n*nrhs + i*nrhs + r] = (y_k)_{i,r}.
+ *     Y holds y_1..y_p (x itself is not copied into Y).
+ *   - x and Y are DEVICE pointers (HIP device memory of the plan's device);
+ *     they must not overlap.  The caller owns them.
+ *   - Calls that take a stream are asynchronous on that stream (NULL = the
+ *     null stream).  Argument errors are reported synchronously through the
+ *     return code; a device-side failure (a dependency wait that exceeded its
+ *     time limit) is reported by mpk_plan_sync.
+ *   - No C++ exception crosses this interface.  On any status other than
+ *     MPK_OK, mpk_last_error() returns a thread-local message.
+ *   - A plan is safe to use from several host threads and streams at once;
+ *     concurrent runs on one plan draw separate dependency workspaces.
+ */
+#ifndef MPK_H
+#define MPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPK_OK = 0,
+    MPK_EINVAL = 1,        /* bad argument (NULL pointer, p < 1, ...)            */
+    MPK_EBADCSR = 2,       /* CSR not valid: rowptr not monotone, col out of range */
+    MPK_ENOMEM = 3,        /* host or device allocation failed                   */
+    MPK_EHIP = 4,          /* a HIP runtime call failed                          */
+    MPK_EUNSUPPORTED = 5,  /* valid but unsupported (nrhs > 16, nnz >= 2^31, ...) */
+    MPK_ETIMEOUT = 6,      /* device dependency wait exceeded its limit          */
+    MPK_ENODEVICE = 7      /* run requested on a host-only plan                  */
+} mpk_status_t;
+
+/* Row order of the vectors passed to the run calls. */
+enum {
+    MPK_ORDER_ORIGINAL = 0, /* x and Y use the caller's row numbering (default)   */
+    MPK_ORDER_PLAN = 1      /* x and Y use the plan's (BFS) numbering; see mpk_permute */
+};
+
+/* Symmetric reordering applied by the planner. */
+enum {
+    MPK_REORDER_BFS = 0,    /* BFS level order from the root (the paper's choice) */
+    MPK_REORDER_NONE = 1    /* keep the caller's order (levels derived from it)   */
+};
+
+/* Traversal order of the (chunk, power) tasks. */
+enum {
+    MPK_SCHED_WAVE = 0,     /* skewed chunk wavefront (default)                    */
+    MPK_SCHED_DIAG = 1,     /* the paper's Lp-diagram diagonals over level groups  */
+    MPK_SCHED_POWERS = 2    /* power by power (all chunks of y_1, then y_2, ...)   */
+};
+
+#define MPK_DEVICE_CURRENT (-1)
+#define MPK_DEVICE_NONE (-2)   /* host-only plan: levels and schedules, no device data */
+#define MPK_MAX_RHS 16
+
+/* Host CSR handed to mpk_plan.  The plan copies it; the caller may free its
+ * arrays when mpk_plan returns.  val may be NULL for a host-only plan. */
+typedef struct {
+    int64_t n;               /* rows = columns                                 */
+    int64_t nnz;             /* rowptr[n]                                      */
+    const int32_t *rowptr;   /* n+1 entries, rowptr[0] = 0, non-decreasing     */
+    const int32_t *col;      /* nnz entries, 0 <= col < n (duplicates allowed) */
+    const double *val;       /* nnz entries                                    */
+} mpk_csr_t;
+
+typedef struct {
+    int value_bits;          /* 64 (default) or 32: values stored as float,
+                                promoted to double before each product        */
+    int reorder;             /* MPK_REORDER_BFS (default) or MPK_REORDER_NONE   */
+    int order;               /* MPK_ORDER_ORIGINAL (default) or MPK_ORDER_PLAN  */
+    int root;                /* BFS root row (default 0)                       */
+    int lanes_per_row;       /* 0 = chosen from the mean row length; else 1..16,
+                                a power of two.  Fixes the per-row summation
+                                order shared by every run kernel of the plan.  */
+    int device;              /* HIP device, MPK_DEVICE_CURRENT or MPK_DEVICE_NONE */
+} mpk_plan_opts_t;
+
+/* Run-time tuning of a plan (mpk_plan_tune).  None of these changes a result
+ * bit: the per-row arithmetic is fixed by lanes_per_row at plan time. */
+typedef struct {
+    int schedule;            /* MPK_SCHED_WAVE (default), _DIAG or _POWERS      */
+    int64_t cache_bytes;     /* blocking budget C in bytes (default 256 MiB)    */
+    double cache_safety;     /* fraction of C the window may use (default 0.5) */
+    int chunk_nnz;           /* target nonzeros per chunk (default 8192)       */
+    int lag;                 /* wavefront slack in chunks; 0 = from the budget  */
+    int workgroups;          /* persistent workgroups; 0 = fill the device      */
+    int rhs_per_thread;      /* 0 = auto; 1, 2, 4 or 8 (must divide nrhs)       */
+    int64_t spin_limit_us;   /* dependency-wait limit in microseconds, 0 = 2 s  */
+} mpk_tune_t;
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t n_levels;        /* BFS levels (or order-derived levels)           */
+    int32_t max_level_rows;
+    int32_t value_bits, reorder, order, lanes_per_row;
+    int64_t matrix_bytes;    /* device CSR bytes: 4(n+1) + (4 + value bytes) nnz */
+    double plan_ms;          /* host preprocessing time                         */
+    int32_t device;
+} mpk_plan_info_t;
+
+typedef struct {
+    int32_t p;               /* the schedule's power count                      */
+    int32_t n_chunks, n_groups, n_tasks;
+    int32_t lag;             /* effective wavefront slack                       */
+    int32_t max_reach;       /* max over chunks of dhi - c (in chunks)          */
+    double window_bytes;     /* estimated matrix bytes touched by one window    */
+    double build_ms;
+} mpk_sched_info_t;
+
+typedef struct mpk_plan_s *mpk_plan_t;
+
+/* Fill *opts / *tune with the defaults documented above. */
+void mpk_plan_opts_default(mpk_plan_opts_t *opts);
+void mpk_tune_default(mpk_tune_t *tune);
+
+/*
+ * Build a plan (host preprocessing + device upload): validate the CSR,
+ * symmetrise its pattern for the level construction, split the graph into BFS
+ * levels from opts->root with ascending original index inside each level,
+ * permute rows and columns symmetrically by level (in-row entry order is
+ * preserved), and upload the matrix.  (Sec. "RACE Applied to the Matrix Power
+ * Kernel": level equation, BFS reordering, and the endnote on non-symmetric
+ * patterns.)  Disconnected graphs restart a new level at the lowest unvisited
+ * row.  Errors: MPK_EINVAL (NULL, bad opts), MPK_EBADCSR, MPK_EUNSUPPORTED
+ * (nnz >= 2^31 or n >= 2^31), MPK_ENOMEM, MPK_EHIP.
+ */
+mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out);
+
+/* Release the plan and all device memory it owns (waits for its runs). */
+void mpk_plan_destroy(mpk_plan_t plan);
+
+/* Set the tuning used by later runs of this plan (NULL = defaults). */
+mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune);
+
+mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info);
+
+/* Copy out the level pointer (n_levels+1 entries) and the permutation
+ * perm[new] = old (n entries); either pointer may be NULL. */
+mpk_status_t mpk_plan_levels(mpk_plan_t plan, int32_t *level_ptr, int32_t *perm);
+
+/*
+ * Build (or fetch from the plan's cache) the schedule for p powers with the
+ * current tuning and describe it.  Arrays are host memory and may be NULL:
+ * chunk_ptr[n_chunks+1] (row ranges in plan order), chunk_group[n_chunks],
+ * dep_lo/dep_hi[n_chunks] (inclusive chunk range a chunk's rows read), and
+ * tasks[2*n_tasks] = (chunk, power) pairs in issue order.
+ */
+mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info,
+                               int32_t *chunk_ptr, int32_t *chunk_group, int32_t *dep_lo,
+                               int32_t *dep_hi, int32_t *tasks);
+
+/*
+ * Level-blocked matrix power kernel: Y = [A x, A^2 x, ..., A^p x].
+ * One persistent kernel walks the (chunk, power) tasks in the schedule's
+ * order; a task starts once the chunks its rows read are done at the previous
+ * power (the Lp-diagram dependency of Sec. "RACE Applied to the Matrix Power
+ * Kernel": level i at power k needs levels i-1..i+1 at power k-1).
+ * x: n*nrhs doubles; Y: p*n*nrhs doubles (device).  1 <= nrhs <= 16.
+ * Errors: MPK_EINVAL (p < 1, NULL), MPK_EUNSUPPORTED (nrhs), MPK_ENODEVICE.
+ */
+mpk_status_t mpk_run(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                     void *hip_stream);
+
+/*
+ * Three-term recurrence, Eq. (anderson_spmv) generalised:
+ *   y_1     = alpha[0] A x   + beta[0] x
+ *   y_{j+1} = alpha[j] A y_j + beta[j] y_j + gamma[j] y_{j-1},  j = 1..p-1
+ * (y_0 = x; gamma[0] is ignored).  Chebyshev: alpha = (1,2,2,...), beta = 0,
+ * gamma = (0,-1,-1,...).  alpha, beta, gamma are HOST arrays of p doubles,
+ * captured at call time.  Same layouts and errors as mpk_run.
+ */
+mpk_status_t mpk_run_recur(mpk_plan_t plan, const double *x, int p, int nrhs,
+                           const double *alpha, const double *beta, const double *gamma,
+                           double *Y, void *hip_stream);
+
+/*
+ * Baseline: p back-to-back CSR SpMVs, one kernel launch per power (Alg. 1
+ * without halo exchange), on the plan's matrix with the plan's per-row
+ * summation order, so its results are bit-identical to mpk_run's.
+ */
+mpk_status_t mpk_run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                              void *hip_stream);
+mpk_status_t mpk_run_baseline_recur(mpk_plan_t plan, const double *x, int p, int nrhs,
+                                    const double *alpha, const double *beta,
+                                    const double *gamma, double *Y, void *hip_stream);
+
+/*
+ * Convert nvec blocks of n*nrhs doubles between the caller's numbering and
+ * the plan's: to_plan != 0 gives out[new] = in[perm[new]], else
+ * out[perm[new]] = in[new].  Device pointers, must not overlap.
+ */
+mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double *out, int nvec,
+                         int nrhs, void *hip_stream);
+
+/* Wait for every run issued on this plan and report device-side failures
+ * (MPK_ETIMEOUT when a dependency wait hit its limit). */
+mpk_status_t mpk_plan_sync(mpk_plan_t plan);
+
+/* Device allocator used for plan data (NULL, NULL restores hipMalloc/hipFree). */
+mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx),
+                               void (*free_fn)(void *ptr, void *ctx), void *ctx);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *mpk_last_error(void);
+
+/* Library version string. */
+const char *mpk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPK_H */

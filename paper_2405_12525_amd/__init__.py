@@ -1,0 +1,270 @@
+"""MI355X level-blocked matrix power kernel (Python binding of libmpk.so).
+
+Computes y_k = A^k x for k = 1..p (all powers kept) for a CSR matrix A, as
+in Lacey et al., "Cache Blocking of Distributed-Memory Parallel Matrix Power
+Kernels": the level-blocked kernel (Sec. "RACE Applied to the Matrix Power
+Kernel"; localLBMPK of Alg. 2 on one process) and its p x SpMV baseline
+(Alg. 1 without halo exchange), plus the Chebyshev-style three-term
+recurrence of Eq. (anderson_spmv).  Every step runs in the HIP kernels of
+libmpk.so; this module only marshals arguments.  PyTorch supplies device
+memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi
+from ._capi import (MPK_DEVICE_CURRENT, MPK_DEVICE_NONE, MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN,
+                    MPK_REORDER_BFS, MPK_REORDER_NONE, MPK_SCHED_DIAG, MPK_SCHED_POWERS,
+                    MPK_SCHED_WAVE, MPKError, check)
+
+__all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN",
+           "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
+           "MPK_SCHED_POWERS", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
+           "flops", "lib"]
+
+_SCHED = {"wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG, "powers": MPK_SCHED_POWERS}
+
+
+def lib():
+    return _capi.load()
+
+
+def version() -> str:
+    return lib().mpk_version().decode()
+
+
+def chebyshev_coefficients(p: int):
+    """Coefficients of v_1 = H v_0, v_{k+1} = 2 H v_k - v_{k-1} for mpk_run_recur."""
+    a = np.full(p, 2.0)
+    a[0] = 1.0
+    g = np.full(p, -1.0)
+    g[0] = 0.0
+    return a, np.zeros(p), g
+
+
+def flops(nnz: int, n: int, p: int, nrhs: int, recur: bool = False) -> float:
+    """2 flops per nonzero and right-hand side per power (plus the recurrence update)."""
+    f = 2.0 * nnz * nrhs * p
+    if recur:
+        f += 2.0 * n * nrhs * max(0, p - 1)
+    return f
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _vec_check(t, n, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.shape[0] != n:
+        raise ValueError(f"{name} has {t.shape[0]} rows, expected {n}")
+
+
+class Plan:
+    """A preprocessed matrix resident on one device (or host-only).
+
+    ``A`` is any object with ``n``, ``rowptr`` (int32), ``col`` (int32) and
+    ``val`` (float64) attributes, e.g. :class:`workloads.CSR`.
+    """
+
+    def __init__(self, A, value_bits: int = 64, reorder: str = "bfs", order: str = "original",
+                 root: int = 0, lanes_per_row: int = 0, device=MPK_DEVICE_CURRENT):
+        L = lib()
+        self._lib = L
+        self._h = ctypes.c_void_p()
+        rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(A.col, dtype=np.int32)
+        val = None if A.val is None else np.ascontiguousarray(A.val, dtype=np.float64)
+        csr = _capi.CSRStruct(int(A.n), int(rowptr[-1]) if rowptr.size else 0,
+                              rowptr.ctypes.data, col.ctypes.data if col.size else None,
+                              val.ctypes.data if (val is not None and val.size) else None)
+        opts = _capi.PlanOpts()
+        L.mpk_plan_opts_default(ctypes.byref(opts))
+        opts.value_bits = int(value_bits)
+        opts.reorder = {"bfs": MPK_REORDER_BFS, "none": MPK_REORDER_NONE}[reorder]
+        opts.order = {"original": MPK_ORDER_ORIGINAL, "plan": MPK_ORDER_PLAN}[order]
+        opts.root = int(root)
+        opts.lanes_per_row = int(lanes_per_row)
+        if device is None or device == "none":
+            device = MPK_DEVICE_NONE
+        opts.device = int(device)
+        check(L.mpk_plan(ctypes.byref(csr), ctypes.byref(opts), ctypes.byref(self._h)))
+        self.n = int(A.n)
+        self.nnz = int(csr.nnz)
+        self.order = order
+        self.host_only = opts.device == MPK_DEVICE_NONE
+        self._tune = self.default_tune()
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.mpk_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------ queries
+    def info(self) -> dict:
+        i = _capi.PlanInfo()
+        check(self._lib.mpk_plan_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _capi.PlanInfo._fields_}
+
+    def levels(self):
+        """(level_ptr, perm) with perm[new] = old."""
+        nl = self.info()["n_levels"]
+        lp = np.zeros(nl + 1, dtype=np.int32)
+        perm = np.zeros(self.n, dtype=np.int32)
+        check(self._lib.mpk_plan_levels(self._h, lp.ctypes.data, perm.ctypes.data))
+        return lp, perm
+
+    def schedule(self, p: int) -> dict:
+        si = _capi.SchedInfo()
+        check(self._lib.mpk_plan_schedule(self._h, int(p), ctypes.byref(si), None, None, None,
+                                          None, None))
+        nc, nt = si.n_chunks, si.n_tasks
+        cp = np.zeros(nc + 1, np.int32)
+        cg = np.zeros(nc, np.int32)
+        lo = np.zeros(nc, np.int32)
+        hi = np.zeros(nc, np.int32)
+        tasks = np.zeros(2 * nt, np.int32)
+        check(self._lib.mpk_plan_schedule(self._h, int(p), ctypes.byref(si), cp.ctypes.data,
+                                          cg.ctypes.data, lo.ctypes.data, hi.ctypes.data,
+                                          tasks.ctypes.data))
+        d = {f: getattr(si, f) for f, _ in _capi.SchedInfo._fields_}
+        d.update(chunk_ptr=cp, chunk_group=cg, dep_lo=lo, dep_hi=hi, tasks=tasks.reshape(-1, 2))
+        return d
+
+    # ------------------------------------------------------------ tuning
+    @staticmethod
+    def default_tune() -> dict:
+        t = _capi.Tune()
+        lib().mpk_tune_default(ctypes.byref(t))
+        d = {f: getattr(t, f) for f, _ in _capi.Tune._fields_}
+        d["schedule"] = {v: k for k, v in _SCHED.items()}[d["schedule"]]
+        return d
+
+    def tune(self, **kw) -> dict:
+        d = dict(self._tune)
+        for k, v in kw.items():
+            if k not in d:
+                raise KeyError(k)
+            d[k] = v
+        t = _capi.Tune()
+        for f, _ in _capi.Tune._fields_:
+            v = d[f]
+            if f == "schedule" and isinstance(v, str):
+                v = _SCHED[v]
+            setattr(t, f, v)
+        check(self._lib.mpk_plan_tune(self._h, ctypes.byref(t)))
+        self._tune = d
+        return dict(d)
+
+    @property
+    def tuning(self) -> dict:
+        return dict(self._tune)
+
+    # ------------------------------------------------------------ runs
+    def _prep(self, x, p, Y):
+        torch = _torch()
+        _vec_check(x, self.n, "x")
+        R = 1 if x.dim() == 1 else int(x.shape[1])
+        if Y is None:
+            Y = torch.empty((p, self.n, R), dtype=torch.float64, device=x.device)
+        else:
+            if tuple(Y.shape) != (p, self.n, R) and tuple(Y.shape) != (p, self.n) or \
+                    Y.numel() != p * self.n * R:
+                raise ValueError("Y must have shape (p, n, nrhs)")
+            if Y.dtype != torch.float64 or not Y.is_contiguous() or not Y.is_cuda:
+                raise TypeError("Y must be a contiguous float64 device tensor")
+        return R, Y
+
+    def run(self, x, p: int, Y=None, stream=None):
+        """Level-blocked MPK: returns Y with Y[k-1] = A^k x."""
+        R, Y = self._prep(x, p, Y)
+        check(self._lib.mpk_run(self._h, ctypes.c_void_p(x.data_ptr()), int(p), R,
+                                ctypes.c_void_p(Y.data_ptr()), _stream_handle(stream)))
+        return Y
+
+    def run_baseline(self, x, p: int, Y=None, stream=None):
+        """p back-to-back SpMVs (one launch per power); bit-identical to run()."""
+        R, Y = self._prep(x, p, Y)
+        check(self._lib.mpk_run_baseline(self._h, ctypes.c_void_p(x.data_ptr()), int(p), R,
+                                         ctypes.c_void_p(Y.data_ptr()), _stream_handle(stream)))
+        return Y
+
+    def _coefs(self, alpha, beta, gamma):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        g = np.ascontiguousarray(gamma, dtype=np.float64)
+        if not (a.size == b.size == g.size) or a.size < 1:
+            raise ValueError("alpha, beta, gamma must have the same length p >= 1")
+        return a, b, g
+
+    def run_recur(self, x, alpha, beta, gamma, Y=None, stream=None):
+        """Three-term recurrence y_{j+1} = alpha_j A y_j + beta_j y_j + gamma_j y_{j-1}."""
+        a, b, g = self._coefs(alpha, beta, gamma)
+        p = a.size
+        R, Y = self._prep(x, p, Y)
+        check(self._lib.mpk_run_recur(self._h, ctypes.c_void_p(x.data_ptr()), p, R,
+                                      a.ctypes.data, b.ctypes.data, g.ctypes.data,
+                                      ctypes.c_void_p(Y.data_ptr()), _stream_handle(stream)))
+        return Y
+
+    def run_baseline_recur(self, x, alpha, beta, gamma, Y=None, stream=None):
+        a, b, g = self._coefs(alpha, beta, gamma)
+        p = a.size
+        R, Y = self._prep(x, p, Y)
+        check(self._lib.mpk_run_baseline_recur(self._h, ctypes.c_void_p(x.data_ptr()), p, R,
+                                               a.ctypes.data, b.ctypes.data, g.ctypes.data,
+                                               ctypes.c_void_p(Y.data_ptr()),
+                                               _stream_handle(stream)))
+        return Y
+
+    def permute(self, v, to_plan: bool, out=None, stream=None):
+        """Convert (nvec, n, R) / (n, R) / (n,) blocks between numberings."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(v)
+        if v.dim() == 1:
+            nvec, R = 1, 1
+        elif v.dim() == 2:
+            nvec, R = 1, int(v.shape[1])
+        else:
+            nvec, R = int(v.shape[0]), int(v.shape[2])
+        if v.dtype != torch.float64 or not v.is_contiguous() or out.shape != v.shape:
+            raise ValueError("permute needs contiguous float64 tensors of equal shape")
+        check(self._lib.mpk_permute(self._h, 1 if to_plan else 0, ctypes.c_void_p(v.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), nvec, R,
+                                    _stream_handle(stream)))
+        return out
+
+    def sync(self):
+        """Wait for this plan's runs; raises MPKError(MPK_ETIMEOUT) on a failed wait."""
+        check(self._lib.mpk_plan_sync(self._h))

@@ -1,0 +1,125 @@
+"""ctypes declarations of the C ABI in include/mpk.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmpk.so")
+
+MPK_OK, MPK_EINVAL, MPK_EBADCSR, MPK_ENOMEM, MPK_EHIP, MPK_EUNSUPPORTED, MPK_ETIMEOUT, \
+    MPK_ENODEVICE = range(8)
+STATUS_NAMES = {0: "MPK_OK", 1: "MPK_EINVAL", 2: "MPK_EBADCSR", 3: "MPK_ENOMEM", 4: "MPK_EHIP",
+                5: "MPK_EUNSUPPORTED", 6: "MPK_ETIMEOUT", 7: "MPK_ENODEVICE"}
+MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN = 0, 1
+MPK_REORDER_BFS, MPK_REORDER_NONE = 0, 1
+MPK_SCHED_WAVE, MPK_SCHED_DIAG, MPK_SCHED_POWERS = 0, 1, 2
+MPK_DEVICE_CURRENT, MPK_DEVICE_NONE = -1, -2
+MPK_MAX_RHS = 16
+
+# every symbol the header declares
+EXPORTS = [
+    "mpk_plan_opts_default", "mpk_tune_default", "mpk_plan", "mpk_plan_destroy", "mpk_plan_tune",
+    "mpk_plan_info", "mpk_plan_levels", "mpk_plan_schedule", "mpk_run", "mpk_run_recur",
+    "mpk_run_baseline", "mpk_run_baseline_recur", "mpk_permute", "mpk_plan_sync",
+    "mpk_set_allocator", "mpk_last_error", "mpk_version",
+]
+
+c_i32p = ctypes.POINTER(ctypes.c_int32)
+c_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class CSRStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("value_bits", ctypes.c_int), ("reorder", ctypes.c_int), ("order", ctypes.c_int),
+                ("root", ctypes.c_int), ("lanes_per_row", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int), ("cache_bytes", ctypes.c_int64),
+                ("cache_safety", ctypes.c_double), ("chunk_nnz", ctypes.c_int),
+                ("lag", ctypes.c_int), ("workgroups", ctypes.c_int),
+                ("rhs_per_thread", ctypes.c_int), ("spin_limit_us", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("max_level_rows", ctypes.c_int32), ("value_bits", ctypes.c_int32),
+                ("reorder", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("lanes_per_row", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
+                ("plan_ms", ctypes.c_double), ("device", ctypes.c_int32)]
+
+
+class SchedInfo(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("n_chunks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+                ("n_tasks", ctypes.c_int32), ("lag", ctypes.c_int32), ("max_reach", ctypes.c_int32),
+                ("window_bytes", ctypes.c_double), ("build_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmpk.so; raise (never fall back) when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2405_12525_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    st = ctypes.c_int
+    lib.mpk_plan_opts_default.argtypes = [ctypes.POINTER(PlanOpts)]
+    lib.mpk_plan_opts_default.restype = None
+    lib.mpk_tune_default.argtypes = [ctypes.POINTER(Tune)]
+    lib.mpk_tune_default.restype = None
+    lib.mpk_plan.argtypes = [ctypes.POINTER(CSRStruct), ctypes.POINTER(PlanOpts),
+                             ctypes.POINTER(ctypes.c_void_p)]
+    lib.mpk_plan.restype = st
+    lib.mpk_plan_destroy.argtypes = [P]
+    lib.mpk_plan_destroy.restype = None
+    lib.mpk_plan_tune.argtypes = [P, ctypes.POINTER(Tune)]
+    lib.mpk_plan_tune.restype = st
+    lib.mpk_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    lib.mpk_plan_info.restype = st
+    lib.mpk_plan_levels.argtypes = [P, P, P]
+    lib.mpk_plan_levels.restype = st
+    lib.mpk_plan_schedule.argtypes = [P, ctypes.c_int, ctypes.POINTER(SchedInfo), P, P, P, P, P]
+    lib.mpk_plan_schedule.restype = st
+    lib.mpk_run.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P]
+    lib.mpk_run.restype = st
+    lib.mpk_run_recur.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+    lib.mpk_run_recur.restype = st
+    lib.mpk_run_baseline.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P]
+    lib.mpk_run_baseline.restype = st
+    lib.mpk_run_baseline_recur.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+    lib.mpk_run_baseline_recur.restype = st
+    lib.mpk_permute.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P]
+    lib.mpk_permute.restype = st
+    lib.mpk_plan_sync.argtypes = [P]
+    lib.mpk_plan_sync.restype = st
+    lib.mpk_set_allocator.argtypes = [P, P, P]
+    lib.mpk_set_allocator.restype = st
+    lib.mpk_last_error.argtypes = []
+    lib.mpk_last_error.restype = ctypes.c_char_p
+    lib.mpk_version.argtypes = []
+    lib.mpk_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class MPKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def check(status: int):
+    if status != MPK_OK:
+        msg = load().mpk_last_error().decode(errors="replace")
+        raise MPKError(status, msg)

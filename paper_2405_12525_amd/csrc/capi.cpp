@@ -1,0 +1,613 @@
+// C ABI: plan construction, schedule cache, dependency workspaces and the run
+// entry points declared in include/mpk.h.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mpk_internal.h"
+
+using namespace mpk;
+
+namespace {
+
+thread_local std::string g_err;
+
+mpk_status_t fail(mpk_status_t st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+mpk_status_t hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return MPK_EHIP;
+}
+
+struct Allocator {
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+// Device allocation through the installed hook (or hipMalloc).  The free
+// function captured at allocation time is kept with the buffer.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    Allocator how;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (!ptr) return;
+        if (how.free_fn) how.free_fn(ptr, how.ctx);
+        else (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    mpk_status_t alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        {
+            std::lock_guard<std::mutex> g(g_alloc_mu);
+            how = g_alloc;
+        }
+        if (how.alloc_fn) {
+            ptr = how.alloc_fn(n, how.ctx);
+            if (!ptr) return fail(MPK_ENOMEM, "device allocator returned NULL");
+        } else {
+            hipError_t e = hipMalloc(&ptr, n);
+            if (e != hipSuccess) {
+                ptr = nullptr;
+                return e == hipErrorOutOfMemory ? fail(MPK_ENOMEM, "hipMalloc: out of memory")
+                                                : hip_fail(e, "hipMalloc");
+            }
+        }
+        bytes = n;
+        return MPK_OK;
+    }
+    mpk_status_t upload(const void *src, size_t n) {
+        mpk_status_t st = alloc(n);
+        if (st) return st;
+        if (n && src) {
+            hipError_t e = hipMemcpy(ptr, src, n, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        }
+        return MPK_OK;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+struct SchedEntry {
+    Schedule host;
+    DevBuf chunk_ptr, dep_lo, dep_hi, tasks;
+    int workgroups = 0;
+};
+
+struct Workspace {
+    DevBuf buf;          // done[cap] | ticket | err
+    int32_t cap = 0;
+    hipEvent_t ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool recorded = false;
+    bool reserved = false;  // owned by a captured graph
+    DevWorkspace view() const {
+        int32_t *b = buf.as<int32_t>();
+        return DevWorkspace{b, b + cap, b + cap + 1};
+    }
+};
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct mpk_plan_s {
+    int64_t n = 0, nnz = 0;
+    int value_bits = 64, reorder = MPK_REORDER_BFS, order = MPK_ORDER_ORIGINAL;
+    int lanes = 1, device = MPK_DEVICE_NONE;
+    bool host_only = true;
+    double plan_ms = 0.0;
+    int wall_khz = 100000;
+    // host data kept for schedules and queries
+    Levels lv;
+    std::vector<int32_t> rowptr, row_lo, row_hi;
+    // device data
+    DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
+    // schedules and workspaces
+    std::mutex mu;
+    mpk_tune_t tune{};
+    std::map<int, std::unique_ptr<SchedEntry>> scheds;
+    std::vector<std::unique_ptr<SchedEntry>> retired;
+    std::vector<std::unique_ptr<Workspace>> pool;
+    std::map<long long, int> wg_cache;
+
+    DevMatrix matrix() const {
+        return DevMatrix{d_rowptr.as<int32_t>(), d_col.as<int32_t>(), d_val.ptr,
+                         d_outrow.as<int32_t>(), (int32_t)n, value_bits, lanes};
+    }
+    ~mpk_plan_s() {
+        if (!host_only) {
+            (void)hipSetDevice(device);
+            for (auto &w : pool) {
+                if (w->ev) {
+                    (void)hipEventSynchronize(w->ev);
+                    (void)hipEventDestroy(w->ev);
+                }
+            }
+            (void)hipDeviceSynchronize();
+        }
+    }
+};
+
+namespace {
+
+int pick_lanes(int64_t n, int64_t nnz) {
+    const double mean = n ? (double)nnz / (double)n : 0.0;
+    int L = 1;
+    while (L < 16 && 2.0 * L * 6.0 <= mean) L *= 2;
+    return L;
+}
+
+int pick_rt(const mpk_tune_t &t, int lanes, int R) {
+    if (t.rhs_per_thread > 0) return t.rhs_per_thread;
+    int rt = 4;  // largest power of two <= 4 that divides R
+    while (rt > 1 && (rt > R || R % rt)) rt >>= 1;
+    (void)lanes;
+    return rt;
+}
+
+mpk_status_t check_device_plan(mpk_plan_t plan) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (plan->host_only) return fail(MPK_ENODEVICE, "plan was built without a device");
+    return MPK_OK;
+}
+
+// Schedule for p powers with the plan's current tuning (plan->mu held).
+mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_wg) {
+    auto it = plan->scheds.find(p);
+    if (it != plan->scheds.end()) {
+        *out = it->second.get();
+        return MPK_OK;
+    }
+    auto e = std::make_unique<SchedEntry>();
+    PlanShape sh{plan->n, plan->nnz, plan->value_bits / 8, &plan->lv.level_ptr, &plan->rowptr,
+                 &plan->row_lo, &plan->row_hi};
+    std::string err;
+    mpk_status_t st = build_schedule(sh, p, plan->tune, default_wg, e->host, err);
+    if (st) return fail(st, err);
+    if (!validate_schedule(e->host, err)) return fail(MPK_EINVAL, "schedule invalid: " + err);
+    if (!plan->host_only) {
+        const Schedule &s = e->host;
+        if ((st = e->chunk_ptr.upload(s.chunk_ptr.data(), s.chunk_ptr.size() * 4))) return st;
+        if ((st = e->dep_lo.upload(s.dep_lo.data(), s.dep_lo.size() * 4))) return st;
+        if ((st = e->dep_hi.upload(s.dep_hi.data(), s.dep_hi.size() * 4))) return st;
+        if ((st = e->tasks.upload(s.tasks.data(), s.tasks.size() * 4))) return st;
+    }
+    *out = e.get();
+    plan->scheds[p] = std::move(e);
+    return MPK_OK;
+}
+
+// A dependency workspace that no unfinished run uses (plan->mu held).
+mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream, bool capturing,
+                           Workspace **out) {
+    for (auto &w : plan->pool) {
+        if (w->reserved || w->cap < n_chunks) continue;
+        bool free_now = !w->recorded || w->last_stream == stream;
+        if (!free_now && !capturing) free_now = hipEventQuery(w->ev) == hipSuccess;
+        if (free_now) {
+            *out = w.get();
+            return MPK_OK;
+        }
+    }
+    if (capturing) {
+        // allocation is not allowed while a stream is being captured
+        return fail(MPK_EINVAL, "no idle workspace: run once outside capture first");
+    }
+    auto w = std::make_unique<Workspace>();
+    w->cap = std::max<int32_t>(n_chunks, 1024);
+    mpk_status_t st = w->buf.alloc(((size_t)w->cap + 2) * sizeof(int32_t));
+    if (st) return st;
+    hipError_t e = hipMemset(w->buf.ptr, 0, ((size_t)w->cap + 2) * sizeof(int32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMemset");
+    e = hipEventCreateWithFlags(&w->ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    *out = w.get();
+    plan->pool.push_back(std::move(w));
+    return MPK_OK;
+}
+
+int default_workgroups(mpk_plan_t plan, int rt) {
+    const long long key = (long long)plan->value_bits * 1000 + plan->lanes * 10 + rt;
+    auto it = plan->wg_cache.find(key);
+    if (it != plan->wg_cache.end()) return it->second;
+    int wg = lb_max_workgroups(plan->value_bits, plan->lanes, rt, plan->device);
+    if (wg <= 0) wg = 1024;
+    plan->wg_cache[key] = wg;
+    return wg;
+}
+
+mpk_status_t check_run_args(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (p < 1) return fail(MPK_EINVAL, "p must be >= 1");
+    if (nrhs < 1 || nrhs > MPK_MAX_RHS) return fail(MPK_EUNSUPPORTED, "nrhs must be in [1, 16]");
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    if (plan->n > 0 && (!x || !Y)) return fail(MPK_EINVAL, "x or Y is NULL");
+    const size_t xb = (size_t)plan->n * nrhs * sizeof(double);
+    const char *xs = reinterpret_cast<const char *>(x), *ys = reinterpret_cast<const char *>(Y);
+    if (plan->n > 0 && xs < ys + xb * (size_t)p && ys < xs + xb)
+        return fail(MPK_EINVAL, "x and Y overlap");
+    return MPK_OK;
+}
+
+mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
+                    const double *beta, const double *gamma, double *Y, void *stream_v) {
+    mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
+    if (st) return st;
+    const bool recur = alpha != nullptr;
+    if (recur && (!beta || !gamma)) return fail(MPK_EINVAL, "alpha, beta and gamma are all required");
+    if (plan->n == 0) return MPK_OK;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (stream) (void)hipStreamIsCapturing(stream, &cap);
+    const bool capturing = cap == hipStreamCaptureStatusActive;
+
+    std::lock_guard<std::mutex> g(plan->mu);
+    const int rt = pick_rt(plan->tune, plan->lanes, nrhs);
+    if (!kernel_config_ok(plan->lanes, rt) || nrhs % rt || plan->lanes * (nrhs / rt) > 256)
+        return fail(MPK_EUNSUPPORTED, "rhs_per_thread does not fit nrhs / lanes");
+    const int wg_default = default_workgroups(plan, rt);
+    const int wg = plan->tune.workgroups > 0 ? plan->tune.workgroups : wg_default;
+    const int64_t limit_us = plan->tune.spin_limit_us > 0 ? plan->tune.spin_limit_us : 2000000;
+    const int64_t spin_ticks = limit_us * (int64_t)plan->wall_khz / 1000;
+    const size_t stride = (size_t)plan->n * nrhs;
+    const DevMatrix m = plan->matrix();
+    for (int base = 0; base < p; base += kMaxSegPowers) {
+        const int ps = std::min(kMaxSegPowers, p - base);
+        SchedEntry *se = nullptr;
+        if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
+        Workspace *ws = nullptr;
+        if ((st = get_workspace(plan, se->host.n_chunks(), stream, capturing, &ws))) return st;
+        SegArgs a;
+        a.in0 = base == 0 ? x : Y + (size_t)(base - 1) * stride;
+        a.inm1 = base == 0 ? nullptr : (base == 1 ? x : Y + (size_t)(base - 2) * stride);
+        a.Y = Y + (size_t)base * stride;
+        a.p = ps;
+        a.R = nrhs;
+        a.recur = recur ? 1 : 0;
+        Coefs cf{};
+        if (recur)
+            for (int j = 0; j < ps; ++j) {
+                cf.alpha[j] = alpha[base + j];
+                cf.beta[j] = beta[base + j];
+                cf.gamma[j] = gamma[base + j];
+            }
+        DevSchedule ds{se->chunk_ptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
+                       se->dep_hi.as<int32_t>(), se->tasks.as<int32_t>(), se->host.n_tasks(),
+                       se->host.n_chunks()};
+        int rc = launch_reset(ws->view(), se->host.n_chunks(), stream);
+        if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
+        rc = launch_lb(m, ds, ws->view(), a, &cf, rt, wg, spin_ticks, stream);
+        if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
+        if (capturing) {
+            ws->reserved = true;
+        } else {
+            e = hipEventRecord(ws->ev, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            ws->recorded = true;
+            ws->last_stream = stream;
+        }
+    }
+    return MPK_OK;
+}
+
+mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
+                          const double *beta, const double *gamma, double *Y, void *stream_v) {
+    mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
+    if (st) return st;
+    const bool recur = alpha != nullptr;
+    if (recur && (!beta || !gamma)) return fail(MPK_EINVAL, "alpha, beta and gamma are all required");
+    if (plan->n == 0) return MPK_OK;
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int rt;
+    {
+        std::lock_guard<std::mutex> g(plan->mu);
+        rt = pick_rt(plan->tune, plan->lanes, nrhs);
+    }
+    if (!kernel_config_ok(plan->lanes, rt) || nrhs % rt || plan->lanes * (nrhs / rt) > 256)
+        return fail(MPK_EUNSUPPORTED, "rhs_per_thread does not fit nrhs / lanes");
+    const size_t stride = (size_t)plan->n * nrhs;
+    const DevMatrix m = plan->matrix();
+    for (int k = 1; k <= p; ++k) {
+        const double *in = k == 1 ? x : Y + (size_t)(k - 2) * stride;
+        const double *prev = k == 1 ? nullptr : (k == 2 ? x : Y + (size_t)(k - 3) * stride);
+        double *out = Y + (size_t)(k - 1) * stride;
+        int rc = launch_spmv_power(m, in, prev, out, nrhs, recur ? 1 : 0,
+                                   recur ? alpha[k - 1] : 1.0, recur ? beta[k - 1] : 0.0,
+                                   recur ? gamma[k - 1] : 0.0, rt, stream_v);
+        if (rc) return hip_fail((hipError_t)rc, "spmv kernel launch");
+    }
+    return MPK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpk_last_error(void) { return g_err.c_str(); }
+
+const char *mpk_version(void) { return "mpk-mi355x 0.1"; }
+
+void mpk_plan_opts_default(mpk_plan_opts_t *o) {
+    if (!o) return;
+    o->value_bits = 64;
+    o->reorder = MPK_REORDER_BFS;
+    o->order = MPK_ORDER_ORIGINAL;
+    o->root = 0;
+    o->lanes_per_row = 0;
+    o->device = MPK_DEVICE_CURRENT;
+}
+
+void mpk_tune_default(mpk_tune_t *t) {
+    if (!t) return;
+    t->schedule = MPK_SCHED_WAVE;
+    t->cache_bytes = (int64_t)256 << 20;
+    t->cache_safety = 0.5;
+    t->chunk_nnz = 8192;
+    t->lag = 0;
+    t->workgroups = 0;
+    t->rhs_per_thread = 0;
+    t->spin_limit_us = 0;
+}
+
+mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
+                               void *ctx) {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+        return fail(MPK_EINVAL, "give both allocator functions or neither");
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc = Allocator{alloc_fn, free_fn, ctx};
+    return MPK_OK;
+}
+
+mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out) {
+    if (!out) return fail(MPK_EINVAL, "out is NULL");
+    *out = nullptr;
+    mpk_plan_opts_t o;
+    mpk_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.value_bits != 64 && o.value_bits != 32) return fail(MPK_EINVAL, "value_bits must be 32 or 64");
+    if (o.reorder != MPK_REORDER_BFS && o.reorder != MPK_REORDER_NONE) return fail(MPK_EINVAL, "bad reorder");
+    if (o.order != MPK_ORDER_ORIGINAL && o.order != MPK_ORDER_PLAN) return fail(MPK_EINVAL, "bad order");
+    if (o.lanes_per_row != 0 && !kernel_config_ok(o.lanes_per_row, 1))
+        return fail(MPK_EINVAL, "lanes_per_row must be 0, 1, 2, 4, 8 or 16");
+    const bool host_only = o.device == MPK_DEVICE_NONE;
+    std::string err;
+    mpk_status_t st = validate_csr(A, !host_only, err);
+    if (st) return fail(st, err);
+    if (A->n > 0 && (o.root < 0 || o.root >= A->n)) return fail(MPK_EINVAL, "root out of range");
+
+    const double t0 = now_ms();
+    std::unique_ptr<mpk_plan_s> plan;
+    try {
+        plan.reset(new mpk_plan_s());
+        plan->n = A->n;
+        plan->nnz = A->nnz;
+        plan->value_bits = o.value_bits;
+        plan->reorder = o.reorder;
+        plan->order = o.order;
+        plan->host_only = host_only;
+        plan->lanes = o.lanes_per_row ? o.lanes_per_row : pick_lanes(A->n, A->nnz);
+        mpk_tune_default(&plan->tune);
+        plan->lv = o.reorder == MPK_REORDER_BFS ? bfs_levels(A->n, A->rowptr, A->col, o.root)
+                                                : order_levels(A->n, A->rowptr, A->col);
+        PermutedCSR pc;
+        const bool plan_cols = o.order == MPK_ORDER_PLAN;
+        permute_csr(A->n, A->rowptr, A->col, host_only ? nullptr : A->val, plan->lv, plan_cols, pc);
+        plan->rowptr = pc.rowptr;
+        plan->row_lo.swap(pc.row_lo);
+        plan->row_hi.swap(pc.row_hi);
+        if (!host_only) {
+            int dev = o.device;
+            if (dev == MPK_DEVICE_CURRENT) {
+                hipError_t e = hipGetDevice(&dev);
+                if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+            }
+            hipError_t e = hipSetDevice(dev);
+            if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+            plan->device = dev;
+            int khz = 0;
+            if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+                plan->wall_khz = khz;
+            const size_t nnz = (size_t)A->nnz;
+            if ((st = plan->d_rowptr.upload(pc.rowptr.data(), pc.rowptr.size() * 4))) return st;
+            if ((st = plan->d_col.upload(pc.col.data(), nnz * 4))) return st;
+            if (o.value_bits == 64) {
+                if ((st = plan->d_val.upload(pc.val.data(), nnz * 8))) return st;
+            } else {
+                std::vector<float> v32(nnz);
+                for (size_t i = 0; i < nnz; ++i) v32[i] = (float)pc.val[i];
+                if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
+            }
+            bool identity = true;
+            for (int64_t i = 0; i < A->n && identity; ++i) identity = plan->lv.perm[i] == i;
+            if (!identity) {
+                if ((st = plan->d_perm.upload(plan->lv.perm.data(), (size_t)A->n * 4))) return st;
+                if (o.order == MPK_ORDER_ORIGINAL)
+                    if ((st = plan->d_outrow.upload(plan->lv.perm.data(), (size_t)A->n * 4))) return st;
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(MPK_ENOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(MPK_EINVAL, ex.what());
+    }
+    plan->plan_ms = now_ms() - t0;
+    *out = plan.release();
+    return MPK_OK;
+}
+
+void mpk_plan_destroy(mpk_plan_t plan) { delete plan; }
+
+mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    mpk_tune_t t;
+    mpk_tune_default(&t);
+    if (tune) t = *tune;
+    if (t.schedule < MPK_SCHED_WAVE || t.schedule > MPK_SCHED_POWERS) return fail(MPK_EINVAL, "bad schedule");
+    if (t.cache_bytes <= 0 || !(t.cache_safety > 0.0) || t.cache_safety > 1.0)
+        return fail(MPK_EINVAL, "cache_bytes must be > 0 and cache_safety in (0, 1]");
+    if (t.chunk_nnz < 1 || t.lag < 0 || t.workgroups < 0 || t.spin_limit_us < 0)
+        return fail(MPK_EINVAL, "negative tuning value");
+    if (t.rhs_per_thread != 0 && !kernel_config_ok(1, t.rhs_per_thread))
+        return fail(MPK_EINVAL, "rhs_per_thread must be 0, 1, 2, 4 or 8");
+    std::lock_guard<std::mutex> g(plan->mu);
+    plan->tune = t;
+    // schedules may still be read by queued kernels: keep them until destroy
+    for (auto &kv : plan->scheds) plan->retired.push_back(std::move(kv.second));
+    plan->scheds.clear();
+    return MPK_OK;
+}
+
+mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info) {
+    if (!plan || !info) return fail(MPK_EINVAL, "NULL argument");
+    info->n = plan->n;
+    info->nnz = plan->nnz;
+    info->n_levels = (int32_t)plan->lv.level_ptr.size() - 1;
+    int32_t mx = 0;
+    for (size_t l = 0; l + 1 < plan->lv.level_ptr.size(); ++l)
+        mx = std::max(mx, plan->lv.level_ptr[l + 1] - plan->lv.level_ptr[l]);
+    info->max_level_rows = mx;
+    info->value_bits = plan->value_bits;
+    info->reorder = plan->reorder;
+    info->order = plan->order;
+    info->lanes_per_row = plan->lanes;
+    info->matrix_bytes = 4 * (plan->n + 1) + (4 + plan->value_bits / 8) * plan->nnz;
+    info->plan_ms = plan->plan_ms;
+    info->device = plan->device;
+    return MPK_OK;
+}
+
+mpk_status_t mpk_plan_levels(mpk_plan_t plan, int32_t *level_ptr, int32_t *perm) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (level_ptr) std::copy(plan->lv.level_ptr.begin(), plan->lv.level_ptr.end(), level_ptr);
+    if (perm) std::copy(plan->lv.perm.begin(), plan->lv.perm.end(), perm);
+    return MPK_OK;
+}
+
+mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info, int32_t *chunk_ptr,
+                               int32_t *chunk_group, int32_t *dep_lo, int32_t *dep_hi,
+                               int32_t *tasks) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (p < 1 || p > kMaxSegPowers) return fail(MPK_EINVAL, "p must be in [1, 64]");
+    std::lock_guard<std::mutex> g(plan->mu);
+    int wg = 2048;
+    if (!plan->host_only) wg = default_workgroups(plan, 1);
+    SchedEntry *se = nullptr;
+    mpk_status_t st = get_schedule(plan, p, &se, wg);
+    if (st) return st;
+    const Schedule &s = se->host;
+    if (info) {
+        info->p = s.p;
+        info->n_chunks = s.n_chunks();
+        info->n_groups = s.n_groups;
+        info->n_tasks = s.n_tasks();
+        info->lag = s.lag;
+        info->max_reach = s.max_reach;
+        info->window_bytes = s.window_bytes;
+        info->build_ms = s.build_ms;
+    }
+    if (chunk_ptr) std::copy(s.chunk_ptr.begin(), s.chunk_ptr.end(), chunk_ptr);
+    if (chunk_group) std::copy(s.chunk_group.begin(), s.chunk_group.end(), chunk_group);
+    if (dep_lo) std::copy(s.dep_lo.begin(), s.dep_lo.end(), dep_lo);
+    if (dep_hi) std::copy(s.dep_hi.begin(), s.dep_hi.end(), dep_hi);
+    if (tasks) std::copy(s.tasks.begin(), s.tasks.end(), tasks);
+    return MPK_OK;
+}
+
+mpk_status_t mpk_run(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y, void *stream) {
+    return run_lb(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream);
+}
+
+mpk_status_t mpk_run_recur(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
+                           const double *beta, const double *gamma, double *Y, void *stream) {
+    if (!alpha || !beta || !gamma) return fail(MPK_EINVAL, "coefficient array is NULL");
+    return run_lb(plan, x, p, nrhs, alpha, beta, gamma, Y, stream);
+}
+
+mpk_status_t mpk_run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                              void *stream) {
+    return run_baseline(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream);
+}
+
+mpk_status_t mpk_run_baseline_recur(mpk_plan_t plan, const double *x, int p, int nrhs,
+                                    const double *alpha, const double *beta, const double *gamma,
+                                    double *Y, void *stream) {
+    if (!alpha || !beta || !gamma) return fail(MPK_EINVAL, "coefficient array is NULL");
+    return run_baseline(plan, x, p, nrhs, alpha, beta, gamma, Y, stream);
+}
+
+mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double *out, int nvec,
+                         int nrhs, void *stream) {
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    if (nvec < 0 || nrhs < 1 || nrhs > MPK_MAX_RHS) return fail(MPK_EINVAL, "bad nvec or nrhs");
+    if (plan->n == 0 || nvec == 0) return MPK_OK;
+    if (!in || !out) return fail(MPK_EINVAL, "NULL vector");
+    const size_t bytes = (size_t)plan->n * nrhs * nvec * sizeof(double);
+    const char *a = reinterpret_cast<const char *>(in), *b = reinterpret_cast<const char *>(out);
+    if (a < b + bytes && b < a + bytes) return fail(MPK_EINVAL, "in and out overlap");
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!plan->d_perm.ptr) {  // identity ordering
+        e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+        return e == hipSuccess ? MPK_OK : hip_fail(e, "hipMemcpyAsync");
+    }
+    int rc = launch_permute(plan->d_perm.as<int32_t>(), plan->n, to_plan, in, out, nvec, nrhs, stream);
+    return rc ? hip_fail((hipError_t)rc, "permute kernel launch") : MPK_OK;
+}
+
+mpk_status_t mpk_plan_sync(mpk_plan_t plan) {
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    std::lock_guard<std::mutex> g(plan->mu);
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    bool timeout = false;
+    for (auto &w : plan->pool) {
+        if (w->recorded) {
+            e = hipEventSynchronize(w->ev);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        }
+        int32_t flag = 0;
+        e = hipMemcpy(&flag, w->view().err, sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        if (flag) {
+            timeout = true;
+            const int32_t zero = 0;
+            e = hipMemcpy(w->view().err, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        }
+    }
+    if (timeout) return fail(MPK_ETIMEOUT, "a dependency wait exceeded its limit; results are invalid");
+    return MPK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal interfaces between the host planner, the C ABI and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mpk.h"
+
+namespace mpk {
+
+// ------------------------------------------------------------------ planner
+
+// Result of the level construction on G(A): levels in plan order plus the
+// symmetric permutation perm[new] = old, iperm[old] = new.
+struct Levels {
+    std::vector<int32_t> level_ptr;  // n_levels + 1, plan-order row ranges
+    std::vector<int32_t> perm, iperm;
+};
+
+// Validates a host CSR; returns MPK_OK or MPK_EBADCSR / MPK_EUNSUPPORTED / MPK_EINVAL.
+mpk_status_t validate_csr(const mpk_csr_t *A, bool need_values, std::string &err);
+
+// BFS levels from `root` on the symmetrised pattern, self-loops ignored,
+// ascending original index inside a level, restart at the lowest unvisited
+// row when the frontier empties.
+Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t root);
+
+// Identity permutation with levels derived from the given order: level j+1
+// ends just past the farthest neighbour of level j, so every row's
+// neighbours lie in its own or an adjacent level.
+Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col);
+
+// The matrix in plan row order.  `col` holds plan-numbered columns when
+// plan_cols is true, else the caller's numbering; row_lo / row_hi are each
+// row's smallest / largest column in PLAN numbering (the dependency extent).
+struct PermutedCSR {
+    std::vector<int32_t> rowptr, col, row_lo, row_hi;
+    std::vector<double> val;
+};
+void permute_csr(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                 const Levels &lv, bool plan_cols, PermutedCSR &out);
+
+// Schedule of (chunk, power) tasks for p powers.
+struct Schedule {
+    int p = 0;
+    std::vector<int32_t> chunk_ptr;    // n_chunks + 1 plan rows
+    std::vector<int32_t> chunk_group;  // n_chunks
+    std::vector<int32_t> dep_lo, dep_hi;
+    std::vector<int32_t> tasks;        // 2 * n_tasks: (chunk, power)
+    int32_t n_groups = 0, lag = 0, max_reach = 0;
+    double window_bytes = 0.0, build_ms = 0.0;
+    int32_t n_chunks() const { return (int32_t)chunk_group.size(); }
+    int32_t n_tasks() const { return (int32_t)(tasks.size() / 2); }
+};
+
+struct PlanShape {
+    int64_t n, nnz;
+    int value_bytes;
+    const std::vector<int32_t> *level_ptr;
+    const std::vector<int32_t> *rowptr;  // plan order
+    const std::vector<int32_t> *row_lo, *row_hi;
+};
+
+mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
+                            int default_workgroups, Schedule &out, std::string &err);
+
+// Checks that the task list covers every (chunk, power) once and that each
+// task's dependencies are issued before it.
+bool validate_schedule(const Schedule &s, std::string &err);
+
+// ------------------------------------------------------------------ device side
+
+struct DevMatrix {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const void *val;          // double or float
+    const int32_t *out_row;   // nullptr: output row = plan row
+    int32_t n;
+    int32_t value_bits;
+    int32_t lanes;            // lanes per row
+};
+
+constexpr int kMaxSegPowers = 64;   // powers per kernel launch
+
+struct Coefs {
+    double alpha[kMaxSegPowers];
+    double beta[kMaxSegPowers];
+    double gamma[kMaxSegPowers];
+};
+
+// One launch covers powers 1..p of a segment: y_0 = in0, y_{-1} = inm1
+// (recurrence only, may be null), outputs Y[(k-1)*n*R ...].
+struct SegArgs {
+    const double *in0;
+    const double *inm1;
+    double *Y;
+    int32_t p;
+    int32_t R;
+    int32_t recur;
+};
+
+struct DevSchedule {
+    const int32_t *chunk_ptr;
+    const int32_t *dep_lo, *dep_hi;
+    const int32_t *tasks;
+    int32_t n_tasks, n_chunks;
+};
+
+struct DevWorkspace {
+    int32_t *done;      // n_chunks completion powers
+    int32_t *ticket;    // next task
+    int32_t *err;       // sticky failure flag
+};
+
+// Launchers (kernels.hip).  All return hipError_t as int.
+int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);
+int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
+              const SegArgs &a, const Coefs *cf, int rhs_per_thread, int workgroups,
+              int64_t spin_limit, void *stream);
+int launch_spmv_power(const DevMatrix &m, const double *in, const double *inm1, double *out,
+                      int32_t R, int recur, double alpha, double beta, double gamma,
+                      int rhs_per_thread, void *stream);
+int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in, double *out,
+                   int nvec, int R, void *stream);
+// Max co-resident persistent workgroups for this configuration.
+int lb_max_workgroups(int value_bits, int lanes, int rhs_per_thread, int device);
+// Whether (lanes, rhs_per_thread) is an instantiated configuration.
+bool kernel_config_ok(int lanes, int rhs_per_thread);
+
+}  // namespace mpk

@@ -1,0 +1,368 @@
+// Host planner: CSR validation, level construction, symmetric permutation,
+// level groups, chunks, dependency ranges and the task schedule.
+//
+// Levels follow Sec. "RACE Applied to the Matrix Power Kernel": L(0) is the
+// root, each next level holds the not yet visited neighbours of the previous
+// one, the pattern is treated as symmetric (endnote on non-symmetric
+// matrices), and the matrix is then permuted symmetrically by level.  The
+// schedule generalises the Lp-diagram traversal of the same section (Fig.
+// lp_basic) from whole levels to chunks of rows.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "mpk_internal.h"
+
+namespace mpk {
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+mpk_status_t validate_csr(const mpk_csr_t *A, bool need_values, std::string &err) {
+    if (!A) { err = "A is NULL"; return MPK_EINVAL; }
+    if (A->n < 0 || A->nnz < 0) { err = "negative n or nnz"; return MPK_EBADCSR; }
+    if (A->n >= (int64_t)INT32_MAX) { err = "n >= 2^31 is not supported"; return MPK_EUNSUPPORTED; }
+    if (A->nnz >= (int64_t)INT32_MAX) { err = "nnz >= 2^31 is not supported"; return MPK_EUNSUPPORTED; }
+    if (!A->rowptr) { err = "rowptr is NULL"; return MPK_EINVAL; }
+    if (A->nnz > 0 && !A->col) { err = "col is NULL"; return MPK_EINVAL; }
+    if (need_values && A->nnz > 0 && !A->val) { err = "val is NULL"; return MPK_EINVAL; }
+    if (A->rowptr[0] != 0) { err = "rowptr[0] != 0"; return MPK_EBADCSR; }
+    for (int64_t i = 0; i < A->n; ++i)
+        if (A->rowptr[i + 1] < A->rowptr[i]) {
+            err = "rowptr decreases at row " + std::to_string(i);
+            return MPK_EBADCSR;
+        }
+    if ((int64_t)A->rowptr[A->n] != A->nnz) { err = "rowptr[n] != nnz"; return MPK_EBADCSR; }
+    for (int64_t e = 0; e < A->nnz; ++e)
+        if (A->col[e] < 0 || (int64_t)A->col[e] >= A->n) {
+            err = "column index out of range at entry " + std::to_string(e);
+            return MPK_EBADCSR;
+        }
+    return MPK_OK;
+}
+
+Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t root) {
+    Levels lv;
+    lv.perm.reserve(n);
+    lv.level_ptr.push_back(0);
+    if (n == 0) return lv;
+    // transpose pattern: in-neighbours, so that the graph is symmetric
+    std::vector<int32_t> tptr(n + 1, 0), tcol(rowptr[n]);
+    for (int64_t e = 0; e < rowptr[n]; ++e) tptr[col[e] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    {
+        std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) tcol[fill[col[e]]++] = (int32_t)i;
+    }
+    std::vector<uint8_t> seen(n, 0);
+    std::vector<int32_t> frontier, next;
+    int64_t lowest = 0;  // every row below this index is already levelled
+    int64_t visited = 0;
+    int32_t start = (root >= 0 && root < n) ? root : 0;
+    while (visited < n) {
+        if (frontier.empty()) {
+            if (visited > 0) {
+                while (seen[lowest]) ++lowest;
+                start = (int32_t)lowest;
+            }
+            seen[start] = 1;
+            frontier.assign(1, start);
+        }
+        // emit the current level
+        lv.perm.insert(lv.perm.end(), frontier.begin(), frontier.end());
+        visited += (int64_t)frontier.size();
+        lv.level_ptr.push_back((int32_t)lv.perm.size());
+        next.clear();
+        for (int32_t u : frontier) {
+            for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+                int32_t v = col[e];
+                if (!seen[v]) { seen[v] = 1; next.push_back(v); }
+            }
+            for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e) {
+                int32_t v = tcol[e];
+                if (!seen[v]) { seen[v] = 1; next.push_back(v); }
+            }
+        }
+        std::sort(next.begin(), next.end());
+        frontier.swap(next);
+    }
+    lv.iperm.assign(n, 0);
+    for (int64_t i = 0; i < n; ++i) lv.iperm[lv.perm[i]] = (int32_t)i;
+    return lv;
+}
+
+Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col) {
+    Levels lv;
+    lv.perm.resize(n);
+    lv.iperm.resize(n);
+    std::iota(lv.perm.begin(), lv.perm.end(), 0);
+    std::iota(lv.iperm.begin(), lv.iperm.end(), 0);
+    lv.level_ptr.push_back(0);
+    if (n == 0) return lv;
+    // farthest symmetric neighbour of each row
+    std::vector<int32_t> far(n);
+    for (int64_t i = 0; i < n; ++i) far[i] = (int32_t)i;
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            int32_t c = col[e];
+            if (c > far[i]) far[i] = c;
+            if ((int32_t)i > far[c]) far[c] = (int32_t)i;
+        }
+    // level 0 = row 0; level j+1 ends just past the farthest neighbour of level j
+    int64_t b_prev = 0, b = 1;
+    lv.level_ptr.push_back(1);
+    while (b < n) {
+        int64_t reach = b;  // exclusive end needed for the next level
+        for (int64_t i = b_prev; i < b; ++i) reach = std::max<int64_t>(reach, (int64_t)far[i] + 1);
+        int64_t nb = std::max<int64_t>(b + 1, std::min<int64_t>(reach, n));
+        b_prev = b;
+        b = nb;
+        lv.level_ptr.push_back((int32_t)b);
+    }
+    return lv;
+}
+
+void permute_csr(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                 const Levels &lv, bool plan_cols, PermutedCSR &out) {
+    out.rowptr.assign(n + 1, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t old = lv.perm[r];
+        out.rowptr[r + 1] = out.rowptr[r] + (rowptr[old + 1] - rowptr[old]);
+    }
+    const int64_t nnz = n ? out.rowptr[n] : 0;
+    out.col.resize(nnz);
+    if (val) out.val.resize(nnz);
+    out.row_lo.resize(n);
+    out.row_hi.resize(n);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t r = 0; r < n; ++r) {
+        const int32_t old = lv.perm[r];
+        int32_t lo = (int32_t)r, hi = (int32_t)r;  // a row always depends on itself
+        int32_t d = out.rowptr[r];
+        for (int32_t e = rowptr[old]; e < rowptr[old + 1]; ++e, ++d) {
+            const int32_t cp = lv.iperm[col[e]];
+            out.col[d] = plan_cols ? cp : col[e];
+            if (val) out.val[d] = val[e];
+            lo = std::min(lo, cp);
+            hi = std::max(hi, cp);
+        }
+        out.row_lo[r] = lo;
+        out.row_hi[r] = hi;
+    }
+}
+
+// ------------------------------------------------------------------ schedule
+
+namespace {
+
+// Range-maximum over a static array (sparse table).
+struct RangeMax {
+    std::vector<std::vector<int64_t>> t;
+    explicit RangeMax(const std::vector<int64_t> &a) {
+        t.push_back(a);
+        for (size_t w = 1; (w << 1) <= a.size(); w <<= 1) {
+            const auto &prev = t.back();
+            std::vector<int64_t> cur(a.size() - (w << 1) + 1);
+            for (size_t i = 0; i < cur.size(); ++i) cur[i] = std::max(prev[i], prev[i + w]);
+            t.push_back(std::move(cur));
+        }
+    }
+    int64_t query(int32_t lo, int32_t hi) const {  // inclusive
+        const uint32_t len = (uint32_t)(hi - lo + 1);
+        const int j = 31 - __builtin_clz(len);
+        return std::max(t[j][lo], t[j][hi - (1 << j) + 1]);
+    }
+};
+
+}  // namespace
+
+mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
+                            int default_workgroups, Schedule &s, std::string &err) {
+    const double t0 = now_ms();
+    s = Schedule();
+    s.p = p;
+    const int64_t n = sh.n;
+    const auto &lp = *sh.level_ptr;
+    const auto &rp = *sh.rowptr;
+    const int32_t n_levels = (int32_t)lp.size() - 1;
+    const double row_bytes = 4.0, nz_bytes = 4.0 + sh.value_bytes;
+    const double budget = (double)tune.cache_bytes * tune.cache_safety;
+    const int64_t chunk_nnz = std::max(1, tune.chunk_nnz);
+    if (n == 0) {
+        s.chunk_ptr.assign(1, 0);
+        s.build_ms = now_ms() - t0;
+        return MPK_OK;
+    }
+
+    // 1. level groups: consecutive levels; p+1 of them should fit the budget
+    const double gmax = budget / (double)(p + 1);
+    std::vector<int32_t> group_ptr(1, 0);  // in levels
+    {
+        double acc = 0.0;
+        for (int32_t l = 0; l < n_levels; ++l) {
+            const int64_t rows = lp[l + 1] - lp[l];
+            const int64_t nz = (int64_t)rp[lp[l + 1]] - rp[lp[l]];
+            const double b = rows * row_bytes + nz * nz_bytes;
+            if (acc > 0.0 && acc + b > gmax) {
+                group_ptr.push_back(l);
+                acc = 0.0;
+            }
+            acc += b;
+        }
+        group_ptr.push_back(n_levels);
+    }
+    s.n_groups = (int32_t)group_ptr.size() - 1;
+
+    // 2. chunks: rows of one group cut at about chunk_nnz nonzeros (never split a row)
+    s.chunk_ptr.push_back(0);
+    for (int32_t g = 0; g < s.n_groups; ++g) {
+        const int64_t r0 = lp[group_ptr[g]], r1 = lp[group_ptr[g + 1]];
+        const int64_t nz0 = rp[r0], nz = (int64_t)rp[r1] - nz0;
+        const int64_t rows = r1 - r0;
+        int64_t pieces = std::max<int64_t>(1, (nz + chunk_nnz - 1) / chunk_nnz);
+        // very short rows: also bound rows per chunk so a chunk stays one task
+        pieces = std::max<int64_t>(pieces, (rows + 65535) / 65536);
+        pieces = std::min<int64_t>(pieces, std::max<int64_t>(1, rows));
+        int64_t r = r0;
+        for (int64_t k = 1; k <= pieces; ++k) {
+            int64_t end;
+            if (k == pieces) {
+                end = r1;
+            } else {
+                const int64_t target = nz0 + (nz * k) / pieces;
+                end = std::upper_bound(rp.begin() + r + 1, rp.begin() + r1, (int32_t)target) -
+                      rp.begin();
+                end = std::max<int64_t>(end - 0, r + 1);
+                end = std::min<int64_t>(end, r1 - (pieces - k));
+                if (end <= r) end = r + 1;
+            }
+            s.chunk_ptr.push_back((int32_t)end);
+            s.chunk_group.push_back(g);
+            r = end;
+        }
+    }
+    const int32_t nc = s.n_chunks();
+
+    // 3. dependency ranges (chunks whose rows a chunk's rows read)
+    std::vector<int32_t> chunk_of(n);
+    for (int32_t c = 0; c < nc; ++c)
+        for (int32_t r = s.chunk_ptr[c]; r < s.chunk_ptr[c + 1]; ++r) chunk_of[r] = c;
+    s.dep_lo.resize(nc);
+    s.dep_hi.resize(nc);
+    double reach_sum = 0.0;
+    for (int32_t c = 0; c < nc; ++c) {
+        int32_t lo = INT32_MAX, hi = -1;
+        for (int32_t r = s.chunk_ptr[c]; r < s.chunk_ptr[c + 1]; ++r) {
+            lo = std::min(lo, (*sh.row_lo)[r]);
+            hi = std::max(hi, (*sh.row_hi)[r]);
+        }
+        s.dep_lo[c] = std::min(chunk_of[lo], c);
+        s.dep_hi[c] = std::max(chunk_of[hi], c);
+        s.max_reach = std::max(s.max_reach, s.dep_hi[c] - c);
+        reach_sum += s.dep_hi[c] - c;
+    }
+    const double avg_reach = reach_sum / nc;
+    const double avg_chunk_bytes = ((double)n * row_bytes + (double)sh.nnz * nz_bytes) / nc;
+
+    // 4. task order
+    s.tasks.reserve((size_t)2 * nc * p);
+    if (tune.schedule == MPK_SCHED_POWERS) {
+        for (int k = 1; k <= p; ++k)
+            for (int32_t c = 0; c < nc; ++c) { s.tasks.push_back(c); s.tasks.push_back(k); }
+        s.window_bytes = (double)n * row_bytes + (double)sh.nnz * nz_bytes;
+    } else if (tune.schedule == MPK_SCHED_DIAG) {
+        // Lp diagram over level groups: diagonals g + k = const, each from the
+        // largest group (smallest power) to the smallest group.
+        std::vector<int32_t> gfirst(s.n_groups + 1, nc);
+        for (int32_t c = nc - 1; c >= 0; --c) gfirst[s.chunk_group[c]] = c;
+        gfirst[s.n_groups] = nc;
+        for (int32_t g = s.n_groups - 1; g >= 0; --g)
+            if (gfirst[g] > gfirst[g + 1]) gfirst[g] = gfirst[g + 1];
+        for (int64_t d = 1; d <= (int64_t)s.n_groups - 1 + p; ++d) {
+            for (int64_t k = std::max<int64_t>(1, d - s.n_groups + 1); k <= std::min<int64_t>(p, d); ++k) {
+                const int64_t g = d - k;
+                for (int32_t c = gfirst[g]; c < gfirst[g + 1]; ++c) {
+                    s.tasks.push_back(c);
+                    s.tasks.push_back((int32_t)k);
+                }
+            }
+        }
+        s.window_bytes = gmax * (p + 1);
+    } else if (tune.schedule == MPK_SCHED_WAVE) {
+        // Skewed chunk wavefront: pos(c,1) = c and pos(c,k) = D + max over the
+        // chunks read of pos(., k-1).  Tasks are issued by increasing pos
+        // (ties: higher power first), so every dependency precedes its user.
+        int64_t D = tune.lag;
+        if (D <= 0) {
+            const double fit = budget / ((double)p * avg_chunk_bytes) - avg_reach;
+            const int64_t par = (default_workgroups + p - 1) / std::max(1, p);
+            D = std::max<int64_t>({(int64_t)std::floor(fit), par, 1});
+        }
+        s.lag = (int32_t)std::min<int64_t>(D, INT32_MAX);
+        std::vector<int64_t> pos(nc);
+        for (int32_t c = 0; c < nc; ++c) pos[c] = c;
+        struct Key { int64_t pos; int32_t negk, c; };
+        std::vector<Key> keyed;
+        keyed.reserve((size_t)nc * p);
+        for (int32_t c = 0; c < nc; ++c) keyed.push_back({pos[c], -1, c});
+        for (int k = 2; k <= p; ++k) {
+            RangeMax rm(pos);
+            std::vector<int64_t> np(nc);
+            for (int32_t c = 0; c < nc; ++c) np[c] = rm.query(s.dep_lo[c], s.dep_hi[c]) + D;
+            pos.swap(np);
+            for (int32_t c = 0; c < nc; ++c) keyed.push_back({pos[c], -k, c});
+        }
+        // ties: higher power first, then ascending chunk
+        std::sort(keyed.begin(), keyed.end(), [](const Key &a, const Key &b) {
+            if (a.pos != b.pos) return a.pos < b.pos;
+            if (a.negk != b.negk) return a.negk < b.negk;
+            return a.c < b.c;
+        });
+        for (const auto &kv : keyed) {
+            s.tasks.push_back(kv.c);
+            s.tasks.push_back(-kv.negk);
+        }
+        s.window_bytes = (double)p * (avg_reach + D) * avg_chunk_bytes;
+    } else {
+        err = "unknown schedule";
+        return MPK_EINVAL;
+    }
+    s.build_ms = now_ms() - t0;
+    return MPK_OK;
+}
+
+bool validate_schedule(const Schedule &s, std::string &err) {
+    const int32_t nc = s.n_chunks();
+    const int p = s.p;
+    if ((int64_t)s.n_tasks() != (int64_t)nc * p) { err = "task count mismatch"; return false; }
+    std::vector<int64_t> when((size_t)nc * p, -1);
+    for (int32_t t = 0; t < s.n_tasks(); ++t) {
+        const int32_t c = s.tasks[2 * t], k = s.tasks[2 * t + 1];
+        if (c < 0 || c >= nc || k < 1 || k > p) { err = "task out of range"; return false; }
+        int64_t &w = when[(size_t)(k - 1) * nc + c];
+        if (w >= 0) { err = "duplicate task"; return false; }
+        w = t;
+    }
+    for (int k = 2; k <= p; ++k) {
+        std::vector<int64_t> prev(when.begin() + (size_t)(k - 2) * nc,
+                                  when.begin() + (size_t)(k - 1) * nc);
+        RangeMax rm(prev);
+        for (int32_t c = 0; c < nc; ++c) {
+            if (s.dep_lo[c] > c || s.dep_hi[c] < c) { err = "range misses own chunk"; return false; }
+            if (rm.query(s.dep_lo[c], s.dep_hi[c]) >= when[(size_t)(k - 1) * nc + c]) {
+                err = "dependency issued after its user: chunk " + std::to_string(c) +
+                      " power " + std::to_string(k);
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace mpk

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: FP64 values <= 1e-12 relative error per power against the oracle;
+FP32-stored values <= 1e-12 against the oracle run on the float-rounded
+values and <= 1e-5 against the FP64 oracle; level-blocked == baseline bit for
+bit (same per-row summation order); integer-valued inputs bit-exact against
+the oracle (every partial sum is an exact integer).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from tests._util import rel_err_per_power
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mpk = pytest.importorskip("paper_2405_12525_amd")
+
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def run_both(P, x, p, recur=None):
+    xd = dev(x)
+    if recur is None:
+        Y = P.run(xd, p)
+        B = P.run_baseline(xd, p)
+    else:
+        Y = P.run_recur(xd, *recur)
+        B = P.run_baseline_recur(xd, *recur)
+    P.sync()
+    return host(Y), host(B)
+
+
+# ------------------------------------------------------------------ small configurations
+
+SCHEDS = ["wave", "diag", "powers"]
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("reorder,order", [("bfs", "original"), ("none", "original"),
+                                           ("bfs", "plan")])
+def test_stencil2d_p4_matches_oracle(sched, reorder, order):
+    A, x, p, _ = w.config("stencil2d5_64_p4")
+    P = mpk.Plan(A, reorder=reorder, order=order)
+    P.tune(schedule=sched, chunk_nnz=512)
+    if order == "plan":
+        lp, perm = P.levels()
+        Ap = oracle.permute_csr(A, perm)
+        xp = x[perm]
+        ref = oracle.powers(Ap, xp, p)
+        Y, B = run_both(P, xp, p)
+    else:
+        ref = oracle.powers(A, x, p)
+        Y, B = run_both(P, x, p)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, ref).max() <= TOL64
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_integer_inputs_bit_exact(lanes):
+    A = w.stencil_3d27(20)
+    x = w.integer_vectors(A.n, 1, 42)
+    P = mpk.Plan(A, lanes_per_row=lanes)
+    P.tune(chunk_nnz=1000)
+    Y, B = run_both(P, x, 6)
+    assert np.array_equal(Y, oracle.powers(A, x, 6))
+    assert np.array_equal(B, Y)
+
+
+def ragged_matrix(n, seed):
+    """Irregular rows (empty, short, long, one dense-ish) with a non-symmetric pattern."""
+    g = w.rng(seed)
+    lens = g.integers(0, 30, size=n)
+    lens[g.integers(0, n, size=n // 20)] = 0
+    lens[n // 3] = min(n, 900)
+    rows, cols = [], []
+    for i in range(n):
+        c = np.unique(np.clip(i + g.integers(-200, 201, size=lens[i]), 0, n - 1))
+        rows.append(np.full(c.size, i))
+        cols.append(c)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    vals = g.standard_normal(cols.size) * 0.2
+    return w.CSR(n, rowptr, cols.astype(np.int32), vals, f"ragged_{n}")
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 8, 16])
+def test_ragged_multi_rhs(R):
+    A = ragged_matrix(5003, 7)
+    x = w.uniform_vectors(A.n, R, 100 + R)
+    p = 5
+    ref = oracle.powers(A, x, p)
+    P = mpk.Plan(A)
+    P.tune(chunk_nnz=700)
+    Y, B = run_both(P, x, p)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, ref).max() <= TOL64
+    # every column equals its own single right-hand-side run
+    for r in range(R):
+        Y1, _ = run_both(P, x[:, r:r + 1], p)
+        assert np.array_equal(Y[:, :, r:r + 1], Y1)
+
+
+@pytest.mark.parametrize("rt", [1, 2, 4, 8])
+def test_rhs_tiling_is_bit_identical(rt):
+    A = w.anderson_3d(12)
+    x = w.uniform_vectors(A.n, 8, 5)
+    P = mpk.Plan(A)
+    Y0, _ = run_both(P, x, 4)
+    P.tune(rhs_per_thread=rt, chunk_nnz=300)
+    Y1, B1 = run_both(P, x, 4)
+    assert np.array_equal(Y0, Y1) and np.array_equal(Y1, B1)
+
+
+def test_fp32_values():
+    A = w.banded_random(60000, half_width=500, window=4096)
+    x = w.uniform_vectors(A.n, 1, 1003)
+    p = 6
+    P = mpk.Plan(A, value_bits=32)
+    P.tune(chunk_nnz=4096)
+    Y, B = run_both(P, x, p)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.powers(A, x, p, value_bits=32)).max() <= TOL64
+    assert rel_err_per_power(Y, oracle.powers(A, x, p)).max() <= TOL32
+
+
+@pytest.mark.parametrize("value_bits", [64, 32])
+def test_chebyshev_recurrence(value_bits):
+    A = w.anderson_3d(24)
+    x = w.random_sign_unit_vectors(A.n, 8, 1004)
+    p = 16
+    coefs = oracle.chebyshev_coefficients(p)
+    P = mpk.Plan(A, value_bits=value_bits)
+    P.tune(chunk_nnz=2000)
+    Y, B = run_both(P, x, p, recur=coefs)
+    assert np.array_equal(Y, B)
+    tol = TOL64 if value_bits == 64 else TOL32
+    assert rel_err_per_power(Y, oracle.recur(A, x, *coefs, value_bits=value_bits)).max() <= TOL64
+    assert rel_err_per_power(Y, oracle.recur(A, x, *coefs)).max() <= tol
+
+
+def test_general_recurrence_coefficients():
+    A = ragged_matrix(3001, 3)
+    x = w.uniform_vectors(A.n, 2, 9)
+    g = w.rng(77)
+    a, b, c = g.uniform(-1, 1, 9), g.uniform(-1, 1, 9), g.uniform(-1, 1, 9)
+    P = mpk.Plan(A)
+    P.tune(chunk_nnz=500)
+    Y, B = run_both(P, x, 9, recur=(a, b, c))
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.recur(A, x, a, b, c)).max() <= TOL64
+
+
+def test_long_p_spans_segments():
+    A = w.anderson_3d(10)
+    x = w.uniform_vectors(A.n, 2, 3)
+    p = 150  # three kernel launches of at most 64 powers
+    P = mpk.Plan(A)
+    Y, B = run_both(P, x, p)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.powers(A, x, p)).max() <= 1e-11
+    coefs = oracle.chebyshev_coefficients(p)
+    Yc, Bc = run_both(P, x, p, recur=coefs)
+    assert np.array_equal(Yc, Bc)
+    assert rel_err_per_power(Yc, oracle.recur(A, x, *coefs)).max() <= 1e-11
+
+
+def test_split_invariant_and_plan_order_permutation():
+    A = w.stencil_2d5(50)
+    x = w.uniform_vectors(A.n, 2, 8)
+    P = mpk.Plan(A)
+    Y, _ = run_both(P, x, 7)
+    Ya, _ = run_both(P, x, 3)
+    Yb, _ = run_both(P, Ya[-1], 4)
+    assert np.array_equal(Y, np.concatenate([Ya, Yb]))
+    # PLAN order: permute in, run, permute out == ORIGINAL order, bit for bit
+    Q = mpk.Plan(A, order="plan")
+    xp = Q.permute(dev(x), to_plan=True)
+    Yp = Q.run(xp, 7)
+    Yo = Q.permute(Yp, to_plan=False)
+    assert np.array_equal(host(Yo), Y)
+
+
+def test_edge_cases():
+    # empty matrix
+    E = w.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    P = mpk.Plan(E)
+    Y = P.run(torch.zeros((0, 1), dtype=torch.float64, device="cuda"), 3)
+    assert Y.shape == (3, 0, 1)
+    # one row
+    one = w.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([0.5]))
+    Y, B = run_both(mpk.Plan(one), np.array([[2.0]]), 4)
+    assert Y[:, 0, 0].tolist() == [1.0, 0.5, 0.25, 0.125]
+    # all-empty rows
+    Z = w.CSR(5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    Y, B = run_both(mpk.Plan(Z), np.ones((5, 1)), 2)
+    assert np.array_equal(Y, np.zeros((2, 5, 1)))
+    # disconnected graph + a dense row
+    A = w.random_sparse(700, 0.002, 11)
+    D = A.to_dense()
+    D[350, :] = 0.01
+    A = w.from_dense(D)
+    x = w.uniform_vectors(A.n, 1, 2)
+    P = mpk.Plan(A)
+    P.tune(chunk_nnz=64)
+    Y, B = run_both(P, x, 5)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.powers(A, x, 5)).max() <= TOL64
+
+
+def test_identity_and_permutation_exact():
+    A = w.identity(3000)
+    x = w.uniform_vectors(3000, 4, 1)
+    Y, _ = run_both(mpk.Plan(A), x, 3)
+    assert all(np.array_equal(Y[k], x) for k in range(3))
+    Pm, sigma = w.permutation_matrix(4000, 5)
+    x = w.uniform_vectors(4000, 1, 2)
+    Y, _ = run_both(mpk.Plan(Pm), x, 4)
+    idx = np.arange(4000)
+    for k in range(4):
+        idx = sigma[idx]
+        assert np.array_equal(Y[k], x[idx])
+
+
+def test_wait_limit_reports_timeout_and_recovers():
+    A = w.stencil_3d27(40)
+    x = w.uniform_vectors(A.n, 1, 4)
+    P = mpk.Plan(A)
+    P.tune(spin_limit_us=1, chunk_nnz=2000)
+    seen_timeout = False
+    for _ in range(3):
+        P.run(dev(x), 24)
+        try:
+            P.sync()
+        except mpk.MPKError as e:
+            assert "MPK_ETIMEOUT" in str(e)
+            seen_timeout = True
+    assert seen_timeout
+    P.tune(spin_limit_us=0, chunk_nnz=2000)
+    Y, B = run_both(P, x, 6)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.powers(A, x, 6)).max() <= TOL64
+
+
+def test_concurrent_streams_share_a_plan():
+    A = w.stencil_3d27(24)
+    xs = [w.uniform_vectors(A.n, 2, s) for s in range(4)]
+    P = mpk.Plan(A)
+    P.tune(chunk_nnz=1500)
+    streams = [torch.cuda.Stream() for _ in xs]
+    outs = []
+    xds = [dev(x) for x in xs]
+    torch.cuda.synchronize()
+    for xd, s in zip(xds, streams):
+        with torch.cuda.stream(s):
+            outs.append(P.run(xd, 5, stream=s))
+    P.sync()
+    for x, Y in zip(xs, outs):
+        assert rel_err_per_power(host(Y), oracle.powers(A, x, 5)).max() <= TOL64
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+@pytest.mark.slow
+def test_full_stencil3d27_128_p8():
+    A, x, p, _ = w.config("stencil3d27_128_p8")
+    P = mpk.Plan(A)
+    xi = w.integer_vectors(A.n, 1, 1002)
+    Yi, Bi = run_both(P, xi, p)
+    assert np.array_equal(Yi, oracle.powers(A, xi, p))
+    assert np.array_equal(Yi, Bi)
+    Y, B = run_both(P, x, p)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.powers(A, x, p)).max() <= TOL64
+
+
+@pytest.mark.slow
+def test_full_anderson160_chebyshev16_r8_fp32():
+    A, x, p, _ = w.config("anderson160_cheb16_r8")
+    coefs = oracle.chebyshev_coefficients(p)
+    P = mpk.Plan(A, value_bits=32)
+    Y, B = run_both(P, x, p, recur=coefs)
+    assert np.array_equal(Y, B)
+    assert rel_err_per_power(Y, oracle.recur(A, x, *coefs, value_bits=32)).max() <= TOL64
+    assert rel_err_per_power(Y, oracle.recur(A, x, *coefs)).max() <= TOL32

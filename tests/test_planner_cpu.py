@@ -1,0 +1,241 @@
+"""Host-side tests of the C ABI: symbol exports, the planner's levels and
+permutation, schedule validity and the error paths (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from tests._util import read_golden
+
+mpk = pytest.importorskip("paper_2405_12525_amd")
+from paper_2405_12525_amd import _capi  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def host_plan(A, **kw):
+    kw.setdefault("device", mpk.MPK_DEVICE_NONE)
+    return mpk.Plan(A, **kw)
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "mpk.h")).read()
+    declared = set(re.findall(r"\b(mpk_[a-z_]+)\s*\(", hdr))
+    assert declared == set(_capi.EXPORTS)
+    lib = _capi.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert mpk.version().startswith("mpk-mi355x")
+
+
+def _golden_graph():
+    rows = read_golden("stencil20_graph.txt")
+    n = int(rows[0][1])
+    D = np.eye(n)
+    for u, v in rows[1:]:
+        D[int(u), int(v)] = D[int(v), int(u)] = -1.0
+    return w.from_dense(D, "stencil20")
+
+
+def test_planner_reproduces_paper_bfs_example():
+    A = _golden_graph()
+    g = read_golden("stencil20_bfs.txt")
+    new_label = [int(v) for v in g[0][1:]]
+    levels = [[int(v) for v in r[1:]] for r in g if r[0] == "level"]
+    P = host_plan(A)
+    lp, perm = P.levels()
+    assert [sorted(perm[lp[i]:lp[i + 1]].tolist()) for i in range(len(lp) - 1)] == levels
+    assert [perm[lp[i]:lp[i + 1]].tolist() for i in range(len(lp) - 1)] == levels  # ascending
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(A.n)
+    assert iperm.tolist() == new_label
+
+
+@pytest.mark.parametrize("seed,sym", [(0, True), (1, False), (2, False), (3, True)])
+def test_planner_levels_match_oracle(seed, sym):
+    A = w.random_sparse(400, 0.004, seed, symmetric_pattern=sym)  # often disconnected
+    lv, perm_o, _ = oracle.bfs_levels(A.n, A.rowptr, A.col, root=0)
+    lp, perm = host_plan(A).levels()
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(np.diff(lp), [len(L) for L in lv])
+
+
+def test_planner_root_option():
+    A = w.stencil_2d5(9)
+    lv, perm_o, _ = oracle.bfs_levels(A.n, A.rowptr, A.col, root=40)
+    lp, perm = host_plan(A, root=40).levels()
+    assert np.array_equal(perm, perm_o)
+
+
+def _level_of(lp, n):
+    lev = np.empty(n, dtype=np.int64)
+    for i in range(len(lp) - 1):
+        lev[lp[i]:lp[i + 1]] = i
+    return lev
+
+
+@pytest.mark.parametrize("reorder", ["bfs", "none"])
+def test_level_neighbour_property(reorder):
+    # a row's neighbours lie in its own or an adjacent level (plan numbering)
+    for A in (w.stencil_2d5(15), w.stencil_3d27(6), w.anderson_3d(6),
+              w.random_sparse(200, 0.02, 7)):
+        lp, perm = host_plan(A, reorder=reorder).levels()
+        iperm = np.empty_like(perm)
+        iperm[perm] = np.arange(A.n)
+        lev = _level_of(lp, A.n)
+        rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+        d = np.abs(lev[iperm[rows]] - lev[iperm[A.col]])
+        assert d.max() <= 1
+        assert sorted(perm.tolist()) == list(range(A.n))
+        if reorder == "none":
+            assert np.array_equal(perm, np.arange(A.n))
+
+
+def _check_schedule(A, s, p):
+    cp, lo, hi, tasks = s["chunk_ptr"], s["dep_lo"], s["dep_hi"], s["tasks"]
+    nc = len(cp) - 1
+    assert cp[0] == 0 and cp[-1] == A.n and np.all(np.diff(cp) > 0)
+    assert tasks.shape == (nc * p, 2)
+    when = -np.ones((p + 1, nc), dtype=np.int64)
+    for t, (c, k) in enumerate(tasks):
+        assert when[k, c] < 0
+        when[k, c] = t
+    assert (when[1:] >= 0).all()
+    for c in range(nc):
+        assert lo[c] <= c <= hi[c]
+        for k in range(2, p + 1):
+            assert when[k - 1, lo[c]:hi[c] + 1].max() < when[k, c]
+
+
+def _deps_cover_reads(A, P, s):
+    """Every column a chunk's rows read lies in its dependency range."""
+    lp, perm = P.levels()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(A.n)
+    cp = s["chunk_ptr"]
+    chunk_of = np.repeat(np.arange(len(cp) - 1), np.diff(cp))
+    for new in range(A.n):
+        old = perm[new]
+        cols = iperm[A.col[A.rowptr[old]:A.rowptr[old + 1]]]
+        c = chunk_of[new]
+        if cols.size:
+            assert chunk_of[cols].min() >= s["dep_lo"][c]
+            assert chunk_of[cols].max() <= s["dep_hi"][c]
+
+
+@pytest.mark.parametrize("sched", ["wave", "diag", "powers"])
+@pytest.mark.parametrize("reorder", ["bfs", "none"])
+def test_schedules_are_topological(sched, reorder):
+    for A in (w.stencil_2d5(30), w.random_sparse(300, 0.01, 3), w.anderson_3d(7)):
+        P = host_plan(A, reorder=reorder)
+        P.tune(schedule=sched, chunk_nnz=64, cache_bytes=20000, cache_safety=1.0, lag=0)
+        for p in (1, 2, 5):
+            s = P.schedule(p)
+            _check_schedule(A, s, p)
+            _deps_cover_reads(A, P, s)
+
+
+def test_diag_schedule_is_the_papers_lp_order():
+    # a path graph has one vertex per BFS level; one chunk per level and one
+    # level per group turn the chunk schedule into the Lp diagram of Fig. lp_basic
+    grid = [[int(v) for v in r[1:]] for r in read_golden("lp_order_10x5.txt")]
+    A = w.tridiag_1d(10)
+    P = host_plan(A)
+    P.tune(schedule="diag", cache_bytes=1, cache_safety=1.0, chunk_nnz=1)
+    s = P.schedule(5)
+    assert s["n_groups"] == 10 and s["n_chunks"] == 10
+    for step, (c, k) in enumerate(s["tasks"]):
+        assert grid[k - 1][c] == step
+    assert list(map(tuple, s["tasks"])) == [(i, p) for i, p in oracle.lp_diagonal_order(10, 5)]
+
+
+def test_wave_lag_changes_order_not_validity():
+    A = w.stencil_2d5(40)
+    P = host_plan(A, reorder="none")
+    orders = []
+    for lag in (1, 3, 50):
+        P.tune(schedule="wave", chunk_nnz=40, lag=lag)
+        s = P.schedule(4)
+        _check_schedule(A, s, 4)
+        assert s["lag"] == lag
+        orders.append(s["tasks"].tolist())
+    assert orders[0] != orders[2]
+
+
+def test_plan_info_fields():
+    A = w.stencil_3d27(5)
+    P = host_plan(A, value_bits=32)
+    i = P.info()
+    assert i["n"] == A.n and i["nnz"] == A.nnz and i["value_bits"] == 32
+    assert i["matrix_bytes"] == 4 * (A.n + 1) + 8 * A.nnz
+    assert i["n_levels"] == 5  # cube shells max(x,y,z) = const from the corner
+    assert i["lanes_per_row"] in (1, 2, 4, 8, 16)
+
+
+# ------------------------------------------------------------------ error paths
+
+def _raw_plan(n, rowptr, col, val, device=mpk.MPK_DEVICE_NONE):
+    L = _capi.load()
+    rowptr = np.asarray(rowptr, np.int32)
+    col = np.asarray(col, np.int32)
+    val = np.asarray(val, np.float64)
+    csr = _capi.CSRStruct(n, int(rowptr[-1]) if rowptr.size else 0, rowptr.ctypes.data,
+                          col.ctypes.data, val.ctypes.data)
+    opts = _capi.PlanOpts()
+    L.mpk_plan_opts_default(ctypes.byref(opts))
+    opts.device = device
+    h = ctypes.c_void_p()
+    st = L.mpk_plan(ctypes.byref(csr), ctypes.byref(opts), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("rowptr,col,status", [
+    ([0, 2, 1, 3], [0, 1, 2], _capi.MPK_EBADCSR),      # decreasing rowptr
+    ([1, 2, 3, 3], [0, 1, 2], _capi.MPK_EBADCSR),      # rowptr[0] != 0
+    ([0, 1, 2, 3], [0, 3, 2], _capi.MPK_EBADCSR),      # column out of range
+    ([0, 1, 2, 3], [0, -1, 2], _capi.MPK_EBADCSR),     # negative column
+])
+def test_bad_csr_rejected(rowptr, col, status):
+    st, h = _raw_plan(3, rowptr, col, np.ones(3))
+    assert st == status
+    assert not h.value
+    assert _capi.load().mpk_last_error()
+
+
+def test_run_argument_errors_without_device():
+    A = w.stencil_2d5(4)
+    P = host_plan(A)
+    L = _capi.load()
+    assert L.mpk_run(P._h, None, 0, 1, None, None) == _capi.MPK_EINVAL
+    assert L.mpk_run(P._h, None, 3, 17, None, None) == _capi.MPK_EUNSUPPORTED
+    assert L.mpk_run(P._h, None, 3, 1, None, None) == _capi.MPK_ENODEVICE
+    assert L.mpk_run_baseline(P._h, None, -1, 1, None, None) == _capi.MPK_EINVAL
+    assert L.mpk_run(None, None, 3, 1, None, None) == _capi.MPK_EINVAL
+    assert L.mpk_plan_sync(P._h) == _capi.MPK_ENODEVICE
+
+
+def test_tune_validation():
+    P = host_plan(w.stencil_2d5(4))
+    with pytest.raises(mpk.MPKError):
+        P.tune(cache_safety=0.0)
+    with pytest.raises(mpk.MPKError):
+        P.tune(rhs_per_thread=3)
+    with pytest.raises(mpk.MPKError):
+        P.tune(chunk_nnz=0)
+    with pytest.raises(mpk.MPKError):
+        mpk.Plan(w.stencil_2d5(4), device=mpk.MPK_DEVICE_NONE, lanes_per_row=3)
+
+
+def test_empty_and_tiny_plans():
+    A = w.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    P = host_plan(A)
+    assert P.info()["n"] == 0
+    s = P.schedule(3)
+    assert s["n_chunks"] == 0 and s["n_tasks"] == 0
+    B = w.identity(1)
+    s = host_plan(B).schedule(4)
+    assert s["n_chunks"] == 1 and s["tasks"].tolist() == [[0, 1], [0, 2], [0, 3], [0, 4]]
