@@ -134,7 +134,7 @@ def main():
         s = P.schedule(p)
         log(f"[bench] plan reorder={ro}: {time.perf_counter() - t0:.2f}s "
             f"(host {info['plan_ms']:.0f} ms) levels={info['n_levels']} "
-            f"lanes={info['lanes_per_row']} chunks={s['n_chunks']} lag={s['lag']} "
+            f"chunks={s['n_chunks']} lag={s['lag']} "
             f"reach={s['max_reach']} window={s['window_bytes'] / 2**20:.0f} MiB")
         lb = time_calls(lambda: P.run(xd, p, Y), args.steps, args.warmup, torch)
         P.sync()
@@ -180,7 +180,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "lb_kernel", "algorithmic_bytes": lb_bytes},
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
-                 "lanes_per_row": info["lanes_per_row"], "chunks": sched["n_chunks"],
+                 "chunks": sched["n_chunks"],
                  "lag": sched["lag"], "spmv_equivalents":
                      round(info["plan_ms"] / base["median_ms"] * p, 1)},
     }

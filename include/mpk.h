@@ -62,9 +62,15 @@ enum {
 
 /* Traversal order of the (chunk, power) tasks. */
 enum {
-    MPK_SCHED_WAVE = 0,     /* skewed chunk wavefront (default)                    */
-    MPK_SCHED_DIAG = 1,     /* the paper's Lp-diagram diagonals over level groups  */
-    MPK_SCHED_POWERS = 2    /* power by power (all chunks of y_1, then y_2, ...)   */
+    MPK_SCHED_STEPS = 0,    /* default: level groups walked along the diagonals
+                               g + 2(k-1) = const; the tasks of one diagonal are
+                               independent and run as one kernel launch, the
+                               launch boundary orders consecutive diagonals    */
+    MPK_SCHED_WAVE = 1,     /* one persistent kernel, skewed chunk wavefront with
+                               per-chunk completion flags                      */
+    MPK_SCHED_DIAG = 2,     /* one persistent kernel, the paper's Lp-diagram
+                               diagonals g + k = const over level groups        */
+    MPK_SCHED_POWERS = 3    /* one persistent kernel, power by power            */
 };
 
 #define MPK_DEVICE_CURRENT (-1)
@@ -87,22 +93,22 @@ typedef struct {
     int reorder;             /* MPK_REORDER_BFS (default) or MPK_REORDER_NONE   */
     int order;               /* MPK_ORDER_ORIGINAL (default) or MPK_ORDER_PLAN  */
     int root;                /* BFS root row (default 0)                       */
-    int lanes_per_row;       /* 0 = chosen from the mean row length; else 1..16,
-                                a power of two.  Fixes the per-row summation
-                                order shared by every run kernel of the plan.  */
     int device;              /* HIP device, MPK_DEVICE_CURRENT or MPK_DEVICE_NONE */
 } mpk_plan_opts_t;
 
 /* Run-time tuning of a plan (mpk_plan_tune).  None of these changes a result
- * bit: the per-row arithmetic is fixed by lanes_per_row at plan time. */
+ * bit: every kernel sums each row sequentially in stored order. */
 typedef struct {
-    int schedule;            /* MPK_SCHED_WAVE (default), _DIAG or _POWERS      */
-    int64_t cache_bytes;     /* blocking budget C in bytes (default 256 MiB)    */
-    double cache_safety;     /* fraction of C the window may use (default 0.5) */
-    int chunk_nnz;           /* target nonzeros per chunk (default 8192)       */
-    int lag;                 /* wavefront slack in chunks; 0 = from the budget  */
-    int workgroups;          /* persistent workgroups; 0 = fill the device      */
-    int rhs_per_thread;      /* 0 = auto; 1, 2, 4 or 8 (must divide nrhs)       */
+    int schedule;            /* MPK_SCHED_STEPS (default), _WAVE, _DIAG, _POWERS */
+    int64_t cache_bytes;     /* blocking budget C in bytes (default 64 MiB:
+                                the measured fast-read plateau of the MI355X
+                                Infinity Cache)                                 */
+    double cache_safety;     /* fraction of C the window may use (default 1.0) */
+    int chunk_nnz;           /* target nonzeros per chunk = per workgroup task
+                                (default 4096)                                  */
+    int lag;                 /* WAVE only: slack in chunks; 0 = from the budget */
+    int workgroups;          /* persistent schedules: workgroups; 0 = fill the
+                                device                                          */
     int64_t spin_limit_us;   /* dependency-wait limit in microseconds, 0 = 2 s  */
 } mpk_tune_t;
 
@@ -110,7 +116,7 @@ typedef struct {
     int64_t n, nnz;
     int32_t n_levels;        /* BFS levels (or order-derived levels)           */
     int32_t max_level_rows;
-    int32_t value_bits, reorder, order, lanes_per_row;
+    int32_t value_bits, reorder, order;
     int64_t matrix_bytes;    /* device CSR bytes: 4(n+1) + (4 + value bytes) nnz */
     double plan_ms;          /* host preprocessing time                         */
     int32_t device;
@@ -119,6 +125,7 @@ typedef struct {
 typedef struct {
     int32_t p;               /* the schedule's power count                      */
     int32_t n_chunks, n_groups, n_tasks;
+    int32_t n_steps;         /* kernel launches per segment (STEPS), else 1     */
     int32_t lag;             /* effective wavefront slack                       */
     int32_t max_reach;       /* max over chunks of dhi - c (in chunks)          */
     double window_bytes;     /* estimated matrix bytes touched by one window    */
@@ -160,19 +167,21 @@ mpk_status_t mpk_plan_levels(mpk_plan_t plan, int32_t *level_ptr, int32_t *perm)
  * Build (or fetch from the plan's cache) the schedule for p powers with the
  * current tuning and describe it.  Arrays are host memory and may be NULL:
  * chunk_ptr[n_chunks+1] (row ranges in plan order), chunk_group[n_chunks],
- * dep_lo/dep_hi[n_chunks] (inclusive chunk range a chunk's rows read), and
- * tasks[2*n_tasks] = (chunk, power) pairs in issue order.
+ * dep_lo/dep_hi[n_chunks] (inclusive chunk range a chunk's rows read),
+ * tasks[2*n_tasks] = (chunk, power) pairs in issue order, and for STEPS
+ * step_ptr[n_steps+1] (task ranges of the launches).
  */
 mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info,
                                int32_t *chunk_ptr, int32_t *chunk_group, int32_t *dep_lo,
-                               int32_t *dep_hi, int32_t *tasks);
+                               int32_t *dep_hi, int32_t *tasks, int32_t *step_ptr);
 
 /*
  * Level-blocked matrix power kernel: Y = [A x, A^2 x, ..., A^p x].
- * One persistent kernel walks the (chunk, power) tasks in the schedule's
- * order; a task starts once the chunks its rows read are done at the previous
- * power (the Lp-diagram dependency of Sec. "RACE Applied to the Matrix Power
- * Kernel": level i at power k needs levels i-1..i+1 at power k-1).
+ * The (chunk, power) tasks run in the schedule's order; a task starts once
+ * the chunks its rows read are done at the previous power (the Lp-diagram
+ * dependency of Sec. "RACE Applied to the Matrix Power Kernel": level i at
+ * power k needs levels i-1..i+1 at power k-1).  STEPS orders tasks by kernel
+ * launches; the persistent schedules by per-chunk completion flags.
  * x: n*nrhs doubles; Y: p*n*nrhs doubles (device).  1 <= nrhs <= 16.
  * Errors: MPK_EINVAL (p < 1, NULL), MPK_EUNSUPPORTED (nrhs), MPK_ENODEVICE.
  */
@@ -193,8 +202,10 @@ mpk_status_t mpk_run_recur(mpk_plan_t plan, const double *x, int p, int nrhs,
 
 /*
  * Baseline: p back-to-back CSR SpMVs, one kernel launch per power (Alg. 1
- * without halo exchange), on the plan's matrix with the plan's per-row
- * summation order, so its results are bit-identical to mpk_run's.
+ * without halo exchange), on the plan's matrix.  Every kernel of this
+ * library forms each entry of y_k as the plain CSR sum: products rounded one
+ * by one, added left to right in stored order from 0.0 (no fused
+ * multiply-add), so baseline and level-blocked results are bit-identical.
  */
 mpk_status_t mpk_run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
                               void *hip_stream);
@@ -213,6 +224,16 @@ mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double 
 /* Wait for every run issued on this plan and report device-side failures
  * (MPK_ETIMEOUT when a dependency wait hit its limit). */
 mpk_status_t mpk_plan_sync(mpk_plan_t plan);
+
+/*
+ * Load-only bandwidth probe (the MI355X counterpart of the paper's
+ * load-bandwidth measurement, Fig. "All Bandwidths"): `workgroups` x 256
+ * threads read the device buffer buf[n] (n even) `passes` times with 16-byte
+ * loads and write one double per workgroup to sink[workgroups] (device).
+ * The caller times the call (e.g. with events on the stream).
+ */
+mpk_status_t mpk_probe_load(const double *buf, int64_t n, int passes, int workgroups,
+                            double *sink, void *hip_stream);
 
 /* Device allocator used for plan data (NULL, NULL restores hipMalloc/hipFree). */
 mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx),

@@ -18,14 +18,15 @@ import numpy as np
 from . import _capi
 from ._capi import (MPK_DEVICE_CURRENT, MPK_DEVICE_NONE, MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN,
                     MPK_REORDER_BFS, MPK_REORDER_NONE, MPK_SCHED_DIAG, MPK_SCHED_POWERS,
-                    MPK_SCHED_WAVE, MPKError, check)
+                    MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPKError, check)
 
 __all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN",
-           "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
+           "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
            "MPK_SCHED_POWERS", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
-           "flops", "lib"]
+           "flops", "lib", "probe_load"]
 
-_SCHED = {"wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG, "powers": MPK_SCHED_POWERS}
+_SCHED = {"steps": MPK_SCHED_STEPS, "wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG,
+          "powers": MPK_SCHED_POWERS}
 
 
 def lib():
@@ -51,6 +52,19 @@ def flops(nnz: int, n: int, p: int, nrhs: int, recur: bool = False) -> float:
     if recur:
         f += 2.0 * n * nrhs * max(0, p - 1)
     return f
+
+
+def probe_load(buf, passes: int = 1, workgroups: int = 2048, sink=None, stream=None):
+    """Launch the load-only bandwidth probe over a float64 device tensor."""
+    torch = _torch()
+    if buf.dtype != torch.float64 or not buf.is_contiguous() or not buf.is_cuda:
+        raise TypeError("buf must be a contiguous float64 device tensor")
+    if sink is None:
+        sink = torch.empty(workgroups, dtype=torch.float64, device=buf.device)
+    check(lib().mpk_probe_load(ctypes.c_void_p(buf.data_ptr()), buf.numel(), int(passes),
+                               int(workgroups), ctypes.c_void_p(sink.data_ptr()),
+                               _stream_handle(stream)))
+    return sink
 
 
 def _torch():
@@ -85,7 +99,7 @@ class Plan:
     """
 
     def __init__(self, A, value_bits: int = 64, reorder: str = "bfs", order: str = "original",
-                 root: int = 0, lanes_per_row: int = 0, device=MPK_DEVICE_CURRENT):
+                 root: int = 0, device=MPK_DEVICE_CURRENT):
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
@@ -101,7 +115,6 @@ class Plan:
         opts.reorder = {"bfs": MPK_REORDER_BFS, "none": MPK_REORDER_NONE}[reorder]
         opts.order = {"original": MPK_ORDER_ORIGINAL, "plan": MPK_ORDER_PLAN}[order]
         opts.root = int(root)
-        opts.lanes_per_row = int(lanes_per_row)
         if device is None or device == "none":
             device = MPK_DEVICE_NONE
         opts.device = int(device)
@@ -147,18 +160,20 @@ class Plan:
     def schedule(self, p: int) -> dict:
         si = _capi.SchedInfo()
         check(self._lib.mpk_plan_schedule(self._h, int(p), ctypes.byref(si), None, None, None,
-                                          None, None))
+                                          None, None, None))
         nc, nt = si.n_chunks, si.n_tasks
         cp = np.zeros(nc + 1, np.int32)
         cg = np.zeros(nc, np.int32)
         lo = np.zeros(nc, np.int32)
         hi = np.zeros(nc, np.int32)
         tasks = np.zeros(2 * nt, np.int32)
+        sp = np.zeros(si.n_steps + 1, np.int32)
         check(self._lib.mpk_plan_schedule(self._h, int(p), ctypes.byref(si), cp.ctypes.data,
                                           cg.ctypes.data, lo.ctypes.data, hi.ctypes.data,
-                                          tasks.ctypes.data))
+                                          tasks.ctypes.data, sp.ctypes.data))
         d = {f: getattr(si, f) for f, _ in _capi.SchedInfo._fields_}
-        d.update(chunk_ptr=cp, chunk_group=cg, dep_lo=lo, dep_hi=hi, tasks=tasks.reshape(-1, 2))
+        d.update(chunk_ptr=cp, chunk_group=cg, dep_lo=lo, dep_hi=hi, tasks=tasks.reshape(-1, 2),
+                 step_ptr=sp)
         return d
 
     # ------------------------------------------------------------ tuning

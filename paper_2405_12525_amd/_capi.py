@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "MPK_OK", 1: "MPK_EINVAL", 2: "MPK_EBADCSR", 3: "MPK_ENOMEM",
                 5: "MPK_EUNSUPPORTED", 6: "MPK_ETIMEOUT", 7: "MPK_ENODEVICE"}
 MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN = 0, 1
 MPK_REORDER_BFS, MPK_REORDER_NONE = 0, 1
-MPK_SCHED_WAVE, MPK_SCHED_DIAG, MPK_SCHED_POWERS = 0, 1, 2
+MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPK_SCHED_DIAG, MPK_SCHED_POWERS = 0, 1, 2, 3
 MPK_DEVICE_CURRENT, MPK_DEVICE_NONE = -1, -2
 MPK_MAX_RHS = 16
 
@@ -22,7 +22,7 @@ EXPORTS = [
     "mpk_plan_opts_default", "mpk_tune_default", "mpk_plan", "mpk_plan_destroy", "mpk_plan_tune",
     "mpk_plan_info", "mpk_plan_levels", "mpk_plan_schedule", "mpk_run", "mpk_run_recur",
     "mpk_run_baseline", "mpk_run_baseline_recur", "mpk_permute", "mpk_plan_sync",
-    "mpk_set_allocator", "mpk_last_error", "mpk_version",
+    "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
 ]
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -36,27 +36,28 @@ class CSRStruct(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("value_bits", ctypes.c_int), ("reorder", ctypes.c_int), ("order", ctypes.c_int),
-                ("root", ctypes.c_int), ("lanes_per_row", ctypes.c_int), ("device", ctypes.c_int)]
+                ("root", ctypes.c_int), ("device", ctypes.c_int)]
 
 
 class Tune(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("cache_bytes", ctypes.c_int64),
                 ("cache_safety", ctypes.c_double), ("chunk_nnz", ctypes.c_int),
                 ("lag", ctypes.c_int), ("workgroups", ctypes.c_int),
-                ("rhs_per_thread", ctypes.c_int), ("spin_limit_us", ctypes.c_int64)]
+                ("spin_limit_us", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_levels", ctypes.c_int32),
                 ("max_level_rows", ctypes.c_int32), ("value_bits", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("lanes_per_row", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
+                ("matrix_bytes", ctypes.c_int64),
                 ("plan_ms", ctypes.c_double), ("device", ctypes.c_int32)]
 
 
 class SchedInfo(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("n_chunks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
-                ("n_tasks", ctypes.c_int32), ("lag", ctypes.c_int32), ("max_reach", ctypes.c_int32),
+                ("n_tasks", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("lag", ctypes.c_int32),
+                ("max_reach", ctypes.c_int32),
                 ("window_bytes", ctypes.c_double), ("build_ms", ctypes.c_double)]
 
 
@@ -89,7 +90,7 @@ def load():
     lib.mpk_plan_info.restype = st
     lib.mpk_plan_levels.argtypes = [P, P, P]
     lib.mpk_plan_levels.restype = st
-    lib.mpk_plan_schedule.argtypes = [P, ctypes.c_int, ctypes.POINTER(SchedInfo), P, P, P, P, P]
+    lib.mpk_plan_schedule.argtypes = [P, ctypes.c_int, ctypes.POINTER(SchedInfo), P, P, P, P, P, P]
     lib.mpk_plan_schedule.restype = st
     lib.mpk_run.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P]
     lib.mpk_run.restype = st
@@ -103,6 +104,8 @@ def load():
     lib.mpk_permute.restype = st
     lib.mpk_plan_sync.argtypes = [P]
     lib.mpk_plan_sync.restype = st
+    lib.mpk_probe_load.argtypes = [P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P]
+    lib.mpk_probe_load.restype = st
     lib.mpk_set_allocator.argtypes = [P, P, P]
     lib.mpk_set_allocator.restype = st
     lib.mpk_last_error.argtypes = []

@@ -118,7 +118,7 @@ double now_ms() {
 struct mpk_plan_s {
     int64_t n = 0, nnz = 0;
     int value_bits = 64, reorder = MPK_REORDER_BFS, order = MPK_ORDER_ORIGINAL;
-    int lanes = 1, device = MPK_DEVICE_NONE;
+    int device = MPK_DEVICE_NONE;
     bool host_only = true;
     double plan_ms = 0.0;
     int wall_khz = 100000;
@@ -127,6 +127,8 @@ struct mpk_plan_s {
     std::vector<int32_t> rowptr, row_lo, row_hi;
     // device data
     DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
+    DevBuf d_bptr;           // row blocks of the p x SpMV baseline kernel
+    int32_t n_bblocks = 0;
     // schedules and workspaces
     std::mutex mu;
     mpk_tune_t tune{};
@@ -137,7 +139,7 @@ struct mpk_plan_s {
 
     DevMatrix matrix() const {
         return DevMatrix{d_rowptr.as<int32_t>(), d_col.as<int32_t>(), d_val.ptr,
-                         d_outrow.as<int32_t>(), (int32_t)n, value_bits, lanes};
+                         d_outrow.as<int32_t>(), (int32_t)n, value_bits};
     }
     ~mpk_plan_s() {
         if (!host_only) {
@@ -155,19 +157,21 @@ struct mpk_plan_s {
 
 namespace {
 
-int pick_lanes(int64_t n, int64_t nnz) {
-    const double mean = n ? (double)nnz / (double)n : 0.0;
-    int L = 1;
-    while (L < 16 && 2.0 * L * 6.0 <= mean) L *= 2;
-    return L;
-}
-
-int pick_rt(const mpk_tune_t &t, int lanes, int R) {
-    if (t.rhs_per_thread > 0) return t.rhs_per_thread;
-    int rt = 4;  // largest power of two <= 4 that divides R
-    while (rt > 1 && (rt > R || R % rt)) rt >>= 1;
-    (void)lanes;
-    return rt;
+// Row blocks of about `target` nonzeros (and at most 4096 rows) for the
+// one-launch-per-power baseline.
+std::vector<int32_t> row_blocks(const std::vector<int32_t> &rowptr, int64_t n, int64_t target) {
+    std::vector<int32_t> b(1, 0);
+    int64_t r = 0;
+    while (r < n) {
+        const int64_t lim = (int64_t)rowptr[r] + target;
+        int64_t e = std::upper_bound(rowptr.begin() + r + 1, rowptr.begin() + n + 1, (int32_t)std::min<int64_t>(lim, INT32_MAX)) -
+                    rowptr.begin() - 1;
+        e = std::max<int64_t>(e, r + 1);
+        e = std::min<int64_t>(e, r + 4096);
+        b.push_back((int32_t)e);
+        r = e;
+    }
+    return b;
 }
 
 mpk_status_t check_device_plan(mpk_plan_t plan) {
@@ -231,11 +235,11 @@ mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream
     return MPK_OK;
 }
 
-int default_workgroups(mpk_plan_t plan, int rt) {
-    const long long key = (long long)plan->value_bits * 1000 + plan->lanes * 10 + rt;
+int default_workgroups(mpk_plan_t plan, int R) {
+    const long long key = (long long)plan->value_bits * 1000 + R;
     auto it = plan->wg_cache.find(key);
     if (it != plan->wg_cache.end()) return it->second;
-    int wg = lb_max_workgroups(plan->value_bits, plan->lanes, rt, plan->device);
+    int wg = lb_max_workgroups(plan->value_bits, R, plan->device);
     if (wg <= 0) wg = 1024;
     plan->wg_cache[key] = wg;
     return wg;
@@ -270,10 +274,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     const bool capturing = cap == hipStreamCaptureStatusActive;
 
     std::lock_guard<std::mutex> g(plan->mu);
-    const int rt = pick_rt(plan->tune, plan->lanes, nrhs);
-    if (!kernel_config_ok(plan->lanes, rt) || nrhs % rt || plan->lanes * (nrhs / rt) > 256)
-        return fail(MPK_EUNSUPPORTED, "rhs_per_thread does not fit nrhs / lanes");
-    const int wg_default = default_workgroups(plan, rt);
+    const int wg_default = default_workgroups(plan, nrhs);
     const int wg = plan->tune.workgroups > 0 ? plan->tune.workgroups : wg_default;
     const int64_t limit_us = plan->tune.spin_limit_us > 0 ? plan->tune.spin_limit_us : 2000000;
     const int64_t spin_ticks = limit_us * (int64_t)plan->wall_khz / 1000;
@@ -283,8 +284,6 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         const int ps = std::min(kMaxSegPowers, p - base);
         SchedEntry *se = nullptr;
         if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
-        Workspace *ws = nullptr;
-        if ((st = get_workspace(plan, se->host.n_chunks(), stream, capturing, &ws))) return st;
         SegArgs a;
         a.in0 = base == 0 ? x : Y + (size_t)(base - 1) * stride;
         a.inm1 = base == 0 ? nullptr : (base == 1 ? x : Y + (size_t)(base - 2) * stride);
@@ -299,12 +298,25 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                 cf.beta[j] = beta[base + j];
                 cf.gamma[j] = gamma[base + j];
             }
+        if (!se->host.step_ptr.empty()) {
+            // one launch per diagonal; stream order separates the diagonals
+            const auto &sp = se->host.step_ptr;
+            for (size_t d = 0; d + 1 < sp.size(); ++d) {
+                int rc = launch_step(m, se->chunk_ptr.as<int32_t>(),
+                                     se->tasks.as<int32_t>() + 2 * (size_t)sp[d], sp[d + 1] - sp[d],
+                                     a, &cf, stream);
+                if (rc) return hip_fail((hipError_t)rc, "step kernel launch");
+            }
+            continue;
+        }
+        Workspace *ws = nullptr;
+        if ((st = get_workspace(plan, se->host.n_chunks(), stream, capturing, &ws))) return st;
         DevSchedule ds{se->chunk_ptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
                        se->dep_hi.as<int32_t>(), se->tasks.as<int32_t>(), se->host.n_tasks(),
                        se->host.n_chunks()};
         int rc = launch_reset(ws->view(), se->host.n_chunks(), stream);
         if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
-        rc = launch_lb(m, ds, ws->view(), a, &cf, rt, wg, spin_ticks, stream);
+        rc = launch_lb(m, ds, ws->view(), a, &cf, wg, spin_ticks, stream);
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
         if (capturing) {
             ws->reserved = true;
@@ -327,22 +339,16 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     if (plan->n == 0) return MPK_OK;
     hipError_t e = hipSetDevice(plan->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    int rt;
-    {
-        std::lock_guard<std::mutex> g(plan->mu);
-        rt = pick_rt(plan->tune, plan->lanes, nrhs);
-    }
-    if (!kernel_config_ok(plan->lanes, rt) || nrhs % rt || plan->lanes * (nrhs / rt) > 256)
-        return fail(MPK_EUNSUPPORTED, "rhs_per_thread does not fit nrhs / lanes");
     const size_t stride = (size_t)plan->n * nrhs;
     const DevMatrix m = plan->matrix();
     for (int k = 1; k <= p; ++k) {
         const double *in = k == 1 ? x : Y + (size_t)(k - 2) * stride;
         const double *prev = k == 1 ? nullptr : (k == 2 ? x : Y + (size_t)(k - 3) * stride);
         double *out = Y + (size_t)(k - 1) * stride;
-        int rc = launch_spmv_power(m, in, prev, out, nrhs, recur ? 1 : 0,
-                                   recur ? alpha[k - 1] : 1.0, recur ? beta[k - 1] : 0.0,
-                                   recur ? gamma[k - 1] : 0.0, rt, stream_v);
+        int rc = launch_spmv_power(m, plan->d_bptr.as<int32_t>(), plan->n_bblocks, in, prev, out,
+                                   nrhs, recur ? 1 : 0, recur ? alpha[k - 1] : 1.0,
+                                   recur ? beta[k - 1] : 0.0, recur ? gamma[k - 1] : 0.0,
+                                   stream_v);
         if (rc) return hip_fail((hipError_t)rc, "spmv kernel launch");
     }
     return MPK_OK;
@@ -362,19 +368,17 @@ void mpk_plan_opts_default(mpk_plan_opts_t *o) {
     o->reorder = MPK_REORDER_BFS;
     o->order = MPK_ORDER_ORIGINAL;
     o->root = 0;
-    o->lanes_per_row = 0;
     o->device = MPK_DEVICE_CURRENT;
 }
 
 void mpk_tune_default(mpk_tune_t *t) {
     if (!t) return;
-    t->schedule = MPK_SCHED_WAVE;
-    t->cache_bytes = (int64_t)256 << 20;
-    t->cache_safety = 0.5;
-    t->chunk_nnz = 8192;
+    t->schedule = MPK_SCHED_STEPS;
+    t->cache_bytes = (int64_t)64 << 20;
+    t->cache_safety = 1.0;
+    t->chunk_nnz = 4096;
     t->lag = 0;
     t->workgroups = 0;
-    t->rhs_per_thread = 0;
     t->spin_limit_us = 0;
 }
 
@@ -396,8 +400,6 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
     if (o.value_bits != 64 && o.value_bits != 32) return fail(MPK_EINVAL, "value_bits must be 32 or 64");
     if (o.reorder != MPK_REORDER_BFS && o.reorder != MPK_REORDER_NONE) return fail(MPK_EINVAL, "bad reorder");
     if (o.order != MPK_ORDER_ORIGINAL && o.order != MPK_ORDER_PLAN) return fail(MPK_EINVAL, "bad order");
-    if (o.lanes_per_row != 0 && !kernel_config_ok(o.lanes_per_row, 1))
-        return fail(MPK_EINVAL, "lanes_per_row must be 0, 1, 2, 4, 8 or 16");
     const bool host_only = o.device == MPK_DEVICE_NONE;
     std::string err;
     mpk_status_t st = validate_csr(A, !host_only, err);
@@ -414,7 +416,6 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         plan->reorder = o.reorder;
         plan->order = o.order;
         plan->host_only = host_only;
-        plan->lanes = o.lanes_per_row ? o.lanes_per_row : pick_lanes(A->n, A->nnz);
         mpk_tune_default(&plan->tune);
         plan->lv = o.reorder == MPK_REORDER_BFS ? bfs_levels(A->n, A->rowptr, A->col, o.root)
                                                 : order_levels(A->n, A->rowptr, A->col);
@@ -446,6 +447,9 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                 for (size_t i = 0; i < nnz; ++i) v32[i] = (float)pc.val[i];
                 if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
             }
+            const std::vector<int32_t> bb = row_blocks(pc.rowptr, A->n, 4096);
+            plan->n_bblocks = (int32_t)bb.size() - 1;
+            if ((st = plan->d_bptr.upload(bb.data(), bb.size() * 4))) return st;
             bool identity = true;
             for (int64_t i = 0; i < A->n && identity; ++i) identity = plan->lv.perm[i] == i;
             if (!identity) {
@@ -471,13 +475,11 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
     mpk_tune_t t;
     mpk_tune_default(&t);
     if (tune) t = *tune;
-    if (t.schedule < MPK_SCHED_WAVE || t.schedule > MPK_SCHED_POWERS) return fail(MPK_EINVAL, "bad schedule");
+    if (t.schedule < MPK_SCHED_STEPS || t.schedule > MPK_SCHED_POWERS) return fail(MPK_EINVAL, "bad schedule");
     if (t.cache_bytes <= 0 || !(t.cache_safety > 0.0) || t.cache_safety > 1.0)
         return fail(MPK_EINVAL, "cache_bytes must be > 0 and cache_safety in (0, 1]");
     if (t.chunk_nnz < 1 || t.lag < 0 || t.workgroups < 0 || t.spin_limit_us < 0)
         return fail(MPK_EINVAL, "negative tuning value");
-    if (t.rhs_per_thread != 0 && !kernel_config_ok(1, t.rhs_per_thread))
-        return fail(MPK_EINVAL, "rhs_per_thread must be 0, 1, 2, 4 or 8");
     std::lock_guard<std::mutex> g(plan->mu);
     plan->tune = t;
     // schedules may still be read by queued kernels: keep them until destroy
@@ -498,7 +500,6 @@ mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info) {
     info->value_bits = plan->value_bits;
     info->reorder = plan->reorder;
     info->order = plan->order;
-    info->lanes_per_row = plan->lanes;
     info->matrix_bytes = 4 * (plan->n + 1) + (4 + plan->value_bits / 8) * plan->nnz;
     info->plan_ms = plan->plan_ms;
     info->device = plan->device;
@@ -514,7 +515,7 @@ mpk_status_t mpk_plan_levels(mpk_plan_t plan, int32_t *level_ptr, int32_t *perm)
 
 mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info, int32_t *chunk_ptr,
                                int32_t *chunk_group, int32_t *dep_lo, int32_t *dep_hi,
-                               int32_t *tasks) {
+                               int32_t *tasks, int32_t *step_ptr) {
     if (!plan) return fail(MPK_EINVAL, "plan is NULL");
     if (p < 1 || p > kMaxSegPowers) return fail(MPK_EINVAL, "p must be in [1, 64]");
     std::lock_guard<std::mutex> g(plan->mu);
@@ -529,6 +530,7 @@ mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info, i
         info->n_chunks = s.n_chunks();
         info->n_groups = s.n_groups;
         info->n_tasks = s.n_tasks();
+        info->n_steps = s.n_steps();
         info->lag = s.lag;
         info->max_reach = s.max_reach;
         info->window_bytes = s.window_bytes;
@@ -539,6 +541,14 @@ mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info, i
     if (dep_lo) std::copy(s.dep_lo.begin(), s.dep_lo.end(), dep_lo);
     if (dep_hi) std::copy(s.dep_hi.begin(), s.dep_hi.end(), dep_hi);
     if (tasks) std::copy(s.tasks.begin(), s.tasks.end(), tasks);
+    if (step_ptr) {
+        if (s.step_ptr.empty()) {
+            step_ptr[0] = 0;
+            step_ptr[1] = s.n_tasks();
+        } else {
+            std::copy(s.step_ptr.begin(), s.step_ptr.end(), step_ptr);
+        }
+    }
     return MPK_OK;
 }
 
@@ -582,6 +592,14 @@ mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double 
     }
     int rc = launch_permute(plan->d_perm.as<int32_t>(), plan->n, to_plan, in, out, nvec, nrhs, stream);
     return rc ? hip_fail((hipError_t)rc, "permute kernel launch") : MPK_OK;
+}
+
+mpk_status_t mpk_probe_load(const double *buf, int64_t n, int passes, int workgroups,
+                            double *sink, void *stream) {
+    if (!buf || !sink || n < 2 || (n & 1) || passes < 1 || workgroups < 1)
+        return fail(MPK_EINVAL, "probe needs buf, sink, an even n >= 2, passes and workgroups >= 1");
+    int rc = launch_load_probe(buf, n, passes, workgroups, sink, stream);
+    return rc ? hip_fail((hipError_t)rc, "probe kernel launch") : MPK_OK;
 }
 
 mpk_status_t mpk_plan_sync(mpk_plan_t plan) {

@@ -1,14 +1,19 @@
-// HIP kernels for gfx950 (MI355X): CSR rows as SpMV / SpMM, the p x SpMV
-// baseline, the persistent level-blocked kernel, permutation and reset.
+// HIP kernels for gfx950 (MI355X): CSR products for one power, the p x SpMV
+// baseline, the persistent level-blocked kernel, permutation, reset and a
+// load-bandwidth probe.
 //
-// All run kernels share one per-row routine (row_block below), so the
-// baseline, the level-blocked kernel and every right-hand-side tiling give
-// bit-identical results for a given lanes-per-row L:
-//   lane l of a row's L lanes accumulates entries e = rs+l, rs+l+L, ... in
-//   stored order with fused multiply-adds starting from 0; the L partial sums
-//   are then combined by an xor butterfly (offsets 1, 2, 4, ...).
-// Values may be stored in float; they are promoted to double before the
-// product, and vectors and sums are always double.
+// Every run kernel goes through one row routine (stream_rows below), which
+// works on slices of consecutive nonzeros:
+//   1. the workgroup reads a slice's column indices and values with
+//      coalesced loads, gathers the matching input entries and stores the
+//      products a_e * x_{col(e), r} in LDS (one rounded multiply each);
+//   2. each (row, right-hand side) pair is then summed by one thread,
+//      sequentially in stored order starting from 0.0, with no fused
+//      multiply-add.
+// The summation order is therefore the plain CSR definition itself, and
+// results do not depend on the slice size, the chunking, the schedule or
+// the right-hand-side count.  Values stored as float are promoted to double
+// before the product; vectors and sums are double.
 #include <hip/hip_runtime.h>
 
 #include "mpk_internal.h"
@@ -17,171 +22,227 @@ namespace mpk {
 
 namespace {
 
-constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kWave = 64;
+constexpr int kSlice = 2048;         // doubles of LDS product staging per workgroup
+constexpr int kPerThread = kSlice / kBlock;
 
 __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename V>
-__device__ __forceinline__ double ldval(const V *v, int32_t e) {
-    return static_cast<double>(v[e]);
-}
-
 struct PowerIO {
     const double *in;     // y_{k-1}
-    const double *prev;   // y_{k-2} (recurrence; null at the first power)
+    const double *prev;   // y_{k-2} (recurrence; null at the very first power)
     double *out;          // y_k
     double alpha, beta, gamma;
     int recur;
 };
 
-// Rows [row_begin, row_end) of one power.  Thread t of `nthreads` owns
-// lane l of right-hand-side group rg of row slot `slot`:
-//   t = (slot * nrg + rg) * L + l,  nrg = R / RT,  RT right-hand sides per thread.
-template <typename V, int L, int RT>
-__device__ __forceinline__ void row_block(const DevMatrix &m, const PowerIO &io, int32_t R,
-                                          int32_t row_begin, int32_t row_end, int tid,
-                                          int nthreads) {
-    const int nrg = R / RT;
-    const int tpr = L * nrg;
-    const int rows_per_pass = nthreads / tpr;
-    const int slot = tid / tpr;
-    const int rem = tid - slot * tpr;
-    const int rg = rem / L;
-    const int l = rem - rg * L;
-    if (slot >= rows_per_pass) return;
-    const int32_t *__restrict__ rowptr = m.rowptr;
-    const int32_t *__restrict__ col = m.col;
-    const V *__restrict__ val = static_cast<const V *>(m.val);
-    const double *in = io.in;  // written by other workgroups of the same launch
-    const int r0 = rg * RT;
-    for (int32_t i = row_begin + slot; i < row_end; i += rows_per_pass) {
-        const int32_t rs = rowptr[i], re = rowptr[i + 1];
-        double acc[RT];
+// y = alpha*s + beta*y_{k-1} + gamma*y_{k-2} evaluated left to right, or s.
+__device__ __forceinline__ double epilogue(const PowerIO &io, double s, size_t idx) {
+    if (!io.recur) return s;
+    double v = io.alpha * s;
+    const double b = io.beta * io.in[idx];
+    v = v + b;
+    if (io.prev) {
+        const double g = io.gamma * io.prev[idx];
+        v = v + g;
+    }
+    return v;
+}
+
+// Products of nz consecutive nonzeros starting at `base`, for every
+// right-hand side: prod[j*R + r] = val[base+j] * in[col[base+j]*R + r].
+template <typename V, int RC>
+__device__ __forceinline__ void slice_products(const DevMatrix &m, const double *in, int R,
+                                               int32_t base, int32_t nz, double *prod) {
+    const int tid = threadIdx.x;
+    const int total = nz * R;
+    const V *val = static_cast<const V *>(m.val);
+    int32_t c[kPerThread];
+    double a[kPerThread];
+    int rr[kPerThread];
 #pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] = 0.0;
-        int32_t e = rs + l;
-        // four entries per step: loads first, then the fma chain in order
-        for (; e + 3 * L < re; e += 4 * L) {
-            int32_t c[4];
-            double a[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                c[u] = col[e + u * L];
-                a[u] = ldval(val, e + u * L);
-            }
-            double xv[4][RT];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double *xp = in + (size_t)c[u] * R + r0;
-#pragma unroll
-                for (int r = 0; r < RT; ++r) xv[u][r] = xp[r];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int r = 0; r < RT; ++r) acc[r] = __builtin_fma(a[u], xv[u][r], acc[r]);
+    for (int j = 0; j < kPerThread; ++j) {
+        const int q = tid + j * kBlock;
+        const int el = RC ? q / RC : q / R;
+        rr[j] = q - el * R;
+        c[j] = 0;
+        a[j] = 0.0;
+        if (q < total) {
+            c[j] = m.col[base + el];
+            a[j] = static_cast<double>(val[base + el]);
         }
-        for (; e < re; e += L) {
-            const int32_t c = col[e];
-            const double a = ldval(val, e);
-            const double *xp = in + (size_t)c * R + r0;
+    }
+    double xv[kPerThread];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) acc[r] = __builtin_fma(a, xp[r], acc[r]);
-        }
+    for (int j = 0; j < kPerThread; ++j) {
+        const int q = tid + j * kBlock;
+        xv[j] = 0.0;
+        if (q < total) xv[j] = in[(size_t)c[j] * R + rr[j]];
+    }
 #pragma unroll
-        for (int off = 1; off < L; off <<= 1)
-#pragma unroll
-            for (int r = 0; r < RT; ++r) acc[r] += __shfl_xor(acc[r], off, L);
-        if (l == 0) {
-            const int32_t o = m.out_row ? m.out_row[i] : i;
-            const size_t base = (size_t)o * R + r0;
-            if (io.recur) {
-#pragma unroll
-                for (int r = 0; r < RT; ++r) {
-                    double v = io.alpha * acc[r];
-                    v = __builtin_fma(io.beta, in[base + r], v);
-                    if (io.prev) v = __builtin_fma(io.gamma, io.prev[base + r], v);
-                    acc[r] = v;
-                }
+    for (int j = 0; j < kPerThread; ++j) {
+        const int q = tid + j * kBlock;
+        if (q < total) prod[q] = a[j] * xv[j];
+    }
+}
+
+// Rows [r0, r1) of one power.  Called by all threads of the workgroup.
+template <typename V, int RC>
+__device__ void stream_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_t r0,
+                            int32_t r1, double *prod) {
+    const int R = RC ? RC : R_rt;
+    const int E = kSlice / R;  // nonzeros per slice
+    const int tid = threadIdx.x;
+    const int32_t *rowptr = m.rowptr;
+    int32_t r = r0;
+    while (r < r1) {
+        const int32_t base = rowptr[r];
+        // rows r .. r+cnt-1 end within E nonzeros of base (a prefix: rowptr is sorted)
+        const int32_t i = r + tid + 1;
+        const int fits = (i <= r1) && (rowptr[i] - base <= E);
+        const int cnt = __builtin_amdgcn_readfirstlane(__syncthreads_count(fits));
+        if (cnt > 0) {
+            const int32_t rb = r + cnt;
+            const int32_t nz = rowptr[rb] - base;
+            slice_products<V, RC>(m, io.in, R, base, nz, prod);
+            __syncthreads();
+            const int npairs = cnt * R;
+            for (int q = tid; q < npairs; q += kBlock) {
+                const int li = RC ? q / RC : q / R;
+                const int rr = q - li * R;
+                const int32_t row = r + li;
+                const int32_t s0 = rowptr[row] - base, s1 = rowptr[row + 1] - base;
+                double s = 0.0;
+                for (int32_t e = s0; e < s1; ++e) s = s + prod[e * R + rr];
+                const int32_t o = m.out_row ? m.out_row[row] : row;
+                const size_t idx = (size_t)o * R + rr;
+                io.out[idx] = epilogue(io, s, idx);
             }
-#pragma unroll
-            for (int r = 0; r < RT; ++r) io.out[base + r] = acc[r];
+            __syncthreads();
+            r = rb;
+        } else {
+            // one row longer than a slice: sum it slice by slice, one thread per RHS
+            const int32_t end = rowptr[r + 1];
+            double s = 0.0;
+            for (int32_t b = base; b < end; b += E) {
+                const int32_t nz = min(E, end - b);
+                slice_products<V, RC>(m, io.in, R, b, nz, prod);
+                __syncthreads();
+                if (tid < R)
+                    for (int32_t e = 0; e < nz; ++e) s = s + prod[e * R + tid];
+                __syncthreads();
+            }
+            if (tid < R) {
+                const int32_t o = m.out_row ? m.out_row[r] : r;
+                const size_t idx = (size_t)o * R + tid;
+                io.out[idx] = epilogue(io, s, idx);
+            }
+            r = r + 1;
         }
     }
 }
 
 // ------------------------------------------------------------------ baseline
 
-template <typename V, int L, int RT>
+template <typename V, int RC>
 __global__ __launch_bounds__(kBlock) void spmv_power_kernel(DevMatrix m, PowerIO io, int32_t R,
-                                                           int32_t rows_per_block) {
-    const int32_t rb = (int32_t)blockIdx.x * rows_per_block;
-    const int32_t re = min(rb + rows_per_block, m.n);
-    row_block<V, L, RT>(m, io, R, rb, re, threadIdx.x, blockDim.x);
+                                                           const int32_t *block_ptr) {
+    __shared__ double prod[kSlice];
+    const int32_t r0 = block_ptr[blockIdx.x], r1 = block_ptr[blockIdx.x + 1];
+    stream_rows<V, RC>(m, io, R, r0, r1, prod);
 }
 
 // ------------------------------------------------------------------ level-blocked
+
+// One diagonal of the STEPS schedule: workgroup b computes task tasks[b] =
+// (chunk c, power k).  All tasks of a diagonal are independent; the previous
+// diagonals' results are visible because they ran in earlier launches.
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock) void step_kernel(DevMatrix m, const int32_t *chunk_ptr,
+                                                     const int32_t *tasks, SegArgs a, Coefs cf) {
+    __shared__ double prod[kSlice];
+    const int32_t c = tasks[2 * blockIdx.x];
+    const int32_t k = tasks[2 * blockIdx.x + 1];
+    const size_t stride = (size_t)m.n * a.R;
+    PowerIO io;
+    io.in = (k == 1) ? a.in0 : a.Y + (size_t)(k - 2) * stride;
+    io.prev = (k == 1) ? a.inm1 : (k == 2 ? a.in0 : a.Y + (size_t)(k - 3) * stride);
+    io.out = a.Y + (size_t)(k - 1) * stride;
+    io.recur = a.recur;
+    io.alpha = cf.alpha[k - 1];
+    io.beta = cf.beta[k - 1];
+    io.gamma = cf.gamma[k - 1];
+    stream_rows<V, RC>(m, io, a.R, chunk_ptr[c], chunk_ptr[c + 1], prod);
+}
 
 struct LBParams {
     DevMatrix m;
     DevSchedule s;
     DevWorkspace ws;
     SegArgs a;
-    int64_t spin_limit;   // 100 MHz ticks
+    int64_t spin_limit;   // wall-clock ticks
 };
 
-// Persistent kernel: workgroups take tasks (chunk c, power k) in schedule order
-// from a shared ticket counter.  Before computing, a task waits until every
-// chunk in [dep_lo[c], dep_hi[c]] has completed power k-1; after computing,
-// it publishes done[c] = k.  Dependencies always carry smaller tickets and a
-// workgroup holds at most the ticket it works on plus the next one, so the
-// smallest unfinished ticket can always proceed; every wait is also bounded
-// by spin_limit, after which the run is flagged as failed and all
-// workgroups leave.
-template <typename V, int L, int RT>
+// Persistent kernel: workgroups take tasks (chunk c, power k) in schedule
+// order from a shared ticket counter.  Before computing, a task waits until
+// every chunk in [dep_lo[c], dep_hi[c]] has completed power k-1; after
+// computing, it publishes done[c] = k.  Dependencies always carry smaller
+// tickets and a workgroup holds one ticket at a time, so the smallest
+// unfinished ticket can always proceed; every wait is also bounded by
+// spin_limit, after which the run is flagged as failed and all workgroups
+// leave.
+template <typename V, int RC>
 __global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
+    __shared__ double prod[kSlice];
     __shared__ int32_t s_ticket;
+    __shared__ int s_ok;
     const int tid = threadIdx.x;
-    const int nt = blockDim.x;
     const size_t stride = (size_t)P.m.n * P.a.R;
-    int32_t next = 0;
-    if (tid == 0) next = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        if (tid == 0) s_ticket = next;
-        __syncthreads();
-        const int32_t t = s_ticket;
-        if (t >= P.s.n_tasks) break;
-        if (tid == 0) next = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0)
+        s_ticket = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // All loop control below is made provably uniform (readfirstlane) and the
+    // loop has a single exit: a loop whose exit the compiler considers
+    // divergent may be restructured so that lanes leave it at different
+    // iterations, which would break the barriers inside it.
+    int32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+    while (t < P.s.n_tasks) {
         const int32_t c = P.s.tasks[2 * t];
         const int32_t k = P.s.tasks[2 * t + 1];
+        int ok = 1;
         if (k > 1) {
-            const int32_t lo = P.s.dep_lo[c], hi = P.s.dep_hi[c];
-            int ok = 1;
-            for (int32_t j = lo + tid; j <= hi && ok; j += nt) {
-                if (ld_relaxed(P.ws.done + j) < k - 1) {
-                    const uint64_t t0 = wall_clock64();
-                    while (ld_relaxed(P.ws.done + j) < k - 1) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (ld_relaxed(P.ws.err) != 0 ||
-                            (int64_t)(wall_clock64() - t0) > P.spin_limit) {
-                            ok = 0;
-                            break;
-                        }
+            // Wavefront 0 alone polls the dependency flags, 64 per coalesced
+            // load, and sleeps between rounds; the other waves wait at the
+            // barrier.  (Polling from every thread floods the memory system
+            // with coherent loads and slows the producers down.)
+            if (tid < kWave) {
+                const int32_t lo = P.s.dep_lo[c], hi = P.s.dep_hi[c];
+                uint64_t t0 = 0;
+                for (int round = 0;; ++round) {
+                    int ready = 1;
+                    for (int32_t j = lo + tid; j <= hi; j += kWave)
+                        ready &= ld_relaxed(P.ws.done + j) >= k - 1;
+                    if (__all(ready)) break;
+                    if (round == 0) t0 = wall_clock64();
+                    if (ld_relaxed(P.ws.err) != 0 ||
+                        (int64_t)(wall_clock64() - t0) > P.spin_limit) {
+                        ok = 0;
+                        break;
                     }
+                    __builtin_amdgcn_s_sleep(2);
                 }
+                if (tid == 0) s_ok = ok;
             }
-            ok = __syncthreads_and(ok);
-            if (!ok) {
-                if (tid == 0)
-                    __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return;
-            }
+            __syncthreads();
+            ok = __builtin_amdgcn_readfirstlane(s_ok);
+            // the producers' rows are visible to every wave of this workgroup
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
         // y_k from y_{k-1} (and y_{k-2} for the recurrence); y_0 = in0, y_{-1} = inm1
         PowerIO io;
         io.in = (k == 1) ? P.a.in0 : P.a.Y + (size_t)(k - 2) * stride;
@@ -191,12 +252,25 @@ __global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
         io.alpha = cf.alpha[k - 1];
         io.beta = cf.beta[k - 1];
         io.gamma = cf.gamma[k - 1];
-        row_block<V, L, RT>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], tid, nt);
-        // make this task's rows visible device-wide before publishing it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        stream_rows<V, RC>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], prod);
+        // Every wave's stores have reached the L2 (vmcnt = 0) before the
+        // barrier; the release store below then writes the L2 back for the
+        // other XCDs and publishes the chunk, and the next ticket is taken.
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters untouched
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) {
+            // write the L2 back, wait for the write-back, then publish
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
+    if (t < P.s.n_tasks && tid == 0)
+        __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks) {
@@ -221,64 +295,79 @@ __global__ void permute_kernel(const int32_t *perm, int64_t n, int to_plan, cons
     }
 }
 
+// Load-only bandwidth probe: each workgroup sums its share of the buffer
+// `passes` times with 16-byte loads; one double per workgroup is written.
+__global__ __launch_bounds__(kBlock) void load_probe_kernel(const double2 *buf, int64_t n2,
+                                                            int passes, double *sink) {
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int p = 0; p < passes; ++p)
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += stride) {
+            const double2 v = buf[i];
+            acc += v.x + v.y;
+        }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = red[0];
+}
+
 // ------------------------------------------------------------------ dispatch
 
-using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, int32_t);
+using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, const int32_t *);
 using LbFn = void (*)(LBParams, Coefs);
+using StepFn = void (*)(DevMatrix, const int32_t *, const int32_t *, SegArgs, Coefs);
 
-template <typename V, int L, int RT>
-struct Inst {
-    static constexpr SpmvFn spmv = spmv_power_kernel<V, L, RT>;
-    static constexpr LbFn lb = lb_kernel<V, L, RT>;
-};
-
-constexpr int kLanes[] = {1, 2, 4, 8, 16};
-constexpr int kRT[] = {1, 2, 4, 8};
-
-int lane_index(int L) {
-    switch (L) { case 1: return 0; case 2: return 1; case 4: return 2; case 8: return 3; case 16: return 4; }
-    return -1;
-}
-int rt_index(int RT) {
-    switch (RT) { case 1: return 0; case 2: return 1; case 4: return 2; case 8: return 3; }
-    return -1;
+int r_index(int R) {
+    switch (R) {
+        case 1: return 0;
+        case 2: return 1;
+        case 4: return 2;
+        case 8: return 3;
+        case 16: return 4;
+    }
+    return 5;  // any other count: generic instantiation
 }
 
-template <typename V, int L>
-void fill_rt(SpmvFn *s, LbFn *b) {
-    s[0] = Inst<V, L, 1>::spmv; b[0] = Inst<V, L, 1>::lb;
-    s[1] = Inst<V, L, 2>::spmv; b[1] = Inst<V, L, 2>::lb;
-    s[2] = Inst<V, L, 4>::spmv; b[2] = Inst<V, L, 4>::lb;
-    s[3] = Inst<V, L, 8>::spmv; b[3] = Inst<V, L, 8>::lb;
-}
-
-struct Table {
-    SpmvFn spmv[2][5][4];
-    LbFn lb[2][5][4];
-    Table() {
-        fill_rt<double, 1>(spmv[0][0], lb[0][0]);
-        fill_rt<double, 2>(spmv[0][1], lb[0][1]);
-        fill_rt<double, 4>(spmv[0][2], lb[0][2]);
-        fill_rt<double, 8>(spmv[0][3], lb[0][3]);
-        fill_rt<double, 16>(spmv[0][4], lb[0][4]);
-        fill_rt<float, 1>(spmv[1][0], lb[1][0]);
-        fill_rt<float, 2>(spmv[1][1], lb[1][1]);
-        fill_rt<float, 4>(spmv[1][2], lb[1][2]);
-        fill_rt<float, 8>(spmv[1][3], lb[1][3]);
-        fill_rt<float, 16>(spmv[1][4], lb[1][4]);
+template <typename V>
+struct VTable {
+    SpmvFn spmv[6];
+    LbFn lb[6];
+    StepFn step[6];
+    VTable() {
+        spmv[0] = spmv_power_kernel<V, 1>;  lb[0] = lb_kernel<V, 1>;  step[0] = step_kernel<V, 1>;
+        spmv[1] = spmv_power_kernel<V, 2>;  lb[1] = lb_kernel<V, 2>;  step[1] = step_kernel<V, 2>;
+        spmv[2] = spmv_power_kernel<V, 4>;  lb[2] = lb_kernel<V, 4>;  step[2] = step_kernel<V, 4>;
+        spmv[3] = spmv_power_kernel<V, 8>;  lb[3] = lb_kernel<V, 8>;  step[3] = step_kernel<V, 8>;
+        spmv[4] = spmv_power_kernel<V, 16>; lb[4] = lb_kernel<V, 16>; step[4] = step_kernel<V, 16>;
+        spmv[5] = spmv_power_kernel<V, 0>;  lb[5] = lb_kernel<V, 0>;  step[5] = step_kernel<V, 0>;
     }
 };
 
-const Table &table() {
-    static Table t;
+const VTable<double> &t64() {
+    static VTable<double> t;
+    return t;
+}
+const VTable<float> &t32() {
+    static VTable<float> t;
     return t;
 }
 
-}  // namespace
-
-bool kernel_config_ok(int lanes, int rhs_per_thread) {
-    return lane_index(lanes) >= 0 && rt_index(rhs_per_thread) >= 0;
+SpmvFn spmv_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().spmv[r_index(R)] : t64().spmv[r_index(R)];
 }
+LbFn lb_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().lb[r_index(R)] : t64().lb[r_index(R)];
+}
+StepFn step_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().step[r_index(R)] : t64().step[r_index(R)];
+}
+
+}  // namespace
 
 int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream) {
     const int32_t n = n_chunks > 0 ? n_chunks : 1;
@@ -287,32 +376,32 @@ int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_spmv_power(const DevMatrix &m, const double *in, const double *inm1, double *out,
-                      int32_t R, int recur, double alpha, double beta, double gamma,
-                      int rhs_per_thread, void *stream) {
-    const int li = lane_index(m.lanes), ri = rt_index(rhs_per_thread);
-    if (li < 0 || ri < 0 || R % rhs_per_thread) return (int)hipErrorInvalidValue;
-    const int tpr = m.lanes * (R / rhs_per_thread);
-    if (tpr > kBlock) return (int)hipErrorInvalidValue;
-    if (m.n == 0) return 0;
-    const int32_t rows_per_pass = kBlock / tpr;
-    // a few passes per workgroup keep the grid large but not tiny-blocked
-    const int32_t rows_per_block = rows_per_pass * 2;
-    const int64_t grid = ((int64_t)m.n + rows_per_block - 1) / rows_per_block;
+int launch_spmv_power(const DevMatrix &m, const int32_t *block_ptr, int32_t n_blocks,
+                      const double *in, const double *inm1, double *out, int32_t R, int recur,
+                      double alpha, double beta, double gamma, void *stream) {
+    if (R < 1 || R > 16) return (int)hipErrorInvalidValue;
+    if (m.n == 0 || n_blocks == 0) return 0;
     PowerIO io{in, inm1, out, alpha, beta, gamma, recur};
-    SpmvFn f = table().spmv[m.value_bits == 32 ? 1 : 0][li][ri];
-    hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), 0, (hipStream_t)stream, m, io, R,
-                       rows_per_block);
+    hipLaunchKernelGGL(spmv_fn(m.value_bits, R), dim3((unsigned)n_blocks), dim3(kBlock), 0,
+                       (hipStream_t)stream, m, io, R, block_ptr);
     return (int)hipGetLastError();
 }
 
-int lb_max_workgroups(int value_bits, int lanes, int rhs_per_thread, int device) {
-    const int li = lane_index(lanes), ri = rt_index(rhs_per_thread);
-    if (li < 0 || ri < 0) return 0;
-    LbFn f = table().lb[value_bits == 32 ? 1 : 0][li][ri];
+int launch_step(const DevMatrix &m, const int32_t *chunk_ptr, const int32_t *tasks,
+                int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream) {
+    if (a.R < 1 || a.R > 16 || a.p < 1 || a.p > kMaxSegPowers) return (int)hipErrorInvalidValue;
+    if (n_tasks <= 0) return 0;
+    Coefs c{};
+    if (cf) c = *cf;
+    hipLaunchKernelGGL(step_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock), 0,
+                       (hipStream_t)stream, m, chunk_ptr, tasks, a, c);
+    return (int)hipGetLastError();
+}
+
+int lb_max_workgroups(int value_bits, int R, int device) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(f),
-                                                     kBlock, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(lb_fn(value_bits, R)), kBlock, 0) != hipSuccess)
         return 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
@@ -320,18 +409,16 @@ int lb_max_workgroups(int value_bits, int lanes, int rhs_per_thread, int device)
 }
 
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
-              const SegArgs &a, const Coefs *cf, int rhs_per_thread, int workgroups,
-              int64_t spin_limit, void *stream) {
-    const int li = lane_index(m.lanes), ri = rt_index(rhs_per_thread);
-    if (li < 0 || ri < 0 || a.R % rhs_per_thread) return (int)hipErrorInvalidValue;
-    if (m.lanes * (a.R / rhs_per_thread) > kBlock) return (int)hipErrorInvalidValue;
+              const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
+              void *stream) {
+    if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (s.n_tasks == 0) return 0;
     LBParams P{m, s, ws, a, spin_limit};
     Coefs c{};
     if (cf) c = *cf;
-    LbFn f = table().lb[m.value_bits == 32 ? 1 : 0][li][ri];
-    hipLaunchKernelGGL(f, dim3(workgroups), dim3(kBlock), 0, (hipStream_t)stream, P, c);
+    hipLaunchKernelGGL(lb_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
+                       (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
 }
 
@@ -343,6 +430,14 @@ int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in
     if (grid > 65536) grid = 65536;
     hipLaunchKernelGGL(permute_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
                        perm, n, to_plan, in, out, nvec, R);
+    return (int)hipGetLastError();
+}
+
+int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int workgroups,
+                      double *sink, void *stream) {
+    if (n_doubles < 2 || passes < 1 || workgroups < 1) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(load_probe_kernel, dim3(workgroups), dim3(kBlock), 0, (hipStream_t)stream,
+                       reinterpret_cast<const double2 *>(buf), n_doubles / 2, passes, sink);
     return (int)hipGetLastError();
 }
 

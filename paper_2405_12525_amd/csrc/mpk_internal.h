@@ -48,10 +48,12 @@ struct Schedule {
     std::vector<int32_t> chunk_group;  // n_chunks
     std::vector<int32_t> dep_lo, dep_hi;
     std::vector<int32_t> tasks;        // 2 * n_tasks: (chunk, power)
+    std::vector<int32_t> step_ptr;     // STEPS: n_steps + 1 task ranges, else empty
     int32_t n_groups = 0, lag = 0, max_reach = 0;
     double window_bytes = 0.0, build_ms = 0.0;
     int32_t n_chunks() const { return (int32_t)chunk_group.size(); }
     int32_t n_tasks() const { return (int32_t)(tasks.size() / 2); }
+    int32_t n_steps() const { return step_ptr.empty() ? 1 : (int32_t)step_ptr.size() - 1; }
 };
 
 struct PlanShape {
@@ -66,7 +68,7 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
                             int default_workgroups, Schedule &out, std::string &err);
 
 // Checks that the task list covers every (chunk, power) once and that each
-// task's dependencies are issued before it.
+// task's dependencies are issued before it (in an earlier step for STEPS).
 bool validate_schedule(const Schedule &s, std::string &err);
 
 // ------------------------------------------------------------------ device side
@@ -78,7 +80,6 @@ struct DevMatrix {
     const int32_t *out_row;   // nullptr: output row = plan row
     int32_t n;
     int32_t value_bits;
-    int32_t lanes;            // lanes per row
 };
 
 constexpr int kMaxSegPowers = 64;   // powers per kernel launch
@@ -116,16 +117,20 @@ struct DevWorkspace {
 // Launchers (kernels.hip).  All return hipError_t as int.
 int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
-              const SegArgs &a, const Coefs *cf, int rhs_per_thread, int workgroups,
-              int64_t spin_limit, void *stream);
-int launch_spmv_power(const DevMatrix &m, const double *in, const double *inm1, double *out,
-                      int32_t R, int recur, double alpha, double beta, double gamma,
-                      int rhs_per_thread, void *stream);
+              const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
+              void *stream);
+// One power over all rows; block_ptr[n_blocks+1] splits the rows among workgroups.
+// One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
+int launch_step(const DevMatrix &m, const int32_t *chunk_ptr, const int32_t *tasks,
+                int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream);
+int launch_spmv_power(const DevMatrix &m, const int32_t *block_ptr, int32_t n_blocks,
+                      const double *in, const double *inm1, double *out, int32_t R, int recur,
+                      double alpha, double beta, double gamma, void *stream);
 int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in, double *out,
                    int nvec, int R, void *stream);
-// Max co-resident persistent workgroups for this configuration.
-int lb_max_workgroups(int value_bits, int lanes, int rhs_per_thread, int device);
-// Whether (lanes, rhs_per_thread) is an instantiated configuration.
-bool kernel_config_ok(int lanes, int rhs_per_thread);
+int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int workgroups,
+                      double *sink, void *stream);
+// Max co-resident persistent workgroups of the level-blocked kernel.
+int lb_max_workgroups(int value_bits, int R, int device);
 
 }  // namespace mpk

@@ -200,8 +200,10 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
         return MPK_OK;
     }
 
-    // 1. level groups: consecutive levels; p+1 of them should fit the budget
-    const double gmax = budget / (double)(p + 1);
+    // 1. level groups: consecutive levels.  The diagonal traversals keep about
+    // p+1 groups (DIAG) or 2p groups (STEPS, two diagonals) in flight, so a
+    // group gets that share of the budget; a level is never split.
+    const double gmax = budget / (double)(tune.schedule == MPK_SCHED_STEPS ? 2 * p : p + 1);
     std::vector<int32_t> group_ptr(1, 0);  // in levels
     {
         double acc = 0.0;
@@ -272,7 +274,28 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
 
     // 4. task order
     s.tasks.reserve((size_t)2 * nc * p);
-    if (tune.schedule == MPK_SCHED_POWERS) {
+    if (tune.schedule == MPK_SCHED_STEPS) {
+        // Diagonals g + 2(k-1) = d.  Group g at power k reads groups g-1..g+1
+        // at power k-1, which sit on diagonals d-3..d-1: every task of a
+        // diagonal depends only on earlier diagonals, so one diagonal is one
+        // launch of independent workgroups.
+        std::vector<int32_t> gfirst(s.n_groups + 1, nc);
+        for (int32_t c = nc - 1; c >= 0; --c) gfirst[s.chunk_group[c]] = c;
+        const int64_t n_diag = (int64_t)s.n_groups + 2 * (int64_t)(p - 1);
+        s.step_ptr.push_back(0);
+        for (int64_t d = 0; d < n_diag; ++d) {
+            for (int k = 1; k <= p; ++k) {
+                const int64_t g = d - 2 * (int64_t)(k - 1);
+                if (g < 0 || g >= s.n_groups) continue;
+                for (int32_t c = gfirst[g]; c < gfirst[g + 1]; ++c) {
+                    s.tasks.push_back(c);
+                    s.tasks.push_back(k);
+                }
+            }
+            s.step_ptr.push_back((int32_t)(s.tasks.size() / 2));
+        }
+        s.window_bytes = gmax * 2 * p;
+    } else if (tune.schedule == MPK_SCHED_POWERS) {
         for (int k = 1; k <= p; ++k)
             for (int32_t c = 0; c < nc; ++c) { s.tasks.push_back(c); s.tasks.push_back(k); }
         s.window_bytes = (double)n * row_bytes + (double)sh.nnz * nz_bytes;
@@ -348,6 +371,21 @@ bool validate_schedule(const Schedule &s, std::string &err) {
         int64_t &w = when[(size_t)(k - 1) * nc + c];
         if (w >= 0) { err = "duplicate task"; return false; }
         w = t;
+    }
+    if (!s.step_ptr.empty()) {
+        // STEPS: a dependency must lie in a strictly earlier launch, so compare
+        // launch numbers instead of issue positions
+        if (s.step_ptr.front() != 0 || s.step_ptr.back() != s.n_tasks()) {
+            err = "step_ptr does not cover the task list";
+            return false;
+        }
+        for (size_t st = 0; st + 1 < s.step_ptr.size(); ++st) {
+            if (s.step_ptr[st + 1] < s.step_ptr[st]) { err = "step_ptr decreases"; return false; }
+            for (int32_t t = s.step_ptr[st]; t < s.step_ptr[st + 1]; ++t) {
+                const int32_t c = s.tasks[2 * t], k = s.tasks[2 * t + 1];
+                when[(size_t)(k - 1) * nc + c] = (int64_t)st;
+            }
+        }
     }
     for (int k = 2; k <= p; ++k) {
         std::vector<int64_t> prev(when.begin() + (size_t)(k - 2) * nc,

@@ -1,10 +1,12 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars: FP64 values <= 1e-12 relative error per power against the oracle;
-FP32-stored values <= 1e-12 against the oracle run on the float-rounded
-values and <= 1e-5 against the FP64 oracle; level-blocked == baseline bit for
-bit (same per-row summation order); integer-valued inputs bit-exact against
-the oracle (every partial sum is an exact integer).
+Every kernel forms each entry as the plain CSR sum (products rounded one by
+one, added in stored order, no fused multiply-add), which is also what the
+oracle computes, so the bar is bit-for-bit equality with the oracle for FP64
+and for FP32-stored values (oracle on the same float-rounded values), and
+level-blocked == baseline.  The tolerance bars of the specification are
+checked as well: <= 1e-12 relative error per power for FP64 and <= 1e-5 for
+FP32-stored values against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -52,7 +54,7 @@ def run_both(P, x, p, recur=None):
 
 # ------------------------------------------------------------------ small configurations
 
-SCHEDS = ["wave", "diag", "powers"]
+SCHEDS = ["steps", "wave", "diag", "powers"]
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
@@ -72,15 +74,16 @@ def test_stencil2d_p4_matches_oracle(sched, reorder, order):
         ref = oracle.powers(A, x, p)
         Y, B = run_both(P, x, p)
     assert np.array_equal(Y, B)
+    assert np.array_equal(Y, ref)
     assert rel_err_per_power(Y, ref).max() <= TOL64
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
-def test_integer_inputs_bit_exact(lanes):
+@pytest.mark.parametrize("chunk_nnz,workgroups", [(64, 0), (1000, 7), (20000, 0), (3000, 300)])
+def test_integer_inputs_bit_exact(chunk_nnz, workgroups):
     A = w.stencil_3d27(20)
     x = w.integer_vectors(A.n, 1, 42)
-    P = mpk.Plan(A, lanes_per_row=lanes)
-    P.tune(chunk_nnz=1000)
+    P = mpk.Plan(A)
+    P.tune(chunk_nnz=chunk_nnz, workgroups=workgroups)
     Y, B = run_both(P, x, 6)
     assert np.array_equal(Y, oracle.powers(A, x, 6))
     assert np.array_equal(B, Y)
@@ -116,22 +119,26 @@ def test_ragged_multi_rhs(R):
     P.tune(chunk_nnz=700)
     Y, B = run_both(P, x, p)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, ref).max() <= TOL64
+    assert np.array_equal(Y, ref)
     # every column equals its own single right-hand-side run
     for r in range(R):
         Y1, _ = run_both(P, x[:, r:r + 1], p)
         assert np.array_equal(Y[:, :, r:r + 1], Y1)
 
 
-@pytest.mark.parametrize("rt", [1, 2, 4, 8])
-def test_rhs_tiling_is_bit_identical(rt):
+@pytest.mark.parametrize("tune", [dict(schedule="wave"), dict(schedule="diag"),
+                                  dict(schedule="powers"),
+                                  dict(lag=1), dict(lag=5000), dict(chunk_nnz=50, workgroups=3),
+                                  dict(cache_bytes=1 << 16)])
+def test_tuning_never_changes_a_bit(tune):
     A = w.anderson_3d(12)
     x = w.uniform_vectors(A.n, 8, 5)
     P = mpk.Plan(A)
     Y0, _ = run_both(P, x, 4)
-    P.tune(rhs_per_thread=rt, chunk_nnz=300)
+    P.tune(**tune)
     Y1, B1 = run_both(P, x, 4)
     assert np.array_equal(Y0, Y1) and np.array_equal(Y1, B1)
+    assert np.array_equal(Y1, oracle.powers(A, x, 4))
 
 
 def test_fp32_values():
@@ -142,7 +149,7 @@ def test_fp32_values():
     P.tune(chunk_nnz=4096)
     Y, B = run_both(P, x, p)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.powers(A, x, p, value_bits=32)).max() <= TOL64
+    assert np.array_equal(Y, oracle.powers(A, x, p, value_bits=32))
     assert rel_err_per_power(Y, oracle.powers(A, x, p)).max() <= TOL32
 
 
@@ -157,7 +164,7 @@ def test_chebyshev_recurrence(value_bits):
     Y, B = run_both(P, x, p, recur=coefs)
     assert np.array_equal(Y, B)
     tol = TOL64 if value_bits == 64 else TOL32
-    assert rel_err_per_power(Y, oracle.recur(A, x, *coefs, value_bits=value_bits)).max() <= TOL64
+    assert np.array_equal(Y, oracle.recur(A, x, *coefs, value_bits=value_bits))
     assert rel_err_per_power(Y, oracle.recur(A, x, *coefs)).max() <= tol
 
 
@@ -170,7 +177,7 @@ def test_general_recurrence_coefficients():
     P.tune(chunk_nnz=500)
     Y, B = run_both(P, x, 9, recur=(a, b, c))
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.recur(A, x, a, b, c)).max() <= TOL64
+    assert np.array_equal(Y, oracle.recur(A, x, a, b, c))
 
 
 def test_long_p_spans_segments():
@@ -180,11 +187,11 @@ def test_long_p_spans_segments():
     P = mpk.Plan(A)
     Y, B = run_both(P, x, p)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.powers(A, x, p)).max() <= 1e-11
+    assert np.array_equal(Y, oracle.powers(A, x, p))
     coefs = oracle.chebyshev_coefficients(p)
     Yc, Bc = run_both(P, x, p, recur=coefs)
     assert np.array_equal(Yc, Bc)
-    assert rel_err_per_power(Yc, oracle.recur(A, x, *coefs)).max() <= 1e-11
+    assert np.array_equal(Yc, oracle.recur(A, x, *coefs))
 
 
 def test_split_invariant_and_plan_order_permutation():
@@ -227,7 +234,7 @@ def test_edge_cases():
     P.tune(chunk_nnz=64)
     Y, B = run_both(P, x, 5)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.powers(A, x, 5)).max() <= TOL64
+    assert np.array_equal(Y, oracle.powers(A, x, 5))
 
 
 def test_identity_and_permutation_exact():
@@ -248,7 +255,7 @@ def test_wait_limit_reports_timeout_and_recovers():
     A = w.stencil_3d27(40)
     x = w.uniform_vectors(A.n, 1, 4)
     P = mpk.Plan(A)
-    P.tune(spin_limit_us=1, chunk_nnz=2000)
+    P.tune(schedule="wave", spin_limit_us=1, chunk_nnz=2000)
     seen_timeout = False
     for _ in range(3):
         P.run(dev(x), 24)
@@ -261,7 +268,7 @@ def test_wait_limit_reports_timeout_and_recovers():
     P.tune(spin_limit_us=0, chunk_nnz=2000)
     Y, B = run_both(P, x, 6)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.powers(A, x, 6)).max() <= TOL64
+    assert np.array_equal(Y, oracle.powers(A, x, 6))
 
 
 def test_concurrent_streams_share_a_plan():
@@ -278,7 +285,7 @@ def test_concurrent_streams_share_a_plan():
             outs.append(P.run(xd, 5, stream=s))
     P.sync()
     for x, Y in zip(xs, outs):
-        assert rel_err_per_power(host(Y), oracle.powers(A, x, 5)).max() <= TOL64
+        assert np.array_equal(host(Y), oracle.powers(A, x, 5))
 
 
 # ------------------------------------------------------------------ full-size workloads
@@ -293,7 +300,9 @@ def test_full_stencil3d27_128_p8():
     assert np.array_equal(Yi, Bi)
     Y, B = run_both(P, x, p)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.powers(A, x, p)).max() <= TOL64
+    ref = oracle.powers(A, x, p)
+    assert np.array_equal(Y, ref)
+    assert rel_err_per_power(Y, ref).max() <= TOL64
 
 
 @pytest.mark.slow
@@ -303,5 +312,5 @@ def test_full_anderson160_chebyshev16_r8_fp32():
     P = mpk.Plan(A, value_bits=32)
     Y, B = run_both(P, x, p, recur=coefs)
     assert np.array_equal(Y, B)
-    assert rel_err_per_power(Y, oracle.recur(A, x, *coefs, value_bits=32)).max() <= TOL64
+    assert np.array_equal(Y, oracle.recur(A, x, *coefs, value_bits=32))
     assert rel_err_per_power(Y, oracle.recur(A, x, *coefs)).max() <= TOL32

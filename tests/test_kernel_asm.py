@@ -1,0 +1,117 @@
+"""Structural checks of the gfx950 code the compiler emits for the kernels.
+
+The persistent level-blocked kernel relies on two properties that source
+review alone cannot guarantee:
+
+* its task loop must be left by all lanes together.  If the compiler cannot
+  prove the loop control uniform it may restructure the loop so that some
+  lanes exit early (an exec-mask exit), which breaks the barriers inside it
+  and can stall the workgroup forever;
+* publishing a chunk must write the L2 back and wait for that write-back
+  before the flag store (release at agent scope), and a consumer must
+  invalidate before reading (acquire).
+
+These tests compile kernels.hip to AMD assembly (CPU only) and check both.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "paper_2405_12525_amd", "csrc", "kernels.hip")
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+pytestmark = pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    out = tmp_path_factory.mktemp("asm") / "kernels.s"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-S",
+           "--cuda-device-only", f"-I{ROOT}/include",
+           f"-I{ROOT}/paper_2405_12525_amd/csrc", "-o", str(out), SRC]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out.read_text()
+
+
+def kernels(asm_text, name):
+    """{symbol: [lines]} for every kernel whose mangled name contains `name`."""
+    out = {}
+    cur = None
+    for line in asm_text.splitlines():
+        m = re.match(r"^(_Z\S+):", line)
+        if m and name in m.group(1):
+            cur = m.group(1)
+            out[cur] = []
+            continue
+        if cur is not None:
+            out[cur].append(line)
+            if "s_endpgm" in line:
+                cur = None
+    return out
+
+
+def loops_with_barrier_and_divergent_exit(lines):
+    """Loops that contain a barrier (directly or in a nested loop) and are
+    left through an exec-mask exit, i.e. not by all lanes together."""
+    parent = {}      # loop header -> enclosing loop header
+    own = {}         # loop header -> instructions of blocks directly in it
+    cur = None       # innermost loop of the current block
+    pending = []     # "Parent Loop" headers listed for the block being read
+    label = None
+    for line in lines:
+        m = re.match(r"^(\.LBB\S+|; %bb\.\d+):", line)
+        if m:
+            label = m.group(1).lstrip(".").lstrip("; %")
+            pending = re.findall(r"Parent Loop (\S+) Depth", line)
+            h = re.search(r"in Loop: Header=(\S+) Depth", line)
+            cur = h.group(1) if h else None
+            continue
+        pm = re.findall(r"Parent Loop (\S+) Depth", line)
+        if pm and line.strip().startswith(";"):
+            pending += pm
+            continue
+        if re.search(r"Loop Header: Depth=\d+", line):
+            cur = label
+            parent[cur] = pending[-1] if pending else None
+            continue
+        if cur is not None and not line.strip().startswith(";"):
+            own.setdefault(cur, []).append(line.strip())
+    def has_barrier(h):
+        if any(l.startswith("s_barrier") for l in own.get(h, [])):
+            return True
+        return any(has_barrier(c) for c, p in parent.items() if p == h)
+    bad = []
+    for h in set(own) | set(parent):
+        exits = [l for l in own.get(h, []) if l.startswith("s_andn2_b64 exec, exec")]
+        if exits and has_barrier(h):
+            bad.append(h)
+    return bad
+
+
+def test_task_loop_has_uniform_exit(asm):
+    ks = kernels(asm, "lb_kernel")
+    assert len(ks) == 12  # 6 right-hand-side variants x 2 value types
+    for sym, lines in ks.items():
+        assert any("s_barrier" in l for l in lines)
+        assert loops_with_barrier_and_divergent_exit(lines) == [], sym
+
+
+def test_baseline_row_loop_has_uniform_exit(asm):
+    ks = kernels(asm, "spmv_power_kernel")
+    assert len(ks) == 12
+    for sym, lines in ks.items():
+        assert loops_with_barrier_and_divergent_exit(lines) == [], sym
+
+
+def test_release_waits_for_writeback_and_acquire_invalidates(asm):
+    for sym, lines in kernels(asm, "lb_kernel").items():
+        body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
+        i = next(j for j, l in enumerate(body) if l.startswith("buffer_wbl2 sc1"))
+        assert body[i + 1].startswith("s_waitcnt vmcnt(0)"), (sym, body[i:i + 3])
+        assert re.match(r"global_store_dword .* sc1", body[i + 2]), (sym, body[i:i + 3])
+        assert any(l.startswith("buffer_inv sc1") for l in body), sym

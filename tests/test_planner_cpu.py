@@ -96,14 +96,19 @@ def test_level_neighbour_property(reorder):
 
 
 def _check_schedule(A, s, p):
+    """Every (chunk, power) once; dependencies strictly earlier (in issue order,
+    or in an earlier launch for the one-launch-per-diagonal schedule)."""
     cp, lo, hi, tasks = s["chunk_ptr"], s["dep_lo"], s["dep_hi"], s["tasks"]
     nc = len(cp) - 1
     assert cp[0] == 0 and cp[-1] == A.n and np.all(np.diff(cp) > 0)
     assert tasks.shape == (nc * p, 2)
+    sp = s["step_ptr"]
+    assert sp[0] == 0 and sp[-1] == len(tasks) and np.all(np.diff(sp) >= 0)
+    launch = np.repeat(np.arange(len(sp) - 1), np.diff(sp))
     when = -np.ones((p + 1, nc), dtype=np.int64)
     for t, (c, k) in enumerate(tasks):
         assert when[k, c] < 0
-        when[k, c] = t
+        when[k, c] = launch[t] if len(sp) > 2 else t
     assert (when[1:] >= 0).all()
     for c in range(nc):
         assert lo[c] <= c <= hi[c]
@@ -127,7 +132,7 @@ def _deps_cover_reads(A, P, s):
             assert chunk_of[cols].max() <= s["dep_hi"][c]
 
 
-@pytest.mark.parametrize("sched", ["wave", "diag", "powers"])
+@pytest.mark.parametrize("sched", ["steps", "wave", "diag", "powers"])
 @pytest.mark.parametrize("reorder", ["bfs", "none"])
 def test_schedules_are_topological(sched, reorder):
     for A in (w.stencil_2d5(30), w.random_sparse(300, 0.01, 3), w.anderson_3d(7)):
@@ -153,6 +158,21 @@ def test_diag_schedule_is_the_papers_lp_order():
     assert list(map(tuple, s["tasks"])) == [(i, p) for i, p in oracle.lp_diagonal_order(10, 5)]
 
 
+def test_steps_schedule_diagonals():
+    # one vertex per level and per group: launch d holds (g, k) with g + 2(k-1) = d
+    A = w.tridiag_1d(12)
+    P = host_plan(A)
+    P.tune(schedule="steps", cache_bytes=1, cache_safety=1.0, chunk_nnz=1)
+    s = P.schedule(4)
+    assert s["n_groups"] == 12 and s["n_steps"] == 12 + 2 * 3
+    sp = s["step_ptr"]
+    for d in range(s["n_steps"]):
+        got = sorted(map(tuple, s["tasks"][sp[d]:sp[d + 1]]))
+        want = sorted((d - 2 * (k - 1), k) for k in range(1, 5) if 0 <= d - 2 * (k - 1) < 12)
+        assert got == want
+    _check_schedule(A, s, 4)
+
+
 def test_wave_lag_changes_order_not_validity():
     A = w.stencil_2d5(40)
     P = host_plan(A, reorder="none")
@@ -173,7 +193,6 @@ def test_plan_info_fields():
     assert i["n"] == A.n and i["nnz"] == A.nnz and i["value_bits"] == 32
     assert i["matrix_bytes"] == 4 * (A.n + 1) + 8 * A.nnz
     assert i["n_levels"] == 5  # cube shells max(x,y,z) = const from the corner
-    assert i["lanes_per_row"] in (1, 2, 4, 8, 16)
 
 
 # ------------------------------------------------------------------ error paths
@@ -223,11 +242,13 @@ def test_tune_validation():
     with pytest.raises(mpk.MPKError):
         P.tune(cache_safety=0.0)
     with pytest.raises(mpk.MPKError):
-        P.tune(rhs_per_thread=3)
+        P.tune(schedule=7)
     with pytest.raises(mpk.MPKError):
         P.tune(chunk_nnz=0)
     with pytest.raises(mpk.MPKError):
-        mpk.Plan(w.stencil_2d5(4), device=mpk.MPK_DEVICE_NONE, lanes_per_row=3)
+        mpk.Plan(w.stencil_2d5(4), device=mpk.MPK_DEVICE_NONE, value_bits=16)
+    with pytest.raises(mpk.MPKError):
+        mpk.Plan(w.stencil_2d5(4), device=mpk.MPK_DEVICE_NONE, root=16)
 
 
 def test_empty_and_tiny_plans():
