@@ -70,7 +70,12 @@ enum {
                                per-chunk completion flags                      */
     MPK_SCHED_DIAG = 2,     /* one persistent kernel, the paper's Lp-diagram
                                diagonals g + k = const over level groups        */
-    MPK_SCHED_POWERS = 3    /* one persistent kernel, power by power            */
+    MPK_SCHED_POWERS = 3,   /* one persistent kernel, power by power            */
+    MPK_SCHED_XCD = 4       /* one persistent kernel; each level is split into
+                               one part per XCD, every XCD walks its parts in a
+                               skewed wavefront from its own queue, and only
+                               results read by another XCD are written back from
+                               the producer's L2                               */
 };
 
 #define MPK_DEVICE_CURRENT (-1)
@@ -99,14 +104,15 @@ typedef struct {
 /* Run-time tuning of a plan (mpk_plan_tune).  None of these changes a result
  * bit: every kernel sums each row sequentially in stored order. */
 typedef struct {
-    int schedule;            /* MPK_SCHED_STEPS (default), _WAVE, _DIAG, _POWERS */
+    int schedule;            /* MPK_SCHED_STEPS (default), _WAVE, _DIAG, _POWERS,
+                                _XCD                                            */
     int64_t cache_bytes;     /* blocking budget C in bytes (default 64 MiB:
                                 the measured fast-read plateau of the MI355X
                                 Infinity Cache)                                 */
     double cache_safety;     /* fraction of C the window may use (default 1.0) */
     int chunk_nnz;           /* target nonzeros per chunk = per workgroup task
                                 (default 4096)                                  */
-    int lag;                 /* WAVE only: slack in chunks; 0 = from the budget */
+    int lag;                 /* WAVE, XCD: slack in chunks; 0 = from the budget  */
     int workgroups;          /* persistent schedules: workgroups; 0 = fill the
                                 device                                          */
     int64_t spin_limit_us;   /* dependency-wait limit in microseconds, 0 = 2 s  */
@@ -130,6 +136,8 @@ typedef struct {
     int32_t max_reach;       /* max over chunks of dhi - c (in chunks)          */
     double window_bytes;     /* estimated matrix bytes touched by one window    */
     double build_ms;
+    int32_t n_queues;        /* XCD: task queues (one per XCD), else 1          */
+    int32_t n_deps;          /* XCD: length of the exact dependency lists, else 0 */
 } mpk_sched_info_t;
 
 typedef struct mpk_plan_s *mpk_plan_t;
@@ -174,6 +182,18 @@ mpk_status_t mpk_plan_levels(mpk_plan_t plan, int32_t *level_ptr, int32_t *perm)
 mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info,
                                int32_t *chunk_ptr, int32_t *chunk_group, int32_t *dep_lo,
                                int32_t *dep_hi, int32_t *tasks, int32_t *step_ptr);
+
+/*
+ * The extra arrays of an MPK_SCHED_XCD schedule (MPK_EINVAL for the other
+ * schedules).  Host memory, each may be NULL: dep_ptr[n_chunks+1] and
+ * dep_idx[n_deps] list, for every chunk, the chunks its rows read (itself
+ * included, ascending); chunk_xcd[n_chunks] the owning queue; remote_out
+ * [n_chunks] = 1 when a chunk is read by a chunk of another queue; qptr
+ * [n_queues+1] splits tasks[] into the per-queue lists, each in dependency
+ * order.  Host-only plans assume the 8 XCDs of the MI355X.
+ */
+mpk_status_t mpk_plan_schedule_xcd(mpk_plan_t plan, int p, int32_t *dep_ptr, int32_t *dep_idx,
+                                   int32_t *chunk_xcd, int32_t *remote_out, int32_t *qptr);
 
 /*
  * Level-blocked matrix power kernel: Y = [A x, A^2 x, ..., A^p x].

@@ -18,15 +18,15 @@ import numpy as np
 from . import _capi
 from ._capi import (MPK_DEVICE_CURRENT, MPK_DEVICE_NONE, MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN,
                     MPK_REORDER_BFS, MPK_REORDER_NONE, MPK_SCHED_DIAG, MPK_SCHED_POWERS,
-                    MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPKError, check)
+                    MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPK_SCHED_XCD, MPKError, check)
 
 __all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN",
            "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
-           "MPK_SCHED_POWERS", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
+           "MPK_SCHED_POWERS", "MPK_SCHED_XCD", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
            "flops", "lib", "probe_load"]
 
 _SCHED = {"steps": MPK_SCHED_STEPS, "wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG,
-          "powers": MPK_SCHED_POWERS}
+          "powers": MPK_SCHED_POWERS, "xcd": MPK_SCHED_XCD}
 
 
 def lib():
@@ -174,6 +174,15 @@ class Plan:
         d = {f: getattr(si, f) for f, _ in _capi.SchedInfo._fields_}
         d.update(chunk_ptr=cp, chunk_group=cg, dep_lo=lo, dep_hi=hi, tasks=tasks.reshape(-1, 2),
                  step_ptr=sp)
+        if si.n_deps > 0:
+            dp = np.zeros(nc + 1, np.int32)
+            di = np.zeros(si.n_deps, np.int32)
+            cx = np.zeros(nc, np.int32)
+            ro = np.zeros(nc, np.int32)
+            qp = np.zeros(si.n_queues + 1, np.int32)
+            check(self._lib.mpk_plan_schedule_xcd(self._h, int(p), dp.ctypes.data, di.ctypes.data,
+                                                  cx.ctypes.data, ro.ctypes.data, qp.ctypes.data))
+            d.update(dep_ptr=dp, dep_idx=di, chunk_xcd=cx, remote_out=ro, qptr=qp)
         return d
 
     # ------------------------------------------------------------ tuning

@@ -13,14 +13,14 @@ STATUS_NAMES = {0: "MPK_OK", 1: "MPK_EINVAL", 2: "MPK_EBADCSR", 3: "MPK_ENOMEM",
                 5: "MPK_EUNSUPPORTED", 6: "MPK_ETIMEOUT", 7: "MPK_ENODEVICE"}
 MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN = 0, 1
 MPK_REORDER_BFS, MPK_REORDER_NONE = 0, 1
-MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPK_SCHED_DIAG, MPK_SCHED_POWERS = 0, 1, 2, 3
+MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPK_SCHED_DIAG, MPK_SCHED_POWERS, MPK_SCHED_XCD = 0, 1, 2, 3, 4
 MPK_DEVICE_CURRENT, MPK_DEVICE_NONE = -1, -2
 MPK_MAX_RHS = 16
 
 # every symbol the header declares
 EXPORTS = [
     "mpk_plan_opts_default", "mpk_tune_default", "mpk_plan", "mpk_plan_destroy", "mpk_plan_tune",
-    "mpk_plan_info", "mpk_plan_levels", "mpk_plan_schedule", "mpk_run", "mpk_run_recur",
+    "mpk_plan_info", "mpk_plan_levels", "mpk_plan_schedule", "mpk_plan_schedule_xcd", "mpk_run", "mpk_run_recur",
     "mpk_run_baseline", "mpk_run_baseline_recur", "mpk_permute", "mpk_plan_sync",
     "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
 ]
@@ -58,7 +58,8 @@ class SchedInfo(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("n_chunks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
                 ("n_tasks", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("lag", ctypes.c_int32),
                 ("max_reach", ctypes.c_int32),
-                ("window_bytes", ctypes.c_double), ("build_ms", ctypes.c_double)]
+                ("window_bytes", ctypes.c_double), ("build_ms", ctypes.c_double),
+                ("n_queues", ctypes.c_int32), ("n_deps", ctypes.c_int32)]
 
 
 _lib = None
@@ -92,6 +93,8 @@ def load():
     lib.mpk_plan_levels.restype = st
     lib.mpk_plan_schedule.argtypes = [P, ctypes.c_int, ctypes.POINTER(SchedInfo), P, P, P, P, P, P]
     lib.mpk_plan_schedule.restype = st
+    lib.mpk_plan_schedule_xcd.argtypes = [P, ctypes.c_int, P, P, P, P, P]
+    lib.mpk_plan_schedule_xcd.restype = st
     lib.mpk_run.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P]
     lib.mpk_run.restype = st
     lib.mpk_run_recur.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]

@@ -92,11 +92,12 @@ struct DevBuf {
 struct SchedEntry {
     Schedule host;
     DevBuf chunk_ptr, dep_lo, dep_hi, tasks;
+    DevBuf dep_ptr, dep_idx, remote_out, qptr;  // XCD schedule
     int workgroups = 0;
 };
 
 struct Workspace {
-    DevBuf buf;          // done[cap] | ticket | err
+    DevBuf buf;          // done[cap] | ticket[kMaxQueues] | err
     int32_t cap = 0;
     hipEvent_t ev = nullptr;
     hipStream_t last_stream = nullptr;
@@ -104,7 +105,7 @@ struct Workspace {
     bool reserved = false;  // owned by a captured graph
     DevWorkspace view() const {
         int32_t *b = buf.as<int32_t>();
-        return DevWorkspace{b, b + cap, b + cap + 1};
+        return DevWorkspace{b, b + cap, b + cap + kMaxQueues};
     }
 };
 
@@ -125,6 +126,9 @@ struct mpk_plan_s {
     // host data kept for schedules and queries
     Levels lv;
     std::vector<int32_t> rowptr, row_lo, row_hi;
+    std::vector<int32_t> pcol;   // plan-numbered columns (exact dependency lists)
+    int n_xcd = 8;               // XCDs found on the device (host-only plans: 8)
+    bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
     // device data
     DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
     DevBuf d_bptr;           // row blocks of the p x SpMV baseline kernel
@@ -188,8 +192,12 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
         return MPK_OK;
     }
     auto e = std::make_unique<SchedEntry>();
+    // the XCD schedule needs a workgroup on every XCD to drain every queue
+    int n_xcd = plan->xcd_bound ? plan->n_xcd : 1;
+    if (plan->tune.workgroups > 0 && plan->tune.workgroups < n_xcd) n_xcd = 1;
     PlanShape sh{plan->n, plan->nnz, plan->value_bits / 8, &plan->lv.level_ptr, &plan->rowptr,
-                 &plan->row_lo, &plan->row_hi};
+                 &plan->row_lo, &plan->row_hi, &plan->pcol, n_xcd,
+                 plan->xcd_bound && n_xcd > 1};
     std::string err;
     mpk_status_t st = build_schedule(sh, p, plan->tune, default_wg, e->host, err);
     if (st) return fail(st, err);
@@ -200,6 +208,12 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
         if ((st = e->dep_lo.upload(s.dep_lo.data(), s.dep_lo.size() * 4))) return st;
         if ((st = e->dep_hi.upload(s.dep_hi.data(), s.dep_hi.size() * 4))) return st;
         if ((st = e->tasks.upload(s.tasks.data(), s.tasks.size() * 4))) return st;
+        if (!s.qptr.empty()) {
+            if ((st = e->dep_ptr.upload(s.dep_ptr.data(), s.dep_ptr.size() * 4))) return st;
+            if ((st = e->dep_idx.upload(s.dep_idx.data(), s.dep_idx.size() * 4))) return st;
+            if ((st = e->remote_out.upload(s.remote_out.data(), s.remote_out.size() * 4))) return st;
+            if ((st = e->qptr.upload(s.qptr.data(), s.qptr.size() * 4))) return st;
+        }
     }
     *out = e.get();
     plan->scheds[p] = std::move(e);
@@ -224,9 +238,10 @@ mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream
     }
     auto w = std::make_unique<Workspace>();
     w->cap = std::max<int32_t>(n_chunks, 1024);
-    mpk_status_t st = w->buf.alloc(((size_t)w->cap + 2) * sizeof(int32_t));
+    const size_t words = (size_t)w->cap + kMaxQueues + 1;
+    mpk_status_t st = w->buf.alloc(words * sizeof(int32_t));
     if (st) return st;
-    hipError_t e = hipMemset(w->buf.ptr, 0, ((size_t)w->cap + 2) * sizeof(int32_t));
+    hipError_t e = hipMemset(w->buf.ptr, 0, words * sizeof(int32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMemset");
     e = hipEventCreateWithFlags(&w->ev, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -316,7 +331,15 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                        se->host.n_chunks()};
         int rc = launch_reset(ws->view(), se->host.n_chunks(), stream);
         if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
-        rc = launch_lb(m, ds, ws->view(), a, &cf, wg, spin_ticks, stream);
+        if (!se->host.qptr.empty()) {
+            DevXcdSchedule xs{se->chunk_ptr.as<int32_t>(), se->dep_ptr.as<int32_t>(),
+                              se->dep_idx.as<int32_t>(), se->remote_out.as<int32_t>(),
+                              se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
+                              se->host.n_queues, se->host.n_chunks()};
+            rc = launch_xcd(m, xs, ws->view(), a, &cf, wg, spin_ticks, stream);
+        } else {
+            rc = launch_lb(m, ds, ws->view(), a, &cf, wg, spin_ticks, stream);
+        }
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
         if (capturing) {
             ws->reserved = true;
@@ -425,6 +448,14 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         plan->rowptr = pc.rowptr;
         plan->row_lo.swap(pc.row_lo);
         plan->row_hi.swap(pc.row_hi);
+        if (plan_cols) {
+            plan->pcol = pc.col;
+        } else {
+            std::vector<int32_t> inv(A->n);
+            for (int64_t i = 0; i < A->n; ++i) inv[plan->lv.perm[i]] = (int32_t)i;
+            plan->pcol.resize((size_t)A->nnz);
+            for (int64_t e2 = 0; e2 < A->nnz; ++e2) plan->pcol[e2] = inv[pc.col[e2]];
+        }
         if (!host_only) {
             int dev = o.device;
             if (dev == MPK_DEVICE_CURRENT) {
@@ -434,6 +465,8 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
             hipError_t e = hipSetDevice(dev);
             if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
             plan->device = dev;
+            plan->n_xcd = detect_xcds(dev);
+            plan->xcd_bound = plan->n_xcd > 1;
             int khz = 0;
             if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
                 plan->wall_khz = khz;
@@ -475,7 +508,7 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
     mpk_tune_t t;
     mpk_tune_default(&t);
     if (tune) t = *tune;
-    if (t.schedule < MPK_SCHED_STEPS || t.schedule > MPK_SCHED_POWERS) return fail(MPK_EINVAL, "bad schedule");
+    if (t.schedule < MPK_SCHED_STEPS || t.schedule > MPK_SCHED_XCD) return fail(MPK_EINVAL, "bad schedule");
     if (t.cache_bytes <= 0 || !(t.cache_safety > 0.0) || t.cache_safety > 1.0)
         return fail(MPK_EINVAL, "cache_bytes must be > 0 and cache_safety in (0, 1]");
     if (t.chunk_nnz < 1 || t.lag < 0 || t.workgroups < 0 || t.spin_limit_us < 0)
@@ -535,6 +568,8 @@ mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info, i
         info->max_reach = s.max_reach;
         info->window_bytes = s.window_bytes;
         info->build_ms = s.build_ms;
+        info->n_queues = s.qptr.empty() ? 1 : s.n_queues;
+        info->n_deps = s.qptr.empty() ? 0 : (int32_t)s.dep_idx.size();
     }
     if (chunk_ptr) std::copy(s.chunk_ptr.begin(), s.chunk_ptr.end(), chunk_ptr);
     if (chunk_group) std::copy(s.chunk_group.begin(), s.chunk_group.end(), chunk_group);
@@ -549,6 +584,26 @@ mpk_status_t mpk_plan_schedule(mpk_plan_t plan, int p, mpk_sched_info_t *info, i
             std::copy(s.step_ptr.begin(), s.step_ptr.end(), step_ptr);
         }
     }
+    return MPK_OK;
+}
+
+mpk_status_t mpk_plan_schedule_xcd(mpk_plan_t plan, int p, int32_t *dep_ptr, int32_t *dep_idx,
+                                   int32_t *chunk_xcd, int32_t *remote_out, int32_t *qptr) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (p < 1 || p > kMaxSegPowers) return fail(MPK_EINVAL, "p must be in [1, 64]");
+    std::lock_guard<std::mutex> g(plan->mu);
+    int wg = 2048;
+    if (!plan->host_only) wg = default_workgroups(plan, 1);
+    SchedEntry *se = nullptr;
+    mpk_status_t st = get_schedule(plan, p, &se, wg);
+    if (st) return st;
+    const Schedule &s = se->host;
+    if (s.qptr.empty()) return fail(MPK_EINVAL, "the current schedule is not MPK_SCHED_XCD");
+    if (dep_ptr) std::copy(s.dep_ptr.begin(), s.dep_ptr.end(), dep_ptr);
+    if (dep_idx) std::copy(s.dep_idx.begin(), s.dep_idx.end(), dep_idx);
+    if (chunk_xcd) std::copy(s.chunk_xcd.begin(), s.chunk_xcd.end(), chunk_xcd);
+    if (remote_out) std::copy(s.remote_out.begin(), s.remote_out.end(), remote_out);
+    if (qptr) std::copy(s.qptr.begin(), s.qptr.end(), qptr);
     return MPK_OK;
 }
 

@@ -16,6 +16,8 @@
 // before the product; vectors and sums are double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mpk_internal.h"
 
 namespace mpk {
@@ -23,9 +25,13 @@ namespace mpk {
 namespace {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
-constexpr int kWave = 64;
-constexpr int kSlice = 2048;         // doubles of LDS product staging per workgroup
+#ifndef MPK_SLICE_DOUBLES
+#define MPK_SLICE_DOUBLES 4096
+#endif
+constexpr int kSlice = MPK_SLICE_DOUBLES;  // doubles of LDS product staging per workgroup
 constexpr int kPerThread = kSlice / kBlock;
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = kBlock / kWave;
 
 __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -54,11 +60,13 @@ __device__ __forceinline__ double epilogue(const PowerIO &io, double s, size_t i
 
 // Products of nz consecutive nonzeros starting at `base`, for every
 // right-hand side: prod[j*R + r] = val[base+j] * in[col[base+j]*R + r].
+// Lanes past the end load a valid entry (clamped index; requires nz >= 1)
+// and their products are never read, so all loads are issued unconditionally.
 template <typename V, int RC>
 __device__ __forceinline__ void slice_products(const DevMatrix &m, const double *in, int R,
                                                int32_t base, int32_t nz, double *prod) {
     const int tid = threadIdx.x;
-    const int total = nz * R;
+    const int last = nz - 1;
     const V *val = static_cast<const V *>(m.val);
     int32_t c[kPerThread];
     double a[kPerThread];
@@ -66,66 +74,83 @@ __device__ __forceinline__ void slice_products(const DevMatrix &m, const double 
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
         const int q = tid + j * kBlock;
-        const int el = RC ? q / RC : q / R;
+        int el = RC ? q / RC : q / R;
         rr[j] = q - el * R;
-        c[j] = 0;
-        a[j] = 0.0;
-        if (q < total) {
-            c[j] = m.col[base + el];
-            a[j] = static_cast<double>(val[base + el]);
-        }
+        el = min(el, last);
+        c[j] = m.col[base + el];
+        a[j] = static_cast<double>(val[base + el]);
     }
     double xv[kPerThread];
 #pragma unroll
-    for (int j = 0; j < kPerThread; ++j) {
-        const int q = tid + j * kBlock;
-        xv[j] = 0.0;
-        if (q < total) xv[j] = in[(size_t)c[j] * R + rr[j]];
-    }
+    for (int j = 0; j < kPerThread; ++j) xv[j] = in[(size_t)c[j] * R + rr[j]];
 #pragma unroll
-    for (int j = 0; j < kPerThread; ++j) {
-        const int q = tid + j * kBlock;
-        if (q < total) prod[q] = a[j] * xv[j];
+    for (int j = 0; j < kPerThread; ++j) prod[tid + j * kBlock] = a[j] * xv[j];
+}
+
+// Sum prod[e*R + rr] for e in [s0, s1) left to right from 0.0; the LDS
+// reads are issued eight at a time ahead of the (ordered) additions.
+__device__ __forceinline__ double ordered_sum(const double *prod, int R, int rr, int32_t s0,
+                                              int32_t s1) {
+    double s = 0.0;
+    int32_t e = s0;
+    for (; e + 8 <= s1; e += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = prod[(e + u) * R + rr];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = s + v[u];
     }
+    for (; e < s1; ++e) s = s + prod[e * R + rr];
+    return s;
 }
 
 // Rows [r0, r1) of one power.  Called by all threads of the workgroup.
 template <typename V, int RC>
 __device__ void stream_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_t r0,
-                            int32_t r1, double *prod) {
+                            int32_t r1, double *prod, int32_t *srp, int32_t *wcnt) {
     const int R = RC ? RC : R_rt;
     const int E = kSlice / R;  // nonzeros per slice
     const int tid = threadIdx.x;
+    const int wave = tid / kWave;
     const int32_t *rowptr = m.rowptr;
     int32_t r = r0;
     while (r < r1) {
         const int32_t base = rowptr[r];
-        // rows r .. r+cnt-1 end within E nonzeros of base (a prefix: rowptr is sorted)
+        // rows r .. r+cnt-1 end within E nonzeros of base (a prefix: rowptr is
+        // sorted); the loaded row ends are kept in srp for the sums below
         const int32_t i = r + tid + 1;
-        const int fits = (i <= r1) && (rowptr[i] - base <= E);
-        const int cnt = __builtin_amdgcn_readfirstlane(__syncthreads_count(fits));
+        const int32_t rp = i <= r1 ? rowptr[i] : INT32_MAX;
+        srp[tid + 1] = rp;
+        if (tid == 0) srp[0] = base;
+        const int fits = rp - base <= E;
+        const int wc = __popcll(__ballot(fits));
+        if ((tid & (kWave - 1)) == 0) wcnt[wave] = wc;
+        __syncthreads();
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) cnt += wcnt[w];
+        cnt = __builtin_amdgcn_readfirstlane(cnt);
         if (cnt > 0) {
-            const int32_t rb = r + cnt;
-            const int32_t nz = rowptr[rb] - base;
-            slice_products<V, RC>(m, io.in, R, base, nz, prod);
+            const int32_t nz = srp[cnt] - base;
+            // (a slice of empty rows has no products; the clamped loads need nz >= 1)
+            if (nz > 0) slice_products<V, RC>(m, io.in, R, base, nz, prod);
             __syncthreads();
             const int npairs = cnt * R;
             for (int q = tid; q < npairs; q += kBlock) {
                 const int li = RC ? q / RC : q / R;
                 const int rr = q - li * R;
                 const int32_t row = r + li;
-                const int32_t s0 = rowptr[row] - base, s1 = rowptr[row + 1] - base;
-                double s = 0.0;
-                for (int32_t e = s0; e < s1; ++e) s = s + prod[e * R + rr];
+                const double s = ordered_sum(prod, R, rr, srp[li] - base, srp[li + 1] - base);
                 const int32_t o = m.out_row ? m.out_row[row] : row;
                 const size_t idx = (size_t)o * R + rr;
                 io.out[idx] = epilogue(io, s, idx);
             }
             __syncthreads();
-            r = rb;
+            r += cnt;
         } else {
             // one row longer than a slice: sum it slice by slice, one thread per RHS
-            const int32_t end = rowptr[r + 1];
+            const int32_t end = srp[1];
+            __syncthreads();
             double s = 0.0;
             for (int32_t b = base; b < end; b += E) {
                 const int32_t nz = min(E, end - b);
@@ -151,8 +176,10 @@ template <typename V, int RC>
 __global__ __launch_bounds__(kBlock) void spmv_power_kernel(DevMatrix m, PowerIO io, int32_t R,
                                                            const int32_t *block_ptr) {
     __shared__ double prod[kSlice];
+    __shared__ int32_t srp[kBlock + 1];
+    __shared__ int32_t wcnt[kWavesPerBlock];
     const int32_t r0 = block_ptr[blockIdx.x], r1 = block_ptr[blockIdx.x + 1];
-    stream_rows<V, RC>(m, io, R, r0, r1, prod);
+    stream_rows<V, RC>(m, io, R, r0, r1, prod, srp, wcnt);
 }
 
 // ------------------------------------------------------------------ level-blocked
@@ -164,6 +191,8 @@ template <typename V, int RC>
 __global__ __launch_bounds__(kBlock) void step_kernel(DevMatrix m, const int32_t *chunk_ptr,
                                                      const int32_t *tasks, SegArgs a, Coefs cf) {
     __shared__ double prod[kSlice];
+    __shared__ int32_t srp[kBlock + 1];
+    __shared__ int32_t wcnt[kWavesPerBlock];
     const int32_t c = tasks[2 * blockIdx.x];
     const int32_t k = tasks[2 * blockIdx.x + 1];
     const size_t stride = (size_t)m.n * a.R;
@@ -175,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevMatrix m, const int32_t
     io.alpha = cf.alpha[k - 1];
     io.beta = cf.beta[k - 1];
     io.gamma = cf.gamma[k - 1];
-    stream_rows<V, RC>(m, io, a.R, chunk_ptr[c], chunk_ptr[c + 1], prod);
+    stream_rows<V, RC>(m, io, a.R, chunk_ptr[c], chunk_ptr[c + 1], prod, srp, wcnt);
 }
 
 struct LBParams {
@@ -197,6 +226,8 @@ struct LBParams {
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
     __shared__ double prod[kSlice];
+    __shared__ int32_t srp[kBlock + 1];
+    __shared__ int32_t wcnt[kWavesPerBlock];
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
@@ -252,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
         io.alpha = cf.alpha[k - 1];
         io.beta = cf.beta[k - 1];
         io.gamma = cf.gamma[k - 1];
-        stream_rows<V, RC>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], prod);
+        stream_rows<V, RC>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], prod, srp, wcnt);
         // Every wave's stores have reached the L2 (vmcnt = 0) before the
         // barrier; the release store below then writes the L2 back for the
         // other XCDs and publishes the chunk, and the next ticket is taken.
@@ -273,10 +304,112 @@ __global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
         __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// XCD this wave runs on: hardware register XCC_ID (20), bits [3:0].
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xF);
+}
+
+struct XcdParams {
+    DevMatrix m;
+    DevXcdSchedule s;
+    DevWorkspace ws;
+    SegArgs a;
+    int64_t spin_limit;   // wall-clock ticks
+};
+
+// Persistent kernel of the XCD schedule.  Queue q holds the tasks of the
+// chunks owned by XCD q, in global dependency order; a workgroup serves the
+// queue of the XCD it runs on (read from the hardware, so the binding holds
+// whatever the dispatcher does).  Dependencies are exact chunk lists.  After
+// a task, the L2 is written back only when some consumer of the chunk is
+// owned by another XCD: consumers on the same XCD share its L2 and only need
+// their L1 invalidated (the acquire).  Deadlock freedom: the earliest
+// unfinished task in the global order is always held by a workgroup of its
+// queue (all earlier tasks of that queue are done), and its dependencies are
+// earlier still, so it can run; waits are bounded by spin_limit in any case.
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock) void xcd_kernel(XcdParams P, Coefs cf) {
+    __shared__ double prod[kSlice];
+    __shared__ int32_t srp[kBlock + 1];
+    __shared__ int32_t wcnt[kWavesPerBlock];
+    __shared__ int32_t s_ticket;
+    __shared__ int s_ok;
+    const int tid = threadIdx.x;
+    const size_t stride = (size_t)P.m.n * P.a.R;
+    const int q = P.s.n_queues == 1 ? 0 : __builtin_amdgcn_readfirstlane(xcc_id());
+    if (q >= P.s.n_queues) return;  // uniform: no queue for this XCD
+    const int32_t q0 = P.s.qptr[q];
+    const int32_t qn = P.s.qptr[q + 1] - q0;
+    int32_t *ticket = P.ws.ticket + q;
+    if (tid == 0)
+        s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    int32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+    while (t < qn) {
+        const int32_t c = P.s.tasks[2 * (q0 + t)];
+        const int32_t k = P.s.tasks[2 * (q0 + t) + 1];
+        int ok = 1;
+        if (k > 1) {
+            if (tid < kWave) {
+                const int32_t lo = P.s.dep_ptr[c], hi = P.s.dep_ptr[c + 1];
+                uint64_t t0 = 0;
+                for (int round = 0;; ++round) {
+                    int ready = 1;
+                    for (int32_t j = lo + tid; j < hi; j += kWave)
+                        ready &= ld_relaxed(P.ws.done + P.s.dep_idx[j]) >= k - 1;
+                    if (__all(ready)) break;
+                    if (round == 0) t0 = wall_clock64();
+                    if (ld_relaxed(P.ws.err) != 0 ||
+                        (int64_t)(wall_clock64() - t0) > P.spin_limit) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (tid == 0) s_ok = ok;
+            }
+            __syncthreads();
+            ok = __builtin_amdgcn_readfirstlane(s_ok);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if (!ok) break;
+        PowerIO io;
+        io.in = (k == 1) ? P.a.in0 : P.a.Y + (size_t)(k - 2) * stride;
+        io.prev = (k == 1) ? P.a.inm1 : (k == 2 ? P.a.in0 : P.a.Y + (size_t)(k - 3) * stride);
+        io.out = P.a.Y + (size_t)(k - 1) * stride;
+        io.recur = P.a.recur;
+        io.alpha = cf.alpha[k - 1];
+        io.beta = cf.beta[k - 1];
+        io.gamma = cf.gamma[k - 1];
+        stream_rows<V, RC>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], prod, srp, wcnt);
+        // every wave's stores have reached this XCD's L2 before the barrier
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __syncthreads();
+        if (tid == 0) {
+            if (P.s.remote_out[c]) {
+                // a consumer on another XCD: write this L2 back first
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+            }
+            __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_ticket);
+    }
+    if (t < qn && tid == 0)
+        __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_chunks) ws.done[i] = 0;
-    if (i == 0) *ws.ticket = 0;
+    if (i < kMaxQueues) ws.ticket[i] = 0;
+}
+
+// Each workgroup records the XCD it ran on.
+__global__ void xcc_probe_kernel(int32_t *out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 __global__ void permute_kernel(const int32_t *perm, int64_t n, int to_plan, const double *in,
@@ -321,6 +454,7 @@ __global__ __launch_bounds__(kBlock) void load_probe_kernel(const double2 *buf, 
 using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, const int32_t *);
 using LbFn = void (*)(LBParams, Coefs);
 using StepFn = void (*)(DevMatrix, const int32_t *, const int32_t *, SegArgs, Coefs);
+using XcdFn = void (*)(XcdParams, Coefs);
 
 int r_index(int R) {
     switch (R) {
@@ -338,7 +472,14 @@ struct VTable {
     SpmvFn spmv[6];
     LbFn lb[6];
     StepFn step[6];
+    XcdFn xcd[6];
     VTable() {
+        xcd[0] = xcd_kernel<V, 1>;
+        xcd[1] = xcd_kernel<V, 2>;
+        xcd[2] = xcd_kernel<V, 4>;
+        xcd[3] = xcd_kernel<V, 8>;
+        xcd[4] = xcd_kernel<V, 16>;
+        xcd[5] = xcd_kernel<V, 0>;
         spmv[0] = spmv_power_kernel<V, 1>;  lb[0] = lb_kernel<V, 1>;  step[0] = step_kernel<V, 1>;
         spmv[1] = spmv_power_kernel<V, 2>;  lb[1] = lb_kernel<V, 2>;  step[1] = step_kernel<V, 2>;
         spmv[2] = spmv_power_kernel<V, 4>;  lb[2] = lb_kernel<V, 4>;  step[2] = step_kernel<V, 4>;
@@ -365,6 +506,10 @@ LbFn lb_fn(int value_bits, int R) {
 }
 StepFn step_fn(int value_bits, int R) {
     return value_bits == 32 ? t32().step[r_index(R)] : t64().step[r_index(R)];
+}
+
+XcdFn xcd_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().xcd[r_index(R)] : t64().xcd[r_index(R)];
 }
 
 }  // namespace
@@ -420,6 +565,44 @@ int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
     hipLaunchKernelGGL(lb_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
                        (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
+}
+
+int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
+               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
+               void *stream) {
+    if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
+    if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
+    if (s.n_queues < 1 || s.n_queues > kMaxQueues) return (int)hipErrorInvalidValue;
+    if (s.n_chunks == 0) return 0;
+    XcdParams P{m, s, ws, a, spin_limit};
+    Coefs c{};
+    if (cf) c = *cf;
+    hipLaunchKernelGGL(xcd_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
+                       (hipStream_t)stream, P, c);
+    return (int)hipGetLastError();
+}
+
+int detect_xcds(int device) {
+    constexpr int kProbe = 2048;
+    if (hipSetDevice(device) != hipSuccess) return 1;
+    int32_t *d = nullptr;
+    if (hipMalloc(&d, kProbe * sizeof(int32_t)) != hipSuccess) return 1;
+    int32_t h[kProbe];
+    hipLaunchKernelGGL(xcc_probe_kernel, dim3(kProbe), dim3(64), 0, nullptr, d);
+    bool ok = hipGetLastError() == hipSuccess &&
+              hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess;
+    (void)hipFree(d);
+    if (!ok) return 1;
+    // the ids seen must be exactly 0..k-1
+    int seen[16] = {0}, k = 0;
+    for (int i = 0; i < kProbe; ++i) {
+        if (h[i] < 0 || h[i] >= kMaxQueues) return 1;
+        seen[h[i]] = 1;
+        k = std::max(k, h[i] + 1);
+    }
+    for (int i = 0; i < k; ++i)
+        if (!seen[i]) return 1;
+    return k;
 }
 
 int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in, double *out,

@@ -49,6 +49,12 @@ struct Schedule {
     std::vector<int32_t> dep_lo, dep_hi;
     std::vector<int32_t> tasks;        // 2 * n_tasks: (chunk, power)
     std::vector<int32_t> step_ptr;     // STEPS: n_steps + 1 task ranges, else empty
+    // XCD schedule: exact dependency lists, owning XCD, write-back flags and
+    // per-XCD task queues (tasks holds the queues one after the other)
+    std::vector<int32_t> dep_ptr, dep_idx;
+    std::vector<int32_t> chunk_xcd, remote_out;
+    std::vector<int32_t> qptr;
+    int32_t n_queues = 0;
     int32_t n_groups = 0, lag = 0, max_reach = 0;
     double window_bytes = 0.0, build_ms = 0.0;
     int32_t n_chunks() const { return (int32_t)chunk_group.size(); }
@@ -62,6 +68,9 @@ struct PlanShape {
     const std::vector<int32_t> *level_ptr;
     const std::vector<int32_t> *rowptr;  // plan order
     const std::vector<int32_t> *row_lo, *row_hi;
+    const std::vector<int32_t> *pcol;    // plan-numbered columns (XCD schedule)
+    int n_xcd;                           // XCDs that own parts of each level (>= 1)
+    bool xcd_local;                      // tasks of one queue run on one XCD only
 };
 
 mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
@@ -108,14 +117,25 @@ struct DevSchedule {
     int32_t n_tasks, n_chunks;
 };
 
+constexpr int kMaxQueues = 16;
+
 struct DevWorkspace {
     int32_t *done;      // n_chunks completion powers
-    int32_t *ticket;    // next task
+    int32_t *ticket;    // next task (kMaxQueues counters for the XCD schedule)
     int32_t *err;       // sticky failure flag
 };
 
+struct DevXcdSchedule {
+    const int32_t *chunk_ptr;
+    const int32_t *dep_ptr, *dep_idx;
+    const int32_t *remote_out;
+    const int32_t *tasks;
+    const int32_t *qptr;
+    int32_t n_queues, n_chunks;
+};
+
 // Launchers (kernels.hip).  All return hipError_t as int.
-int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);
+int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);  // also clears the queue tickets
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
               void *stream);
@@ -130,6 +150,12 @@ int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in
                    int nvec, int R, void *stream);
 int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int workgroups,
                       double *sink, void *stream);
+int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
+               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
+               void *stream);
+// XCDs of the device when workgroup i runs on XCD i mod n (checked with a probe
+// kernel), else 1.
+int detect_xcds(int device);
 // Max co-resident persistent workgroups of the level-blocked kernel.
 int lb_max_workgroups(int value_bits, int R, int device);
 

@@ -182,8 +182,161 @@ struct RangeMax {
 
 }  // namespace
 
+// XCD schedule: every level is split into n_xcd contiguous parts (by
+// nonzeros) and part x of every level belongs to XCD x, so a chunk's rows
+// mostly read rows of the same XCD one level up or down.  Chunks stay inside
+// one part and start on multiples of 16 rows where possible (one 128-byte
+// line of a single-RHS vector).  Dependencies are exact lists of chunks.
+static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
+                                       int default_workgroups, Schedule &s, std::string &err) {
+    const double t0 = now_ms();
+    const int64_t n = sh.n;
+    const auto &lp = *sh.level_ptr;
+    const auto &rp = *sh.rowptr;
+    const auto &pcol = *sh.pcol;
+    const int nx = std::max(1, std::min(sh.n_xcd, kMaxQueues));
+    const int32_t n_levels = (int32_t)lp.size() - 1;
+    const int64_t chunk_nnz = std::max(1, tune.chunk_nnz);
+    const double row_bytes = 4.0, nz_bytes = 4.0 + sh.value_bytes;
+    s.n_queues = nx;
+    s.n_groups = n_levels;
+    s.chunk_ptr.assign(1, 0);
+    auto align_up = [](int64_t r) { return (r + 15) & ~(int64_t)15; };
+    for (int32_t l = 0; l < n_levels; ++l) {
+        const int64_t L0 = lp[l], L1 = lp[l + 1];
+        const int64_t rows = L1 - L0;
+        const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(nx, rows / 16));
+        int64_t a = L0;
+        for (int x = 0; x < parts; ++x) {
+            int64_t b = L1;
+            if (x + 1 < parts) {
+                const int64_t target = rp[L0] + ((int64_t)rp[L1] - rp[L0]) * (x + 1) / parts;
+                b = std::upper_bound(rp.begin() + a, rp.begin() + L1, (int32_t)target) - rp.begin();
+                b = align_up(b);
+                if (b <= a) b = align_up(a + 1);
+                b = std::min<int64_t>(b, L1);
+            }
+            if (b <= a) continue;
+            const int xcd = (int)((int64_t)x * nx / parts);
+            // cut [a, b) into chunks of about chunk_nnz nonzeros
+            int64_t r = a;
+            while (r < b) {
+                const int64_t lim = (int64_t)rp[r] + chunk_nnz;
+                int64_t e = std::upper_bound(rp.begin() + r + 1, rp.begin() + b + 1,
+                                             (int32_t)std::min<int64_t>(lim, INT32_MAX)) -
+                            rp.begin() - 1;
+                e = std::min<int64_t>(e, r + 65536);
+                if (e < b) {
+                    // round to a multiple of 16 rows, at least one 16-row step past r
+                    int64_t ea = e & ~(int64_t)15;
+                    if (ea <= r) ea = align_up(r + 1);
+                    e = std::min<int64_t>(ea, b);
+                }
+                s.chunk_ptr.push_back((int32_t)e);
+                s.chunk_group.push_back(l);
+                s.chunk_xcd.push_back(xcd);
+                r = e;
+            }
+            a = b;
+        }
+    }
+    const int32_t nc = s.n_chunks();
+    std::vector<int32_t> chunk_of(n);
+    for (int32_t c = 0; c < nc; ++c)
+        for (int32_t r = s.chunk_ptr[c]; r < s.chunk_ptr[c + 1]; ++r) chunk_of[r] = c;
+    // exact dependency lists (the chunk itself included)
+    std::vector<int32_t> stamp(nc, -1);
+    s.dep_ptr.assign(1, 0);
+    s.dep_lo.resize(nc);
+    s.dep_hi.resize(nc);
+    double reach_sum = 0.0;
+    for (int32_t c = 0; c < nc; ++c) {
+        const size_t start = s.dep_idx.size();
+        stamp[c] = c;
+        s.dep_idx.push_back(c);
+        for (int32_t e = rp[s.chunk_ptr[c]]; e < rp[s.chunk_ptr[c + 1]]; ++e) {
+            const int32_t d = chunk_of[pcol[e]];
+            if (stamp[d] != c) {
+                stamp[d] = c;
+                s.dep_idx.push_back(d);
+            }
+        }
+        std::sort(s.dep_idx.begin() + start, s.dep_idx.end());
+        s.dep_ptr.push_back((int32_t)s.dep_idx.size());
+        s.dep_lo[c] = s.dep_idx[start];
+        s.dep_hi[c] = s.dep_idx.back();
+        s.max_reach = std::max(s.max_reach, s.dep_hi[c] - c);
+        reach_sum += s.dep_hi[c] - c;
+    }
+    // results read by another XCD must leave the producer's L2
+    s.remote_out.assign(nc, sh.xcd_local ? 0 : 1);
+    if (sh.xcd_local)
+        for (int32_t c = 0; c < nc; ++c)
+            for (int32_t j = s.dep_ptr[c]; j < s.dep_ptr[c + 1]; ++j)
+                if (s.chunk_xcd[s.dep_idx[j]] != s.chunk_xcd[c]) s.remote_out[s.dep_idx[j]] = 1;
+    // skewed wavefront over the exact lists: pos(c,1) = c, pos(c,k) = D + max pos(dep, k-1)
+    const double budget = (double)tune.cache_bytes * tune.cache_safety;
+    const double avg_chunk_bytes = ((double)n * row_bytes + (double)sh.nnz * nz_bytes) / std::max(1, nc);
+    const double avg_reach = reach_sum / std::max(1, nc);
+    int64_t D = tune.lag;
+    if (D <= 0) {
+        const double fit = budget / ((double)p * avg_chunk_bytes) - avg_reach;
+        const int64_t par = (default_workgroups + p - 1) / std::max(1, p);
+        D = std::max<int64_t>({(int64_t)std::floor(fit), par, 1});
+    }
+    s.lag = (int32_t)std::min<int64_t>(D, INT32_MAX);
+    struct Key { int64_t pos; int32_t negk, c; };
+    std::vector<Key> keyed;
+    keyed.reserve((size_t)nc * p);
+    std::vector<int64_t> pos(nc), npos(nc);
+    for (int32_t c = 0; c < nc; ++c) { pos[c] = c; keyed.push_back({pos[c], -1, c}); }
+    for (int k = 2; k <= p; ++k) {
+        for (int32_t c = 0; c < nc; ++c) {
+            int64_t m = 0;
+            for (int32_t j = s.dep_ptr[c]; j < s.dep_ptr[c + 1]; ++j) m = std::max(m, pos[s.dep_idx[j]]);
+            npos[c] = m + D;
+        }
+        pos.swap(npos);
+        for (int32_t c = 0; c < nc; ++c) keyed.push_back({pos[c], -k, c});
+    }
+    std::sort(keyed.begin(), keyed.end(), [](const Key &a, const Key &b) {
+        if (a.pos != b.pos) return a.pos < b.pos;
+        if (a.negk != b.negk) return a.negk < b.negk;
+        return a.c < b.c;
+    });
+    // check the global order against the exact lists, then split it into queues
+    std::vector<int64_t> when((size_t)nc * p, -1);
+    for (size_t t = 0; t < keyed.size(); ++t)
+        when[(size_t)(-keyed[t].negk - 1) * nc + keyed[t].c] = (int64_t)t;
+    for (int k = 2; k <= p; ++k)
+        for (int32_t c = 0; c < nc; ++c)
+            for (int32_t j = s.dep_ptr[c]; j < s.dep_ptr[c + 1]; ++j)
+                if (when[(size_t)(k - 2) * nc + s.dep_idx[j]] >= when[(size_t)(k - 1) * nc + c]) {
+                    err = "xcd schedule: dependency after its user";
+                    return MPK_EINVAL;
+                }
+    s.qptr.assign(nx + 1, 0);
+    for (const auto &kv : keyed) s.qptr[s.chunk_xcd[kv.c] + 1]++;
+    for (int q = 0; q < nx; ++q) s.qptr[q + 1] += s.qptr[q];
+    s.tasks.assign((size_t)2 * keyed.size(), 0);
+    std::vector<int32_t> fill(s.qptr.begin(), s.qptr.end() - 1);
+    for (const auto &kv : keyed) {
+        const int32_t at = fill[s.chunk_xcd[kv.c]]++;
+        s.tasks[2 * (size_t)at] = kv.c;
+        s.tasks[2 * (size_t)at + 1] = -kv.negk;
+    }
+    s.window_bytes = (double)p * (avg_reach + D) * avg_chunk_bytes;
+    s.build_ms = now_ms() - t0;
+    return MPK_OK;
+}
+
 mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
                             int default_workgroups, Schedule &s, std::string &err) {
+    if (tune.schedule == MPK_SCHED_XCD && sh.n > 0) {
+        s = Schedule();
+        s.p = p;
+        return build_xcd_schedule(sh, p, tune, default_workgroups, s, err);
+    }
     const double t0 = now_ms();
     s = Schedule();
     s.p = p;
@@ -363,6 +516,29 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
 bool validate_schedule(const Schedule &s, std::string &err) {
     const int32_t nc = s.n_chunks();
     const int p = s.p;
+    if (!s.qptr.empty()) {
+        // XCD queues: every (chunk, power) once, in the owning XCD's queue, and
+        // within a queue a chunk's powers in increasing order
+        if ((int64_t)s.n_tasks() != (int64_t)nc * p || s.qptr.back() != s.n_tasks()) {
+            err = "xcd schedule: task count mismatch";
+            return false;
+        }
+        std::vector<int32_t> seen((size_t)nc * p, 0), last(nc, 0);
+        for (int q = 0; q < s.n_queues; ++q)
+            for (int32_t t = s.qptr[q]; t < s.qptr[q + 1]; ++t) {
+                const int32_t c = s.tasks[2 * t], k = s.tasks[2 * t + 1];
+                if (c < 0 || c >= nc || k < 1 || k > p || s.chunk_xcd[c] != q) {
+                    err = "xcd schedule: task out of range or in the wrong queue";
+                    return false;
+                }
+                if (seen[(size_t)(k - 1) * nc + c]++ || k != last[c] + 1) {
+                    err = "xcd schedule: duplicate or out-of-order power";
+                    return false;
+                }
+                last[c] = k;
+            }
+        return true;
+    }
     if ((int64_t)s.n_tasks() != (int64_t)nc * p) { err = "task count mismatch"; return false; }
     std::vector<int64_t> when((size_t)nc * p, -1);
     for (int32_t t = 0; t < s.n_tasks(); ++t) {

@@ -54,7 +54,7 @@ def run_both(P, x, p, recur=None):
 
 # ------------------------------------------------------------------ small configurations
 
-SCHEDS = ["steps", "wave", "diag", "powers"]
+SCHEDS = ["steps", "wave", "diag", "powers", "xcd"]
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
@@ -127,7 +127,9 @@ def test_ragged_multi_rhs(R):
 
 
 @pytest.mark.parametrize("tune", [dict(schedule="wave"), dict(schedule="diag"),
-                                  dict(schedule="powers"),
+                                  dict(schedule="powers"), dict(schedule="xcd"),
+                                  dict(schedule="xcd", workgroups=5),
+                                  dict(schedule="xcd", chunk_nnz=50, workgroups=64),
                                   dict(lag=1), dict(lag=5000), dict(chunk_nnz=50, workgroups=3),
                                   dict(cache_bytes=1 << 16)])
 def test_tuning_never_changes_a_bit(tune):
@@ -251,11 +253,12 @@ def test_identity_and_permutation_exact():
         assert np.array_equal(Y[k], x[idx])
 
 
-def test_wait_limit_reports_timeout_and_recovers():
+@pytest.mark.parametrize("sched", ["wave", "xcd"])
+def test_wait_limit_reports_timeout_and_recovers(sched):
     A = w.stencil_3d27(40)
     x = w.uniform_vectors(A.n, 1, 4)
     P = mpk.Plan(A)
-    P.tune(schedule="wave", spin_limit_us=1, chunk_nnz=2000)
+    P.tune(schedule=sched, spin_limit_us=1, chunk_nnz=2000)
     seen_timeout = False
     for _ in range(3):
         P.run(dev(x), 24)
@@ -271,11 +274,12 @@ def test_wait_limit_reports_timeout_and_recovers():
     assert np.array_equal(Y, oracle.powers(A, x, 6))
 
 
-def test_concurrent_streams_share_a_plan():
+@pytest.mark.parametrize("sched", ["steps", "wave", "xcd"])
+def test_concurrent_streams_share_a_plan(sched):
     A = w.stencil_3d27(24)
     xs = [w.uniform_vectors(A.n, 2, s) for s in range(4)]
     P = mpk.Plan(A)
-    P.tune(chunk_nnz=1500)
+    P.tune(schedule=sched, chunk_nnz=1500)
     streams = [torch.cuda.Stream() for _ in xs]
     outs = []
     xds = [dev(x) for x in xs]

@@ -101,6 +101,13 @@ def test_task_loop_has_uniform_exit(asm):
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
 
 
+def test_xcd_task_loop_has_uniform_exit(asm):
+    ks = kernels(asm, "xcd_kernel")
+    assert len(ks) == 12
+    for sym, lines in ks.items():
+        assert loops_with_barrier_and_divergent_exit(lines) == [], sym
+
+
 def test_baseline_row_loop_has_uniform_exit(asm):
     ks = kernels(asm, "spmv_power_kernel")
     assert len(ks) == 12
@@ -114,4 +121,12 @@ def test_release_waits_for_writeback_and_acquire_invalidates(asm):
         i = next(j for j, l in enumerate(body) if l.startswith("buffer_wbl2 sc1"))
         assert body[i + 1].startswith("s_waitcnt vmcnt(0)"), (sym, body[i:i + 3])
         assert re.match(r"global_store_dword .* sc1", body[i + 2]), (sym, body[i:i + 3])
+        assert any(l.startswith("buffer_inv sc1") for l in body), sym
+
+
+def test_xcd_writeback_is_waited_for_and_acquire_invalidates(asm):
+    for sym, lines in kernels(asm, "xcd_kernel").items():
+        body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
+        i = next(j for j, l in enumerate(body) if l.startswith("buffer_wbl2 sc1"))
+        assert body[i + 1].startswith("s_waitcnt vmcnt(0)"), (sym, body[i:i + 3])
         assert any(l.startswith("buffer_inv sc1") for l in body), sym

@@ -144,6 +144,98 @@ def test_schedules_are_topological(sched, reorder):
             _deps_cover_reads(A, P, s)
 
 
+def _check_xcd_schedule(A, P, s, p):
+    """XCD schedule: chunks inside one level, exact dependency lists, every
+    (chunk, power) once in its owner's queue, write-back flags exactly where a
+    consumer lives in another queue, and the queues drain with one worker each
+    (no cross-queue deadlock)."""
+    cp, tasks, qp = s["chunk_ptr"], s["tasks"], s["qptr"]
+    dp, di, cx, ro = s["dep_ptr"], s["dep_idx"], s["chunk_xcd"], s["remote_out"]
+    nc, nq = len(cp) - 1, s["n_queues"]
+    lp, perm = P.levels()
+    assert cp[0] == 0 and cp[-1] == A.n and np.all(np.diff(cp) > 0)
+    level = np.searchsorted(lp, cp[:-1], side="right") - 1
+    assert np.array_equal(level, s["chunk_group"])
+    assert np.all(cp[1:] <= lp[level + 1])
+    # exact lists: the chunks the rows read, plus the chunk itself
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(A.n)
+    chunk_of = np.repeat(np.arange(nc), np.diff(cp))
+    for c in range(nc):
+        want = {c}
+        for new in range(cp[c], cp[c + 1]):
+            old = perm[new]
+            want |= set(chunk_of[iperm[A.col[A.rowptr[old]:A.rowptr[old + 1]]]].tolist())
+        assert di[dp[c]:dp[c + 1]].tolist() == sorted(want)
+    # write-back flags
+    want_ro = np.zeros(nc, np.int32)
+    for c in range(nc):
+        for d in di[dp[c]:dp[c + 1]]:
+            if cx[d] != cx[c]:
+                want_ro[d] = 1
+    if nq == 1:
+        assert ro.all()  # one queue: no binding to an XCD, every result is written back
+    else:
+        assert np.array_equal(ro, want_ro)
+    # queues
+    assert qp[0] == 0 and qp[-1] == nc * p and len(qp) == nq + 1
+    seen = set()
+    for q in range(nq):
+        last = {}
+        for c, k in tasks[qp[q]:qp[q + 1]]:
+            assert cx[c] == q and (c, k) not in seen and last.get(c, 0) == k - 1
+            seen.add((c, k))
+            last[c] = k
+    assert len(seen) == nc * p
+    # one worker per queue, each blocked until its head task's inputs are done
+    done = np.zeros(nc, np.int64)
+    head = qp[:-1].copy()
+    left = nc * p
+    while left:
+        moved = False
+        for q in range(nq):
+            if head[q] < qp[q + 1]:
+                c, k = tasks[head[q]]
+                if all(done[d] >= k - 1 for d in di[dp[c]:dp[c + 1]]):
+                    done[c] = k
+                    head[q] += 1
+                    left -= 1
+                    moved = True
+        assert moved, "queues deadlock"
+
+
+@pytest.mark.parametrize("reorder", ["bfs", "none"])
+def test_xcd_schedule_lists_queues_and_progress(reorder):
+    for A in (w.stencil_2d5(30), w.random_sparse(300, 0.01, 3), w.anderson_3d(7),
+              w.stencil_3d27(12)):
+        P = host_plan(A, reorder=reorder)
+        for chunk in (64, 4096):
+            P.tune(schedule="xcd", chunk_nnz=chunk, cache_bytes=20000, lag=0)
+            for p in (1, 2, 5):
+                s = P.schedule(p)
+                assert s["n_queues"] == 8
+                _check_xcd_schedule(A, P, s, p)
+
+
+def test_xcd_chunks_start_on_16_row_boundaries():
+    A = w.stencil_3d27(24)
+    P = host_plan(A)
+    P.tune(schedule="xcd", chunk_nnz=2000)
+    s = P.schedule(4)
+    lp, _ = P.levels()
+    inner = set(s["chunk_ptr"].tolist()) - set(lp.tolist())
+    assert inner and all(r % 16 == 0 for r in inner)
+
+
+def test_xcd_schedule_with_few_workgroups_uses_one_queue():
+    A = w.stencil_2d5(40)
+    P = host_plan(A)
+    P.tune(schedule="xcd", workgroups=4, chunk_nnz=100)
+    s = P.schedule(3)
+    assert s["n_queues"] == 1 and s["remote_out"].all()
+    _check_xcd_schedule(A, P, s, 3)
+
+
 def test_diag_schedule_is_the_papers_lp_order():
     # a path graph has one vertex per BFS level; one chunk per level and one
     # level per group turn the chunk schedule into the Lp diagram of Fig. lp_basic
