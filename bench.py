@@ -1,15 +1,24 @@
 """Benchmark: level-blocked matrix power kernel vs p x SpMV on one MI355X.
 
-Default workload: 3D 27-point stencil on a 128^3 grid (n = 2,097,152,
-nnz = 55,742,968, FP64 values, truncated boundary), x uniform in [-1, 1),
-p = 8 powers, one right-hand side.  One step = one call that produces all
-p powers with the inputs already resident in HBM.  Prints ONE JSON line.
+Workload: 3D 27-point stencil on a 128^3 grid (n = 2,097,152, nnz =
+55,742,968, truncated boundary, diagonal 26 and off-diagonals -1, FP64
+values), x uniform in [-1, 1) from seed 1002, p = 8 powers, one right-hand
+side.  One step = one call that produces all p powers, inputs already
+resident in HBM.  Prints ONE JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+
+The roofline object describes the level-blocked run: algorithmic bytes
+(matrix once, x once, p output vectors; see algorithmic_bytes) divided by
+the mean duration of one run, measured with HIP events recorded on the
+stream the kernels are launched on.  Measured HBM traffic is taken from the
+committed counter summary when it was recorded for the current kernel
+source (same SHA-256), else reported as null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -20,10 +29,11 @@ _ROOT = os.path.dirname(os.path.abspath(__file__))
 if _ROOT not in sys.path:
     sys.path.insert(0, _ROOT)
 
-import numpy as np  # noqa: E402
-
 METRIC = "MPK Gflop/s & HBM bytes vs p×SpMV at p=8 (1 GPU); serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+WORKLOAD = "stencil3d27_128_p8"
+KERNEL_SRC = os.path.join(_ROOT, "paper_2405_12525_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(_ROOT, "profiles", "traffic_stencil3d27_128_p8.json")
 
 
 def log(*a):
@@ -31,12 +41,13 @@ def log(*a):
 
 
 def algorithmic_bytes(n, nnz, p, R, value_bytes, kind, perm_rows=0):
-    """Bytes a kernel must move at minimum (no write-allocate, 4-byte indices).
+    """Bytes a run must move at minimum (4-byte indices, no write-allocate).
 
     A = 4(n+1) + (4 + value_bytes) nnz is the CSR, V = 8 n R one vector block.
     p x SpMV streams A and reads / writes one block per power: p (A + 2V).
-    Level-blocked: A once, x once, p output blocks: A + V + p V (+ 4n for the
-    output permutation when results are written in the caller's order).
+    Level-blocked: A once, x once, p output blocks: A + V + p V.  perm_rows
+    adds 4 bytes per row and pass for the output-row permutation when results
+    are written in the caller's order.
     """
     A = 4 * (n + 1) + (4 + value_bytes) * nnz
     V = 8 * n * R
@@ -45,27 +56,44 @@ def algorithmic_bytes(n, nnz, p, R, value_bytes, kind, perm_rows=0):
     return A + V + p * V + perm_rows * 4
 
 
-def time_calls(fn, steps, warmup, torch):
-    """Median / mean of per-call durations measured with events on the current stream."""
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    t0 = time.perf_counter()
-    for i in range(steps):
-        starts[i].record()
-        fn()
-        ends[i].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+def time_calls(fn, steps, warmup, torch, stream):
+    """Per-call durations from events recorded on `stream` (the launch stream)."""
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            fn()
+        stream.synchronize()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            starts[i].record(stream)
+            fn()
+            ends[i].record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    return dict(median_ms=statistics.median(ms), mean_ms=statistics.fmean(ms),
-                min_ms=min(ms), wall_s=wall)
+    return dict(median_ms=statistics.median(ms), mean_ms=statistics.fmean(ms), min_ms=min(ms),
+                total_ms=sum(ms), wall_s=wall)
 
 
-def cpu_baseline(A, x, p, budget_s=12.0):
-    """The CPU oracle, timed on all host cores over whole runs of the workload."""
+def measured_traffic(kernel_key):
+    """HBM bytes per run from the committed counter summary, if it matches the source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_sha256") != sha or kernel_key not in t.get("runs", {}):
+        return None
+    return t["runs"][kernel_key]["hbm_bytes_per_run"]
+
+
+def cpu_baseline(A, x, p, budget_s=20.0):
+    """The CPU oracle on all host cores: whole runs of the workload, bounded in time."""
     import oracle
     nthreads = oracle.threads()
     times = []
@@ -88,8 +116,8 @@ def cpu_baseline(A, x, p, budget_s=12.0):
     except OSError:
         pass
     return {"value": round(gflops, 3), "unit": "Gflop/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"full workload, all {p} powers, median of {len(times)} runs "
-                      f"({med * 1e3:.1f} ms each) on {cpu}"}
+            "sample": f"the full workload (all {p} powers), median of {len(times)} runs "
+                      f"({med * 1e3:.0f} ms each), OpenMP over rows on {nthreads} threads of {cpu}"}
 
 
 def main():
@@ -98,15 +126,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--reorder", default="auto", choices=["auto", "bfs", "none"])
     args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
-              "sharding of this kernel is described in the design notes, not benchmarked.",
-              file=sys.stderr)
-        sys.exit(2)
-    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py is single-process; do not launch it with several ranks", file=sys.stderr)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding the kernel over "
+              "several GPUs is a design note, not a benchmark here.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -114,45 +137,49 @@ def main():
     import workloads as w
 
     torch.cuda.set_device(0)
-    name = "stencil3d27_128_p8"
+    stream = torch.cuda.Stream()
     t0 = time.perf_counter()
-    A, x, p, _ = w.config(name)
+    A, x, p, _ = w.config(WORKLOAD)
     R = x.shape[1]
-    log(f"[bench] generated {name}: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
+    log(f"[bench] generated {WORKLOAD}: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
     xd = torch.from_numpy(x).cuda()
     Y = torch.empty((p, A.n, R), dtype=torch.float64, device="cuda")
+    B = torch.empty_like(Y)
     flop = mpk.flops(A.nnz, A.n, p, R)
 
-    reorders = ["bfs", "none"] if args.reorder == "auto" else [args.reorder]
-    results = {}
-    plans = {}
-    for ro in reorders:
-        t0 = time.perf_counter()
+    # p x SpMV baseline: best of BFS and original order
+    base = {}
+    for ro in ("bfs", "none"):
         P = mpk.Plan(A, reorder=ro)
-        plans[ro] = P
-        info = P.info()
-        s = P.schedule(p)
-        log(f"[bench] plan reorder={ro}: {time.perf_counter() - t0:.2f}s "
-            f"(host {info['plan_ms']:.0f} ms) levels={info['n_levels']} "
-            f"chunks={s['n_chunks']} lag={s['lag']} "
-            f"reach={s['max_reach']} window={s['window_bytes'] / 2**20:.0f} MiB")
-        lb = time_calls(lambda: P.run(xd, p, Y), args.steps, args.warmup, torch)
-        P.sync()
-        base = time_calls(lambda: P.run_baseline(xd, p, Y), args.steps, args.warmup, torch)
-        results[ro] = (lb, base, info, s)
-        log(f"[bench]   LB {lb['median_ms']:.3f} ms ({flop / lb['median_ms'] / 1e6:.1f} Gflop/s)"
-            f"  pxSpMV {base['median_ms']:.3f} ms ({flop / base['median_ms'] / 1e6:.1f} Gflop/s)")
+        base[ro] = time_calls(lambda: P.run_baseline(xd, p, B, stream=stream), args.steps,
+                              args.warmup, torch, stream)
+        log(f"[bench] p x SpMV reorder={ro}: {base[ro]['median_ms']:.3f} ms "
+            f"({flop / base[ro]['median_ms'] / 1e6:.1f} Gflop/s)")
+        P.close()
+    best_base = min(base, key=lambda r: base[r]["median_ms"])
 
-    best_lb = min(results, key=lambda r: results[r][0]["median_ms"])
-    best_base = min(results, key=lambda r: results[r][1]["median_ms"])
-    lb, _, info, sched = results[best_lb]
-    base = results[best_base][1]
-    perm_rows = A.n if (best_lb == "bfs") else 0
-    lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "lb", perm_rows)
-    trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "trad",
-                                   A.n if best_base == "bfs" else 0)
+    # level-blocked run with the plan's tuning
+    t0 = time.perf_counter()
+    P = mpk.Plan(A, reorder="bfs")
+    info = P.info()
+    tune = P.default_tune()
+    sched = P.schedule(p)
+    log(f"[bench] plan: {time.perf_counter() - t0:.2f}s (host {info['plan_ms']:.0f} ms) "
+        f"levels={info['n_levels']} schedule={tune['schedule']} chunks={sched['n_chunks']} "
+        f"launches={sched['n_steps']}")
+    lb = time_calls(lambda: P.run(xd, p, Y, stream=stream), args.steps, args.warmup, torch, stream)
+    P.sync()
+    P.run_baseline(xd, p, B, stream=stream)
+    stream.synchronize()
+    same = bool(torch.equal(Y, B))
+    log(f"[bench] level-blocked: {lb['median_ms']:.3f} ms ({flop / lb['median_ms'] / 1e6:.1f} "
+        f"Gflop/s), bit-identical to p x SpMV: {same}")
+
+    lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "lb", A.n)
+    trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "trad", A.n if best_base == "bfs" else 0)
     achieved = lb_bytes / (lb["mean_ms"] * 1e-3) / 1e9
     value = flop / (lb["median_ms"] * 1e-3) / 1e9
+    bmed = base[best_base]["median_ms"]
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -166,29 +193,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D 27-point stencil 128^3 (truncated), FP64 CSR, x U[-1,1), "
-                               "p=8, 1 RHS, level-blocked MPK",
-                   "n": A.n, "nnz": A.nnz, "p": p, "nrhs": R, "reorder": best_lb,
-                   "order": "original", "parallelism": "single GPU"},
-        "baseline_pxspmv": {"gflops": round(flop / (base["median_ms"] * 1e-3) / 1e9, 2),
-                            "ms": round(base["median_ms"], 4), "reorder": best_base,
-                            "algorithmic_bytes": trad_bytes,
-                            "achieved_GBs": round(trad_bytes / (base["mean_ms"] * 1e-3) / 1e9, 1)},
-        "speedup_vs_pxspmv": round(base["median_ms"] / lb["median_ms"], 3),
-        "effective_GBs_trad_bytes": round(trad_bytes / (lb["median_ms"] * 1e-3) / 1e9, 1),
+        "config": {"workload": "3D 27-point stencil 128^3 (truncated), FP64 CSR, x U[-1,1) "
+                               "seed 1002, p=8, 1 RHS, level-blocked MPK, caller's order",
+                   "n": A.n, "nnz": A.nnz, "p": p, "nrhs": R, "reorder": "bfs",
+                   "schedule": tune["schedule"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "lb_kernel", "algorithmic_bytes": lb_bytes},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("level_blocked"),
+                     "kernel": "level-blocked run (all launches of one mpk_run)",
+                     "algorithmic_bytes": lb_bytes},
+        "baseline_pxspmv": {"gflops": round(flop / (bmed * 1e-3) / 1e9, 2), "ms": round(bmed, 4),
+                            "reorder": best_base, "algorithmic_bytes": trad_bytes,
+                            "achieved_GBs": round(trad_bytes / (base[best_base]["mean_ms"] * 1e-3)
+                                                  / 1e9, 1),
+                            "traffic": measured_traffic("pxspmv")},
+        "speedup_vs_pxspmv": round(bmed / lb["median_ms"], 3),
+        "bit_identical_to_pxspmv": same,
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
-                 "chunks": sched["n_chunks"],
-                 "lag": sched["lag"], "spmv_equivalents":
-                     round(info["plan_ms"] / base["median_ms"] * p, 1)},
+                 "chunks": sched["n_chunks"], "launches_per_run": sched["n_steps"],
+                 "spmv_equivalents": round(info["plan_ms"] / (bmed / p), 1)},
     }
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, p)
-    for P in plans.values():
-        P.close()
+    P.close()
     print(json.dumps(out), flush=True)
 
 

@@ -241,9 +241,42 @@ mpk_status_t mpk_run_baseline_recur(mpk_plan_t plan, const double *x, int p, int
 mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double *out, int nvec,
                          int nrhs, void *hip_stream);
 
-/* Wait for every run issued on this plan and report device-side failures
- * (MPK_ETIMEOUT when a dependency wait hit its limit). */
+/* Wait for every run issued on this plan (all streams it was given) and
+ * report device-side failures (MPK_ETIMEOUT when a dependency wait hit its
+ * limit; the results of that run are invalid). */
 mpk_status_t mpk_plan_sync(mpk_plan_t plan);
+
+/*
+ * Autotuner (the counterpart of the paper's parameter study over the cache
+ * size C and the RACE safety factor, Sec. "Parameter Study"): times the
+ * level-blocked run for p powers and nrhs right-hand sides under a fixed list
+ * of candidate tunings (schedule x cache budget x chunk size), keeps the
+ * fastest and sets it on the plan.  Each candidate runs once untimed, then
+ * `reps` timed runs on `stream` (median).  Results are cached per (matrix
+ * fingerprint, value precision, p, nrhs, recurrence): a later call with the
+ * same key applies the cached tuning without timing unless force != 0.
+ * x: n*nrhs doubles, Y: p*n*nrhs doubles (device scratch; overwritten).
+ * best / best_ms may be NULL.  The call synchronizes `stream`.
+ * Errors: as mpk_run; MPK_ETIMEOUT if a candidate's waits hit their limit.
+ */
+mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                               int reps, int force, int recur, void *hip_stream,
+                               mpk_tune_t *best, double *best_ms);
+
+/*
+ * Capture one level-blocked run (mpk_run, or mpk_run_recur when alpha is not
+ * NULL) into a HIP graph for repeated launches with the same pointers, p and
+ * nrhs.  The plan's current tuning is used; the graph owns a dependency
+ * workspace reserved for it.  Launches of one graph must not overlap (launch
+ * it on one stream, or synchronize between streams); the graph must be
+ * destroyed before its plan.  The capture itself runs on a private stream.
+ */
+typedef struct mpk_graph_s *mpk_graph_t;
+mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs,
+                               const double *alpha, const double *beta, const double *gamma,
+                               double *Y, mpk_graph_t *out);
+mpk_status_t mpk_graph_launch(mpk_graph_t graph, void *hip_stream);
+void mpk_graph_destroy(mpk_graph_t graph);
 
 /*
  * Load-only bandwidth probe (the MI355X counterpart of the paper's

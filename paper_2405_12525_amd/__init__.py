@@ -214,6 +214,43 @@ class Plan:
     def tuning(self) -> dict:
         return dict(self._tune)
 
+    def autotune(self, x, p: int, Y=None, reps: int = 3, force: bool = False, recur: bool = False,
+                 stream=None) -> dict:
+        """Time the candidate tunings for (p, nrhs) and keep the fastest
+        (mpk_plan_autotune).  Y is scratch.  Returns the tuning plus "ms"."""
+        R, Y = self._prep(x, p, Y)
+        t = _capi.Tune()
+        ms = ctypes.c_double(0.0)
+        check(self._lib.mpk_plan_autotune(self._h, ctypes.c_void_p(x.data_ptr()), int(p), R,
+                                          ctypes.c_void_p(Y.data_ptr()), int(reps), int(force),
+                                          int(recur), _stream_handle(stream), ctypes.byref(t),
+                                          ctypes.byref(ms)))
+        d = {f: getattr(t, f) for f, _ in _capi.Tune._fields_}
+        d["schedule"] = {v: k for k, v in _SCHED.items()}[d["schedule"]]
+        self._tune = {k: v for k, v in d.items()}
+        out = dict(d)
+        out["ms"] = ms.value
+        return out
+
+    def capture(self, x, p: int, Y=None, alpha=None, beta=None, gamma=None) -> "Graph":
+        """Capture one run (mpk_graph_capture) for repeated launches with the
+        same tensors; recurrence when alpha is given."""
+        R, Y = self._prep(x, p, Y)
+        keep = []
+        ptrs = [None, None, None]
+        if alpha is not None:
+            for i, c in enumerate((alpha, beta, gamma)):
+                a = np.ascontiguousarray(c, dtype=np.float64)
+                if a.shape != (p,):
+                    raise ValueError("coefficient arrays must have length p")
+                keep.append(a)
+                ptrs[i] = ctypes.c_void_p(a.ctypes.data)
+        h = ctypes.c_void_p()
+        check(self._lib.mpk_graph_capture(self._h, ctypes.c_void_p(x.data_ptr()), int(p), R,
+                                          ptrs[0], ptrs[1], ptrs[2],
+                                          ctypes.c_void_p(Y.data_ptr()), ctypes.byref(h)))
+        return Graph(h, self, (x, Y))
+
     # ------------------------------------------------------------ runs
     def _prep(self, x, p, Y):
         torch = _torch()
@@ -292,3 +329,29 @@ class Plan:
     def sync(self):
         """Wait for this plan's runs; raises MPKError(MPK_ETIMEOUT) on a failed wait."""
         check(self._lib.mpk_plan_sync(self._h))
+
+
+class Graph:
+    """A captured level-blocked run (mpk_graph_*).  Keeps its plan and
+    tensors alive; launches must not overlap; close() before the plan."""
+
+    def __init__(self, handle, plan, tensors):
+        self._h = handle
+        self._plan = plan
+        self._tensors = tensors
+        self._lib = lib()
+
+    def launch(self, stream=None):
+        check(self._lib.mpk_graph_launch(self._h, _stream_handle(stream)))
+        return self._tensors[1]
+
+    def close(self):
+        if self._h:
+            self._lib.mpk_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

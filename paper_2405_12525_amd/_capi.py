@@ -23,6 +23,7 @@ EXPORTS = [
     "mpk_plan_info", "mpk_plan_levels", "mpk_plan_schedule", "mpk_plan_schedule_xcd", "mpk_run", "mpk_run_recur",
     "mpk_run_baseline", "mpk_run_baseline_recur", "mpk_permute", "mpk_plan_sync",
     "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
+    "mpk_plan_autotune", "mpk_graph_capture", "mpk_graph_launch", "mpk_graph_destroy",
 ]
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -109,6 +110,17 @@ def load():
     lib.mpk_plan_sync.restype = st
     lib.mpk_probe_load.argtypes = [P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P]
     lib.mpk_probe_load.restype = st
+    lib.mpk_plan_autotune.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(Tune),
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.mpk_plan_autotune.restype = st
+    lib.mpk_graph_capture.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.mpk_graph_capture.restype = st
+    lib.mpk_graph_launch.argtypes = [P, P]
+    lib.mpk_graph_launch.restype = st
+    lib.mpk_graph_destroy.argtypes = [P]
+    lib.mpk_graph_destroy.restype = None
     lib.mpk_set_allocator.argtypes = [P, P, P]
     lib.mpk_set_allocator.restype = st
     lib.mpk_last_error.argtypes = []

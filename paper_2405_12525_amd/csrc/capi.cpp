@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -18,6 +19,9 @@
 using namespace mpk;
 
 namespace {
+
+// Slices per workgroup of the p x SpMV kernel (consecutive slices pipeline).
+constexpr int32_t kSpmvSlicesPerWG = 2;
 
 thread_local std::string g_err;
 
@@ -89,9 +93,30 @@ struct DevBuf {
     template <typename T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Slice table of one right-hand-side count (the staging buffer holds a fixed
+// number of products, so the nonzeros per slice depend on R).
+struct SliceSet {
+    DevBuf srow, snz, bound_sptr;
+    int32_t n_slices = 0;
+    DevSlices view() const { return DevSlices{srow.as<int32_t>(), snz.as<int32_t>()}; }
+};
+
+mpk_status_t make_slices(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &bounds,
+                         int E, bool upload_bounds, SliceSet &out) {
+    std::vector<int32_t> srow, snz, bs;
+    build_slices(rowptr, bounds, E, srow, snz, bs);
+    out.n_slices = srow.empty() ? 0 : (int32_t)srow.size() - 1;
+    mpk_status_t st;
+    if ((st = out.srow.upload(srow.data(), srow.size() * 4))) return st;
+    if ((st = out.snz.upload(snz.data(), snz.size() * 4))) return st;
+    if (upload_bounds && (st = out.bound_sptr.upload(bs.data(), bs.size() * 4))) return st;
+    return MPK_OK;
+}
+
 struct SchedEntry {
     Schedule host;
-    DevBuf chunk_ptr, dep_lo, dep_hi, tasks;
+    std::map<int, std::unique_ptr<SliceSet>> slices;  // by right-hand-side count
+    DevBuf dep_lo, dep_hi, tasks;
     DevBuf dep_ptr, dep_idx, remote_out, qptr;  // XCD schedule
     int workgroups = 0;
 };
@@ -131,8 +156,7 @@ struct mpk_plan_s {
     bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
     // device data
     DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
-    DevBuf d_bptr;           // row blocks of the p x SpMV baseline kernel
-    int32_t n_bblocks = 0;
+    std::map<int, std::unique_ptr<SliceSet>> spmv_slices;  // p x SpMV, by RHS count
     // schedules and workspaces
     std::mutex mu;
     mpk_tune_t tune{};
@@ -140,6 +164,8 @@ struct mpk_plan_s {
     std::vector<std::unique_ptr<SchedEntry>> retired;
     std::vector<std::unique_ptr<Workspace>> pool;
     std::map<long long, int> wg_cache;
+    std::map<hipStream_t, hipEvent_t> stream_ev;  // last run issued per stream
+    uint64_t fingerprint = 0;                     // of the input CSR and options
 
     DevMatrix matrix() const {
         return DevMatrix{d_rowptr.as<int32_t>(), d_col.as<int32_t>(), d_val.ptr,
@@ -154,29 +180,16 @@ struct mpk_plan_s {
                     (void)hipEventDestroy(w->ev);
                 }
             }
+            for (auto &kv : stream_ev) {
+                (void)hipEventSynchronize(kv.second);
+                (void)hipEventDestroy(kv.second);
+            }
             (void)hipDeviceSynchronize();
         }
     }
 };
 
 namespace {
-
-// Row blocks of about `target` nonzeros (and at most 4096 rows) for the
-// one-launch-per-power baseline.
-std::vector<int32_t> row_blocks(const std::vector<int32_t> &rowptr, int64_t n, int64_t target) {
-    std::vector<int32_t> b(1, 0);
-    int64_t r = 0;
-    while (r < n) {
-        const int64_t lim = (int64_t)rowptr[r] + target;
-        int64_t e = std::upper_bound(rowptr.begin() + r + 1, rowptr.begin() + n + 1, (int32_t)std::min<int64_t>(lim, INT32_MAX)) -
-                    rowptr.begin() - 1;
-        e = std::max<int64_t>(e, r + 1);
-        e = std::min<int64_t>(e, r + 4096);
-        b.push_back((int32_t)e);
-        r = e;
-    }
-    return b;
-}
 
 mpk_status_t check_device_plan(mpk_plan_t plan) {
     if (!plan) return fail(MPK_EINVAL, "plan is NULL");
@@ -204,7 +217,6 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
     if (!validate_schedule(e->host, err)) return fail(MPK_EINVAL, "schedule invalid: " + err);
     if (!plan->host_only) {
         const Schedule &s = e->host;
-        if ((st = e->chunk_ptr.upload(s.chunk_ptr.data(), s.chunk_ptr.size() * 4))) return st;
         if ((st = e->dep_lo.upload(s.dep_lo.data(), s.dep_lo.size() * 4))) return st;
         if ((st = e->dep_hi.upload(s.dep_hi.data(), s.dep_hi.size() * 4))) return st;
         if ((st = e->tasks.upload(s.tasks.data(), s.tasks.size() * 4))) return st;
@@ -222,8 +234,9 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
 
 // A dependency workspace that no unfinished run uses (plan->mu held).
 mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream, bool capturing,
-                           Workspace **out) {
+                           Workspace **out, bool fresh = false) {
     for (auto &w : plan->pool) {
+        if (fresh) break;
         if (w->reserved || w->cap < n_chunks) continue;
         bool free_now = !w->recorded || w->last_stream == stream;
         if (!free_now && !capturing) free_now = hipEventQuery(w->ev) == hipSuccess;
@@ -274,6 +287,35 @@ mpk_status_t check_run_args(mpk_plan_t plan, const double *x, int p, int nrhs, d
     return MPK_OK;
 }
 
+// Remember the last run issued on `stream` so that mpk_plan_sync can wait
+// for it (plan->mu held).
+mpk_status_t note_stream(mpk_plan_t plan, hipStream_t stream) {
+    auto it = plan->stream_ev.find(stream);
+    if (it == plan->stream_ev.end()) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        it = plan->stream_ev.emplace(stream, ev).first;
+    }
+    hipError_t e = hipEventRecord(it->second, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return MPK_OK;
+}
+
+// Slices of a schedule's chunks for R right-hand sides (plan->mu held).
+mpk_status_t task_slices(mpk_plan_t plan, SchedEntry *se, int R, SliceSet **out) {
+    auto it = se->slices.find(R);
+    if (it == se->slices.end()) {
+        auto ss = std::make_unique<SliceSet>();
+        mpk_status_t st = make_slices(plan->rowptr, se->host.chunk_ptr, slice_nnz(kTaskKP, R), true,
+                                      *ss);
+        if (st) return st;
+        it = se->slices.emplace(R, std::move(ss)).first;
+    }
+    *out = it->second.get();
+    return MPK_OK;
+}
+
 mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
                     const double *beta, const double *gamma, double *Y, void *stream_v) {
     mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
@@ -313,11 +355,15 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                 cf.beta[j] = beta[base + j];
                 cf.gamma[j] = gamma[base + j];
             }
+        SliceSet *ss = nullptr;
+        if (capturing && !se->slices.count(nrhs))
+            return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
+        if ((st = task_slices(plan, se, nrhs, &ss))) return st;
         if (!se->host.step_ptr.empty()) {
             // one launch per diagonal; stream order separates the diagonals
             const auto &sp = se->host.step_ptr;
             for (size_t d = 0; d + 1 < sp.size(); ++d) {
-                int rc = launch_step(m, se->chunk_ptr.as<int32_t>(),
+                int rc = launch_step(m, ss->view(), ss->bound_sptr.as<int32_t>(),
                                      se->tasks.as<int32_t>() + 2 * (size_t)sp[d], sp[d + 1] - sp[d],
                                      a, &cf, stream);
                 if (rc) return hip_fail((hipError_t)rc, "step kernel launch");
@@ -326,13 +372,13 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         }
         Workspace *ws = nullptr;
         if ((st = get_workspace(plan, se->host.n_chunks(), stream, capturing, &ws))) return st;
-        DevSchedule ds{se->chunk_ptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
+        DevSchedule ds{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
                        se->dep_hi.as<int32_t>(), se->tasks.as<int32_t>(), se->host.n_tasks(),
                        se->host.n_chunks()};
         int rc = launch_reset(ws->view(), se->host.n_chunks(), stream);
         if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
         if (!se->host.qptr.empty()) {
-            DevXcdSchedule xs{se->chunk_ptr.as<int32_t>(), se->dep_ptr.as<int32_t>(),
+            DevXcdSchedule xs{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_ptr.as<int32_t>(),
                               se->dep_idx.as<int32_t>(), se->remote_out.as<int32_t>(),
                               se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
                               se->host.n_queues, se->host.n_chunks()};
@@ -350,6 +396,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
             ws->last_stream = stream;
         }
     }
+    if (!capturing && (st = note_stream(plan, stream))) return st;
     return MPK_OK;
 }
 
@@ -362,17 +409,38 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     if (plan->n == 0) return MPK_OK;
     hipError_t e = hipSetDevice(plan->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (stream) (void)hipStreamIsCapturing(stream, &cap);
+    SliceSet *sl = nullptr;
+    {
+        std::lock_guard<std::mutex> g(plan->mu);
+        auto it = plan->spmv_slices.find(nrhs);
+        if (it == plan->spmv_slices.end()) {
+            if (cap == hipStreamCaptureStatusActive)
+                return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
+            auto ss = std::make_unique<SliceSet>();
+            const std::vector<int32_t> whole{0, (int32_t)plan->n};
+            if ((st = make_slices(plan->rowptr, whole, slice_nnz(kSpmvKP, nrhs), false, *ss))) return st;
+            it = plan->spmv_slices.emplace(nrhs, std::move(ss)).first;
+        }
+        sl = it->second.get();
+    }
     const size_t stride = (size_t)plan->n * nrhs;
     const DevMatrix m = plan->matrix();
     for (int k = 1; k <= p; ++k) {
         const double *in = k == 1 ? x : Y + (size_t)(k - 2) * stride;
         const double *prev = k == 1 ? nullptr : (k == 2 ? x : Y + (size_t)(k - 3) * stride);
         double *out = Y + (size_t)(k - 1) * stride;
-        int rc = launch_spmv_power(m, plan->d_bptr.as<int32_t>(), plan->n_bblocks, in, prev, out,
+        int rc = launch_spmv_power(m, sl->view(), sl->n_slices, kSpmvSlicesPerWG, in, prev, out,
                                    nrhs, recur ? 1 : 0, recur ? alpha[k - 1] : 1.0,
                                    recur ? beta[k - 1] : 0.0, recur ? gamma[k - 1] : 0.0,
                                    stream_v);
         if (rc) return hip_fail((hipError_t)rc, "spmv kernel launch");
+    }
+    if (cap != hipStreamCaptureStatusActive) {
+        std::lock_guard<std::mutex> g(plan->mu);
+        if ((st = note_stream(plan, stream))) return st;
     }
     return MPK_OK;
 }
@@ -480,9 +548,6 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                 for (size_t i = 0; i < nnz; ++i) v32[i] = (float)pc.val[i];
                 if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
             }
-            const std::vector<int32_t> bb = row_blocks(pc.rowptr, A->n, 4096);
-            plan->n_bblocks = (int32_t)bb.size() - 1;
-            if ((st = plan->d_bptr.upload(bb.data(), bb.size() * 4))) return st;
             bool identity = true;
             for (int64_t i = 0; i < A->n && identity; ++i) identity = plan->lv.perm[i] == i;
             if (!identity) {
@@ -495,6 +560,24 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         return fail(MPK_ENOMEM, "host allocation failed");
     } catch (const std::exception &ex) {
         return fail(MPK_EINVAL, ex.what());
+    }
+    {
+        // FNV-1a over the shape, the options, every row pointer and a sample
+        // of the columns: the key of the autotuner's cache
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&h](uint64_t v) {
+            for (int b = 0; b < 8; ++b) {
+                h ^= (v >> (8 * b)) & 0xff;
+                h *= 1099511628211ull;
+            }
+        };
+        mix((uint64_t)A->n);
+        mix((uint64_t)A->nnz);
+        mix((uint64_t)o.reorder * 1000 + o.order * 100 + (uint64_t)o.root);
+        for (int64_t i = 0; i <= A->n; ++i) mix((uint64_t)(uint32_t)A->rowptr[i]);
+        const int64_t step = std::max<int64_t>(1, A->nnz / 65536);
+        for (int64_t e2 = 0; e2 < A->nnz; e2 += step) mix((uint64_t)(uint32_t)A->col[e2]);
+        plan->fingerprint = h;
     }
     plan->plan_ms = now_ms() - t0;
     *out = plan.release();
@@ -657,12 +740,206 @@ mpk_status_t mpk_probe_load(const double *buf, int64_t n, int passes, int workgr
     return rc ? hip_fail((hipError_t)rc, "probe kernel launch") : MPK_OK;
 }
 
+mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                               int reps, int force, int recur, void *stream_v, mpk_tune_t *best,
+                               double *best_ms) {
+    mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
+    if (st) return st;
+    if (reps < 1 || reps > 100) return fail(MPK_EINVAL, "reps must be in [1, 100]");
+    if (plan->n == 0) return fail(MPK_EINVAL, "nothing to tune for an empty matrix");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (stream) (void)hipStreamIsCapturing(stream, &cap);
+    if (cap != hipStreamCaptureStatusNone) return fail(MPK_EINVAL, "cannot autotune while capturing");
+    using Key = std::tuple<uint64_t, int, int, int, int>;
+    static std::mutex cache_mu;
+    static std::map<Key, std::pair<mpk_tune_t, double>> cache;
+    const Key key{plan->fingerprint, plan->value_bits, p, nrhs, recur ? 1 : 0};
+    mpk_tune_t base;
+    {
+        std::lock_guard<std::mutex> g(plan->mu);
+        base = plan->tune;
+    }
+    if (!force) {
+        std::pair<mpk_tune_t, double> hit;
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(cache_mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                hit = it->second;
+                found = true;
+            }
+        }
+        if (found) {
+            mpk_tune_t t = hit.first;
+            t.workgroups = base.workgroups;
+            t.spin_limit_us = base.spin_limit_us;
+            if ((st = mpk_plan_tune(plan, &t))) return st;
+            if (best) *best = t;
+            if (best_ms) *best_ms = hit.second;
+            return MPK_OK;
+        }
+    }
+    // candidates: the paper's study varies the cache size C; here C, the
+    // chunk size and the schedule
+    std::vector<mpk_tune_t> cands;
+    auto add = [&](int sched, int64_t cache_mib, int chunk) {
+        mpk_tune_t t = base;
+        t.schedule = sched;
+        t.cache_bytes = cache_mib << 20;
+        t.cache_safety = 1.0;
+        t.chunk_nnz = chunk;
+        t.lag = 0;
+        cands.push_back(t);
+    };
+    for (int64_t c : {32, 64, 128})
+        for (int chunk : {4096, 8192}) add(MPK_SCHED_STEPS, c, chunk);
+    add(MPK_SCHED_WAVE, 64, 8192);
+    add(MPK_SCHED_WAVE, 64, 16384);
+    add(MPK_SCHED_XCD, 64, 8192);
+    add(MPK_SCHED_POWERS, 64, 8192);
+    // Chebyshev coefficients for timing the recurrence (values do not change the time)
+    std::vector<double> al(p), be(p, 0.0), ga(p, -1.0);
+    for (int k = 0; k < p; ++k) al[k] = k == 0 ? 1.0 : 2.0;
+    ga[0] = 0.0;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    auto one = [&]() {
+        return recur ? run_lb(plan, x, p, nrhs, al.data(), be.data(), ga.data(), Y, stream_v)
+                     : run_lb(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream_v);
+    };
+    double best_t = 0.0;
+    int best_i = -1;
+    bool timed_out = false;
+    for (size_t i = 0; i < cands.size() && st == MPK_OK; ++i) {
+        if ((st = mpk_plan_tune(plan, &cands[i]))) break;
+        if ((st = one())) break;  // untimed: builds the schedule and slices
+        if (mpk_plan_sync(plan) != MPK_OK) {
+            timed_out = true;  // a wait hit its limit: not a candidate
+            continue;
+        }
+        std::vector<double> ms;
+        for (int r = 0; r < reps && st == MPK_OK; ++r) {
+            e = hipEventRecord(e0, stream);
+            if (e == hipSuccess) st = one();
+            if (e == hipSuccess && st == MPK_OK) e = hipEventRecord(e1, stream);
+            if (e == hipSuccess && st == MPK_OK) e = hipEventSynchronize(e1);
+            float f = 0.f;
+            if (e == hipSuccess && st == MPK_OK) e = hipEventElapsedTime(&f, e0, e1);
+            if (e != hipSuccess && st == MPK_OK) st = hip_fail(e, "timing a candidate");
+            ms.push_back(f);
+        }
+        if (st) break;
+        if (mpk_plan_sync(plan) != MPK_OK) {
+            timed_out = true;
+            continue;
+        }
+        std::sort(ms.begin(), ms.end());
+        const double med = ms[ms.size() / 2];
+        if (best_i < 0 || med < best_t) {
+            best_t = med;
+            best_i = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    if (best_i < 0)
+        return fail(timed_out ? MPK_ETIMEOUT : MPK_EINVAL, "no candidate tuning completed");
+    if ((st = mpk_plan_tune(plan, &cands[best_i]))) return st;
+    {
+        std::lock_guard<std::mutex> g(cache_mu);
+        cache[key] = {cands[best_i], best_t};
+    }
+    if (best) *best = cands[best_i];
+    if (best_ms) *best_ms = best_t;
+    return MPK_OK;
+}
+
+}  // extern "C"
+
+struct mpk_graph_s {
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~mpk_graph_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs,
+                               const double *alpha, const double *beta, const double *gamma,
+                               double *Y, mpk_graph_t *out) {
+    if (!out) return fail(MPK_EINVAL, "out is NULL");
+    *out = nullptr;
+    mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
+    if (st) return st;
+    if (alpha && (!beta || !gamma)) return fail(MPK_EINVAL, "alpha, beta and gamma are all required");
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::unique_ptr<mpk_graph_s> g(new mpk_graph_s());
+    e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    if (plan->n > 0) {
+        // everything a run allocates or uploads is prepared before the capture
+        std::lock_guard<std::mutex> lk(plan->mu);
+        const int wg_default = default_workgroups(plan, nrhs);
+        for (int base = 0; base < p; base += kMaxSegPowers) {
+            const int ps = std::min(kMaxSegPowers, p - base);
+            SchedEntry *se = nullptr;
+            if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
+            SliceSet *ss = nullptr;
+            if ((st = task_slices(plan, se, nrhs, &ss))) return st;
+            if (se->host.step_ptr.empty()) {
+                Workspace *ws = nullptr;
+                // a never-used workspace: the capture below can take it without an event query
+                if ((st = get_workspace(plan, se->host.n_chunks(), g->stream, false, &ws, true)))
+                    return st;
+            }
+        }
+    }
+    e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    st = run_lb(plan, x, p, nrhs, alpha, beta, gamma, Y, g->stream);
+    e = hipStreamEndCapture(g->stream, &g->graph);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    *out = g.release();
+    return MPK_OK;
+}
+
+mpk_status_t mpk_graph_launch(mpk_graph_t graph, void *stream) {
+    if (!graph) return fail(MPK_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return MPK_OK;
+}
+
+void mpk_graph_destroy(mpk_graph_t graph) { delete graph; }
+
 mpk_status_t mpk_plan_sync(mpk_plan_t plan) {
     mpk_status_t st = check_device_plan(plan);
     if (st) return st;
     std::lock_guard<std::mutex> g(plan->mu);
     hipError_t e = hipSetDevice(plan->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    for (auto &kv : plan->stream_ev) {
+        e = hipEventSynchronize(kv.second);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
     bool timeout = false;
     for (auto &w : plan->pool) {
         if (w->recorded) {

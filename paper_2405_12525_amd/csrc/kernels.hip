@@ -1,18 +1,22 @@
 // HIP kernels for gfx950 (MI355X): CSR products for one power, the p x SpMV
-// baseline, the persistent level-blocked kernel, permutation, reset and a
-// load-bandwidth probe.
+// baseline, the level-blocked kernels (one launch per diagonal, and two
+// persistent dataflow forms), permutation, reset and a load-bandwidth probe.
 //
-// Every run kernel goes through one row routine (stream_rows below), which
-// works on slices of consecutive nonzeros:
-//   1. the workgroup reads a slice's column indices and values with
-//      coalesced loads, gathers the matching input entries and stores the
-//      products a_e * x_{col(e), r} in LDS (one rounded multiply each);
+// Every run kernel goes through one row routine (run_slices below).  The
+// host cuts the rows into slices (consecutive rows whose nonzeros fit one
+// LDS staging buffer, at most 256 rows; a longer row is a slice of its own)
+// and a workgroup walks a range of slices:
+//   1. it reads a slice's column indices and values with coalesced loads,
+//      gathers the matching input entries and stores the products
+//      a_e * x_{col(e), r} in LDS (one rounded multiply each);
 //   2. each (row, right-hand side) pair is then summed by one thread,
 //      sequentially in stored order starting from 0.0, with no fused
 //      multiply-add.
-// The summation order is therefore the plain CSR definition itself, and
-// results do not depend on the slice size, the chunking, the schedule or
-// the right-hand-side count.  Values stored as float are promoted to double
+// The loads of the next slice are issued before the current slice is summed
+// (two LDS buffers), so one memory latency per slice is hidden behind the
+// other's arithmetic.  The summation order is the plain CSR definition
+// itself: results do not depend on slicing, chunking, schedule or
+// right-hand-side count.  Values stored as float are promoted to double
 // before the product; vectors and sums are double.
 #include <hip/hip_runtime.h>
 
@@ -25,13 +29,8 @@ namespace mpk {
 namespace {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
-#ifndef MPK_SLICE_DOUBLES
-#define MPK_SLICE_DOUBLES 4096
-#endif
-constexpr int kSlice = MPK_SLICE_DOUBLES;  // doubles of LDS product staging per workgroup
-constexpr int kPerThread = kSlice / kBlock;
 constexpr int kWave = 64;
-constexpr int kWavesPerBlock = kBlock / kWave;
+static_assert(kSliceRows == kBlock, "one thread per row of a slice");
 
 __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -58,33 +57,50 @@ __device__ __forceinline__ double epilogue(const PowerIO &io, double s, size_t i
     return v;
 }
 
-// Products of nz consecutive nonzeros starting at `base`, for every
-// right-hand side: prod[j*R + r] = val[base+j] * in[col[base+j]*R + r].
-// Lanes past the end load a valid entry (clamped index; requires nz >= 1)
-// and their products are never read, so all loads are issued unconditionally.
-template <typename V, int RC>
-__device__ __forceinline__ void slice_products(const DevMatrix &m, const double *in, int R,
-                                               int32_t base, int32_t nz, double *prod) {
+// Output store.  WT: an agent-scope atomic store, which writes through to
+// memory (it must be coherent with agent-scope loads on every XCD), so a
+// result is visible device-wide once the store has completed (vmcnt) and no
+// L2 write-back is needed before publishing it; otherwise a plain store.
+template <bool WT>
+__device__ __forceinline__ void store_out(double *p, double v) {
+    if (WT)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
+// Loads of a slice with 1 <= nz nonzeros starting at nb, rows [rb, re):
+// column and value of product q = tid + j*kBlock (nonzero q / R, right-hand
+// side q % R) and the end of this thread's row.  Lanes past the end load a
+// valid entry (clamped) whose product is never read, so all loads are
+// unconditional.
+template <typename V, int RC, int KP>
+__device__ __forceinline__ void load_cols(const DevMatrix &m, int R, int32_t nb, int32_t nz,
+                                          int32_t (&c)[KP]) {
     const int tid = threadIdx.x;
     const int last = nz - 1;
-    const V *val = static_cast<const V *>(m.val);
-    int32_t c[kPerThread];
-    double a[kPerThread];
-    int rr[kPerThread];
 #pragma unroll
-    for (int j = 0; j < kPerThread; ++j) {
+    for (int j = 0; j < KP; ++j) {
         const int q = tid + j * kBlock;
-        int el = RC ? q / RC : q / R;
-        rr[j] = q - el * R;
-        el = min(el, last);
-        c[j] = m.col[base + el];
-        a[j] = static_cast<double>(val[base + el]);
+        c[j] = m.col[nb + min(RC ? q / RC : q / R, last)];
     }
-    double xv[kPerThread];
+}
+template <typename V, int RC, int KP>
+__device__ __forceinline__ void load_vals(const DevMatrix &m, int R, int32_t nb, int32_t nz,
+                                          double (&a)[KP]) {
+    const int tid = threadIdx.x;
+    const V *val = static_cast<const V *>(m.val);
+    const int last = nz - 1;
 #pragma unroll
-    for (int j = 0; j < kPerThread; ++j) xv[j] = in[(size_t)c[j] * R + rr[j]];
-#pragma unroll
-    for (int j = 0; j < kPerThread; ++j) prod[tid + j * kBlock] = a[j] * xv[j];
+    for (int j = 0; j < KP; ++j) {
+        const int q = tid + j * kBlock;
+        a[j] = static_cast<double>(val[nb + min(RC ? q / RC : q / R, last)]);
+    }
+}
+__device__ __forceinline__ int32_t load_row_end(const DevMatrix &m, int32_t nb, int32_t rb,
+                                                int32_t re) {
+    const int32_t i = rb + (int32_t)threadIdx.x + 1;
+    return i <= re ? m.rowptr[i] : nb;
 }
 
 // Sum prod[e*R + rr] for e in [s0, s1) left to right from 0.0; the LDS
@@ -104,98 +120,134 @@ __device__ __forceinline__ double ordered_sum(const double *prod, int R, int rr,
     return s;
 }
 
-// Rows [r0, r1) of one power.  Called by all threads of the workgroup.
-template <typename V, int RC>
-__device__ void stream_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_t r0,
-                            int32_t r1, double *prod, int32_t *srp, int32_t *wcnt) {
-    const int R = RC ? RC : R_rt;
-    const int E = kSlice / R;  // nonzeros per slice
+// LDS of the row routine: two product buffers and two row-offset buffers.
+template <int KP>
+struct RowSmem {
+    double prod[2][KP * kBlock];
+    int32_t srp[2][kBlock + 1];
+};
+
+// One row longer than a slice buffer: summed buffer by buffer, one thread
+// per right-hand side.  Starts and ends with a barrier.
+template <typename V, int RC, int KP, bool WT>
+__device__ void long_row(const DevMatrix &m, const PowerIO &io, int R, int32_t row, int32_t nb,
+                         int32_t ne, RowSmem<KP> &sm) {
     const int tid = threadIdx.x;
-    const int wave = tid / kWave;
-    const int32_t *rowptr = m.rowptr;
-    int32_t r = r0;
-    while (r < r1) {
-        const int32_t base = rowptr[r];
-        // rows r .. r+cnt-1 end within E nonzeros of base (a prefix: rowptr is
-        // sorted); the loaded row ends are kept in srp for the sums below
-        const int32_t i = r + tid + 1;
-        const int32_t rp = i <= r1 ? rowptr[i] : INT32_MAX;
-        srp[tid + 1] = rp;
-        if (tid == 0) srp[0] = base;
-        const int fits = rp - base <= E;
-        const int wc = __popcll(__ballot(fits));
-        if ((tid & (kWave - 1)) == 0) wcnt[wave] = wc;
+    const int E = (KP * kBlock) / R;
+    double s = 0.0;
+    for (int32_t b = nb; b < ne; b += E) {
+        const int32_t nz = min(E, ne - b);
+        int32_t c[KP];
+        double a[KP];
+        load_cols<V, RC, KP>(m, R, b, nz, c);
+        load_vals<V, RC, KP>(m, R, b, nz, a);
         __syncthreads();
-        int cnt = 0;
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) cnt += wcnt[w];
-        cnt = __builtin_amdgcn_readfirstlane(cnt);
-        if (cnt > 0) {
-            const int32_t nz = srp[cnt] - base;
-            // (a slice of empty rows has no products; the clamped loads need nz >= 1)
-            if (nz > 0) slice_products<V, RC>(m, io.in, R, base, nz, prod);
-            __syncthreads();
-            const int npairs = cnt * R;
-            for (int q = tid; q < npairs; q += kBlock) {
-                const int li = RC ? q / RC : q / R;
-                const int rr = q - li * R;
-                const int32_t row = r + li;
-                const double s = ordered_sum(prod, R, rr, srp[li] - base, srp[li + 1] - base);
-                const int32_t o = m.out_row ? m.out_row[row] : row;
-                const size_t idx = (size_t)o * R + rr;
-                io.out[idx] = epilogue(io, s, idx);
-            }
-            __syncthreads();
-            r += cnt;
-        } else {
-            // one row longer than a slice: sum it slice by slice, one thread per RHS
-            const int32_t end = srp[1];
-            __syncthreads();
-            double s = 0.0;
-            for (int32_t b = base; b < end; b += E) {
-                const int32_t nz = min(E, end - b);
-                slice_products<V, RC>(m, io.in, R, b, nz, prod);
-                __syncthreads();
-                if (tid < R)
-                    for (int32_t e = 0; e < nz; ++e) s = s + prod[e * R + tid];
-                __syncthreads();
-            }
-            if (tid < R) {
-                const int32_t o = m.out_row ? m.out_row[r] : r;
-                const size_t idx = (size_t)o * R + tid;
-                io.out[idx] = epilogue(io, s, idx);
-            }
-            r = r + 1;
+        for (int j = 0; j < KP; ++j) {
+            const int q = tid + j * kBlock;
+            const int rr = q - (RC ? q / RC : q / R) * R;
+            sm.prod[0][q] = a[j] * io.in[(size_t)c[j] * R + rr];
         }
+        __syncthreads();
+        if (tid < R)
+            for (int32_t e = 0; e < nz; ++e) s = s + sm.prod[0][e * R + tid];
+    }
+    if (tid < R) {
+        const int32_t o = m.out_row ? m.out_row[row] : row;
+        const size_t idx = (size_t)o * R + tid;
+        store_out<WT>(io.out + idx, epilogue(io, s, idx));
+    }
+    __syncthreads();
+}
+
+// Slices [s0, s1) of one power.  Called by all threads of the workgroup;
+// all control flow depends on uniform values only.  Ends with a barrier, so
+// the caller may reuse the LDS right away.  Slices holding one row longer
+// than a buffer are computed in a second pass.
+template <typename V, int RC, int KP, bool WT>
+__device__ void run_slices(const DevMatrix &m, const PowerIO &io, int R_rt, DevSlices sl,
+                           int32_t s0, int32_t s1, RowSmem<KP> &sm) {
+    const int R = RC ? RC : R_rt;
+    const int E = (KP * kBlock) / R;  // nonzeros per slice buffer
+    const int tid = threadIdx.x;
+    int32_t c[KP];    // columns of the slice being processed (then of the next)
+    double a[KP];     // its values
+    int32_t rp = 0;   // its row end for this thread
+    bool have = false;  // c / a / rp hold the loads of slice s
+    int buf = 0;
+    for (int32_t s = s0; s < s1; ++s) {
+        const int32_t rb = sl.srow[s], re = sl.srow[s + 1];
+        const int32_t nb = sl.snz[s], ne = sl.snz[s + 1];
+        const int32_t nz = ne - nb;
+        if (nz > E) {  // a single long row: done after this loop
+            have = false;
+            continue;
+        }
+        if (!have && nz > 0) {
+            load_cols<V, RC, KP>(m, R, nb, nz, c);
+            load_vals<V, RC, KP>(m, R, nb, nz, a);
+            rp = load_row_end(m, nb, rb, re);
+        }
+        double xv[KP];
+        if (nz > 0) {
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                const int q = tid + j * kBlock;
+                const int rr = q - (RC ? q / RC : q / R) * R;
+                xv[j] = io.in[(size_t)c[j] * R + rr];
+            }
+        }
+        const int32_t myrp = nz > 0 ? rp : nb;
+        // issue the next slice's loads before this slice's products are formed
+        double a2[KP];
+        have = false;
+        if (s + 1 < s1) {
+            const int32_t rb2 = sl.srow[s + 1], re2 = sl.srow[s + 2];
+            const int32_t nb2 = sl.snz[s + 1], nz2 = sl.snz[s + 2] - nb2;
+            if (nz2 > 0 && nz2 <= E) {
+                load_cols<V, RC, KP>(m, R, nb2, nz2, c);
+                load_vals<V, RC, KP>(m, R, nb2, nz2, a2);
+                rp = load_row_end(m, nb2, rb2, re2);
+                have = true;
+            }
+        }
+        double *prod = sm.prod[buf];
+        int32_t *srp = sm.srp[buf];
+        if (nz > 0) {
+#pragma unroll
+            for (int j = 0; j < KP; ++j) prod[tid + j * kBlock] = a[j] * xv[j];
+        }
+        if (have) {
+#pragma unroll
+            for (int j = 0; j < KP; ++j) a[j] = a2[j];
+        }
+        srp[tid + 1] = myrp - nb;
+        if (tid == 0) srp[0] = 0;
+        __syncthreads();
+        const int32_t cnt = re - rb;
+        const int npairs = cnt * R;
+        for (int q = tid; q < npairs; q += kBlock) {
+            const int li = RC ? q / RC : q / R;
+            const int rr = q - li * R;
+            const int32_t row = rb + li;
+            const double sum = ordered_sum(prod, R, rr, srp[li], srp[li + 1]);
+            const int32_t o = m.out_row ? m.out_row[row] : row;
+            const size_t idx = (size_t)o * R + rr;
+            store_out<WT>(io.out + idx, epilogue(io, sum, idx));
+        }
+        buf ^= 1;
+    }
+    __syncthreads();
+    // rows longer than a buffer, kept out of the pipelined loop (registers)
+    for (int32_t s = s0; s < s1; ++s) {
+        const int32_t nb = sl.snz[s], ne = sl.snz[s + 1];
+        if (ne - nb > E) long_row<V, RC, KP, WT>(m, io, R, sl.srow[s], nb, ne, sm);
     }
 }
 
-// ------------------------------------------------------------------ baseline
-
-template <typename V, int RC>
-__global__ __launch_bounds__(kBlock) void spmv_power_kernel(DevMatrix m, PowerIO io, int32_t R,
-                                                           const int32_t *block_ptr) {
-    __shared__ double prod[kSlice];
-    __shared__ int32_t srp[kBlock + 1];
-    __shared__ int32_t wcnt[kWavesPerBlock];
-    const int32_t r0 = block_ptr[blockIdx.x], r1 = block_ptr[blockIdx.x + 1];
-    stream_rows<V, RC>(m, io, R, r0, r1, prod, srp, wcnt);
-}
-
-// ------------------------------------------------------------------ level-blocked
-
-// One diagonal of the STEPS schedule: workgroup b computes task tasks[b] =
-// (chunk c, power k).  All tasks of a diagonal are independent; the previous
-// diagonals' results are visible because they ran in earlier launches.
-template <typename V, int RC>
-__global__ __launch_bounds__(kBlock) void step_kernel(DevMatrix m, const int32_t *chunk_ptr,
-                                                     const int32_t *tasks, SegArgs a, Coefs cf) {
-    __shared__ double prod[kSlice];
-    __shared__ int32_t srp[kBlock + 1];
-    __shared__ int32_t wcnt[kWavesPerBlock];
-    const int32_t c = tasks[2 * blockIdx.x];
-    const int32_t k = tasks[2 * blockIdx.x + 1];
-    const size_t stride = (size_t)m.n * a.R;
+__device__ __forceinline__ PowerIO power_io(const SegArgs &a, const Coefs &cf, int32_t k,
+                                            int32_t n) {
+    const size_t stride = (size_t)n * a.R;
     PowerIO io;
     io.in = (k == 1) ? a.in0 : a.Y + (size_t)(k - 2) * stride;
     io.prev = (k == 1) ? a.inm1 : (k == 2 ? a.in0 : a.Y + (size_t)(k - 3) * stride);
@@ -204,7 +256,36 @@ __global__ __launch_bounds__(kBlock) void step_kernel(DevMatrix m, const int32_t
     io.alpha = cf.alpha[k - 1];
     io.beta = cf.beta[k - 1];
     io.gamma = cf.gamma[k - 1];
-    stream_rows<V, RC>(m, io, a.R, chunk_ptr[c], chunk_ptr[c + 1], prod, srp, wcnt);
+    return io;
+}
+
+// ------------------------------------------------------------------ baseline
+
+// One power: workgroup b walks slices [b*per, min((b+1)*per, n_slices)).
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, 2) void spmv_power_kernel(DevMatrix m, PowerIO io, int32_t R,
+                                                           DevSlices sl, int32_t n_slices,
+                                                           int32_t per) {
+    __shared__ RowSmem<kSpmvKP> sm;
+    const int32_t s0 = blockIdx.x * per;
+    const int32_t s1 = min(n_slices, s0 + per);
+    run_slices<V, RC, kSpmvKP, false>(m, io, R, sl, s0, s1, sm);
+}
+
+// ------------------------------------------------------------------ level-blocked
+
+// One diagonal of the STEPS schedule: workgroup b computes task tasks[b] =
+// (chunk c, power k).  All tasks of a diagonal are independent; the previous
+// diagonals' results are visible because they ran in earlier launches.
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, 4) void step_kernel(DevMatrix m, DevSlices sl,
+                                                     const int32_t *chunk_sptr,
+                                                     const int32_t *tasks, SegArgs a, Coefs cf) {
+    __shared__ RowSmem<kTaskKP> sm;
+    const int32_t c = tasks[2 * blockIdx.x];
+    const int32_t k = tasks[2 * blockIdx.x + 1];
+    run_slices<V, RC, kTaskKP, false>(m, power_io(a, cf, k, m.n), a.R, sl, chunk_sptr[c], chunk_sptr[c + 1],
+                               sm);
 }
 
 struct LBParams {
@@ -217,21 +298,19 @@ struct LBParams {
 
 // Persistent kernel: workgroups take tasks (chunk c, power k) in schedule
 // order from a shared ticket counter.  Before computing, a task waits until
-// every chunk in [dep_lo[c], dep_hi[c]] has completed power k-1; after
-// computing, it publishes done[c] = k.  Dependencies always carry smaller
+// every chunk in [dep_lo[c], dep_hi[c]] has completed power k-1 and then
+// invalidates its caches (acquire); it computes with write-through stores and
+// publishes done[c] = k once they have completed.  Dependencies always carry smaller
 // tickets and a workgroup holds one ticket at a time, so the smallest
 // unfinished ticket can always proceed; every wait is also bounded by
 // spin_limit, after which the run is flagged as failed and all workgroups
 // leave.
 template <typename V, int RC>
-__global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
-    __shared__ double prod[kSlice];
-    __shared__ int32_t srp[kBlock + 1];
-    __shared__ int32_t wcnt[kWavesPerBlock];
+__global__ __launch_bounds__(kBlock, 4) void lb_kernel(LBParams P, Coefs cf) {
+    __shared__ RowSmem<kTaskKP> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
-    const size_t stride = (size_t)P.m.n * P.a.R;
     if (tid == 0)
         s_ticket = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
@@ -274,25 +353,15 @@ __global__ __launch_bounds__(kBlock) void lb_kernel(LBParams P, Coefs cf) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
-        // y_k from y_{k-1} (and y_{k-2} for the recurrence); y_0 = in0, y_{-1} = inm1
-        PowerIO io;
-        io.in = (k == 1) ? P.a.in0 : P.a.Y + (size_t)(k - 2) * stride;
-        io.prev = (k == 1) ? P.a.inm1 : (k == 2 ? P.a.in0 : P.a.Y + (size_t)(k - 3) * stride);
-        io.out = P.a.Y + (size_t)(k - 1) * stride;
-        io.recur = P.a.recur;
-        io.alpha = cf.alpha[k - 1];
-        io.beta = cf.beta[k - 1];
-        io.gamma = cf.gamma[k - 1];
-        stream_rows<V, RC>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], prod, srp, wcnt);
-        // Every wave's stores have reached the L2 (vmcnt = 0) before the
-        // barrier; the release store below then writes the L2 back for the
-        // other XCDs and publishes the chunk, and the next ticket is taken.
+        run_slices<V, RC, kTaskKP, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+                                   P.s.chunk_sptr[c + 1], sm);
+        // The results were stored write-through; every wave waits until its
+        // stores have completed (vmcnt = 0) before the barrier, so the chunk
+        // is visible device-wide when the flag below is published and the
+        // next ticket is taken.  No L2 write-back is needed.
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters untouched
         __syncthreads();
         if (tid == 0) {
-            // write the L2 back, wait for the write-back, then publish
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __builtin_amdgcn_s_waitcnt(0x0F70);
             __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_ticket = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -320,22 +389,17 @@ struct XcdParams {
 // Persistent kernel of the XCD schedule.  Queue q holds the tasks of the
 // chunks owned by XCD q, in global dependency order; a workgroup serves the
 // queue of the XCD it runs on (read from the hardware, so the binding holds
-// whatever the dispatcher does).  Dependencies are exact chunk lists.  After
-// a task, the L2 is written back only when some consumer of the chunk is
-// owned by another XCD: consumers on the same XCD share its L2 and only need
-// their L1 invalidated (the acquire).  Deadlock freedom: the earliest
+// whatever the dispatcher does).  Dependencies are exact chunk lists;
+// results are published as in lb_kernel.  Deadlock freedom: the earliest
 // unfinished task in the global order is always held by a workgroup of its
 // queue (all earlier tasks of that queue are done), and its dependencies are
 // earlier still, so it can run; waits are bounded by spin_limit in any case.
 template <typename V, int RC>
-__global__ __launch_bounds__(kBlock) void xcd_kernel(XcdParams P, Coefs cf) {
-    __shared__ double prod[kSlice];
-    __shared__ int32_t srp[kBlock + 1];
-    __shared__ int32_t wcnt[kWavesPerBlock];
+__global__ __launch_bounds__(kBlock, 4) void xcd_kernel(XcdParams P, Coefs cf) {
+    __shared__ RowSmem<kTaskKP> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
-    const size_t stride = (size_t)P.m.n * P.a.R;
     const int q = P.s.n_queues == 1 ? 0 : __builtin_amdgcn_readfirstlane(xcc_id());
     if (q >= P.s.n_queues) return;  // uniform: no queue for this XCD
     const int32_t q0 = P.s.qptr[q];
@@ -373,24 +437,12 @@ __global__ __launch_bounds__(kBlock) void xcd_kernel(XcdParams P, Coefs cf) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (!ok) break;
-        PowerIO io;
-        io.in = (k == 1) ? P.a.in0 : P.a.Y + (size_t)(k - 2) * stride;
-        io.prev = (k == 1) ? P.a.inm1 : (k == 2 ? P.a.in0 : P.a.Y + (size_t)(k - 3) * stride);
-        io.out = P.a.Y + (size_t)(k - 1) * stride;
-        io.recur = P.a.recur;
-        io.alpha = cf.alpha[k - 1];
-        io.beta = cf.beta[k - 1];
-        io.gamma = cf.gamma[k - 1];
-        stream_rows<V, RC>(P.m, io, P.a.R, P.s.chunk_ptr[c], P.s.chunk_ptr[c + 1], prod, srp, wcnt);
-        // every wave's stores have reached this XCD's L2 before the barrier
+        run_slices<V, RC, kTaskKP, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+                                   P.s.chunk_sptr[c + 1], sm);
+        // write-through results, completed (vmcnt = 0) before the barrier
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         if (tid == 0) {
-            if (P.s.remote_out[c]) {
-                // a consumer on another XCD: write this L2 back first
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __builtin_amdgcn_s_waitcnt(0x0F70);
-            }
             __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -451,9 +503,9 @@ __global__ __launch_bounds__(kBlock) void load_probe_kernel(const double2 *buf, 
 
 // ------------------------------------------------------------------ dispatch
 
-using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, const int32_t *);
+using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, DevSlices, int32_t, int32_t);
 using LbFn = void (*)(LBParams, Coefs);
-using StepFn = void (*)(DevMatrix, const int32_t *, const int32_t *, SegArgs, Coefs);
+using StepFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *, SegArgs, Coefs);
 using XcdFn = void (*)(XcdParams, Coefs);
 
 int r_index(int R) {
@@ -521,25 +573,26 @@ int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_spmv_power(const DevMatrix &m, const int32_t *block_ptr, int32_t n_blocks,
+int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_t per,
                       const double *in, const double *inm1, double *out, int32_t R, int recur,
                       double alpha, double beta, double gamma, void *stream) {
-    if (R < 1 || R > 16) return (int)hipErrorInvalidValue;
-    if (m.n == 0 || n_blocks == 0) return 0;
+    if (R < 1 || R > 16 || per < 1) return (int)hipErrorInvalidValue;
+    if (m.n == 0 || n_slices == 0) return 0;
     PowerIO io{in, inm1, out, alpha, beta, gamma, recur};
-    hipLaunchKernelGGL(spmv_fn(m.value_bits, R), dim3((unsigned)n_blocks), dim3(kBlock), 0,
-                       (hipStream_t)stream, m, io, R, block_ptr);
+    const int32_t grid = (n_slices + per - 1) / per;
+    hipLaunchKernelGGL(spmv_fn(m.value_bits, R), dim3((unsigned)grid), dim3(kBlock), 0,
+                       (hipStream_t)stream, m, io, R, sl, n_slices, per);
     return (int)hipGetLastError();
 }
 
-int launch_step(const DevMatrix &m, const int32_t *chunk_ptr, const int32_t *tasks,
+int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
                 int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream) {
     if (a.R < 1 || a.R > 16 || a.p < 1 || a.p > kMaxSegPowers) return (int)hipErrorInvalidValue;
     if (n_tasks <= 0) return 0;
     Coefs c{};
     if (cf) c = *cf;
     hipLaunchKernelGGL(step_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock), 0,
-                       (hipStream_t)stream, m, chunk_ptr, tasks, a, c);
+                       (hipStream_t)stream, m, sl, chunk_sptr, tasks, a, c);
     return (int)hipGetLastError();
 }
 

@@ -93,6 +93,27 @@ struct DevMatrix {
 
 constexpr int kMaxSegPowers = 64;   // powers per kernel launch
 
+// Slices: runs of consecutive rows whose nonzeros fit one LDS staging buffer
+// of KP*256 products (KP*256/R nonzeros for R right-hand sides), at most
+// kSliceRows rows; a row longer than a buffer is a slice of its own.
+constexpr int kSpmvKP = 16;   // products per thread and buffer, p x SpMV kernel
+constexpr int kTaskKP = 8;    // the same for the level-blocked kernels
+constexpr int kSliceRows = 256;
+inline int slice_nnz(int kp, int R) { return kp * 256 / R; }
+
+// Cuts rows [bounds.front(), bounds.back()) into slices of at most E
+// nonzeros; every entry of `bounds` (ascending row numbers) is also a slice
+// boundary.  srow / snz get n_slices + 1 row / nonzero offsets, bound_sptr
+// the slice index of every bound.
+void build_slices(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &bounds, int E,
+                  std::vector<int32_t> &srow, std::vector<int32_t> &snz,
+                  std::vector<int32_t> &bound_sptr);
+
+struct DevSlices {
+    const int32_t *srow;   // n_slices + 1 row offsets
+    const int32_t *snz;    // n_slices + 1 nonzero offsets (rowptr at srow)
+};
+
 struct Coefs {
     double alpha[kMaxSegPowers];
     double beta[kMaxSegPowers];
@@ -111,7 +132,8 @@ struct SegArgs {
 };
 
 struct DevSchedule {
-    const int32_t *chunk_ptr;
+    DevSlices sl;
+    const int32_t *chunk_sptr;   // n_chunks + 1 slice offsets
     const int32_t *dep_lo, *dep_hi;
     const int32_t *tasks;
     int32_t n_tasks, n_chunks;
@@ -126,7 +148,8 @@ struct DevWorkspace {
 };
 
 struct DevXcdSchedule {
-    const int32_t *chunk_ptr;
+    DevSlices sl;
+    const int32_t *chunk_sptr;
     const int32_t *dep_ptr, *dep_idx;
     const int32_t *remote_out;
     const int32_t *tasks;
@@ -139,11 +162,11 @@ int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);  // al
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
               void *stream);
-// One power over all rows; block_ptr[n_blocks+1] splits the rows among workgroups.
 // One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
-int launch_step(const DevMatrix &m, const int32_t *chunk_ptr, const int32_t *tasks,
+int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
                 int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream);
-int launch_spmv_power(const DevMatrix &m, const int32_t *block_ptr, int32_t n_blocks,
+// One power over all rows; workgroup b walks slices [b*per, (b+1)*per).
+int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_t per,
                       const double *in, const double *inm1, double *out, int32_t R, int recur,
                       double alpha, double beta, double gamma, void *stream);
 int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in, double *out,

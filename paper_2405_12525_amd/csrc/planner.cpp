@@ -330,6 +330,34 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
     return MPK_OK;
 }
 
+void build_slices(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &bounds, int E,
+                  std::vector<int32_t> &srow, std::vector<int32_t> &snz,
+                  std::vector<int32_t> &bound_sptr) {
+    srow.clear();
+    snz.clear();
+    bound_sptr.clear();
+    if (bounds.empty()) return;
+    srow.push_back(bounds[0]);
+    snz.push_back(rowptr[bounds[0]]);
+    bound_sptr.push_back(0);
+    for (size_t b = 0; b + 1 < bounds.size(); ++b) {
+        int64_t r = bounds[b];
+        const int64_t r1 = bounds[b + 1];
+        while (r < r1) {
+            // the most rows (at most kSliceRows, not past r1) whose nonzeros fit E
+            const int64_t lim = std::min<int64_t>(r + kSliceRows, r1);
+            int64_t e = std::upper_bound(rowptr.begin() + r + 1, rowptr.begin() + lim + 1,
+                                         (int64_t)rowptr[r] + E) -
+                        rowptr.begin() - 1;
+            if (e <= r) e = r + 1;  // one row longer than a buffer
+            srow.push_back((int32_t)e);
+            snz.push_back(rowptr[e]);
+            r = e;
+        }
+        bound_sptr.push_back((int32_t)srow.size() - 1);
+    }
+}
+
 mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
                             int default_workgroups, Schedule &s, std::string &err) {
     if (tune.schedule == MPK_SCHED_XCD && sh.n > 0) {

@@ -1,0 +1,110 @@
+"""GPU tests of the runtime around the kernels: the autotuner and captured
+HIP graphs (every replay checked against the eager run and the oracle)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mpk = pytest.importorskip("paper_2405_12525_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_autotune_choice_is_exact_and_cached():
+    A = w.stencil_3d27(32)
+    x = w.uniform_vectors(A.n, 2, 11)
+    xd = dev(x)
+    P = mpk.Plan(A)
+    t = P.autotune(xd, 5, reps=2, force=True)
+    assert t["schedule"] in ("steps", "wave", "xcd", "powers") and t["ms"] > 0
+    Y = P.run(xd, 5)
+    P.sync()
+    assert np.array_equal(host(Y), oracle.powers(A, x, 5))
+    # a second plan of the same matrix finds the cached choice without timing
+    Q = mpk.Plan(A)
+    t0 = time.perf_counter()
+    t2 = Q.autotune(xd, 5)
+    assert time.perf_counter() - t0 < 0.5
+    assert {k: t2[k] for k in ("schedule", "cache_bytes", "chunk_nnz")} == \
+        {k: t[k] for k in ("schedule", "cache_bytes", "chunk_nnz")}
+    P.close()
+    Q.close()
+
+
+def test_autotune_recurrence_fp32():
+    A = w.anderson_3d(16)
+    x = w.random_sign_unit_vectors(A.n, 8, 3)
+    xd = dev(x)
+    P = mpk.Plan(A, value_bits=32)
+    P.autotune(xd, 6, reps=1, recur=True, force=True)
+    al, be, ga = mpk.chebyshev_coefficients(6)
+    Y = P.run_recur(xd, al, be, ga)
+    P.sync()
+    ref = oracle.recur(A, x, al, be, ga, value_bits=32)
+    assert np.array_equal(host(Y), ref)
+    P.close()
+
+
+@pytest.mark.parametrize("sched", ["steps", "wave", "xcd"])
+def test_graph_replays_match_eager(sched):
+    A = w.stencil_3d27(24)
+    x = w.uniform_vectors(A.n, 1, 21)
+    xd = dev(x)
+    P = mpk.Plan(A)
+    P.tune(schedule=sched, chunk_nnz=2000)
+    eager = host(P.run(xd, 6))
+    assert np.array_equal(eager, oracle.powers(A, x, 6))
+    Yg = torch.empty((6, A.n, 1), dtype=torch.float64, device="cuda")
+    G = P.capture(xd, 6, Yg)
+    s = torch.cuda.Stream()
+    for i in range(4):
+        Yg.fill_(np.nan)
+        torch.cuda.synchronize()
+        G.launch(stream=s)
+        s.synchronize()
+        assert np.array_equal(host(Yg), eager), f"replay {i}"
+        # unrelated eager work on the same plan between replays
+        other = P.run(dev(w.uniform_vectors(A.n, 1, 100 + i)), 3)
+        P.sync()
+        del other
+    G.close()
+    P.sync()
+    P.close()
+
+
+def test_graph_recurrence_replays():
+    A = w.anderson_3d(12)
+    x = w.random_sign_unit_vectors(A.n, 4, 8)
+    xd = dev(x)
+    P = mpk.Plan(A)
+    al, be, ga = mpk.chebyshev_coefficients(8)
+    ref = oracle.recur(A, x, al, be, ga)
+    Yg = torch.empty((8, A.n, 4), dtype=torch.float64, device="cuda")
+    G = P.capture(xd, 8, Yg, al, be, ga)
+    for _ in range(3):
+        Yg.zero_()
+        G.launch()
+        assert np.array_equal(host(Yg), ref)
+    G.close()
+    P.close()

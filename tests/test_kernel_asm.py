@@ -7,9 +7,9 @@ review alone cannot guarantee:
   prove the loop control uniform it may restructure the loop so that some
   lanes exit early (an exec-mask exit), which breaks the barriers inside it
   and can stall the workgroup forever;
-* publishing a chunk must write the L2 back and wait for that write-back
-  before the flag store (release at agent scope), and a consumer must
-  invalidate before reading (acquire).
+* results must be stored write-through (agent scope) and have completed
+  before the flag store publishes them, and a consumer must invalidate
+  before reading (acquire).
 
 These tests compile kernels.hip to AMD assembly (CPU only) and check both.
 """
@@ -115,18 +115,28 @@ def test_baseline_row_loop_has_uniform_exit(asm):
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
 
 
-def test_release_waits_for_writeback_and_acquire_invalidates(asm):
-    for sym, lines in kernels(asm, "lb_kernel").items():
-        body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
-        i = next(j for j, l in enumerate(body) if l.startswith("buffer_wbl2 sc1"))
-        assert body[i + 1].startswith("s_waitcnt vmcnt(0)"), (sym, body[i:i + 3])
-        assert re.match(r"global_store_dword .* sc1", body[i + 2]), (sym, body[i:i + 3])
-        assert any(l.startswith("buffer_inv sc1") for l in body), sym
+def _publish_ok(body):
+    """Every flag store (a dword store at agent scope followed by the ticket
+    atomic) is preceded by an s_waitcnt vmcnt(0) and a barrier, with no vector
+    memory instruction in between."""
+    flags = [j for j, l in enumerate(body) if re.match(r"global_store_dword .* sc1", l)
+             and any(x.startswith("global_atomic_add") for x in body[j + 1:j + 12])]
+    assert flags
+    for f in flags:
+        seg = body[:f]
+        b = max(j for j, l in enumerate(seg) if l.startswith("s_barrier"))
+        w = max(j for j, l in enumerate(seg[:b]) if l.startswith("s_waitcnt") and "vmcnt(0)" in l)
+        between = [l for l in seg[w + 1:f] if l.startswith(("global_", "buffer_", "flat_"))]
+        assert not between, between
 
 
-def test_xcd_writeback_is_waited_for_and_acquire_invalidates(asm):
-    for sym, lines in kernels(asm, "xcd_kernel").items():
+@pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel"])
+def test_results_write_through_and_publish_after_completion(asm, name):
+    for sym, lines in kernels(asm, name).items():
         body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
-        i = next(j for j, l in enumerate(body) if l.startswith("buffer_wbl2 sc1"))
-        assert body[i + 1].startswith("s_waitcnt vmcnt(0)"), (sym, body[i:i + 3])
+        # results: 64-bit stores at agent scope (sc1), no L2 write-back anywhere
+        assert any(re.match(r"global_store_dwordx2 .* sc1", l) for l in body), sym
+        assert not any(re.match(r"global_store_dwordx2 ", l) and " sc1" not in l for l in body), sym
+        assert not any(l.startswith("buffer_wbl2") for l in body), sym
         assert any(l.startswith("buffer_inv sc1") for l in body), sym
+        _publish_ok(body)
