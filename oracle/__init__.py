@@ -110,6 +110,8 @@ def recur(A, x: np.ndarray, alpha, beta, gamma, value_bits: int = 64,
     """Three-term recurrence y_{j+1} = alpha_j A y_j + beta_j y_j + gamma_j y_{j-1}.
 
     j = 0..p-1 with y_0 = x and no gamma term at j = 0; returns (p, n, R).
+    A coefficient that is exactly zero omits its term (the Chebyshev form has
+    no beta term at all).
     The Chebyshev recurrence of Eq. (anderson_spmv) is alpha = (1, 2, 2, ...),
     beta = 0, gamma = (0, -1, -1, ...).
     """

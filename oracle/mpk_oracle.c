@@ -94,7 +94,10 @@ int oracle_powers(int64_t n, const int32_t *rowptr, const int32_t *col, const vo
 }
 
 /* Recurrence: y_{j+1} = alpha_j (A y_j) + beta_j y_j + gamma_j y_{j-1}, j = 0..p-1,
- * with y_0 = x; the gamma term is absent for j = 0. */
+ * with y_0 = x; the gamma term is absent for j = 0.  A coefficient that is
+ * exactly zero omits its term: the Chebyshev recurrence of Sec. "Application:
+ * Chebyshev Time Propagation" has no beta term, and the general form reduces
+ * to it term by term. */
 int oracle_recur(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                  int value_bits, int R, const double *x, int p, const double *alpha,
                  const double *beta, const double *gamma, double *Y, int nthreads) {
@@ -115,8 +118,8 @@ int oracle_recur(int64_t n, const int32_t *rowptr, const int32_t *col, const voi
 #pragma omp parallel for schedule(static)
         for (m = 0; m < stride; ++m) {
             double v = alpha[j] * t[m];
-            v += beta[j] * yj[m];
-            if (yjm1) v += gamma[j] * yjm1[m];
+            if (beta[j] != 0.0) v += beta[j] * yj[m];
+            if (yjm1 && gamma[j] != 0.0) v += gamma[j] * yjm1[m];
             out[m] = v;
         }
     }

@@ -45,12 +45,16 @@ struct PowerIO {
 };
 
 // y = alpha*s + beta*y_{k-1} + gamma*y_{k-2} evaluated left to right, or s.
+// A coefficient that is exactly zero omits its term (and its vector read):
+// the Chebyshev recurrence has no beta term.
 __device__ __forceinline__ double epilogue(const PowerIO &io, double s, size_t idx) {
     if (!io.recur) return s;
     double v = io.alpha * s;
-    const double b = io.beta * io.in[idx];
-    v = v + b;
-    if (io.prev) {
+    if (io.beta != 0.0) {
+        const double b = io.beta * io.in[idx];
+        v = v + b;
+    }
+    if (io.prev && io.gamma != 0.0) {
         const double g = io.gamma * io.prev[idx];
         v = v + g;
     }

@@ -1,0 +1,213 @@
+"""Continuous-batching request loop over device-resident plans.
+
+Requests ask for the powers (or a Chebyshev recurrence) of one of the
+matrices whose plans the server holds on the device.  They arrive over time;
+the loop admits them as stream slots and memory free up:
+
+* requests for the same matrix and kind that are waiting together form one
+  batch: their right-hand sides are stacked (at most 16 columns) and the
+  batch runs p = max p_i powers.  Every column is computed exactly as if it
+  ran alone (the kernels' per-column arithmetic does not depend on the
+  right-hand-side count) and powers are prefix-consistent, so request i takes
+  the first p_i powers of its own columns;
+* batches for different matrices run concurrently on separate HIP streams;
+* a batch is admitted only while the device memory held by running batches
+  (stacked inputs plus outputs) stays within the budget.
+
+All arithmetic runs in the library's kernels; this module only schedules.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import Plan, chebyshev_coefficients, flops, _torch
+
+MAX_RHS = 16
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    arrival: float            # seconds from the start of serving
+    matrix: int               # index into the server's plans
+    p: int
+    x: object                 # device tensor (n, R), float64
+    kind: str = "powers"      # "powers" or "chebyshev"
+
+    @property
+    def R(self) -> int:
+        return 1 if self.x.dim() == 1 else int(self.x.shape[1])
+
+
+@dataclasses.dataclass
+class Result:
+    id: int
+    Y: object                 # device tensor view (p, n, R)
+    arrival: float
+    start: float              # batch launch time
+    done: float               # completion observed by the loop
+    batch_size: int
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def batch_bytes(n: int, p: int, R: int) -> int:
+    """Device bytes a batch holds while running: stacked x plus Y."""
+    return 8 * n * R * (p + 1)
+
+
+def form_batch(queue: collections.deque, max_rhs: int = MAX_RHS) -> List[Request]:
+    """Take the head request and then later ones of the same kind, in arrival
+    order, while the stacked right-hand sides fit max_rhs."""
+    head = queue[0]
+    batch, total = [], 0
+    keep = collections.deque()
+    while queue:
+        r = queue.popleft()
+        if r.kind == head.kind and total + r.R <= max_rhs:
+            batch.append(r)
+            total += r.R
+        else:
+            keep.append(r)
+    queue.extend(keep)
+    return batch
+
+
+class Server:
+    """Holds plans on the device and serves request streams.
+
+    plans: one Plan per matrix (device plans, already tuned as wished).
+    n_streams: batches that may run at once.
+    mem_budget: bytes of batch memory (inputs plus outputs) in flight.
+    """
+
+    def __init__(self, plans: Sequence[Plan], n_streams: int = 4,
+                 mem_budget: Optional[int] = None, max_rhs: int = MAX_RHS):
+        torch = _torch()
+        self.plans = list(plans)
+        self.max_rhs = int(max_rhs)
+        if not 1 <= self.max_rhs <= MAX_RHS:
+            raise ValueError("max_rhs must be in [1, 16]")
+        if mem_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            mem_budget = int(free * 0.6)
+        self.mem_budget = int(mem_budget)
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, int(n_streams)))]
+
+    # one batch on one stream
+    def _launch(self, batch: List[Request], stream):
+        torch = _torch()
+        P = self.plans[batch[0].matrix]
+        p = max(r.p for r in batch)
+        with torch.cuda.stream(stream):
+            xs = [r.x.reshape(P.n, -1) for r in batch]
+            X = xs[0] if len(xs) == 1 else torch.cat(xs, dim=1).contiguous()
+            if batch[0].kind == "chebyshev":
+                Y = P.run_recur(X, *chebyshev_coefficients(p), stream=stream)
+            else:
+                Y = P.run(X, p, stream=stream)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return Y, ev, p
+
+    def serve(self, requests: Sequence[Request], realtime: bool = True,
+              keep: bool = True) -> List[Result]:
+        """Serve the requests (sorted by arrival); returns results by id.
+
+        realtime=True replays the arrival times against the wall clock;
+        realtime=False makes every request available at once (saturation).
+        keep=False drops each output once its batch has finished (Result.Y is
+        None): for measuring streams whose outputs would not fit at once."""
+        torch = _torch()
+        for r in requests:
+            if not 0 <= r.matrix < len(self.plans):
+                raise ValueError(f"request {r.id}: no matrix {r.matrix}")
+            if r.R > self.max_rhs or r.p < 1:
+                raise ValueError(f"request {r.id}: bad p or R")
+            need = batch_bytes(self.plans[r.matrix].n, r.p, r.R)
+            if need > self.mem_budget:
+                raise ValueError(f"request {r.id} needs {need} bytes, above the budget")
+        order = sorted(requests, key=lambda r: r.arrival)
+        pending: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+        free_streams = list(range(len(self.streams)))
+        running = []   # (stream index, event, batch, Y, p, bytes, start)
+        results: Dict[int, Result] = {}
+        in_use = 0
+        i = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while len(results) < len(order):
+            now = time.perf_counter() - t0
+            while i < len(order) and (not realtime or order[i].arrival <= now):
+                pending[order[i].matrix].append(order[i])
+                i += 1
+            # completions
+            still = []
+            for item in running:
+                si, ev, batch, Y, p, nbytes, start = item
+                if ev.query():
+                    done = time.perf_counter() - t0
+                    c0 = 0
+                    for r in batch:
+                        view = Y[:r.p, :, c0:c0 + r.R] if keep else None
+                        c0 += r.R
+                        arr = r.arrival if realtime else 0.0
+                        results[r.id] = Result(r.id, view, arr, start, done, len(batch))
+                    in_use -= nbytes
+                    free_streams.append(si)
+                else:
+                    still.append(item)
+            running = still
+            # dispatch: oldest waiting request first, while slots and memory allow
+            while free_streams:
+                heads = [(q[0].arrival, m) for m, q in pending.items() if q]
+                if not heads:
+                    break
+                _, m = min(heads)
+                q = pending[m]
+                batch = form_batch(q, self.max_rhs)
+                p = max(r.p for r in batch)
+                nbytes = batch_bytes(self.plans[m].n, p, sum(r.R for r in batch))
+                if in_use + nbytes > self.mem_budget and running:
+                    for r in reversed(batch):
+                        q.appendleft(r)
+                    break
+                si = free_streams.pop()
+                start = time.perf_counter() - t0
+                Y, ev, p = self._launch(batch, self.streams[si])
+                in_use += nbytes
+                running.append((si, ev, batch, Y, p, nbytes, start))
+            # idle until the next arrival or a completion can be observed
+            now = time.perf_counter() - t0
+            if not (i < len(order) and order[i].arrival <= now):
+                wait = 20e-6 if running else (order[i].arrival - now if i < len(order) else 0.0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+        for P in self.plans:
+            P.sync()
+        return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
+
+
+def summarize(results: Sequence[Result], requests: Sequence[Request], plans: Sequence[Plan]) -> dict:
+    """Latency percentiles, throughput and delivered Gflop/s of a served stream."""
+    lat = np.array([r.latency for r in results])
+    by_id = {r.id: r for r in requests}
+    fl = 0.0
+    for res in results:
+        rq = by_id[res.id]
+        P = plans[rq.matrix]
+        fl += flops(P.nnz, P.n, rq.p, rq.R, recur=rq.kind == "chebyshev")
+    first = min(r.arrival for r in results)
+    last = max(r.done for r in results)
+    span = max(last - first, 1e-9)
+    return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "throughput_rps": len(results) / span, "gflops": fl / span / 1e9,
+            "mean_batch": float(np.mean([r.batch_size for r in results])), "span_s": span}

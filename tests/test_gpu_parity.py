@@ -292,6 +292,17 @@ def test_concurrent_streams_share_a_plan(sched):
         assert np.array_equal(host(Y), oracle.powers(A, x, 5))
 
 
+def test_zero_coefficient_omits_its_term():
+    A = w.CSR(2, np.array([0, 0, 1], np.int32), np.array([1], np.int32), np.array([2.0]), "t")
+    x = np.array([[np.inf], [1.0]])
+    P = mpk.Plan(A)
+    for beta in (0.0, 1.0):
+        coefs = (np.array([3.0, 2.0]), np.array([beta, 0.0]), np.array([0.0, -1.0]))
+        ref = oracle.recur(A, x, *coefs)
+        Y, B = run_both(P, x, 2, recur=coefs)
+        assert np.array_equal(Y, ref, equal_nan=True) and np.array_equal(B, ref, equal_nan=True)
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 @pytest.mark.slow

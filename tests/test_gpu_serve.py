@@ -1,0 +1,61 @@
+"""GPU: continuous batching returns, for every request, exactly what the
+request gives when run alone (bit for bit), and reports sane latencies."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mpk = pytest.importorskip("paper_2405_12525_amd")
+from paper_2405_12525_amd import serve  # noqa: E402
+
+
+def device_x(n, R, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return (torch.rand((n, R), generator=g, device="cuda", dtype=torch.float64) * 2 - 1)
+
+
+@pytest.mark.parametrize("realtime", [False, True])
+def test_mix_equals_alone(realtime):
+    torch.cuda.set_device(0)
+    mats = [w.stencil_2d5(40), w.stencil_3d27(14), w.anderson_3d(10)]
+    plans = [mpk.Plan(A) for A in mats]
+    plans[1].tune(schedule="wave", chunk_nnz=3000)
+    plans[2].tune(schedule="xcd", chunk_nnz=2000)
+    specs = w.serving_requests(60, rate_per_s=4000.0, seed=77, pool_size=3, p_range=(1, 9),
+                               rhs_choices=(1, 2, 3, 4, 8, 16))
+    reqs = []
+    for s in specs:
+        kind = "chebyshev" if s["id"] % 5 == 0 else "powers"
+        reqs.append(serve.Request(id=s["id"], arrival=s["t"], matrix=s["matrix"], p=s["p"],
+                                  x=device_x(mats[s["matrix"]].n, s["R"], s["x_seed"]),
+                                  kind=kind))
+    srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20)
+    res = srv.serve(reqs, realtime=realtime)
+    assert [r.id for r in res] == [q.id for q in reqs]
+    assert max(r.batch_size for r in res) > 1          # batching happened
+    for q, r in zip(reqs, res):
+        P = plans[q.matrix]
+        if q.kind == "chebyshev":
+            alone = P.run_recur(q.x, *mpk.chebyshev_coefficients(q.p))
+        else:
+            alone = P.run(q.x, q.p)
+        torch.cuda.synchronize()
+        assert r.Y.shape == alone.shape
+        assert torch.equal(r.Y, alone), q.id
+        assert r.done >= r.start >= 0 and r.latency >= 0
+    # and against the oracle for a few
+    for q, r in list(zip(reqs, res))[:6]:
+        x = q.x.cpu().numpy()
+        A = mats[q.matrix]
+        ref = (oracle.recur(A, x, *mpk.chebyshev_coefficients(q.p)) if q.kind == "chebyshev"
+               else oracle.powers(A, x, q.p))
+        assert np.array_equal(r.Y.cpu().numpy(), ref)
+    st = serve.summarize(res, reqs, plans)
+    assert st["requests"] == 60 and st["p99_ms"] >= st["p50_ms"] > 0
+    for P in plans:
+        P.close()

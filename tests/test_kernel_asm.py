@@ -115,19 +115,42 @@ def test_baseline_row_loop_has_uniform_exit(asm):
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
 
 
-def _publish_ok(body):
-    """Every flag store (a dword store at agent scope followed by the ticket
-    atomic) is preceded by an s_waitcnt vmcnt(0) and a barrier, with no vector
-    memory instruction in between."""
-    flags = [j for j, l in enumerate(body) if re.match(r"global_store_dword .* sc1", l)
-             and any(x.startswith("global_atomic_add") for x in body[j + 1:j + 12])]
+def _instructions_with_loop_flag(lines):
+    """(instruction, inside a loop) for the kernel's instructions in order."""
+    out, in_loop = [], False
+    for line in lines:
+        if re.match(r"^(\.LBB\S+|; %bb\.\d+):", line):
+            in_loop = "in Loop:" in line
+            continue
+        if "Loop Header:" in line:
+            in_loop = True
+            continue
+        t = line.strip()
+        if t and not t.startswith(";") and not t.startswith("."):
+            out.append((t, in_loop))
+    return out
+
+
+def _publish_ok(lines):
+    """Every flag store inside the task loop (a dword store at agent scope)
+    follows a barrier that is entered only through an s_waitcnt vmcnt(0)
+    (the line just before the barrier, with no label in between), and no
+    vector memory instruction lies between that barrier and the store."""
+    ins = _instructions_with_loop_flag(lines)
+    flags = [t for t, loop in ins if loop and re.match(r"global_store_dword .* sc1", t)]
     assert flags
-    for f in flags:
-        seg = body[:f]
-        b = max(j for j, l in enumerate(seg) if l.startswith("s_barrier"))
-        w = max(j for j, l in enumerate(seg[:b]) if l.startswith("s_waitcnt") and "vmcnt(0)" in l)
-        between = [l for l in seg[w + 1:f] if l.startswith(("global_", "buffer_", "flat_"))]
+    raw = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
+    n_checked = 0
+    for f, line in enumerate(raw):
+        if not (re.match(r"global_store_dword .* sc1", line) and line in flags):
+            continue
+        b = max(j for j in range(f) if raw[j].startswith("s_barrier"))
+        assert re.match(r"s_waitcnt .*vmcnt\(0\)", raw[b - 1]), raw[b - 3:b + 1]
+        between = [l for l in raw[b + 1:f] if l.startswith(("global_", "buffer_", "flat_"))
+                   or re.match(r"^\.LBB", l)]
         assert not between, between
+        n_checked += 1
+    assert n_checked >= 1
 
 
 @pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel"])
@@ -139,4 +162,4 @@ def test_results_write_through_and_publish_after_completion(asm, name):
         assert not any(re.match(r"global_store_dwordx2 ", l) and " sc1" not in l for l in body), sym
         assert not any(l.startswith("buffer_wbl2") for l in body), sym
         assert any(l.startswith("buffer_inv sc1") for l in body), sym
-        _publish_ok(body)
+        _publish_ok(lines)

@@ -230,3 +230,14 @@ def test_permute_csr_symmetric():
     B = oracle.permute_csr(A, perm)
     D, E = A.to_dense(), B.to_dense()
     assert np.array_equal(E, D[np.ix_(perm, perm)])
+
+
+def test_zero_coefficient_omits_its_term():
+    # row 0 is empty, so (A x)[0] = 0 exactly; x[0] = inf.  With beta = 0 the
+    # beta term is absent (finite result); with beta != 0 it is inf.
+    A = w.CSR(2, np.array([0, 0, 1], np.int32), np.array([1], np.int32), np.array([2.0]), "t")
+    x = np.array([[np.inf], [1.0]])
+    Y = oracle.recur(A, x, [3.0], [0.0], [0.0])
+    assert Y[0, 0, 0] == 0.0 and Y[0, 1, 0] == 6.0
+    Y = oracle.recur(A, x, [3.0], [1.0], [0.0])
+    assert np.isinf(Y[0, 0, 0]) and Y[0, 1, 0] == 7.0

@@ -1,0 +1,43 @@
+"""Host logic of the serving loop: batch formation and memory accounting."""
+import collections
+
+import pytest
+
+pytest.importorskip("paper_2405_12525_amd")
+from paper_2405_12525_amd import serve  # noqa: E402
+
+
+class FakeX:
+    def __init__(self, R):
+        self.shape = (10, R)
+
+    def dim(self):
+        return 2
+
+
+def req(i, R, kind="powers", p=4):
+    return serve.Request(id=i, arrival=float(i), matrix=0, p=p, x=FakeX(R), kind=kind)
+
+
+def test_batch_stacks_in_arrival_order_up_to_16_columns():
+    q = collections.deque([req(0, 8), req(1, 4), req(2, 8), req(3, 4), req(4, 1)])
+    b = serve.form_batch(q)
+    assert [r.id for r in b] == [0, 1, 3]          # 8 + 4 + 4 = 16; request 2 waits
+    assert [r.id for r in q] == [2, 4]             # the rest keeps its order
+    b = serve.form_batch(q)
+    assert [r.id for r in b] == [2, 4] and not q
+
+
+def test_batch_keeps_kinds_apart():
+    q = collections.deque([req(0, 1, "chebyshev"), req(1, 1), req(2, 2, "chebyshev")])
+    assert [r.id for r in serve.form_batch(q)] == [0, 2]
+    assert [r.id for r in serve.form_batch(q)] == [1]
+
+
+def test_batch_respects_a_smaller_cap():
+    q = collections.deque([req(0, 2), req(1, 2), req(2, 2)])
+    assert [r.id for r in serve.form_batch(q, max_rhs=4)] == [0, 1]
+
+
+def test_batch_bytes():
+    assert serve.batch_bytes(1000, 8, 4) == 8 * 1000 * 4 * 9
