@@ -85,7 +85,9 @@ def time_calls(fn, steps, warmup, torch, stream):
 
 
 def measured_traffic(kernel_key):
-    """HBM bytes per run from the committed counter summary, if it matches the source."""
+    """HBM bytes per run from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, scaled by what the same counters read for a 1 GiB
+    copy), if it was taken for the current kernel source and this tuning."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -176,6 +178,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving session")
+    ap.add_argument("--schedule", default=None,
+                    help="run this level-blocked schedule instead of autotuning (profiling)")
+    ap.add_argument("--chunk", type=int, default=16384, help="chunk nonzeros with --schedule")
+    ap.add_argument("--cache-mib", type=int, default=64, help="cache budget with --schedule")
+    ap.add_argument("--lag", type=int, default=0, help="wavefront lag with --schedule")
+    ap.add_argument("--reorder", default="bfs", choices=["bfs", "none"],
+                    help="level construction with --schedule")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 1 GiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding the kernel over "
@@ -188,6 +199,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": a.numel() * 8, "copies": 3}), flush=True)
+        return
     t0 = time.perf_counter()
     A, x, p, _ = w.config(WORKLOAD)
     R = x.shape[1]
@@ -199,7 +218,7 @@ def main():
 
     # p x SpMV baseline: best of BFS and original order
     base = {}
-    for ro in ("bfs", "none"):
+    for ro in (("bfs", "none") if args.schedule is None else (args.reorder,)):
         P = mpk.Plan(A, reorder=ro)
         base[ro] = time_calls(lambda: P.run_baseline(xd, p, B, stream=stream), args.steps,
                               args.warmup, torch, stream)
@@ -210,10 +229,14 @@ def main():
 
     # level-blocked run: the autotuner's choice in each order, the faster one reported
     lb = None
-    for ro in ("bfs", "none"):
+    for ro in (("bfs", "none") if args.schedule is None else (args.reorder,)):
         t0 = time.perf_counter()
         Q = mpk.Plan(A, reorder=ro)
-        tq = Q.autotune(xd, p, Y, reps=3, stream=stream)
+        if args.schedule is None:
+            tq = Q.autotune(xd, p, Y, reps=3, stream=stream)
+        else:
+            tq = Q.tune(schedule=args.schedule, chunk_nnz=args.chunk,
+                        cache_bytes=args.cache_mib << 20, lag=args.lag)
         r = time_calls(lambda: Q.run(xd, p, Y, stream=stream), args.steps, args.warmup, torch,
                        stream)
         Q.sync()
@@ -260,14 +283,16 @@ def main():
                    "chunk_nnz": tune["chunk_nnz"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("level_blocked"),
+                     "traffic": measured_traffic("level_blocked:{schedule}:{chunk_nnz}:{cm}:{lag}:{ro}"
+                                                 .format(cm=tune["cache_bytes"] >> 20, ro=reorder,
+                                                         **tune)),
                      "kernel": "level-blocked run (all launches of one mpk_run)",
                      "algorithmic_bytes": lb_bytes},
         "baseline_pxspmv": {"gflops": round(flop / (bmed * 1e-3) / 1e9, 2), "ms": round(bmed, 4),
                             "reorder": best_base, "algorithmic_bytes": trad_bytes,
                             "achieved_GBs": round(trad_bytes / (base[best_base]["mean_ms"] * 1e-3)
                                                   / 1e9, 1),
-                            "traffic": measured_traffic("pxspmv")},
+                            "traffic": measured_traffic("pxspmv:" + best_base)},
         "speedup_vs_pxspmv": round(bmed / lb["median_ms"], 3),
         "bit_identical_to_pxspmv": same,
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
