@@ -116,6 +116,9 @@ typedef struct {
     int workgroups;          /* persistent schedules: workgroups; 0 = fill the
                                 device                                          */
     int64_t spin_limit_us;   /* dependency-wait limit in microseconds, 0 = 2 s  */
+    int seg_powers;          /* powers blocked together per launch (1..64);
+                                p is run as ceil(p / seg_powers) segments that
+                                each read the matrix once; 0 = 64 (at most)    */
 } mpk_tune_t;
 
 typedef struct {

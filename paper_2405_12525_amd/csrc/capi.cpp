@@ -337,8 +337,9 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     const int64_t spin_ticks = limit_us * (int64_t)plan->wall_khz / 1000;
     const size_t stride = (size_t)plan->n * nrhs;
     const DevMatrix m = plan->matrix();
-    for (int base = 0; base < p; base += kMaxSegPowers) {
-        const int ps = std::min(kMaxSegPowers, p - base);
+    const int seg = plan->tune.seg_powers > 0 ? plan->tune.seg_powers : kMaxSegPowers;
+    for (int base = 0; base < p; base += seg) {
+        const int ps = std::min(seg, p - base);
         SchedEntry *se = nullptr;
         if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
         SegArgs a;
@@ -471,6 +472,7 @@ void mpk_tune_default(mpk_tune_t *t) {
     t->lag = 0;
     t->workgroups = 0;
     t->spin_limit_us = 0;
+    t->seg_powers = 0;
 }
 
 mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
@@ -594,6 +596,8 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
     if (t.schedule < MPK_SCHED_STEPS || t.schedule > MPK_SCHED_XCD) return fail(MPK_EINVAL, "bad schedule");
     if (t.cache_bytes <= 0 || !(t.cache_safety > 0.0) || t.cache_safety > 1.0)
         return fail(MPK_EINVAL, "cache_bytes must be > 0 and cache_safety in (0, 1]");
+    if (t.seg_powers < 0 || t.seg_powers > kMaxSegPowers)
+        return fail(MPK_EINVAL, "seg_powers must be in [0, 64]");
     if (t.chunk_nnz < 1 || t.lag < 0 || t.workgroups < 0 || t.spin_limit_us < 0)
         return fail(MPK_EINVAL, "negative tuning value");
     std::lock_guard<std::mutex> g(plan->mu);
@@ -895,8 +899,9 @@ mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs
         // everything a run allocates or uploads is prepared before the capture
         std::lock_guard<std::mutex> lk(plan->mu);
         const int wg_default = default_workgroups(plan, nrhs);
-        for (int base = 0; base < p; base += kMaxSegPowers) {
-            const int ps = std::min(kMaxSegPowers, p - base);
+        const int seg = plan->tune.seg_powers > 0 ? plan->tune.seg_powers : kMaxSegPowers;
+        for (int base = 0; base < p; base += seg) {
+            const int ps = std::min(seg, p - base);
             SchedEntry *se = nullptr;
             if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
             SliceSet *ss = nullptr;

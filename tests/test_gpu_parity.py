@@ -130,6 +130,8 @@ def test_ragged_multi_rhs(R):
                                   dict(schedule="powers"), dict(schedule="xcd"),
                                   dict(schedule="xcd", workgroups=5),
                                   dict(schedule="xcd", chunk_nnz=50, workgroups=64),
+                                  dict(schedule="wave", seg_powers=1), dict(seg_powers=3),
+                                  dict(schedule="xcd", seg_powers=2),
                                   dict(lag=1), dict(lag=5000), dict(chunk_nnz=50, workgroups=3),
                                   dict(cache_bytes=1 << 16)])
 def test_tuning_never_changes_a_bit(tune):
@@ -290,6 +292,18 @@ def test_concurrent_streams_share_a_plan(sched):
     P.sync()
     for x, Y in zip(xs, outs):
         assert np.array_equal(host(Y), oracle.powers(A, x, 5))
+
+
+@pytest.mark.parametrize("seg", [1, 2, 5])
+def test_segmented_recurrence_matches_oracle(seg):
+    A = w.anderson_3d(11)
+    x = w.random_sign_unit_vectors(A.n, 2, 9)
+    P = mpk.Plan(A, value_bits=32)
+    P.tune(schedule="wave", seg_powers=seg, chunk_nnz=700)
+    coefs = mpk.chebyshev_coefficients(7)
+    Y, B = run_both(P, x, 7, recur=coefs)
+    ref = oracle.recur(A, x, *coefs, value_bits=32)
+    assert np.array_equal(Y, ref) and np.array_equal(B, ref)
 
 
 def test_zero_coefficient_omits_its_term():
