@@ -164,6 +164,55 @@ __device__ void long_row(const DevMatrix &m, const PowerIO &io, int R, int32_t r
     __syncthreads();
 }
 
+// Rows [r0, r1) of one power with one thread per (row, right-hand side): the
+// thread sums its row in stored order from 0.0 (the same order as the
+// slices), the R threads of a row share each column / value load and read
+// the R entries of an input row together.  Used for R >= 4, where a row's
+// R entries already fill a coalesced access; no LDS, no barrier.
+template <typename V, int RC, bool WT>
+__device__ void run_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_t r0,
+                         int32_t r1) {
+    const int R = RC ? RC : R_rt;
+    const int rows_per_step = kBlock / R;
+    const int tid = threadIdx.x;
+    const int rr = tid % R;
+    const int li = tid / R;
+    const V *val = static_cast<const V *>(m.val);
+    if (li >= rows_per_step) return;  // idle lanes when R does not divide the block
+    for (int32_t row = r0 + li; row < r1; row += rows_per_step) {
+        const int32_t e0 = m.rowptr[row], e1 = m.rowptr[row + 1];
+        double s = 0.0;
+        // blocks of 8 nonzeros, the last one masked: all loads of a block are
+        // issued before its products (lanes past the row end load its last
+        // entry again and add nothing)
+        for (int32_t e = e0; e < e1; e += 8) {
+            int32_t c[8];
+            double a[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t q = min(e + u, e1 - 1);
+                c[u] = m.col[q];
+                a[u] = static_cast<double>(val[q]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xv[u] = io.in[(size_t)c[u] * R + rr];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < e1) s = s + a[u] * xv[u];
+        }
+        const int32_t o = m.out_row ? m.out_row[row] : row;
+        const size_t idx = (size_t)o * R + rr;
+        store_out<WT>(io.out + idx, epilogue(io, s, idx));
+    }
+}
+
+// Products staged per thread and buffer: the slice path for R < 4 (R = 0 is
+// the generic instantiation, which takes either path at run time).
+template <int RC, int KP>
+struct Staging {
+    static constexpr int value = (RC >= 4) ? 1 : KP;
+};
+
 // Slices [s0, s1) of one power.  Called by all threads of the workgroup;
 // all control flow depends on uniform values only.  Ends with a barrier, so
 // the caller may reuse the LDS right away.  Slices holding one row longer
@@ -172,6 +221,11 @@ template <typename V, int RC, int KP, bool WT>
 __device__ void run_slices(const DevMatrix &m, const PowerIO &io, int R_rt, DevSlices sl,
                            int32_t s0, int32_t s1, RowSmem<KP> &sm) {
     const int R = RC ? RC : R_rt;
+    if (R >= 4) {
+        run_rows<V, RC, WT>(m, io, R, sl.srow[s0], sl.srow[s1]);
+        __syncthreads();
+        return;
+    }
     const int E = (KP * kBlock) / R;  // nonzeros per slice buffer
     const int tid = threadIdx.x;
     int32_t c[KP];    // columns of the slice being processed (then of the next)
@@ -270,10 +324,10 @@ template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, 2) void spmv_power_kernel(DevMatrix m, PowerIO io, int32_t R,
                                                            DevSlices sl, int32_t n_slices,
                                                            int32_t per) {
-    __shared__ RowSmem<kSpmvKP> sm;
+    __shared__ RowSmem<Staging<RC, kSpmvKP>::value> sm;
     const int32_t s0 = blockIdx.x * per;
     const int32_t s1 = min(n_slices, s0 + per);
-    run_slices<V, RC, kSpmvKP, false>(m, io, R, sl, s0, s1, sm);
+    run_slices<V, RC, Staging<RC, kSpmvKP>::value, false>(m, io, R, sl, s0, s1, sm);
 }
 
 // ------------------------------------------------------------------ level-blocked
@@ -285,10 +339,10 @@ template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, 4) void step_kernel(DevMatrix m, DevSlices sl,
                                                      const int32_t *chunk_sptr,
                                                      const int32_t *tasks, SegArgs a, Coefs cf) {
-    __shared__ RowSmem<kTaskKP> sm;
+    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     const int32_t c = tasks[2 * blockIdx.x];
     const int32_t k = tasks[2 * blockIdx.x + 1];
-    run_slices<V, RC, kTaskKP, false>(m, power_io(a, cf, k, m.n), a.R, sl, chunk_sptr[c], chunk_sptr[c + 1],
+    run_slices<V, RC, Staging<RC, kTaskKP>::value, false>(m, power_io(a, cf, k, m.n), a.R, sl, chunk_sptr[c], chunk_sptr[c + 1],
                                sm);
 }
 
@@ -311,7 +365,7 @@ struct LBParams {
 // leave.
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, 4) void lb_kernel(LBParams P, Coefs cf) {
-    __shared__ RowSmem<kTaskKP> sm;
+    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
@@ -357,7 +411,7 @@ __global__ __launch_bounds__(kBlock, 4) void lb_kernel(LBParams P, Coefs cf) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
-        run_slices<V, RC, kTaskKP, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
                                    P.s.chunk_sptr[c + 1], sm);
         // The results were stored write-through; every wave waits until its
         // stores have completed (vmcnt = 0) before the barrier, so the chunk
@@ -400,7 +454,7 @@ struct XcdParams {
 // earlier still, so it can run; waits are bounded by spin_limit in any case.
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, 4) void xcd_kernel(XcdParams P, Coefs cf) {
-    __shared__ RowSmem<kTaskKP> sm;
+    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
@@ -441,7 +495,7 @@ __global__ __launch_bounds__(kBlock, 4) void xcd_kernel(XcdParams P, Coefs cf) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (!ok) break;
-        run_slices<V, RC, kTaskKP, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
                                    P.s.chunk_sptr[c + 1], sm);
         // write-through results, completed (vmcnt = 0) before the barrier
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)

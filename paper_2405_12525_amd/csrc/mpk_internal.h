@@ -95,11 +95,13 @@ constexpr int kMaxSegPowers = 64;   // powers per kernel launch
 
 // Slices: runs of consecutive rows whose nonzeros fit one LDS staging buffer
 // of KP*256 products (KP*256/R nonzeros for R right-hand sides), at most
-// kSliceRows rows; a row longer than a buffer is a slice of its own.
+// kSliceRows rows; a row longer than a buffer is a slice of its own.  For
+// R >= 4 the kernels work on whole rows without staging, and slices are only
+// row blocks of about KP*256 nonzeros.
 constexpr int kSpmvKP = 16;   // products per thread and buffer, p x SpMV kernel
 constexpr int kTaskKP = 8;    // the same for the level-blocked kernels
 constexpr int kSliceRows = 256;
-inline int slice_nnz(int kp, int R) { return kp * 256 / R; }
+inline int slice_nnz(int kp, int R) { return R >= 4 ? kp * 256 : kp * 256 / R; }
 
 // Cuts rows [bounds.front(), bounds.back()) into slices of at most E
 // nonzeros; every entry of `bounds` (ascending row numbers) is also a slice
