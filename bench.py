@@ -143,6 +143,63 @@ def serving(torch, mpk, w, n_requests=512):
             "saturated_gflops": round(sat["gflops"], 1)}
 
 
+def other_configs(torch, mpk, w, steps, warmup, stream):
+    """The banded random matrix (FP64 and FP32 values, p = 6) and the Anderson
+    lattice (Chebyshev p = 16, 8 RHS, FP32 values): autotuned level-blocked
+    run vs p x SpMV in the faster order, and the largest per-power relative
+    error of the result against the FP64 oracle."""
+    import numpy as np
+    import oracle
+    out = {}
+    for name, vbs in (("banded_4m_p6", (64, 32)), ("anderson160_cheb16_r8", (32,))):
+        A, x, p, kind = w.config(name)
+        R = x.shape[1]
+        xd = torch.from_numpy(x).cuda()
+        cheb = kind == "chebyshev"
+        coefs = mpk.chebyshev_coefficients(p) if cheb else None
+        ref = oracle.recur(A, x, *coefs) if cheb else oracle.powers(A, x, p)
+        flop = mpk.flops(A.nnz, A.n, p, R, recur=cheb)
+        Y = torch.empty((p, A.n, R), dtype=torch.float64, device="cuda")
+        for vb in vbs:
+            best = {}
+            for ro in ("bfs", "none"):
+                P = mpk.Plan(A, reorder=ro, value_bits=vb)
+                if cheb:
+                    lbf = lambda: P.run_recur(xd, *coefs, Y=Y, stream=stream)
+                    trf = lambda: P.run_baseline_recur(xd, *coefs, Y=Y, stream=stream)
+                else:
+                    lbf = lambda: P.run(xd, p, Y, stream=stream)
+                    trf = lambda: P.run_baseline(xd, p, Y, stream=stream)
+                tr = time_calls(trf, steps, warmup, torch, stream)["median_ms"]
+                tq = P.autotune(xd, p, Y, reps=3, recur=cheb, stream=stream)
+                lb = time_calls(lbf, steps, warmup, torch, stream)["median_ms"]
+                P.sync()
+                got = Y.cpu().numpy()
+                num = np.linalg.norm((got - ref).reshape(p, -1, R), axis=1)
+                den = np.linalg.norm(ref.reshape(p, -1, R), axis=1)
+                rel = float(np.max(num / np.where(den > 0, den, 1.0)))
+                for key, ms in (("trad", tr), ("lb", lb)):
+                    if key not in best or ms < best[key][0]:
+                        best[key] = (ms, ro, tq["schedule"] if key == "lb" else None)
+                best.setdefault("rel", 0.0)
+                best["rel"] = max(best["rel"], rel)
+                P.close()
+            tag = f"{name}_fp{vb}"
+            out[tag] = {"n": A.n, "nnz": A.nnz, "p": p, "nrhs": R, "kind": kind,
+                        "lb_ms": round(best["lb"][0], 4), "lb_reorder": best["lb"][1],
+                        "lb_schedule": best["lb"][2],
+                        "lb_gflops": round(flop / best["lb"][0] / 1e6, 1),
+                        "pxspmv_ms": round(best["trad"][0], 4), "pxspmv_reorder": best["trad"][1],
+                        "pxspmv_gflops": round(flop / best["trad"][0] / 1e6, 1),
+                        "speedup_vs_pxspmv": round(best["trad"][0] / best["lb"][0], 3),
+                        "max_rel_err_vs_fp64_oracle": rel,
+                        "tolerance": 1e-12 if vb == 64 else 1e-5}
+            log(f"[bench] {tag}: level-blocked {best['lb'][0]:.3f} ms ({best['lb'][2]}, "
+                f"{best['lb'][1]}), p x SpMV {best['trad'][0]:.3f} ms, max rel err {rel:.2e}")
+        del Y, xd
+    return out
+
+
 def cpu_baseline(A, x, p, budget_s=20.0):
     """The CPU oracle on all host cores: whole runs of the workload, bounded in time."""
     import oracle
@@ -178,6 +235,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving session")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the banded and Anderson workloads")
     ap.add_argument("--schedule", default=None,
                     help="run this level-blocked schedule instead of autotuning (profiling)")
     ap.add_argument("--chunk", type=int, default=16384, help="chunk nonzeros with --schedule")
@@ -301,6 +360,8 @@ def main():
     }
     P.close()
     del Y, B
+    if not args.no_configs and args.schedule is None:
+        out["other_configs"] = other_configs(torch, mpk, w, args.steps, args.warmup, stream)
     if not args.no_serve:
         out["serving"] = serving(torch, mpk, w)
     if not args.no_cpu:
