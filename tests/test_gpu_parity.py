@@ -109,7 +109,7 @@ def ragged_matrix(n, seed):
     return w.CSR(n, rowptr, cols.astype(np.int32), vals, f"ragged_{n}")
 
 
-@pytest.mark.parametrize("R", [1, 2, 3, 4, 8, 16])
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 5, 7, 8, 12, 16])
 def test_ragged_multi_rhs(R):
     A = ragged_matrix(5003, 7)
     x = w.uniform_vectors(A.n, R, 100 + R)
@@ -304,6 +304,21 @@ def test_segmented_recurrence_matches_oracle(seg):
     Y, B = run_both(P, x, 7, recur=coefs)
     ref = oracle.recur(A, x, *coefs, value_bits=32)
     assert np.array_equal(Y, ref) and np.array_equal(B, ref)
+
+
+@pytest.mark.parametrize("sched", ["wave", "xcd", "powers", "steps"])
+@pytest.mark.parametrize("R", [4, 6, 16])
+def test_multi_rhs_schedules_fp32(sched, R):
+    A = w.anderson_3d(14)
+    x = w.random_sign_unit_vectors(A.n, R, 40 + R)
+    P = mpk.Plan(A, value_bits=32)
+    P.tune(schedule=sched, chunk_nnz=900)
+    coefs = mpk.chebyshev_coefficients(6)
+    Y, B = run_both(P, x, 6, recur=coefs)
+    ref = oracle.recur(A, x, *coefs, value_bits=32)
+    assert np.array_equal(Y, ref) and np.array_equal(B, ref)
+    ref64 = oracle.recur(A, x, *coefs)
+    assert rel_err_per_power(Y, ref64).max() <= TOL32
 
 
 def test_zero_coefficient_omits_its_term():
