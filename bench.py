@@ -159,6 +159,7 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
         coefs = mpk.chebyshev_coefficients(p) if cheb else None
         ref = oracle.recur(A, x, *coefs) if cheb else oracle.powers(A, x, p)
         flop = mpk.flops(A.nnz, A.n, p, R, recur=cheb)
+        extra_v = p - 1 if cheb else 0   # y_{k-1} read again by the recurrence (powers 2..p)
         Y = torch.empty((p, A.n, R), dtype=torch.float64, device="cuda")
         for vb in vbs:
             best = {}
@@ -185,6 +186,9 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
                 best["rel"] = max(best["rel"], rel)
                 P.close()
             tag = f"{name}_fp{vb}"
+            vbytes = 8 * A.n * R
+            trad_b = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "trad") + extra_v * vbytes
+            lb_b = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "lb")
             out[tag] = {"n": A.n, "nnz": A.nnz, "p": p, "nrhs": R, "kind": kind,
                         "lb_ms": round(best["lb"][0], 4), "lb_reorder": best["lb"][1],
                         "lb_schedule": best["lb"][2],
@@ -193,6 +197,12 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
                         "pxspmv_gflops": round(flop / best["trad"][0] / 1e6, 1),
                         "speedup_vs_pxspmv": round(best["trad"][0] / best["lb"][0], 3),
                         "max_rel_err_vs_fp64_oracle": rel,
+                        "pxspmv_roofline": {"bound": "hbm", "algorithmic_bytes": trad_b,
+                                            "achieved_GBs": round(trad_b / best["trad"][0] / 1e6, 1),
+                                            "frac": round(trad_b / best["trad"][0] / 1e6 / HBM_PEAK_GBS, 4)},
+                        "lb_roofline": {"bound": "hbm", "algorithmic_bytes": lb_b,
+                                        "achieved_GBs": round(lb_b / best["lb"][0] / 1e6, 1),
+                                        "frac": round(lb_b / best["lb"][0] / 1e6 / HBM_PEAK_GBS, 4)},
                         "tolerance": 1e-12 if vb == 64 else 1e-5}
             log(f"[bench] {tag}: level-blocked {best['lb'][0]:.3f} ms ({best['lb'][2]}, "
                 f"{best['lb'][1]}), p x SpMV {best['trad'][0]:.3f} ms, max rel err {rel:.2e}")
@@ -316,6 +326,13 @@ def main():
     P.sync()
     same = bool(torch.equal(Y, B))
     log(f"[bench] level-blocked bit-identical to p x SpMV: {same}")
+    # the same run captured in a HIP graph and replayed
+    G = P.capture(xd, p, Y)
+    gr = time_calls(lambda: G.launch(stream=stream), args.steps, args.warmup, torch, stream)
+    stream.synchronize()
+    graph_same = bool(torch.equal(Y, B))
+    G.close()
+    log(f"[bench] HIP graph replay: {gr['median_ms']:.3f} ms, equal: {graph_same}")
 
     lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "lb", A.n if reorder == "bfs" else 0)
     trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "trad", A.n if best_base == "bfs" else 0)
@@ -353,6 +370,8 @@ def main():
                                                   / 1e9, 1),
                             "traffic": measured_traffic("pxspmv:" + best_base)},
         "speedup_vs_pxspmv": round(bmed / lb["median_ms"], 3),
+        "hip_graph": {"ms": round(gr["median_ms"], 4), "bit_identical": graph_same,
+                      "launches_per_run": sched["n_steps"]},
         "bit_identical_to_pxspmv": same,
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
                  "chunks": sched["n_chunks"], "launches_per_run": sched["n_steps"],

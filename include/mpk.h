@@ -255,7 +255,7 @@ mpk_status_t mpk_plan_sync(mpk_plan_t plan);
  * level-blocked run for p powers and nrhs right-hand sides under a fixed list
  * of candidate tunings (schedule x cache budget x chunk size), keeps the
  * fastest and sets it on the plan.  Each candidate runs once untimed, then
- * `reps` timed runs on `stream` (median).  Results are cached per (matrix
+ * `reps` timed runs on `stream` (mean).  Results are cached per (matrix
  * fingerprint, value precision, p, nrhs, recurrence): a later call with the
  * same key applies the cached tuning without timing unless force != 0.
  * x: n*nrhs doubles, Y: p*n*nrhs doubles (device scratch; overwritten).

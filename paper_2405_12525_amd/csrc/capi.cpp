@@ -788,21 +788,22 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     // candidates: the paper's study varies the cache size C; here C, the
     // chunk size and the schedule
     std::vector<mpk_tune_t> cands;
-    auto add = [&](int sched, int64_t cache_mib, int chunk) {
+    auto add = [&](int sched, int64_t cache_mib, int chunk, int lag) {
         mpk_tune_t t = base;
         t.schedule = sched;
         t.cache_bytes = cache_mib << 20;
         t.cache_safety = 1.0;
         t.chunk_nnz = chunk;
-        t.lag = 0;
+        t.lag = lag;
+        t.seg_powers = 0;
         cands.push_back(t);
     };
     for (int64_t c : {32, 64, 128})
-        for (int chunk : {4096, 8192}) add(MPK_SCHED_STEPS, c, chunk);
-    add(MPK_SCHED_WAVE, 64, 8192);
-    add(MPK_SCHED_WAVE, 64, 16384);
-    add(MPK_SCHED_XCD, 64, 8192);
-    add(MPK_SCHED_POWERS, 64, 8192);
+        for (int chunk : {4096, 8192}) add(MPK_SCHED_STEPS, c, chunk, 0);
+    for (int chunk : {8192, 16384, 32768})
+        for (int lag : {0, 2048}) add(MPK_SCHED_WAVE, 64, chunk, lag);
+    add(MPK_SCHED_XCD, 64, 16384, 0);
+    add(MPK_SCHED_POWERS, 64, 8192, 0);
     // Chebyshev coefficients for timing the recurrence (values do not change the time)
     std::vector<double> al(p), be(p, 0.0), ga(p, -1.0);
     for (int k = 0; k < p; ++k) al[k] = k == 0 ? 1.0 : 2.0;
@@ -845,10 +846,13 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
             timed_out = true;
             continue;
         }
-        std::sort(ms.begin(), ms.end());
-        const double med = ms[ms.size() / 2];
-        if (best_i < 0 || med < best_t) {
-            best_t = med;
+        // the mean, not the median: a schedule whose run time is bimodal
+        // (waits that cascade only sometimes) must not win on a lucky draw
+        double mean = 0.0;
+        for (double v : ms) mean += v;
+        mean /= (double)ms.size();
+        if (best_i < 0 || mean < best_t) {
+            best_t = mean;
             best_i = (int)i;
         }
     }

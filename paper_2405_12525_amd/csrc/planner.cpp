@@ -281,7 +281,11 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
     int64_t D = tune.lag;
     if (D <= 0) {
         const double fit = budget / ((double)p * avg_chunk_bytes) - avg_reach;
-        const int64_t par = (default_workgroups + p - 1) / std::max(1, p);
+        // Slack so that a task's inputs lie about 8x the running workgroups
+        // back in ticket order (p tasks share each position): with less, the
+        // producer of an input is often still running when its consumer
+        // starts, and the waits cascade.
+        const int64_t par = (8 * (int64_t)default_workgroups + p - 1) / std::max(1, p);
         D = std::max<int64_t>({(int64_t)std::floor(fit), par, 1});
     }
     s.lag = (int32_t)std::min<int64_t>(D, INT32_MAX);
@@ -505,7 +509,11 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
         int64_t D = tune.lag;
         if (D <= 0) {
             const double fit = budget / ((double)p * avg_chunk_bytes) - avg_reach;
-            const int64_t par = (default_workgroups + p - 1) / std::max(1, p);
+            // Slack so that a task's inputs lie about 8x the running workgroups
+            // back in ticket order (p tasks share each position): with less, the
+            // producer of an input is often still running when its consumer
+            // starts, and the waits cascade.
+            const int64_t par = (8 * (int64_t)default_workgroups + p - 1) / std::max(1, p);
             D = std::max<int64_t>({(int64_t)std::floor(fit), par, 1});
         }
         s.lag = (int32_t)std::min<int64_t>(D, INT32_MAX);
