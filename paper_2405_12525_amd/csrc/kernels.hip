@@ -29,6 +29,9 @@ namespace mpk {
 namespace {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+// Waves per SIMD the level-blocked kernels are built for: two 66 KB staging
+// footprints fit a CU with 16 products per thread, four with 8.
+constexpr int kTaskWaves = kTaskKP >= 16 ? 2 : 4;
 constexpr int kWave = 64;
 static_assert(kSliceRows == kBlock, "one thread per row of a slice");
 
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(kBlock, 2) void spmv_power_kernel(DevMatrix m, Powe
 // (chunk c, power k).  All tasks of a diagonal are independent; the previous
 // diagonals' results are visible because they ran in earlier launches.
 template <typename V, int RC>
-__global__ __launch_bounds__(kBlock, 4) void step_kernel(DevMatrix m, DevSlices sl,
+__global__ __launch_bounds__(kBlock, kTaskWaves) void step_kernel(DevMatrix m, DevSlices sl,
                                                      const int32_t *chunk_sptr,
                                                      const int32_t *tasks, SegArgs a, Coefs cf) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
@@ -364,7 +367,7 @@ struct LBParams {
 // spin_limit, after which the run is flagged as failed and all workgroups
 // leave.
 template <typename V, int RC>
-__global__ __launch_bounds__(kBlock, 4) void lb_kernel(LBParams P, Coefs cf) {
+__global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coefs cf) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
@@ -453,7 +456,7 @@ struct XcdParams {
 // queue (all earlier tasks of that queue are done), and its dependencies are
 // earlier still, so it can run; waits are bounded by spin_limit in any case.
 template <typename V, int RC>
-__global__ __launch_bounds__(kBlock, 4) void xcd_kernel(XcdParams P, Coefs cf) {
+__global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_kernel(XcdParams P, Coefs cf) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;

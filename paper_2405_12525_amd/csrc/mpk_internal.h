@@ -99,7 +99,7 @@ constexpr int kMaxSegPowers = 64;   // powers per kernel launch
 // R >= 4 the kernels work on whole rows without staging, and slices are only
 // row blocks of about KP*256 nonzeros.
 constexpr int kSpmvKP = 16;   // products per thread and buffer, p x SpMV kernel
-constexpr int kTaskKP = 8;    // the same for the level-blocked kernels
+constexpr int kTaskKP = 16;   // the same for the level-blocked kernels
 constexpr int kSliceRows = 256;
 inline int slice_nnz(int kp, int R) { return R >= 4 ? kp * 256 : kp * 256 / R; }
 
