@@ -800,8 +800,7 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     };
     for (int64_t c : {32, 64, 128})
         for (int chunk : {4096, 8192}) add(MPK_SCHED_STEPS, c, chunk, 0);
-    for (int chunk : {8192, 16384, 32768})
-        for (int lag : {0, 2048}) add(MPK_SCHED_WAVE, 64, chunk, lag);
+    for (int chunk : {8192, 16384, 32768}) add(MPK_SCHED_WAVE, 64, chunk, 0);
     add(MPK_SCHED_XCD, 64, 16384, 0);
     add(MPK_SCHED_POWERS, 64, 8192, 0);
     // Chebyshev coefficients for timing the recurrence (values do not change the time)
