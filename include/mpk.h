@@ -119,6 +119,9 @@ typedef struct {
     int seg_powers;          /* powers blocked together per launch (1..64);
                                 p is run as ceil(p / seg_powers) segments that
                                 each read the matrix once; 0 = 64 (at most)    */
+    int skip_ahead;          /* WAVE, DIAG, POWERS: tasks a workgroup may park
+                                while their inputs are not ready, taking newer
+                                tickets meanwhile (0..8; 0 = wait in order)     */
 } mpk_tune_t;
 
 typedef struct {

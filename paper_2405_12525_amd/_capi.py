@@ -44,7 +44,8 @@ class Tune(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("cache_bytes", ctypes.c_int64),
                 ("cache_safety", ctypes.c_double), ("chunk_nnz", ctypes.c_int),
                 ("lag", ctypes.c_int), ("workgroups", ctypes.c_int),
-                ("spin_limit_us", ctypes.c_int64), ("seg_powers", ctypes.c_int)]
+                ("spin_limit_us", ctypes.c_int64), ("seg_powers", ctypes.c_int),
+                ("skip_ahead", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -385,7 +385,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                               se->host.n_queues, se->host.n_chunks()};
             rc = launch_xcd(m, xs, ws->view(), a, &cf, wg, spin_ticks, stream);
         } else {
-            rc = launch_lb(m, ds, ws->view(), a, &cf, wg, spin_ticks, stream);
+            rc = launch_lb(m, ds, ws->view(), a, &cf, wg, spin_ticks, plan->tune.skip_ahead, stream);
         }
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
         if (capturing) {
@@ -473,6 +473,7 @@ void mpk_tune_default(mpk_tune_t *t) {
     t->workgroups = 0;
     t->spin_limit_us = 0;
     t->seg_powers = 0;
+    t->skip_ahead = 0;
 }
 
 mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
@@ -596,6 +597,7 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
     if (t.schedule < MPK_SCHED_STEPS || t.schedule > MPK_SCHED_XCD) return fail(MPK_EINVAL, "bad schedule");
     if (t.cache_bytes <= 0 || !(t.cache_safety > 0.0) || t.cache_safety > 1.0)
         return fail(MPK_EINVAL, "cache_bytes must be > 0 and cache_safety in (0, 1]");
+    if (t.skip_ahead < 0 || t.skip_ahead > 8) return fail(MPK_EINVAL, "skip_ahead must be in [0, 8]");
     if (t.seg_powers < 0 || t.seg_powers > kMaxSegPowers)
         return fail(MPK_EINVAL, "seg_powers must be in [0, 64]");
     if (t.chunk_nnz < 1 || t.lag < 0 || t.workgroups < 0 || t.spin_limit_us < 0)

@@ -355,7 +355,21 @@ struct LBParams {
     DevWorkspace ws;
     SegArgs a;
     int64_t spin_limit;   // wall-clock ticks
+    int32_t pending;      // skip-ahead slots (lbs_kernel)
 };
+
+// One non-blocking look at task t's inputs by wavefront 0 (all 64 lanes):
+// true when every chunk it reads has completed the previous power.
+__device__ __forceinline__ bool inputs_ready(const LBParams &P, int32_t t) {
+    const int32_t c = P.s.tasks[2 * t];
+    const int32_t k = P.s.tasks[2 * t + 1];
+    if (k == 1) return true;
+    const int32_t lo = P.s.dep_lo[c], hi = P.s.dep_hi[c];
+    int ready = 1;
+    for (int32_t j = lo + (int)threadIdx.x; j <= hi; j += kWave)
+        ready &= ld_relaxed(P.ws.done + j) >= k - 1;
+    return __all(ready);
+}
 
 // Persistent kernel: workgroups take tasks (chunk c, power k) in schedule
 // order from a shared ticket counter.  Before computing, a task waits until
@@ -431,6 +445,96 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coef
         t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
     if (t < P.s.n_tasks && tid == 0)
+        __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kMaxPending = 8;
+
+// Persistent kernel with skip-ahead: when the inputs of a workgroup's task
+// are not ready, the task is parked in a small list (up to P.pending slots)
+// and the workgroup takes the next ticket instead of waiting.  Parked tasks
+// are retried oldest first before any new ticket; a workgroup whose list is
+// full, or that has no tickets left, waits for its oldest parked task.
+// Deadlock freedom: the smallest unfinished ticket has all its inputs done
+// (they carry smaller tickets), and its holder, for which it is the oldest
+// task held, either runs it when retrying or blocks on it; every wait is
+// bounded by spin_limit as in lb_kernel.  Wavefront 0 makes every choice and
+// the other wavefronts learn it through LDS, so control stays uniform.
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void lbs_kernel(LBParams P, Coefs cf) {
+    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
+    __shared__ int32_t s_task;
+    const int tid = threadIdx.x;
+    const int lim = min(P.pending, kMaxPending);
+    int32_t pend[kMaxPending];  // wavefront 0 only: parked tickets, oldest first
+    int npend = 0;
+    bool exhausted = false;
+    bool failed = false;        // a wait hit its limit (reported after the loop)
+    for (;;) {
+        if (tid < kWave) {
+            int32_t chosen = -1;
+            // 1. parked tasks, oldest first
+            for (int i = 0; i < npend && chosen < 0; ++i) {
+                if (inputs_ready(P, pend[i])) {
+                    chosen = pend[i];
+                    for (int j = i + 1; j < npend; ++j) pend[j - 1] = pend[j];
+                    --npend;
+                }
+            }
+            // 2. new tickets while there is room to park
+            while (chosen < 0 && !exhausted && npend < lim) {
+                int32_t t = 0;
+                if (tid == 0)
+                    t = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                t = __shfl(t, 0);
+                if (t >= P.s.n_tasks)
+                    exhausted = true;
+                else if (inputs_ready(P, t))
+                    chosen = t;
+                else
+                    pend[npend++] = t;
+            }
+            // 3. wait for the oldest parked task
+            if (chosen < 0 && npend > 0) {
+                uint64_t t0 = wall_clock64();
+                bool ok = true;
+                while (!inputs_ready(P, pend[0])) {
+                    if (ld_relaxed(P.ws.err) != 0 ||
+                        (int64_t)(wall_clock64() - t0) > P.spin_limit) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (ok) {
+                    chosen = pend[0];
+                    for (int j = 1; j < npend; ++j) pend[j - 1] = pend[j];
+                    --npend;
+                } else {
+                    failed = true;
+                    chosen = -1;
+                    npend = 0;
+                    exhausted = true;
+                }
+            }
+            if (tid == 0) s_task = chosen;
+        }
+        __syncthreads();
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
+        if (t < 0) break;  // uniform: no work left (or a wait failed)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int32_t c = P.s.tasks[2 * t];
+        const int32_t k = P.s.tasks[2 * t + 1];
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R,
+                                                           P.s.sl, P.s.chunk_sptr[c],
+                                                           P.s.chunk_sptr[c + 1], sm);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): write-through results completed
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (failed && tid == 0)
         __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -584,9 +688,16 @@ template <typename V>
 struct VTable {
     SpmvFn spmv[6];
     LbFn lb[6];
+    LbFn lbs[6];
     StepFn step[6];
     XcdFn xcd[6];
     VTable() {
+        lbs[0] = lbs_kernel<V, 1>;
+        lbs[1] = lbs_kernel<V, 2>;
+        lbs[2] = lbs_kernel<V, 4>;
+        lbs[3] = lbs_kernel<V, 8>;
+        lbs[4] = lbs_kernel<V, 16>;
+        lbs[5] = lbs_kernel<V, 0>;
         xcd[0] = xcd_kernel<V, 1>;
         xcd[1] = xcd_kernel<V, 2>;
         xcd[2] = xcd_kernel<V, 4>;
@@ -613,6 +724,9 @@ const VTable<float> &t32() {
 
 SpmvFn spmv_fn(int value_bits, int R) {
     return value_bits == 32 ? t32().spmv[r_index(R)] : t64().spmv[r_index(R)];
+}
+LbFn lbs_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().lbs[r_index(R)] : t64().lbs[r_index(R)];
 }
 LbFn lb_fn(int value_bits, int R) {
     return value_bits == 32 ? t32().lb[r_index(R)] : t64().lb[r_index(R)];
@@ -669,15 +783,16 @@ int lb_max_workgroups(int value_bits, int R, int device) {
 
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
-              void *stream) {
+              int pending, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
+    if (pending < 0 || pending > kMaxPending) return (int)hipErrorInvalidValue;
     if (s.n_tasks == 0) return 0;
-    LBParams P{m, s, ws, a, spin_limit};
+    LBParams P{m, s, ws, a, spin_limit, pending};
     Coefs c{};
     if (cf) c = *cf;
-    hipLaunchKernelGGL(lb_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
-                       (hipStream_t)stream, P, c);
+    hipLaunchKernelGGL(pending > 0 ? lbs_fn(m.value_bits, a.R) : lb_fn(m.value_bits, a.R),
+                       dim3(workgroups), dim3(kBlock), 0, (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
 }
 

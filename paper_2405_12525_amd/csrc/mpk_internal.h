@@ -161,9 +161,10 @@ struct DevXcdSchedule {
 
 // Launchers (kernels.hip).  All return hipError_t as int.
 int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);  // also clears the queue tickets
+// pending > 0 selects the skip-ahead kernel with that many parked tasks (<= 8).
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
-              void *stream);
+              int pending, void *stream);
 // One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
 int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
                 int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream);

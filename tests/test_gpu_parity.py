@@ -132,6 +132,9 @@ def test_ragged_multi_rhs(R):
                                   dict(schedule="xcd", chunk_nnz=50, workgroups=64),
                                   dict(schedule="wave", seg_powers=1), dict(seg_powers=3),
                                   dict(schedule="xcd", seg_powers=2),
+                                  dict(schedule="wave", skip_ahead=4, lag=3),
+                                  dict(schedule="powers", skip_ahead=1),
+                                  dict(schedule="diag", skip_ahead=8, chunk_nnz=300),
                                   dict(lag=1), dict(lag=5000), dict(chunk_nnz=50, workgroups=3),
                                   dict(cache_bytes=1 << 16)])
 def test_tuning_never_changes_a_bit(tune):
@@ -255,12 +258,12 @@ def test_identity_and_permutation_exact():
         assert np.array_equal(Y[k], x[idx])
 
 
-@pytest.mark.parametrize("sched", ["wave", "xcd"])
-def test_wait_limit_reports_timeout_and_recovers(sched):
+@pytest.mark.parametrize("sched,skip", [("wave", 0), ("xcd", 0), ("wave", 3)])
+def test_wait_limit_reports_timeout_and_recovers(sched, skip):
     A = w.stencil_3d27(40)
     x = w.uniform_vectors(A.n, 1, 4)
     P = mpk.Plan(A)
-    P.tune(schedule=sched, spin_limit_us=1, chunk_nnz=2000)
+    P.tune(schedule=sched, spin_limit_us=1, chunk_nnz=2000, skip_ahead=skip, lag=1)
     seen_timeout = False
     for _ in range(3):
         P.run(dev(x), 24)
@@ -270,18 +273,18 @@ def test_wait_limit_reports_timeout_and_recovers(sched):
             assert "MPK_ETIMEOUT" in str(e)
             seen_timeout = True
     assert seen_timeout
-    P.tune(spin_limit_us=0, chunk_nnz=2000)
+    P.tune(spin_limit_us=0, chunk_nnz=2000, lag=0)
     Y, B = run_both(P, x, 6)
     assert np.array_equal(Y, B)
     assert np.array_equal(Y, oracle.powers(A, x, 6))
 
 
-@pytest.mark.parametrize("sched", ["steps", "wave", "xcd"])
-def test_concurrent_streams_share_a_plan(sched):
+@pytest.mark.parametrize("sched,skip", [("steps", 0), ("wave", 0), ("xcd", 0), ("wave", 4)])
+def test_concurrent_streams_share_a_plan(sched, skip):
     A = w.stencil_3d27(24)
     xs = [w.uniform_vectors(A.n, 2, s) for s in range(4)]
     P = mpk.Plan(A)
-    P.tune(schedule=sched, chunk_nnz=1500)
+    P.tune(schedule=sched, chunk_nnz=1500, skip_ahead=skip)
     streams = [torch.cuda.Stream() for _ in xs]
     outs = []
     xds = [dev(x) for x in xs]

@@ -101,8 +101,9 @@ def test_task_loop_has_uniform_exit(asm):
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
 
 
-def test_xcd_task_loop_has_uniform_exit(asm):
-    ks = kernels(asm, "xcd_kernel")
+@pytest.mark.parametrize("name", ["xcd_kernel", "lbs_kernel"])
+def test_other_task_loops_have_uniform_exit(asm, name):
+    ks = kernels(asm, name)
     assert len(ks) == 12
     for sym, lines in ks.items():
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
@@ -153,7 +154,7 @@ def _publish_ok(lines):
     assert n_checked >= 1
 
 
-@pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel"])
+@pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel", "lbs_kernel"])
 def test_results_write_through_and_publish_after_completion(asm, name):
     for sym, lines in kernels(asm, name).items():
         body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]

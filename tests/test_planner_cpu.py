@@ -340,6 +340,8 @@ def test_tune_validation():
     with pytest.raises(mpk.MPKError):
         P.tune(seg_powers=65)
     with pytest.raises(mpk.MPKError):
+        P.tune(skip_ahead=9)
+    with pytest.raises(mpk.MPKError):
         P.tune(seg_powers=-1)
     with pytest.raises(mpk.MPKError):
         mpk.Plan(w.stencil_2d5(4), device=mpk.MPK_DEVICE_NONE, value_bits=16)
