@@ -62,11 +62,11 @@ enum {
 
 /* Traversal order of the (chunk, power) tasks. */
 enum {
-    MPK_SCHED_STEPS = 0,    /* default: level groups walked along the diagonals
+    MPK_SCHED_STEPS = 0,    /* level groups walked along the diagonals
                                g + 2(k-1) = const; the tasks of one diagonal are
                                independent and run as one kernel launch, the
                                launch boundary orders consecutive diagonals    */
-    MPK_SCHED_WAVE = 1,     /* one persistent kernel, skewed chunk wavefront with
+    MPK_SCHED_WAVE = 1,     /* default: one persistent kernel, skewed chunk wavefront with
                                per-chunk completion flags                      */
     MPK_SCHED_DIAG = 2,     /* one persistent kernel, the paper's Lp-diagram
                                diagonals g + k = const over level groups        */
@@ -104,17 +104,19 @@ typedef struct {
 /* Run-time tuning of a plan (mpk_plan_tune).  None of these changes a result
  * bit: every kernel sums each row sequentially in stored order. */
 typedef struct {
-    int schedule;            /* MPK_SCHED_STEPS (default), _WAVE, _DIAG, _POWERS,
-                                _XCD                                            */
+    int schedule;            /* MPK_SCHED_WAVE (default), _STEPS, _DIAG,
+                                _POWERS, _XCD                                   */
     int64_t cache_bytes;     /* blocking budget C in bytes (default 64 MiB:
                                 the measured fast-read plateau of the MI355X
                                 Infinity Cache)                                 */
     double cache_safety;     /* fraction of C the window may use (default 1.0) */
     int chunk_nnz;           /* target nonzeros per chunk = per workgroup task
-                                (default 4096)                                  */
+                                (default 32768; capped at nnz / (2 x running
+                                workgroups), at least 1024, so that small
+                                matrices still fill the device)                 */
     int lag;                 /* WAVE, XCD: slack in chunks; 0 = from the budget  */
-    int workgroups;          /* persistent schedules: workgroups; 0 = fill the
-                                device                                          */
+    int workgroups;          /* persistent schedules: workgroups; 0 = two per
+                                compute unit (where they fit)                   */
     int64_t spin_limit_us;   /* dependency-wait limit in microseconds, 0 = 2 s  */
     int seg_powers;          /* powers blocked together per launch (1..64);
                                 p is run as ceil(p / seg_powers) segments that

@@ -465,10 +465,10 @@ void mpk_plan_opts_default(mpk_plan_opts_t *o) {
 
 void mpk_tune_default(mpk_tune_t *t) {
     if (!t) return;
-    t->schedule = MPK_SCHED_STEPS;
+    t->schedule = MPK_SCHED_WAVE;
     t->cache_bytes = (int64_t)64 << 20;
     t->cache_safety = 1.0;
-    t->chunk_nnz = 4096;
+    t->chunk_nnz = 32768;
     t->lag = 0;
     t->workgroups = 0;
     t->spin_limit_us = 0;

@@ -776,6 +776,10 @@ int lb_max_workgroups(int value_bits, int R, int device) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, reinterpret_cast<const void *>(lb_fn(value_bits, R)), kBlock, 0) != hipSuccess)
         return 0;
+    // At most kTaskWaves workgroups per CU even where registers and LDS would
+    // allow more (the unstaged path for R >= 4): more persistent workgroups
+    // only add ticket and flag traffic and were measured 2-3x slower.
+    per_cu = std::min(per_cu, kTaskWaves);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
     return per_cu * prop.multiProcessorCount;

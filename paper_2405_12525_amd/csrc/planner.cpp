@@ -182,6 +182,16 @@ struct RangeMax {
 
 }  // namespace
 
+// Chunk size actually used: the tuning's, but small enough that every one of
+// the running workgroups gets about two chunks of each power (at least 1024
+// nonzeros): on small matrices large chunks would leave most of the device idle.
+static int64_t effective_chunk_nnz(const PlanShape &sh, const mpk_tune_t &tune,
+                                   int default_workgroups) {
+    const int64_t want = std::max(1, tune.chunk_nnz);
+    const int64_t fill = std::max<int64_t>(1024, sh.nnz / (2 * (int64_t)std::max(1, default_workgroups)));
+    return std::min(want, fill);
+}
+
 // XCD schedule: every level is split into n_xcd contiguous parts (by
 // nonzeros) and part x of every level belongs to XCD x, so a chunk's rows
 // mostly read rows of the same XCD one level up or down.  Chunks stay inside
@@ -196,7 +206,7 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
     const auto &pcol = *sh.pcol;
     const int nx = std::max(1, std::min(sh.n_xcd, kMaxQueues));
     const int32_t n_levels = (int32_t)lp.size() - 1;
-    const int64_t chunk_nnz = std::max(1, tune.chunk_nnz);
+    const int64_t chunk_nnz = effective_chunk_nnz(sh, tune, default_workgroups);
     const double row_bytes = 4.0, nz_bytes = 4.0 + sh.value_bytes;
     s.n_queues = nx;
     s.n_groups = n_levels;
@@ -378,7 +388,7 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
     const int32_t n_levels = (int32_t)lp.size() - 1;
     const double row_bytes = 4.0, nz_bytes = 4.0 + sh.value_bytes;
     const double budget = (double)tune.cache_bytes * tune.cache_safety;
-    const int64_t chunk_nnz = std::max(1, tune.chunk_nnz);
+    const int64_t chunk_nnz = effective_chunk_nnz(sh, tune, default_workgroups);
     if (n == 0) {
         s.chunk_ptr.assign(1, 0);
         s.build_ms = now_ms() - t0;
