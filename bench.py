@@ -38,8 +38,16 @@ if _ROOT not in sys.path:
 METRIC = "MPK Gflop/s & HBM bytes vs p×SpMV at p=8 (1 GPU); serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "stencil3d27_128_p8"
+WORKLOAD_TEXT = {
+    "stencil3d27_128_p8": ("3D 27-point stencil 128^3 (truncated), {vb} CSR, x U[-1,1) seed 1002, "
+                           "p=8, 1 RHS, level-blocked MPK, caller's order", 64),
+    "banded_4m_p6": ("banded random N=2^22 (half-width 5000, ~16 nnz/row, 64k-window "
+                     "permutation), {vb} CSR, x U[-1,1) seed 1003, p=6, 1 RHS", 64),
+    "anderson160_cheb16_r8": ("Anderson 160^3 periodic (W=16.5, /14.25), {vb} CSR, Chebyshev "
+                              "recurrence p=16, 8 random-sign RHS seed 1004", 32),
+}
 KERNEL_SRC = os.path.join(_ROOT, "paper_2405_12525_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(_ROOT, "profiles", "traffic_stencil3d27_128_p8.json")
+TRAFFIC_FILE = os.path.join(_ROOT, "profiles", "traffic_{workload}_fp{vb}.json")
 
 
 def log(*a):
@@ -84,12 +92,12 @@ def time_calls(fn, steps, warmup, torch, stream):
                 total_ms=sum(ms), wall_s=wall)
 
 
-def measured_traffic(kernel_key):
+def measured_traffic(workload, vb, kernel_key):
     """HBM bytes per run from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE per dispatch, scaled by what the same counters read for a 1 GiB
     copy), if it was taken for the current kernel source and this tuning."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload=workload, vb=vb)) as f:
             t = json.load(f)
         with open(KERNEL_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
@@ -260,6 +268,10 @@ def main():
     ap.add_argument("--lag", type=int, default=0, help="wavefront lag with --schedule")
     ap.add_argument("--reorder", default="bfs", choices=["bfs", "none"],
                     help="level construction with --schedule")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
+                    help="headline workload (default: the 128^3 stencil; others for profiling)")
+    ap.add_argument("--value-bits", type=int, default=None, choices=[32, 64],
+                    help="matrix value precision (default: the workload's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
@@ -283,20 +295,31 @@ def main():
         print(json.dumps({"copy_bytes_each": a.numel() * 8, "copies": 3}), flush=True)
         return
     t0 = time.perf_counter()
-    A, x, p, _ = w.config(WORKLOAD)
+    A, x, p, kind = w.config(args.workload)
+    text, default_vb = WORKLOAD_TEXT[args.workload]
+    vb = args.value_bits or default_vb
+    cheb = kind == "chebyshev"
+    coefs = mpk.chebyshev_coefficients(p) if cheb else None
     R = x.shape[1]
-    log(f"[bench] generated {WORKLOAD}: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
+    log(f"[bench] generated {args.workload}: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
     xd = torch.from_numpy(x).cuda()
     Y = torch.empty((p, A.n, R), dtype=torch.float64, device="cuda")
     B = torch.empty_like(Y)
-    flop = mpk.flops(A.nnz, A.n, p, R)
+    flop = mpk.flops(A.nnz, A.n, p, R, recur=cheb)
+
+    def run_lb(P, out):
+        return (P.run_recur(xd, *coefs, Y=out, stream=stream) if cheb
+                else P.run(xd, p, out, stream=stream))
+
+    def run_base(P, out):
+        return (P.run_baseline_recur(xd, *coefs, Y=out, stream=stream) if cheb
+                else P.run_baseline(xd, p, out, stream=stream))
 
     # p x SpMV baseline: best of BFS and original order
     base = {}
     for ro in (("bfs", "none") if args.schedule is None else (args.reorder,)):
-        P = mpk.Plan(A, reorder=ro)
-        base[ro] = time_calls(lambda: P.run_baseline(xd, p, B, stream=stream), args.steps,
-                              args.warmup, torch, stream)
+        P = mpk.Plan(A, reorder=ro, value_bits=vb)
+        base[ro] = time_calls(lambda: run_base(P, B), args.steps, args.warmup, torch, stream)
         log(f"[bench] p x SpMV reorder={ro}: {base[ro]['median_ms']:.3f} ms "
             f"({flop / base[ro]['median_ms'] / 1e6:.1f} Gflop/s)")
         P.close()
@@ -306,14 +329,13 @@ def main():
     lb = None
     for ro in (("bfs", "none") if args.schedule is None else (args.reorder,)):
         t0 = time.perf_counter()
-        Q = mpk.Plan(A, reorder=ro)
+        Q = mpk.Plan(A, reorder=ro, value_bits=vb)
         if args.schedule is None:
-            tq = Q.autotune(xd, p, Y, reps=3, stream=stream)
+            tq = Q.autotune(xd, p, Y, reps=3, recur=cheb, stream=stream)
         else:
             tq = Q.tune(schedule=args.schedule, chunk_nnz=args.chunk,
                         cache_bytes=args.cache_mib << 20, lag=args.lag)
-        r = time_calls(lambda: Q.run(xd, p, Y, stream=stream), args.steps, args.warmup, torch,
-                       stream)
+        r = time_calls(lambda: run_lb(Q, Y), args.steps, args.warmup, torch, stream)
         Q.sync()
         log(f"[bench] level-blocked reorder={ro}: autotuned in {time.perf_counter() - t0:.1f}s "
             f"-> {tq['schedule']} C={tq['cache_bytes'] >> 20} MiB chunk={tq['chunk_nnz']}: "
@@ -326,22 +348,24 @@ def main():
             Q.close()
     info = P.info()
     sched = P.schedule(p)
-    P.run_baseline(xd, p, B, stream=stream)
-    P.run(xd, p, Y, stream=stream)
+    run_base(P, B)
+    run_lb(P, Y)
     stream.synchronize()
     P.sync()
     same = bool(torch.equal(Y, B))
     log(f"[bench] level-blocked bit-identical to p x SpMV: {same}")
     # the same run captured in a HIP graph and replayed
-    G = P.capture(xd, p, Y)
+    G = P.capture(xd, p, Y, *(coefs if cheb else ()))
     gr = time_calls(lambda: G.launch(stream=stream), args.steps, args.warmup, torch, stream)
     stream.synchronize()
     graph_same = bool(torch.equal(Y, B))
     G.close()
     log(f"[bench] HIP graph replay: {gr['median_ms']:.3f} ms, equal: {graph_same}")
 
-    lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "lb", A.n if reorder == "bfs" else 0)
-    trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, 8, "trad", A.n if best_base == "bfs" else 0)
+    extra = (p - 1) * 8 * A.n * R if cheb else 0  # y_{k-1} read again by the recurrence
+    lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "lb", A.n if reorder == "bfs" else 0)
+    trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "trad",
+                                   A.n if best_base == "bfs" else 0) + extra
     achieved = lb_bytes / (lb["mean_ms"] * 1e-3) / 1e9
     value = flop / (lb["median_ms"] * 1e-3) / 1e9
     bmed = base[best_base]["median_ms"]
@@ -356,16 +380,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if vb == 64 else "f64 (f32-stored values)",
         "data": "synthetic",
-        "config": {"workload": "3D 27-point stencil 128^3 (truncated), FP64 CSR, x U[-1,1) "
-                               "seed 1002, p=8, 1 RHS, level-blocked MPK, caller's order",
+        "config": {"workload": text.format(vb="FP64" if vb == 64 else "FP32-value"),
                    "n": A.n, "nnz": A.nnz, "p": p, "nrhs": R, "reorder": reorder,
                    "schedule": tune["schedule"], "cache_mib": tune["cache_bytes"] >> 20,
                    "chunk_nnz": tune["chunk_nnz"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("level_blocked:{schedule}:{chunk_nnz}:{cm}:{lag}:{ro}"
+                     "traffic": measured_traffic(args.workload, vb,
+                                                 "level_blocked:{schedule}:{chunk_nnz}:{cm}:{lag}:{ro}"
                                                  .format(cm=tune["cache_bytes"] >> 20, ro=reorder,
                                                          **tune)),
                      "kernel": "level-blocked run (all launches of one mpk_run)",
@@ -374,7 +398,7 @@ def main():
                             "reorder": best_base, "algorithmic_bytes": trad_bytes,
                             "achieved_GBs": round(trad_bytes / (base[best_base]["mean_ms"] * 1e-3)
                                                   / 1e9, 1),
-                            "traffic": measured_traffic("pxspmv:" + best_base)},
+                            "traffic": measured_traffic(args.workload, vb, "pxspmv:" + best_base)},
         "speedup_vs_pxspmv": round(bmed / lb["median_ms"], 3),
         "hip_graph": {"ms": round(gr["median_ms"], 4), "bit_identical": graph_same,
                       "launches_per_run": sched["n_steps"]},
@@ -385,11 +409,11 @@ def main():
     }
     P.close()
     del Y, B
-    if not args.no_configs and args.schedule is None:
+    if not args.no_configs and args.schedule is None and args.workload == WORKLOAD:
         out["other_configs"] = other_configs(torch, mpk, w, args.steps, args.warmup, stream)
-    if not args.no_serve:
+    if not args.no_serve and args.workload == WORKLOAD:
         out["serving"] = serving(torch, mpk, w)
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == WORKLOAD:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, p)
     print(json.dumps(out), flush=True)
