@@ -72,10 +72,10 @@ enum {
                                diagonals g + k = const over level groups        */
     MPK_SCHED_POWERS = 3,   /* one persistent kernel, power by power            */
     MPK_SCHED_XCD = 4       /* one persistent kernel; each level is split into
-                               one part per XCD, every XCD walks its parts in a
-                               skewed wavefront from its own queue, and only
-                               results read by another XCD are written back from
-                               the producer's L2                               */
+                               one part per XCD and every XCD walks its parts in
+                               a skewed wavefront from its own queue (exact
+                               dependency lists), so most inputs were produced
+                               on the same XCD                                 */
 };
 
 #define MPK_DEVICE_CURRENT (-1)

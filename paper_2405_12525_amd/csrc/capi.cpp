@@ -117,7 +117,7 @@ struct SchedEntry {
     Schedule host;
     std::map<int, std::unique_ptr<SliceSet>> slices;  // by right-hand-side count
     DevBuf dep_lo, dep_hi, tasks;
-    DevBuf dep_ptr, dep_idx, remote_out, qptr;  // XCD schedule
+    DevBuf dep_ptr, dep_idx, qptr;  // XCD schedule
     int workgroups = 0;
 };
 
@@ -223,7 +223,6 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
         if (!s.qptr.empty()) {
             if ((st = e->dep_ptr.upload(s.dep_ptr.data(), s.dep_ptr.size() * 4))) return st;
             if ((st = e->dep_idx.upload(s.dep_idx.data(), s.dep_idx.size() * 4))) return st;
-            if ((st = e->remote_out.upload(s.remote_out.data(), s.remote_out.size() * 4))) return st;
             if ((st = e->qptr.upload(s.qptr.data(), s.qptr.size() * 4))) return st;
         }
     }
@@ -380,7 +379,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
         if (!se->host.qptr.empty()) {
             DevXcdSchedule xs{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_ptr.as<int32_t>(),
-                              se->dep_idx.as<int32_t>(), se->remote_out.as<int32_t>(),
+                              se->dep_idx.as<int32_t>(),
                               se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
                               se->host.n_queues, se->host.n_chunks()};
             rc = launch_xcd(m, xs, ws->view(), a, &cf, wg, spin_ticks, stream);

@@ -1,11 +1,12 @@
 // HIP kernels for gfx950 (MI355X): CSR products for one power, the p x SpMV
-// baseline, the level-blocked kernels (one launch per diagonal, and two
-// persistent dataflow forms), permutation, reset and a load-bandwidth probe.
+// baseline, the level-blocked kernels (one launch per diagonal, and three
+// persistent dataflow forms: in ticket order, with skip-ahead parking, and
+// with per-XCD queues), permutation, reset and a load-bandwidth probe.
 //
-// Every run kernel goes through one row routine (run_slices below).  The
-// host cuts the rows into slices (consecutive rows whose nonzeros fit one
-// LDS staging buffer, at most 256 rows; a longer row is a slice of its own)
-// and a workgroup walks a range of slices:
+// Every run kernel goes through one row routine.  For R < 4 right-hand sides
+// (run_slices) the host cuts the rows into slices (consecutive rows whose
+// products fit one LDS staging buffer, at most 256 rows; a longer row is a
+// slice of its own) and a workgroup walks a range of slices:
 //   1. it reads a slice's column indices and values with coalesced loads,
 //      gathers the matching input entries and stores the products
 //      a_e * x_{col(e), r} in LDS (one rounded multiply each);
@@ -14,10 +15,12 @@
 //      multiply-add.
 // The loads of the next slice are issued before the current slice is summed
 // (two LDS buffers), so one memory latency per slice is hidden behind the
-// other's arithmetic.  The summation order is the plain CSR definition
-// itself: results do not depend on slicing, chunking, schedule or
-// right-hand-side count.  Values stored as float are promoted to double
-// before the product; vectors and sums are double.
+// other's arithmetic.  For R >= 4 (run_rows) one thread per (row, right-hand
+// side) sums its row directly, in the same order.  Either way the summation
+// order is the plain CSR definition itself: results do not depend on
+// slicing, chunking, schedule or right-hand-side count.  Values stored as
+// float are promoted to double before the product; vectors and sums are
+// double.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

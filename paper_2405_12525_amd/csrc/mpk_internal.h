@@ -52,7 +52,8 @@ struct Schedule {
     // XCD schedule: exact dependency lists, owning XCD, write-back flags and
     // per-XCD task queues (tasks holds the queues one after the other)
     std::vector<int32_t> dep_ptr, dep_idx;
-    std::vector<int32_t> chunk_xcd, remote_out;
+    std::vector<int32_t> chunk_xcd;
+    std::vector<int32_t> remote_out;   // XCD: chunk read by another XCD (reported only)
     std::vector<int32_t> qptr;
     int32_t n_queues = 0;
     int32_t n_groups = 0, lag = 0, max_reach = 0;
@@ -153,7 +154,6 @@ struct DevXcdSchedule {
     DevSlices sl;
     const int32_t *chunk_sptr;
     const int32_t *dep_ptr, *dep_idx;
-    const int32_t *remote_out;
     const int32_t *tasks;
     const int32_t *qptr;
     int32_t n_queues, n_chunks;
