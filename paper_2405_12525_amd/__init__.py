@@ -22,7 +22,7 @@ from ._capi import (MPK_DEVICE_CURRENT, MPK_DEVICE_NONE, MPK_ORDER_ORIGINAL, MPK
 
 __all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN",
            "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
-           "MPK_SCHED_POWERS", "MPK_SCHED_XCD", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
+           "MPK_SCHED_POWERS", "MPK_SCHED_XCD", "use_torch_allocator", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
            "flops", "lib", "probe_load"]
 
 _SCHED = {"steps": MPK_SCHED_STEPS, "wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG,
@@ -70,6 +70,44 @@ def probe_load(buf, passes: int = 1, workgroups: int = 2048, sink=None, stream=N
 def _torch():
     import torch
     return torch
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = None                       # the installed callbacks (kept alive here)
+allocator_stats = {"allocs": 0, "frees": 0, "bytes": 0}
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device allocations (plan data, schedules,
+    workspaces) through PyTorch's caching allocator (mpk_set_allocator);
+    enable=False restores hipMalloc / hipFree.  Buffers keep the free function
+    they were allocated with."""
+    global _hooks
+    if not enable:
+        check(lib().mpk_set_allocator(None, None, None))
+        return
+    torch = _torch()
+
+    def _alloc(nbytes, ctx):
+        try:
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device())
+        except Exception:
+            return None
+        allocator_stats["allocs"] += 1
+        allocator_stats["bytes"] += int(nbytes)
+        return ptr
+
+    def _free(ptr, ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+            allocator_stats["frees"] += 1
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    check(lib().mpk_set_allocator(ctypes.cast(hooks[0], ctypes.c_void_p),
+                                  ctypes.cast(hooks[1], ctypes.c_void_p), None))
+    # earlier hooks stay referenced: buffers allocated with them free through them
+    _hooks = (hooks, _hooks)
 
 
 def _stream_handle(stream):

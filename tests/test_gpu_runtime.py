@@ -108,3 +108,37 @@ def test_graph_recurrence_replays():
         assert np.array_equal(host(Yg), ref)
     G.close()
     P.close()
+
+
+def test_torch_allocator_hook():
+    mpk.use_torch_allocator(True)
+    try:
+        before = dict(mpk.allocator_stats)
+        A = w.stencil_3d27(20)
+        x = w.uniform_vectors(A.n, 2, 5)
+        P = mpk.Plan(A)
+        P.tune(schedule="wave", chunk_nnz=3000)
+        Y = P.run(dev(x), 4)
+        P.sync()
+        assert np.array_equal(host(Y), oracle.powers(A, x, 4))
+        used = mpk.allocator_stats["allocs"] - before["allocs"]
+        assert used >= 4  # matrix arrays, slices, schedule, workspace
+        P.close()
+        torch.cuda.synchronize()
+        assert mpk.allocator_stats["frees"] - before["frees"] == used
+    finally:
+        mpk.use_torch_allocator(False)
+    # plans made afterwards use hipMalloc again
+    n0 = mpk.allocator_stats["allocs"]
+    Q = mpk.Plan(w.stencil_2d5(10))
+    Q.close()
+    assert mpk.allocator_stats["allocs"] == n0
+
+
+def test_load_probe_sums_exactly():
+    n = 1 << 20
+    buf = torch.arange(n, dtype=torch.float64, device="cuda") % 7   # small integers: exact sums
+    sink = mpk.probe_load(buf, passes=3, workgroups=512)
+    torch.cuda.synchronize()
+    assert sink.shape == (512,)
+    assert float(sink.sum().item()) == 3 * float(buf.sum().item())
