@@ -151,7 +151,9 @@ struct mpk_plan_s {
     // host data kept for schedules and queries
     Levels lv;
     std::vector<int32_t> rowptr, row_lo, row_hi;
-    std::vector<int32_t> pcol;   // plan-numbered columns (exact dependency lists)
+    std::vector<int32_t> col;    // stored columns (plan numbering if plan_cols)
+    bool plan_cols = false;
+    std::vector<int32_t> pcol;   // plan-numbered columns, built for the XCD schedule
     int n_xcd = 8;               // XCDs found on the device (host-only plans: 8)
     bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
     // device data
@@ -208,8 +210,21 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
     // the XCD schedule needs a workgroup on every XCD to drain every queue
     int n_xcd = plan->xcd_bound ? plan->n_xcd : 1;
     if (plan->tune.workgroups > 0 && plan->tune.workgroups < n_xcd) n_xcd = 1;
+    const std::vector<int32_t> *pcol = &plan->col;
+    if (plan->tune.schedule == MPK_SCHED_XCD && !plan->plan_cols) {
+        // exact dependency lists need plan-numbered columns (built once)
+        if (plan->pcol.size() != (size_t)plan->nnz) {
+            plan->pcol.resize((size_t)plan->nnz);
+            const int32_t *inv = plan->lv.iperm.data(), *c = plan->col.data();
+            int32_t *out = plan->pcol.data();
+            const int64_t nz = plan->nnz;
+#pragma omp parallel for schedule(static)
+            for (int64_t e2 = 0; e2 < nz; ++e2) out[e2] = inv[c[e2]];
+        }
+        pcol = &plan->pcol;
+    }
     PlanShape sh{plan->n, plan->nnz, plan->value_bits / 8, &plan->lv.level_ptr, &plan->rowptr,
-                 &plan->row_lo, &plan->row_hi, &plan->pcol, n_xcd,
+                 &plan->row_lo, &plan->row_hi, pcol, n_xcd,
                  plan->xcd_bound && n_xcd > 1};
     std::string err;
     mpk_status_t st = build_schedule(sh, p, plan->tune, default_wg, e->host, err);
@@ -518,14 +533,7 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         plan->rowptr = pc.rowptr;
         plan->row_lo.swap(pc.row_lo);
         plan->row_hi.swap(pc.row_hi);
-        if (plan_cols) {
-            plan->pcol = pc.col;
-        } else {
-            std::vector<int32_t> inv(A->n);
-            for (int64_t i = 0; i < A->n; ++i) inv[plan->lv.perm[i]] = (int32_t)i;
-            plan->pcol.resize((size_t)A->nnz);
-            for (int64_t e2 = 0; e2 < A->nnz; ++e2) plan->pcol[e2] = inv[pc.col[e2]];
-        }
+        plan->plan_cols = plan_cols;
         if (!host_only) {
             int dev = o.device;
             if (dev == MPK_DEVICE_CURRENT) {
@@ -547,7 +555,9 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                 if ((st = plan->d_val.upload(pc.val.data(), nnz * 8))) return st;
             } else {
                 std::vector<float> v32(nnz);
-                for (size_t i = 0; i < nnz; ++i) v32[i] = (float)pc.val[i];
+                const double *v64 = pc.val.data();
+#pragma omp parallel for schedule(static)
+                for (int64_t i = 0; i < (int64_t)nnz; ++i) v32[i] = (float)v64[i];
                 if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
             }
             bool identity = true;
@@ -558,6 +568,7 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                     if ((st = plan->d_outrow.upload(plan->lv.perm.data(), (size_t)A->n * 4))) return st;
             }
         }
+        plan->col.swap(pc.col);  // kept for the schedules' dependency lists
     } catch (const std::bad_alloc &) {
         return fail(MPK_ENOMEM, "host allocation failed");
     } catch (const std::exception &ex) {

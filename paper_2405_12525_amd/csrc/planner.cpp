@@ -32,17 +32,29 @@ mpk_status_t validate_csr(const mpk_csr_t *A, bool need_values, std::string &err
     if (A->nnz > 0 && !A->col) { err = "col is NULL"; return MPK_EINVAL; }
     if (need_values && A->nnz > 0 && !A->val) { err = "val is NULL"; return MPK_EINVAL; }
     if (A->rowptr[0] != 0) { err = "rowptr[0] != 0"; return MPK_EBADCSR; }
-    for (int64_t i = 0; i < A->n; ++i)
-        if (A->rowptr[i + 1] < A->rowptr[i]) {
-            err = "rowptr decreases at row " + std::to_string(i);
-            return MPK_EBADCSR;
-        }
-    if ((int64_t)A->rowptr[A->n] != A->nnz) { err = "rowptr[n] != nnz"; return MPK_EBADCSR; }
-    for (int64_t e = 0; e < A->nnz; ++e)
-        if (A->col[e] < 0 || (int64_t)A->col[e] >= A->n) {
-            err = "column index out of range at entry " + std::to_string(e);
-            return MPK_EBADCSR;
-        }
+    // parallel scans; the first offending index is found serially on failure
+    const int64_t n = A->n, nnz = A->nnz;
+    const int32_t *rp = A->rowptr, *col = A->col;
+    int bad_rows = 0, bad_cols = 0;
+#pragma omp parallel for reduction(| : bad_rows) schedule(static)
+    for (int64_t i = 0; i < n; ++i) bad_rows |= rp[i + 1] < rp[i];
+    if (bad_rows) {
+        for (int64_t i = 0; i < n; ++i)
+            if (rp[i + 1] < rp[i]) {
+                err = "rowptr decreases at row " + std::to_string(i);
+                return MPK_EBADCSR;
+            }
+    }
+    if ((int64_t)rp[n] != nnz) { err = "rowptr[n] != nnz"; return MPK_EBADCSR; }
+#pragma omp parallel for reduction(| : bad_cols) schedule(static)
+    for (int64_t e = 0; e < nnz; ++e) bad_cols |= col[e] < 0 || (int64_t)col[e] >= n;
+    if (bad_cols) {
+        for (int64_t e = 0; e < nnz; ++e)
+            if (col[e] < 0 || (int64_t)col[e] >= n) {
+                err = "column index out of range at entry " + std::to_string(e);
+                return MPK_EBADCSR;
+            }
+    }
     return MPK_OK;
 }
 
@@ -51,20 +63,30 @@ Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t 
     lv.perm.reserve(n);
     lv.level_ptr.push_back(0);
     if (n == 0) return lv;
-    // transpose pattern: in-neighbours, so that the graph is symmetric
-    std::vector<int32_t> tptr(n + 1, 0), tcol(rowptr[n]);
-    for (int64_t e = 0; e < rowptr[n]; ++e) tptr[col[e] + 1]++;
+    // transpose pattern: in-neighbours, so that the graph is symmetric (the
+    // order inside a transposed row is irrelevant: frontiers are sorted)
+    const int64_t nnz = rowptr[n];
+    std::vector<int32_t> tptr(n + 1, 0), tcol(nnz);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < nnz; ++e) __atomic_fetch_add(&tptr[col[e] + 1], 1, __ATOMIC_RELAXED);
     for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
     {
         std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+#pragma omp parallel for schedule(dynamic, 4096)
         for (int64_t i = 0; i < n; ++i)
-            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) tcol[fill[col[e]]++] = (int32_t)i;
+            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                tcol[__atomic_fetch_add(&fill[col[e]], 1, __ATOMIC_RELAXED)] = (int32_t)i;
     }
     std::vector<uint8_t> seen(n, 0);
     std::vector<int32_t> frontier, next;
     int64_t lowest = 0;  // every row below this index is already levelled
     int64_t visited = 0;
     int32_t start = (root >= 0 && root < n) ? root : 0;
+    // claim v for the next level (several threads may find it at once)
+    auto claim = [&seen](int32_t v) {
+        return __atomic_load_n(&seen[v], __ATOMIC_RELAXED) == 0 &&
+               __atomic_exchange_n(&seen[v], (uint8_t)1, __ATOMIC_RELAXED) == 0;
+    };
     while (visited < n) {
         if (frontier.empty()) {
             if (visited > 0) {
@@ -79,14 +101,28 @@ Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t 
         visited += (int64_t)frontier.size();
         lv.level_ptr.push_back((int32_t)lv.perm.size());
         next.clear();
-        for (int32_t u : frontier) {
-            for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
-                int32_t v = col[e];
-                if (!seen[v]) { seen[v] = 1; next.push_back(v); }
+        const int64_t fs = (int64_t)frontier.size();
+        if (fs < 2048) {
+            for (int32_t u : frontier) {
+                for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
+                    if (claim(col[e])) next.push_back(col[e]);
+                for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e)
+                    if (claim(tcol[e])) next.push_back(tcol[e]);
             }
-            for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e) {
-                int32_t v = tcol[e];
-                if (!seen[v]) { seen[v] = 1; next.push_back(v); }
+        } else {
+#pragma omp parallel
+            {
+                std::vector<int32_t> mine;
+#pragma omp for schedule(dynamic, 256) nowait
+                for (int64_t f = 0; f < fs; ++f) {
+                    const int32_t u = frontier[f];
+                    for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
+                        if (claim(col[e])) mine.push_back(col[e]);
+                    for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e)
+                        if (claim(tcol[e])) mine.push_back(tcol[e]);
+                }
+#pragma omp critical
+                next.insert(next.end(), mine.begin(), mine.end());
             }
         }
         std::sort(next.begin(), next.end());
@@ -108,11 +144,17 @@ Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col) {
     // farthest symmetric neighbour of each row
     std::vector<int32_t> far(n);
     for (int64_t i = 0; i < n; ++i) far[i] = (int32_t)i;
+    auto raise = [&far](int32_t at, int32_t v) {
+        int32_t cur = __atomic_load_n(&far[at], __ATOMIC_RELAXED);
+        while (v > cur &&
+               !__atomic_compare_exchange_n(&far[at], &cur, v, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+        }
+    };
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t i = 0; i < n; ++i)
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-            int32_t c = col[e];
-            if (c > far[i]) far[i] = c;
-            if ((int32_t)i > far[c]) far[c] = (int32_t)i;
+            raise((int32_t)i, col[e]);
+            raise(col[e], (int32_t)i);
         }
     // level 0 = row 0; level j+1 ends just past the farthest neighbour of level j
     int64_t b_prev = 0, b = 1;
