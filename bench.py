@@ -158,14 +158,16 @@ def serving(torch, mpk, w, n_requests=512):
 
 
 def other_configs(torch, mpk, w, steps, warmup, stream):
-    """The banded random matrix (FP64 and FP32 values, p = 6) and the Anderson
-    lattice (Chebyshev p = 16, 8 RHS, FP32 values): autotuned level-blocked
-    run vs p x SpMV in the faster order, and the largest per-power relative
-    error of the result against the FP64 oracle."""
+    """The banded random matrix (FP64 and FP32 values, p = 6), the Anderson
+    lattice (Chebyshev p = 16, 8 RHS, FP32 values) and a 64^3 27-point
+    stencil with 16 RHS (p = 16): autotuned level-blocked run vs p x SpMV in
+    the faster order, and the largest per-power relative error of the result
+    against the FP64 oracle."""
     import numpy as np
     import oracle
     out = {}
-    for name, vbs in (("banded_4m_p6", (64, 32)), ("anderson160_cheb16_r8", (32,))):
+    for name, vbs in (("banded_4m_p6", (64, 32)), ("anderson160_cheb16_r8", (32,)),
+                      ("stencil3d27_64_p16_r16", (64,))):
         A, x, p, kind = w.config(name)
         R = x.shape[1]
         xd = torch.from_numpy(x).cuda()

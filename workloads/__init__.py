@@ -296,6 +296,10 @@ CONFIGS = {
                          kind="powers"),
     "anderson160_cheb16_r8": dict(matrix=("anderson_3d", 160), p=16, R=8,
                                   x=("sign_unit", 1004), kind="chebyshev"),
+    # a block of 16 right-hand sides on a mid-size stencil: vector traffic
+    # dominates and the blocking window fits the cache
+    "stencil3d27_64_p16_r16": dict(matrix=("stencil_3d27", 64), p=16, R=16, x=("uniform", 1006),
+                                   kind="powers"),
 }
 
 
