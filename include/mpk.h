@@ -251,7 +251,10 @@ mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double 
 
 /* Wait for every run issued on this plan (all streams it was given) and
  * report device-side failures (MPK_ETIMEOUT when a dependency wait hit its
- * limit; the results of that run are invalid). */
+ * limit; the results of that run are invalid).  The failure is sticky: runs
+ * issued after it on the same dependency workspace are abandoned as well
+ * (their results are invalid too) until this call has reported and cleared
+ * it. */
 mpk_status_t mpk_plan_sync(mpk_plan_t plan);
 
 /*
