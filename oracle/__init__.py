@@ -13,6 +13,13 @@ Distributed-Memory Parallel Matrix Power Kernels", that it follows):
   accumulation, no fused multiply-add.
 * :func:`recur`   -- the three-term recurrence of the Chebyshev application,
   Eq. (anderson_spmv), with general coefficients.
+* :func:`poly_sums` -- weighted sums sum_k w_k y_k of the recurrence's
+  vectors, the polynomial that one Chebyshev time step evaluates
+  (Sec. "Application: Chebyshev Time Propagation", the expansion of
+  exp(-i dt H) in J_k(dt) and the vectors v_k).
+* :func:`cheb_time_coefficients` / :func:`cheb_time_step` -- that expansion
+  written out: c_0 = J_0(dt), c_k = 2 (-i)^k J_k(dt), applied to a complex
+  state stored as pairs of real columns.
 * :func:`bfs_levels` -- the level sets of Sec. "RACE Applied to the Matrix
   Power Kernel" (the case equation for L(i)), computed literally with set
   operations on the symmetrised graph G(A).
@@ -139,6 +146,96 @@ def chebyshev_coefficients(p: int):
     gamma = np.full(p, -1.0)
     gamma[0] = 0.0
     return alpha, beta, gamma
+
+
+def poly_sums(A, x: np.ndarray, alpha, beta, gamma, wa, wb=None, value_bits: int = 64,
+              nthreads: int = 0):
+    """Weighted sums acc = sum_{k=0..p} w[k] y_k of the recurrence's vectors.
+
+    y_0 = x and y_1..y_p come from :func:`recur` (p = len(alpha)); wa and wb
+    hold p + 1 weights each.  The sum runs in increasing k: its first term
+    with a nonzero weight is w[k]*y_k, every later one is added as
+    acc + w[k]*y_k; a weight that is exactly zero omits its term, and a sum
+    whose weights are all zero is the zero vector.  This is the polynomial
+    evaluation of one Chebyshev time step (Sec. "Application: Chebyshev Time
+    Propagation").  Returns (acc_a, acc_b), each (n, R); acc_b is None when
+    wb is None.
+    """
+    rowptr, col, val, x = _prep(A, x, value_bits)
+    Y = recur(A, x, alpha, beta, gamma, value_bits=value_bits, nthreads=nthreads)
+    p = Y.shape[0]
+
+    def one(w):
+        w = np.asarray(w, dtype=np.float64)
+        if w.shape != (p + 1,):
+            raise ValueError("weights must hold p + 1 values")
+        acc = None
+        for k in range(p + 1):
+            if w[k] == 0.0:
+                continue
+            t = w[k] * (x if k == 0 else Y[k - 1])
+            acc = t if acc is None else acc + t
+        return np.zeros_like(x) if acc is None else acc
+
+    return one(wa), (None if wb is None else one(wb))
+
+
+def cheb_time_coefficients(M: int, dt: float):
+    """Chebyshev expansion of exp(-i dt H) kept to M + 1 terms.
+
+    Sec. "Application: Chebyshev Time Propagation": the step is
+    J_0(dt) v_0 + 2 sum_{k=1..M} (-i)^k J_k(dt) v_k with v_0 = psi,
+    v_1 = H psi and v_{k+1} = 2 H v_k - v_{k-1} (valid for a spectrum inside
+    [-1, 1]).  Returns (alpha, beta, gamma) of that recurrence (M powers) and
+    (wa, wb), the real and imaginary parts of the M + 1 expansion weights.
+    (-i)^k cycles through 1, -i, -1, i, so every weight is purely real (k
+    even) or purely imaginary (k odd), with the other part exactly zero.
+    """
+    from scipy.special import jv
+    if M < 1:
+        raise ValueError("M must be at least 1")
+    J = jv(np.arange(M + 1), float(dt))
+    wa = np.zeros(M + 1)
+    wb = np.zeros(M + 1)
+    wa[0] = J[0]
+    for k in range(1, M + 1):
+        re, im = ((1.0, 0.0), (0.0, -1.0), (-1.0, 0.0), (0.0, 1.0))[k % 4]
+        if re:
+            wa[k] = 2.0 * re * J[k]
+        if im:
+            wb[k] = 2.0 * im * J[k]
+    alpha, beta, gamma = chebyshev_coefficients(M)
+    return alpha, beta, gamma, wa, wb
+
+
+def combine_complex(acc_a: np.ndarray, acc_b: np.ndarray) -> np.ndarray:
+    """Complex result of the two real weighted sums, on column pairs.
+
+    With column 2j the real and 2j+1 the imaginary part of state j and
+    complex weights c_k = wa_k + i wb_k, sum_k c_k v_k has real part
+    acc_a[:, 2j] - acc_b[:, 2j+1] and imaginary part
+    acc_a[:, 2j+1] + acc_b[:, 2j] (H is real, so it acts on each part alone).
+    """
+    out = np.empty_like(acc_a)
+    out[:, 0::2] = acc_a[:, 0::2] - acc_b[:, 1::2]
+    out[:, 1::2] = acc_a[:, 1::2] + acc_b[:, 0::2]
+    return out
+
+
+def cheb_time_step(A, psi: np.ndarray, dt: float, M: int, value_bits: int = 64,
+                   nthreads: int = 0) -> np.ndarray:
+    """One Chebyshev time step psi -> exp(-i dt H) psi (truncated after M).
+
+    psi is real (n, 2m): column 2j holds the real and 2j+1 the imaginary part
+    of state j.  Returns the stepped states in the same layout.
+    """
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    if psi.ndim != 2 or psi.shape[1] % 2:
+        raise ValueError("psi must be (n, 2m): real and imaginary columns")
+    al, be, ga, wa, wb = cheb_time_coefficients(M, dt)
+    acc_a, acc_b = poly_sums(A, psi, al, be, ga, wa, wb, value_bits=value_bits,
+                             nthreads=nthreads)
+    return combine_complex(acc_a, acc_b)
 
 
 # ------------------------------------------------------------ graph side

@@ -241,3 +241,85 @@ def test_zero_coefficient_omits_its_term():
     assert Y[0, 0, 0] == 0.0 and Y[0, 1, 0] == 6.0
     Y = oracle.recur(A, x, [3.0], [1.0], [0.0])
     assert np.isinf(Y[0, 0, 0]) and Y[0, 1, 0] == 7.0
+
+
+# ------------------------------------------------- polynomial sums (time step)
+
+def test_poly_single_weight_selects_one_vector():
+    A = w.stencil_2d5(9)
+    x = w.uniform_vectors(A.n, 2, 31)
+    al, be, ga = oracle.chebyshev_coefficients(6)
+    Y = oracle.recur(A, x, al, be, ga)
+    for k in range(7):
+        wa = np.zeros(7)
+        wa[k] = 1.0
+        acc, none = oracle.poly_sums(A, x, al, be, ga, wa)
+        assert none is None
+        assert np.array_equal(acc, x if k == 0 else Y[k - 1]), k
+    zero, _ = oracle.poly_sums(A, x, al, be, ga, np.zeros(7))
+    assert np.array_equal(zero, np.zeros_like(x))
+
+
+def test_poly_integer_weights_on_laplacian_binomials():
+    # plain powers of tridiag(-1, 2, -1) on a delta are (-1)^j C(2k, k+j);
+    # integer weights keep every partial sum an exact integer
+    n, c, p = 81, 40, 18
+    A = w.tridiag_1d(n)
+    x = np.zeros((n, 1))
+    x[c, 0] = 1.0
+    wts = np.array([(k % 5) - 2 for k in range(p + 1)], dtype=np.float64)
+    acc, _ = oracle.poly_sums(A, x, np.ones(p), np.zeros(p), np.zeros(p), wts)
+    expect = np.zeros(n)
+    expect[c] = wts[0]
+    for k in range(1, p + 1):
+        for j in range(-k, k + 1):
+            expect[c + j] += wts[k] * (-1) ** j * math.comb(2 * k, k + j)
+    assert np.array_equal(acc[:, 0], expect)
+
+
+def test_bessel_weights_textbook_values():
+    # J_0(1) and J_1(1) from Abramowitz & Stegun, Table 9.1
+    al, be, ga, wa, wb = oracle.cheb_time_coefficients(4, 1.0)
+    assert abs(wa[0] - 0.7651976865579666) < 1e-15
+    assert abs(wb[1] + 2 * 0.4400505857449335) < 1e-15
+    # (-i)^k: real at even k (sign +, -, ...), imaginary at odd k (-, +, ...)
+    assert wb[0] == 0 and wa[1] == 0 and wb[2] == 0 and wa[3] == 0 and wb[4] == 0
+    assert wa[2] < 0 and wb[3] > 0 and wa[4] > 0
+    assert np.array_equal(al, [1, 2, 2, 2]) and not be.any() and np.array_equal(ga, [0, -1, -1, -1])
+
+
+def _complex_pairs(z):
+    out = np.empty((z.shape[0], 2 * z.shape[1]))
+    out[:, 0::2] = z.real
+    out[:, 1::2] = z.imag
+    return out
+
+
+def test_time_step_on_diagonal_is_jacobi_anger():
+    # for H = diag(cos th) the step is exp(-i dt cos th) psi (Jacobi-Anger);
+    # truncation after M = 30 at dt = 2.5 leaves < 1e-20
+    th = np.linspace(0.0, math.pi, 41)
+    n = th.size
+    A = w.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.cos(th))
+    g = np.random.default_rng(77)
+    psi = g.standard_normal((n, 2)) + 1j * g.standard_normal((n, 2))
+    out = oracle.cheb_time_step(A, _complex_pairs(psi), 2.5, 30)
+    expect = np.exp(-1j * 2.5 * np.cos(th))[:, None] * psi
+    np.testing.assert_allclose(out, _complex_pairs(expect), rtol=0, atol=1e-13)
+
+
+def test_time_step_dense_matches_matrix_exponential():
+    from scipy.linalg import expm
+    g = np.random.default_rng(78)
+    n = 40
+    B = g.standard_normal((n, n)) * (g.random((n, n)) < 0.2)
+    H = (B + B.T) / 2
+    H /= np.abs(H).sum(axis=1).max()          # Gershgorin: spectrum in [-1, 1]
+    A = w.from_dense(H)
+    psi = g.standard_normal((n, 1)) + 1j * g.standard_normal((n, 1))
+    out = oracle.cheb_time_step(A, _complex_pairs(psi), 1.7, 40)
+    expect = expm(-1j * 1.7 * H) @ psi
+    np.testing.assert_allclose(out, _complex_pairs(expect), rtol=0, atol=1e-12)
+    # a unitary step keeps the norm
+    z = out[:, 0] + 1j * out[:, 1]
+    assert abs(np.linalg.norm(z) - np.linalg.norm(psi)) < 1e-12
