@@ -242,6 +242,74 @@ mpk_status_t mpk_run_baseline_recur(mpk_plan_t plan, const double *x, int p, int
                                     const double *gamma, double *Y, void *hip_stream);
 
 /*
+ * Weighted sums of the powers: the polynomial that one step of the
+ * Chebyshev time propagation evaluates (Sec. "Application: Chebyshev Time
+ * Propagation": the new state is a weighted sum of v_0 .. v_M):
+ *   acc_a = sum_{k=0..p} wa[k] y_k,   acc_b = sum_{k=0..p} wb[k] y_k,
+ * y_0 = x, y_1..y_p from the recurrence of mpk_run_recur (alpha, beta and
+ * gamma all NULL: plain powers y_k = A^k x).  The sequence itself is not
+ * kept: y_k lives in the ring `work` at work + ((k-1) mod 2)*n*nrhs, so on
+ * return work holds y_p and (p >= 2) y_{p-1}.
+ * Each sum is updated in the epilogue of the task that computes y_k, in
+ * increasing k: its first term with a nonzero weight sets it to w[k]*y_k,
+ * each later one adds w[k]*y_k (no fused multiply-add), a weight that is
+ * exactly zero omits its term and its vector traffic, and a sum whose
+ * weights are all zero is written as zeros.  The results are therefore the
+ * same bit for bit as mpk_run_baseline_poly, and as forming these sums
+ * from the output of mpk_run_recur.
+ * alpha, beta, gamma: HOST arrays of p doubles (or all NULL); wa, wb: HOST
+ * arrays of p + 1 doubles (wb may be NULL: no acc_b), read at call time.
+ * acc: device, n*nrhs doubles, or 2*n*nrhs with wb (acc_b at acc + n*nrhs);
+ * work: device, 2*n*nrhs doubles.  x, work and acc must not overlap.
+ * A ring slot is rewritten only after every task that reads its old value
+ * has finished; the schedules' dependencies guarantee that when the
+ * pattern is structurally symmetric (every stored (i, j) has a stored
+ * (j, i)), which is checked once per plan.  Other patterns give
+ * MPK_EUNSUPPORTED here; mpk_run_baseline_poly accepts them.
+ * Errors: as mpk_run_recur; MPK_EINVAL (NULL wa / acc / work, overlap).
+ */
+mpk_status_t mpk_run_poly(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
+                          const double *beta, const double *gamma, const double *wa,
+                          const double *wb, double *acc, double *work, void *hip_stream);
+
+/* The same sums with one p x SpMV launch per power (any pattern). */
+mpk_status_t mpk_run_baseline_poly(mpk_plan_t plan, const double *x, int p, int nrhs,
+                                   const double *alpha, const double *beta, const double *gamma,
+                                   const double *wa, const double *wb, double *acc, double *work,
+                                   void *hip_stream);
+
+/*
+ * Coefficients of one Chebyshev time step (Sec. "Application: Chebyshev
+ * Time Propagation"): exp(-i dt H) psi is approximated by
+ * J_0(dt) v_0 + 2 sum_{k=1..M} (-i)^k J_k(dt) v_k with v_0 = psi,
+ * v_1 = H psi, v_{k+1} = 2 H v_k - v_{k-1}, for H with its spectrum in
+ * [-1, 1] (scale and shift H first).  Writes alpha, beta, gamma (M doubles
+ * each: that recurrence for mpk_run_poly) and wa, wb (M + 1 doubles: real
+ * and imaginary parts of the weights; a weight is real for even k and
+ * imaginary for odd k, the other part exactly 0).  J_k(dt) comes from
+ * Miller's backward recurrence, normalised by J_0 + 2 sum_k J_2k = 1.
+ * Host only; all arrays are HOST memory owned by the caller.
+ * Errors: MPK_EINVAL (M outside [1, 100000], dt not finite or |dt| > 1e4,
+ * NULL array).
+ */
+mpk_status_t mpk_cheb_time_coefficients(int M, double dt, double *alpha, double *beta,
+                                        double *gamma, double *wa, double *wb);
+
+/*
+ * Complex states from the two sums of mpk_run_poly (same Section): with
+ * column 2j of each vector the real and 2j+1 the imaginary part of state j,
+ * complex weights wa + i wb and a real matrix,
+ *   out[i][2j]   = acc_a[i][2j]   - acc_b[i][2j+1]
+ *   out[i][2j+1] = acc_a[i][2j+1] + acc_b[i][2j].
+ * acc: device, 2*n*nrhs doubles (acc_b at acc + n*nrhs); out: device,
+ * n*nrhs doubles, not overlapping acc; both 16-byte aligned.  nrhs even,
+ * 2..16.  Asynchronous on hip_stream.
+ * Errors: MPK_EINVAL (odd nrhs, NULL, alignment, overlap), MPK_ENODEVICE.
+ */
+mpk_status_t mpk_combine_complex(mpk_plan_t plan, const double *acc, int nrhs, double *out,
+                                 void *hip_stream);
+
+/*
  * Convert nvec blocks of n*nrhs doubles between the caller's numbering and
  * the plan's: to_plan != 0 gives out[new] = in[perm[new]], else
  * out[perm[new]] = in[new].  Device pointers, must not overlap.

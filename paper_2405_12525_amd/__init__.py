@@ -23,6 +23,7 @@ from ._capi import (MPK_DEVICE_CURRENT, MPK_DEVICE_NONE, MPK_ORDER_ORIGINAL, MPK
 __all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN",
            "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
            "MPK_SCHED_POWERS", "MPK_SCHED_XCD", "use_torch_allocator", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
+           "cheb_time_coefficients",
            "flops", "lib", "probe_load"]
 
 _SCHED = {"steps": MPK_SCHED_STEPS, "wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG,
@@ -44,6 +45,17 @@ def chebyshev_coefficients(p: int):
     g = np.full(p, -1.0)
     g[0] = 0.0
     return a, np.zeros(p), g
+
+
+def cheb_time_coefficients(M: int, dt: float):
+    """alpha, beta, gamma (M each) and the weights wa, wb (M + 1 each) of one
+    Chebyshev time step exp(-i dt H) (mpk_cheb_time_coefficients)."""
+    L = lib()
+    a, b, g = np.empty(M), np.empty(M), np.empty(M)
+    wa, wb = np.empty(M + 1), np.empty(M + 1)
+    check(L.mpk_cheb_time_coefficients(int(M), float(dt), a.ctypes.data, b.ctypes.data,
+                                       g.ctypes.data, wa.ctypes.data, wb.ctypes.data))
+    return a, b, g, wa, wb
 
 
 def flops(nnz: int, n: int, p: int, nrhs: int, recur: bool = False) -> float:
@@ -345,6 +357,83 @@ class Plan:
                                                ctypes.c_void_p(Y.data_ptr()),
                                                _stream_handle(stream)))
         return Y
+
+    def _poly(self, fn, x, wa, wb, alpha, beta, gamma, acc, work, stream):
+        torch = _torch()
+        _vec_check(x, self.n, "x")
+        R = 1 if x.dim() == 1 else int(x.shape[1])
+        wa = np.ascontiguousarray(wa, dtype=np.float64)
+        p = wa.size - 1
+        if p < 1:
+            raise ValueError("wa needs p + 1 >= 2 weights")
+        if wb is not None:
+            wb = np.ascontiguousarray(wb, dtype=np.float64)
+            if wb.size != p + 1:
+                raise ValueError("wa and wb must have the same length")
+        if alpha is None and beta is None and gamma is None:
+            ptrs = (None, None, None)
+        else:
+            a, b, g = self._coefs(alpha, beta, gamma)
+            if a.size != p:
+                raise ValueError("alpha, beta, gamma need p = len(wa) - 1 values")
+            ptrs = (a.ctypes.data, b.ctypes.data, g.ctypes.data)
+        nsum = 1 if wb is None else 2
+
+        def buf(t, k, name):
+            if t is None:
+                return torch.empty((k, self.n, R), dtype=torch.float64, device=x.device)
+            if t.numel() != k * self.n * R or t.dtype != torch.float64 or \
+                    not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of "
+                                 f"{k} x n x nrhs values")
+            return t
+        acc = buf(acc, nsum, "acc")
+        work = buf(work, 2, "work")
+        check(fn(self._h, ctypes.c_void_p(x.data_ptr()), p, R, *ptrs, wa.ctypes.data,
+                 None if wb is None else wb.ctypes.data, ctypes.c_void_p(acc.data_ptr()),
+                 ctypes.c_void_p(work.data_ptr()), _stream_handle(stream)))
+        return acc, work
+
+    def run_poly(self, x, wa, wb=None, alpha=None, beta=None, gamma=None, acc=None, work=None,
+                 stream=None):
+        """Weighted sums acc[0] = sum_k wa[k] y_k (and acc[1] with wb), k = 0..p
+        with p = len(wa) - 1, y_0 = x and y_k the recurrence (plain powers when
+        alpha, beta, gamma are None), level-blocked, keeping only a ring of
+        two vectors (mpk_run_poly).  Returns (acc, work); work[(k-1) % 2]
+        holds y_k for k = p-1, p."""
+        return self._poly(self._lib.mpk_run_poly, x, wa, wb, alpha, beta, gamma, acc, work,
+                          stream)
+
+    def run_baseline_poly(self, x, wa, wb=None, alpha=None, beta=None, gamma=None, acc=None,
+                          work=None, stream=None):
+        """The same sums with one p x SpMV launch per power (mpk_run_baseline_poly)."""
+        return self._poly(self._lib.mpk_run_baseline_poly, x, wa, wb, alpha, beta, gamma, acc,
+                          work, stream)
+
+    def cheb_time_step(self, psi, dt: float, M: int, out=None, baseline: bool = False,
+                       stream=None):
+        """One Chebyshev time step psi -> exp(-i dt H) psi for a matrix whose
+        spectrum lies in [-1, 1].  psi: (n, 2m) float64, column 2j the real
+        and 2j+1 the imaginary part of state j.  Returns the stepped states
+        in the same layout (mpk_run_poly + mpk_combine_complex)."""
+        torch = _torch()
+        _vec_check(psi, self.n, "psi")
+        if psi.dim() != 2 or psi.shape[1] % 2:
+            raise ValueError("psi must be (n, 2m): real and imaginary columns")
+        R = int(psi.shape[1])
+        al, be, ga, wa, wb = cheb_time_coefficients(M, dt)
+        run = self.run_baseline_poly if baseline else self.run_poly
+        acc, work = run(psi, wa, wb, al, be, ga, stream=stream)
+        if out is None:
+            out = torch.empty_like(psi)
+        check(self._lib.mpk_combine_complex(self._h, ctypes.c_void_p(acc.data_ptr()), R,
+                                            ctypes.c_void_p(out.data_ptr()),
+                                            _stream_handle(stream)))
+        if stream is not None:
+            # the temporaries stay reserved until the work queued on `stream` is done
+            acc.record_stream(stream)
+            work.record_stream(stream)
+        return out
 
     def permute(self, v, to_plan: bool, out=None, stream=None):
         """Convert (nvec, n, R) / (n, R) / (n,) blocks between numberings."""

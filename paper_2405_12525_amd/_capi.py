@@ -24,6 +24,7 @@ EXPORTS = [
     "mpk_run_baseline", "mpk_run_baseline_recur", "mpk_permute", "mpk_plan_sync",
     "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
     "mpk_plan_autotune", "mpk_graph_capture", "mpk_graph_launch", "mpk_graph_destroy",
+    "mpk_run_poly", "mpk_run_baseline_poly", "mpk_cheb_time_coefficients", "mpk_combine_complex",
 ]
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -105,6 +106,13 @@ def load():
     lib.mpk_run_baseline.restype = st
     lib.mpk_run_baseline_recur.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
     lib.mpk_run_baseline_recur.restype = st
+    for f in (lib.mpk_run_poly, lib.mpk_run_baseline_poly):
+        f.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P]
+        f.restype = st
+    lib.mpk_cheb_time_coefficients.argtypes = [ctypes.c_int, ctypes.c_double, P, P, P, P, P]
+    lib.mpk_cheb_time_coefficients.restype = st
+    lib.mpk_combine_complex.argtypes = [P, P, ctypes.c_int, P, P]
+    lib.mpk_combine_complex.restype = st
     lib.mpk_permute.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P]
     lib.mpk_permute.restype = st
     lib.mpk_plan_sync.argtypes = [P]

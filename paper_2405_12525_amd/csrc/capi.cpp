@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -154,6 +155,7 @@ struct mpk_plan_s {
     std::vector<int32_t> col;    // stored columns (plan numbering if plan_cols)
     bool plan_cols = false;
     std::vector<int32_t> pcol;   // plan-numbered columns, built for the XCD schedule
+    int pattern_sym = -1;        // structurally symmetric pattern (-1: not checked yet)
     int n_xcd = 8;               // XCDs found on the device (host-only plans: 8)
     bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
     // device data
@@ -200,6 +202,49 @@ mpk_status_t check_device_plan(mpk_plan_t plan) {
 }
 
 // Schedule for p powers with the plan's current tuning (plan->mu held).
+// Stored columns in plan numbering (built once when the plan keeps the
+// caller's numbering; plan->mu held).
+const std::vector<int32_t> &plan_columns(mpk_plan_t plan) {
+    if (plan->plan_cols) return plan->col;
+    if (plan->pcol.size() != (size_t)plan->nnz) {
+        plan->pcol.resize((size_t)plan->nnz);
+        const int32_t *inv = plan->lv.iperm.data(), *c = plan->col.data();
+        int32_t *out = plan->pcol.data();
+        const int64_t nz = plan->nnz;
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < nz; ++e) out[e] = inv[c[e]];
+    }
+    return plan->pcol;
+}
+
+// Whether every stored off-diagonal entry (i, j) has a stored mirror (j, i).
+// A symmetric permutation keeps this property, so the plan-order copy is
+// checked.  Computed once (plan->mu held).
+bool pattern_symmetric(mpk_plan_t plan) {
+    if (plan->pattern_sym >= 0) return plan->pattern_sym == 1;
+    const std::vector<int32_t> &pc = plan_columns(plan);
+    const int32_t *rp = plan->rowptr.data();
+    const int64_t n = plan->n;
+    std::vector<int32_t> sorted(pc);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; ++i) std::sort(sorted.begin() + rp[i], sorted.begin() + rp[i + 1]);
+    int ok = 1;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(min : ok)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!ok) continue;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t j = pc[e];
+            if (j == i) continue;
+            if (!std::binary_search(sorted.begin() + rp[j], sorted.begin() + rp[j + 1], (int32_t)i)) {
+                ok = 0;
+                break;
+            }
+        }
+    }
+    plan->pattern_sym = ok;
+    return ok == 1;
+}
+
 mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_wg) {
     auto it = plan->scheds.find(p);
     if (it != plan->scheds.end()) {
@@ -211,18 +256,7 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
     int n_xcd = plan->xcd_bound ? plan->n_xcd : 1;
     if (plan->tune.workgroups > 0 && plan->tune.workgroups < n_xcd) n_xcd = 1;
     const std::vector<int32_t> *pcol = &plan->col;
-    if (plan->tune.schedule == MPK_SCHED_XCD && !plan->plan_cols) {
-        // exact dependency lists need plan-numbered columns (built once)
-        if (plan->pcol.size() != (size_t)plan->nnz) {
-            plan->pcol.resize((size_t)plan->nnz);
-            const int32_t *inv = plan->lv.iperm.data(), *c = plan->col.data();
-            int32_t *out = plan->pcol.data();
-            const int64_t nz = plan->nnz;
-#pragma omp parallel for schedule(static)
-            for (int64_t e2 = 0; e2 < nz; ++e2) out[e2] = inv[c[e2]];
-        }
-        pcol = &plan->pcol;
-    }
+    if (plan->tune.schedule == MPK_SCHED_XCD) pcol = &plan_columns(plan);  // exact dependency lists
     PlanShape sh{plan->n, plan->nnz, plan->value_bits / 8, &plan->lv.level_ptr, &plan->rowptr,
                  &plan->row_lo, &plan->row_hi, pcol, n_xcd,
                  plan->xcd_bound && n_xcd > 1};
@@ -330,10 +364,37 @@ mpk_status_t task_slices(mpk_plan_t plan, SchedEntry *se, int R, SliceSet **out)
     return MPK_OK;
 }
 
+// Weighted sums of the powers (mpk_run_poly): host weights, device sums and
+// the AccMode of each power 1..p (index k) per sum.
+struct Poly {
+    const double *wa, *wb;
+    double *acc_a, *acc_b;
+    std::vector<int8_t> ma, mb;
+};
+
+// Modes that make the device sum equal sum_{k=0..p} w[k] y_k taken in
+// increasing k with zero weights skipped (all zero: the sum is zero).
+void acc_modes(const double *w, int p, std::vector<int8_t> &mode) {
+    mode.assign((size_t)p + 1, kAccNone);
+    if (!w) return;
+    const bool h0 = w[0] != 0.0, h1 = w[1] != 0.0;
+    mode[1] = h0 && h1 ? kAccSetWithX : (h0 ? kAccSetX : (h1 ? kAccSet : kAccNone));
+    bool started = h0 || h1;
+    for (int k = 2; k <= p; ++k)
+        if (w[k] != 0.0) {
+            mode[k] = started ? kAccAdd : kAccSet;
+            started = true;
+        }
+    if (!started) mode[p] = kAccZero;
+}
+
+// Y is the output (p vectors), or with poly the two-slot ring.
 mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
-                    const double *beta, const double *gamma, double *Y, void *stream_v) {
-    mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
+                    const double *beta, const double *gamma, double *Y, void *stream_v,
+                    const Poly *poly = nullptr) {
+    mpk_status_t st = check_run_args(plan, x, poly ? 2 : p, nrhs, Y);
     if (st) return st;
+    if (p < 1) return fail(MPK_EINVAL, "p must be >= 1");
     const bool recur = alpha != nullptr;
     if (recur && (!beta || !gamma)) return fail(MPK_EINVAL, "alpha, beta and gamma are all required");
     if (plan->n == 0) return MPK_OK;
@@ -345,6 +406,10 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     const bool capturing = cap == hipStreamCaptureStatusActive;
 
     std::lock_guard<std::mutex> g(plan->mu);
+    if (poly && !pattern_symmetric(plan))
+        return fail(MPK_EUNSUPPORTED,
+                    "the level-blocked weighted sums need a structurally symmetric pattern "
+                    "(use the p x SpMV form)");
     const int wg_default = default_workgroups(plan, nrhs);
     const int wg = plan->tune.workgroups > 0 ? plan->tune.workgroups : wg_default;
     const int64_t limit_us = plan->tune.spin_limit_us > 0 ? plan->tune.spin_limit_us : 2000000;
@@ -356,10 +421,19 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         const int ps = std::min(seg, p - base);
         SchedEntry *se = nullptr;
         if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
-        SegArgs a;
-        a.in0 = base == 0 ? x : Y + (size_t)(base - 1) * stride;
-        a.inm1 = base == 0 ? nullptr : (base == 1 ? x : Y + (size_t)(base - 2) * stride);
-        a.Y = Y + (size_t)base * stride;
+        SegArgs a{};
+        if (poly) {  // ring of two: power g in slot (g-1) mod 2
+            a.in0 = base == 0 ? x : Y + (size_t)((base - 1) & 1) * stride;
+            a.inm1 = base == 0 ? nullptr : (base == 1 ? x : Y + (size_t)((base - 2) & 1) * stride);
+            a.Y = Y;
+            a.acc_a = poly->acc_a;
+            a.acc_b = poly->acc_b;
+        } else {
+            a.in0 = base == 0 ? x : Y + (size_t)(base - 1) * stride;
+            a.inm1 = base == 0 ? nullptr : (base == 1 ? x : Y + (size_t)(base - 2) * stride);
+            a.Y = Y + (size_t)base * stride;
+        }
+        a.k0 = base;
         a.p = ps;
         a.R = nrhs;
         a.recur = recur ? 1 : 0;
@@ -370,6 +444,20 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                 cf.beta[j] = beta[base + j];
                 cf.gamma[j] = gamma[base + j];
             }
+        AccCoefs ac{};
+        if (poly) {  // y_0's weights matter at the first power only
+            ac.wa0 = poly->wa[0];
+            ac.wb0 = poly->wb ? poly->wb[0] : 0.0;
+            for (int j = 0; j < ps; ++j) {
+                ac.wa[j] = poly->wa[base + j + 1];
+                ac.ma[j] = poly->ma[base + j + 1];
+                if (poly->wb) {
+                    ac.wb[j] = poly->wb[base + j + 1];
+                    ac.mb[j] = poly->mb[base + j + 1];
+                }
+            }
+        }
+        const AccCoefs *acp = poly ? &ac : nullptr;
         SliceSet *ss = nullptr;
         if (capturing && !se->slices.count(nrhs))
             return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
@@ -380,7 +468,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
             for (size_t d = 0; d + 1 < sp.size(); ++d) {
                 int rc = launch_step(m, ss->view(), ss->bound_sptr.as<int32_t>(),
                                      se->tasks.as<int32_t>() + 2 * (size_t)sp[d], sp[d + 1] - sp[d],
-                                     a, &cf, stream);
+                                     a, &cf, acp, stream);
                 if (rc) return hip_fail((hipError_t)rc, "step kernel launch");
             }
             continue;
@@ -397,9 +485,10 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                               se->dep_idx.as<int32_t>(),
                               se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
                               se->host.n_queues, se->host.n_chunks()};
-            rc = launch_xcd(m, xs, ws->view(), a, &cf, wg, spin_ticks, stream);
+            rc = launch_xcd(m, xs, ws->view(), a, &cf, acp, wg, spin_ticks, stream);
         } else {
-            rc = launch_lb(m, ds, ws->view(), a, &cf, wg, spin_ticks, plan->tune.skip_ahead, stream);
+            rc = launch_lb(m, ds, ws->view(), a, &cf, acp, wg, spin_ticks, plan->tune.skip_ahead,
+                           stream);
         }
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
         if (capturing) {
@@ -416,9 +505,11 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
 }
 
 mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
-                          const double *beta, const double *gamma, double *Y, void *stream_v) {
-    mpk_status_t st = check_run_args(plan, x, p, nrhs, Y);
+                          const double *beta, const double *gamma, double *Y, void *stream_v,
+                          const Poly *poly = nullptr) {
+    mpk_status_t st = check_run_args(plan, x, poly ? 2 : p, nrhs, Y);
     if (st) return st;
+    if (p < 1) return fail(MPK_EINVAL, "p must be >= 1");
     const bool recur = alpha != nullptr;
     if (recur && (!beta || !gamma)) return fail(MPK_EINVAL, "alpha, beta and gamma are all required");
     if (plan->n == 0) return MPK_OK;
@@ -444,13 +535,30 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     const size_t stride = (size_t)plan->n * nrhs;
     const DevMatrix m = plan->matrix();
     for (int k = 1; k <= p; ++k) {
-        const double *in = k == 1 ? x : Y + (size_t)(k - 2) * stride;
-        const double *prev = k == 1 ? nullptr : (k == 2 ? x : Y + (size_t)(k - 3) * stride);
-        double *out = Y + (size_t)(k - 1) * stride;
+        // with poly, Y is a ring of two: power k in slot (k-1) mod 2
+        const size_t o_in = poly ? (size_t)((k - 2) & 1) : (size_t)(k - 2);
+        const size_t o_prev = poly ? (size_t)((k - 3) & 1) : (size_t)(k - 3);
+        const size_t o_out = poly ? (size_t)((k - 1) & 1) : (size_t)(k - 1);
+        const double *in = k == 1 ? x : Y + o_in * stride;
+        const double *prev = k == 1 ? nullptr : (k == 2 ? x : Y + o_prev * stride);
+        double *out = Y + o_out * stride;
+        AccStep as{};
+        if (poly) {
+            as.acc_a = poly->acc_a;
+            as.acc_b = poly->acc_b;
+            as.wa = poly->wa[k];
+            as.wa0 = poly->wa[0];
+            as.ma = poly->ma[k];
+            if (poly->wb) {
+                as.wb = poly->wb[k];
+                as.wb0 = poly->wb[0];
+                as.mb = poly->mb[k];
+            }
+        }
         int rc = launch_spmv_power(m, sl->view(), sl->n_slices, kSpmvSlicesPerWG, in, prev, out,
                                    nrhs, recur ? 1 : 0, recur ? alpha[k - 1] : 1.0,
                                    recur ? beta[k - 1] : 0.0, recur ? gamma[k - 1] : 0.0,
-                                   stream_v);
+                                   poly ? &as : nullptr, stream_v);
         if (rc) return hip_fail((hipError_t)rc, "spmv kernel launch");
     }
     if (cap != hipStreamCaptureStatusActive) {
@@ -458,6 +566,80 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
         if ((st = note_stream(plan, stream))) return st;
     }
     return MPK_OK;
+}
+
+// Weighted sums: argument checks shared by both forms.
+mpk_status_t run_poly(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
+                      const double *beta, const double *gamma, const double *wa,
+                      const double *wb, double *acc, double *work, void *stream, bool baseline) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (p < 1) return fail(MPK_EINVAL, "p must be >= 1");
+    if (!wa) return fail(MPK_EINVAL, "wa is NULL");
+    if ((alpha || beta || gamma) && !(alpha && beta && gamma))
+        return fail(MPK_EINVAL, "alpha, beta and gamma are all given or all NULL");
+    if (nrhs < 1 || nrhs > MPK_MAX_RHS) return fail(MPK_EUNSUPPORTED, "nrhs must be in [1, 16]");
+    if (plan->n > 0 && (!acc || !work)) return fail(MPK_EINVAL, "acc or work is NULL");
+    const size_t vb = (size_t)plan->n * nrhs * sizeof(double);
+    const size_t accb = vb * (wb ? 2 : 1);
+    const char *ac = reinterpret_cast<const char *>(acc), *wk = reinterpret_cast<const char *>(work),
+               *xs = reinterpret_cast<const char *>(x);
+    if (plan->n > 0 && ((ac < wk + 2 * vb && wk < ac + accb) || (ac < xs + vb && xs < ac + accb)))
+        return fail(MPK_EINVAL, "acc overlaps x or work");
+    Poly poly;
+    poly.wa = wa;
+    poly.wb = wb;
+    poly.acc_a = acc;
+    poly.acc_b = wb ? acc + (size_t)plan->n * nrhs : nullptr;
+    acc_modes(wa, p, poly.ma);
+    acc_modes(wb, p, poly.mb);
+    return baseline ? run_baseline(plan, x, p, nrhs, alpha, beta, gamma, work, stream, &poly)
+                    : run_lb(plan, x, p, nrhs, alpha, beta, gamma, work, stream, &poly);
+}
+
+// J_0(x) .. J_M(x), Bessel functions of the first kind, by Miller's backward
+// recurrence: starting far above max(M, |x|) with J_{N+1} = 0 and J_N tiny,
+// J_{k-1} = (2k/x) J_k - J_{k+1} runs down to k = 0 (the recurrence is
+// stable downwards), and the unknown scale is fixed by the identity
+// J_0 + 2 (J_2 + J_4 + ...) = 1.  The start never lies far beyond the order
+// where |J_k(x)| <= (|x|/2)^k / k! drops below the smallest double, since
+// every order past it is zero anyway.  J_k(-x) = (-1)^k J_k(x).
+void bessel_j(int M, double x, double *J) {
+    std::fill(J, J + M + 1, 0.0);
+    if (x == 0.0) {
+        J[0] = 1.0;
+        return;
+    }
+    const double ax = std::fabs(x);
+    const int m = std::max(M, (int)ax);
+    int N = m + (int)std::sqrt(160.0 * m) + 30;
+    for (int k = 1; k < N; ++k)  // first order whose bound is below 1e-330
+        if (k > ax && k * std::log(ax / 2.0) - std::lgamma(k + 1.0) < -760.0) {
+            N = std::min(N, k + 20);
+            break;
+        }
+    N += N & 1;
+    const int top = std::min(M, N);
+    double bp1 = 0.0, b = 1e-300, even = 0.0;  // b = J_k up to scale, k = N
+    if (N <= M) J[N] = b;
+    for (int k = N; k >= 1; --k) {
+        const double bm1 = (2.0 * k / ax) * b - bp1;
+        bp1 = b;
+        b = bm1;  // J_{k-1}
+        if (k - 1 <= M) J[k - 1] = b;
+        if (k - 1 >= 2 && !((k - 1) & 1)) even += b;
+        if (std::fabs(b) > 1e250) {
+            b *= 1e-250;
+            bp1 *= 1e-250;
+            even *= 1e-250;
+            for (int j = k - 1; j <= top; ++j) J[j] *= 1e-250;
+        }
+    }
+    const double norm = b + 2.0 * even;
+    for (int k = 0; k <= top; ++k) {
+        double v = J[k] / norm;
+        if (x < 0.0 && (k & 1)) v = -v;
+        J[k] = v;
+    }
 }
 
 }  // namespace
@@ -726,6 +908,65 @@ mpk_status_t mpk_run_baseline_recur(mpk_plan_t plan, const double *x, int p, int
                                     double *Y, void *stream) {
     if (!alpha || !beta || !gamma) return fail(MPK_EINVAL, "coefficient array is NULL");
     return run_baseline(plan, x, p, nrhs, alpha, beta, gamma, Y, stream);
+}
+
+mpk_status_t mpk_run_poly(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
+                          const double *beta, const double *gamma, const double *wa,
+                          const double *wb, double *acc, double *work, void *stream) {
+    return run_poly(plan, x, p, nrhs, alpha, beta, gamma, wa, wb, acc, work, stream, false);
+}
+
+mpk_status_t mpk_run_baseline_poly(mpk_plan_t plan, const double *x, int p, int nrhs,
+                                   const double *alpha, const double *beta, const double *gamma,
+                                   const double *wa, const double *wb, double *acc, double *work,
+                                   void *stream) {
+    return run_poly(plan, x, p, nrhs, alpha, beta, gamma, wa, wb, acc, work, stream, true);
+}
+
+mpk_status_t mpk_cheb_time_coefficients(int M, double dt, double *alpha, double *beta,
+                                        double *gamma, double *wa, double *wb) {
+    if (M < 1 || M > 100000) return fail(MPK_EINVAL, "M must be in [1, 100000]");
+    if (!std::isfinite(dt) || std::fabs(dt) > 1e4)
+        return fail(MPK_EINVAL, "dt must be finite with |dt| <= 1e4");
+    if (!alpha || !beta || !gamma || !wa || !wb) return fail(MPK_EINVAL, "NULL array");
+    std::vector<double> J((size_t)M + 1);
+    bessel_j(M, dt, J.data());
+    for (int k = 0; k < M; ++k) {  // v_1 = H v_0, v_{k+1} = 2 H v_k - v_{k-1}
+        alpha[k] = k == 0 ? 1.0 : 2.0;
+        beta[k] = 0.0;
+        gamma[k] = k == 0 ? 0.0 : -1.0;
+    }
+    wa[0] = J[0];
+    wb[0] = 0.0;
+    for (int k = 1; k <= M; ++k) {  // 2 (-i)^k J_k: (-i)^k cycles 1, -i, -1, i
+        const double c = 2.0 * J[(size_t)k];
+        switch (k & 3) {
+        case 0: wa[k] = c; wb[k] = 0.0; break;
+        case 1: wa[k] = 0.0; wb[k] = -c; break;
+        case 2: wa[k] = -c; wb[k] = 0.0; break;
+        default: wa[k] = 0.0; wb[k] = c; break;
+        }
+    }
+    return MPK_OK;
+}
+
+mpk_status_t mpk_combine_complex(mpk_plan_t plan, const double *acc, int nrhs, double *out,
+                                 void *stream) {
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    if (nrhs < 2 || nrhs > MPK_MAX_RHS || (nrhs & 1))
+        return fail(MPK_EINVAL, "nrhs must be even, 2..16 (real and imaginary columns)");
+    if (plan->n == 0) return MPK_OK;
+    if (!acc || !out) return fail(MPK_EINVAL, "NULL vector");
+    if ((reinterpret_cast<uintptr_t>(acc) | reinterpret_cast<uintptr_t>(out)) & 15)
+        return fail(MPK_EINVAL, "acc and out must be 16-byte aligned");
+    const size_t vb = (size_t)plan->n * nrhs * sizeof(double);
+    const char *a = reinterpret_cast<const char *>(acc), *b = reinterpret_cast<const char *>(out);
+    if (a < b + vb && b < a + 2 * vb) return fail(MPK_EINVAL, "acc and out overlap");
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int rc = launch_combine_complex(acc, acc + (size_t)plan->n * nrhs, plan->n, nrhs, out, stream);
+    return rc ? hip_fail((hipError_t)rc, "combine kernel launch") : MPK_OK;
 }
 
 mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double *out, int nvec,

@@ -48,6 +48,10 @@ struct PowerIO {
     double *out;          // y_k
     double alpha, beta, gamma;
     int recur;
+    // weighted sums of the powers (AccMode per sum; both kAccNone: none)
+    double *acc_a, *acc_b;
+    double wa, wb, wa0, wb0;
+    int ma, mb;
 };
 
 // y = alpha*s + beta*y_{k-1} + gamma*y_{k-2} evaluated left to right, or s.
@@ -67,6 +71,49 @@ __device__ __forceinline__ double epilogue(const PowerIO &io, double s, size_t i
     return v;
 }
 
+template <bool WT>
+__device__ __forceinline__ void store_out(double *p, double v);
+
+// One weighted sum at one element, after y_k = v has been computed (y_0 is
+// io.in at the first power).  Terms are formed and added left to right
+// without contraction, as the host-side definition of the sum states.
+template <bool WT>
+__device__ __forceinline__ void accumulate(double *acc, int mode, double w, double w0,
+                                           const PowerIO &io, double v, size_t idx) {
+    double r;
+    switch (mode) {
+    case kAccSet:
+        r = w * v;
+        break;
+    case kAccAdd: {
+        const double t = w * v;
+        r = acc[idx] + t;
+        break;
+    }
+    case kAccSetWithX: {
+        const double t0 = w0 * io.in[idx];
+        const double t = w * v;
+        r = t0 + t;
+        break;
+    }
+    case kAccSetX:
+        r = w0 * io.in[idx];
+        break;
+    case kAccZero:
+        r = 0.0;
+        break;
+    default:
+        return;
+    }
+    store_out<WT>(acc + idx, r);
+}
+
+// Result of one (row, right-hand side): y_k from the row sum, stored, and
+// the weighted sums updated.  The sums' loads and stores use the same
+// element index as y_k, so each is touched by this thread only.
+template <bool WT, bool ACC>
+__device__ __forceinline__ void finish(const PowerIO &io, double s, size_t idx);
+
 // Output store.  WT: an agent-scope atomic store, which writes through to
 // memory (it must be coherent with agent-scope loads on every XCD), so a
 // result is visible device-wide once the store has completed (vmcnt) and no
@@ -77,6 +124,16 @@ __device__ __forceinline__ void store_out(double *p, double v) {
         __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
         *p = v;
+}
+
+template <bool WT, bool ACC>
+__device__ __forceinline__ void finish(const PowerIO &io, double s, size_t idx) {
+    const double v = epilogue(io, s, idx);
+    store_out<WT>(io.out + idx, v);
+    if (ACC) {
+        accumulate<WT>(io.acc_a, io.ma, io.wa, io.wa0, io, v, idx);
+        accumulate<WT>(io.acc_b, io.mb, io.wb, io.wb0, io, v, idx);
+    }
 }
 
 // Loads of a slice with 1 <= nz nonzeros starting at nb, rows [rb, re):
@@ -139,7 +196,7 @@ struct RowSmem {
 
 // One row longer than a slice buffer: summed buffer by buffer, one thread
 // per right-hand side.  Starts and ends with a barrier.
-template <typename V, int RC, int KP, bool WT>
+template <typename V, int RC, int KP, bool WT, bool ACC>
 __device__ void long_row(const DevMatrix &m, const PowerIO &io, int R, int32_t row, int32_t nb,
                          int32_t ne, RowSmem<KP> &sm) {
     const int tid = threadIdx.x;
@@ -165,7 +222,7 @@ __device__ void long_row(const DevMatrix &m, const PowerIO &io, int R, int32_t r
     if (tid < R) {
         const int32_t o = m.out_row ? m.out_row[row] : row;
         const size_t idx = (size_t)o * R + tid;
-        store_out<WT>(io.out + idx, epilogue(io, s, idx));
+        finish<WT, ACC>(io, s, idx);
     }
     __syncthreads();
 }
@@ -175,7 +232,7 @@ __device__ void long_row(const DevMatrix &m, const PowerIO &io, int R, int32_t r
 // slices), the R threads of a row share each column / value load and read
 // the R entries of an input row together.  Used for R >= 4, where a row's
 // R entries already fill a coalesced access; no LDS, no barrier.
-template <typename V, int RC, bool WT>
+template <typename V, int RC, bool WT, bool ACC>
 __device__ void run_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_t r0,
                          int32_t r1) {
     const int R = RC ? RC : R_rt;
@@ -208,7 +265,7 @@ __device__ void run_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_
         }
         const int32_t o = m.out_row ? m.out_row[row] : row;
         const size_t idx = (size_t)o * R + rr;
-        store_out<WT>(io.out + idx, epilogue(io, s, idx));
+        finish<WT, ACC>(io, s, idx);
     }
 }
 
@@ -223,12 +280,12 @@ struct Staging {
 // all control flow depends on uniform values only.  Ends with a barrier, so
 // the caller may reuse the LDS right away.  Slices holding one row longer
 // than a buffer are computed in a second pass.
-template <typename V, int RC, int KP, bool WT>
+template <typename V, int RC, int KP, bool WT, bool ACC>
 __device__ void run_slices(const DevMatrix &m, const PowerIO &io, int R_rt, DevSlices sl,
                            int32_t s0, int32_t s1, RowSmem<KP> &sm) {
     const int R = RC ? RC : R_rt;
     if (R >= 4) {
-        run_rows<V, RC, WT>(m, io, R, sl.srow[s0], sl.srow[s1]);
+        run_rows<V, RC, WT, ACC>(m, io, R, sl.srow[s0], sl.srow[s1]);
         __syncthreads();
         return;
     }
@@ -297,7 +354,7 @@ __device__ void run_slices(const DevMatrix &m, const PowerIO &io, int R_rt, DevS
             const double sum = ordered_sum(prod, R, rr, srp[li], srp[li + 1]);
             const int32_t o = m.out_row ? m.out_row[row] : row;
             const size_t idx = (size_t)o * R + rr;
-            store_out<WT>(io.out + idx, epilogue(io, sum, idx));
+            finish<WT, ACC>(io, sum, idx);
         }
         buf ^= 1;
     }
@@ -305,17 +362,36 @@ __device__ void run_slices(const DevMatrix &m, const PowerIO &io, int R_rt, DevS
     // rows longer than a buffer, kept out of the pipelined loop (registers)
     for (int32_t s = s0; s < s1; ++s) {
         const int32_t nb = sl.snz[s], ne = sl.snz[s + 1];
-        if (ne - nb > E) long_row<V, RC, KP, WT>(m, io, R, sl.srow[s], nb, ne, sm);
+        if (ne - nb > E) long_row<V, RC, KP, WT, ACC>(m, io, R, sl.srow[s], nb, ne, sm);
     }
 }
 
-__device__ __forceinline__ PowerIO power_io(const SegArgs &a, const Coefs &cf, int32_t k,
-                                            int32_t n) {
+// Inputs and outputs of the segment's power k.  ACC: the sequence is kept in
+// a ring of two vectors (power g = k0 + k in slot (g-1) mod 2) and the
+// weighted sums are updated.
+template <bool ACC>
+__device__ __forceinline__ PowerIO power_io(const SegArgs &a, const Coefs &cf,
+                                            const AccCoefs *ac, int32_t k, int32_t n) {
     const size_t stride = (size_t)n * a.R;
     PowerIO io;
-    io.in = (k == 1) ? a.in0 : a.Y + (size_t)(k - 2) * stride;
-    io.prev = (k == 1) ? a.inm1 : (k == 2 ? a.in0 : a.Y + (size_t)(k - 3) * stride);
-    io.out = a.Y + (size_t)(k - 1) * stride;
+    if (ACC) {
+        const int32_t g = a.k0 + k;
+        io.in = (k == 1) ? a.in0 : a.Y + (size_t)((g - 2) & 1) * stride;
+        io.prev = (k == 1) ? a.inm1 : (k == 2 ? a.in0 : a.Y + (size_t)((g - 3) & 1) * stride);
+        io.out = a.Y + (size_t)((g - 1) & 1) * stride;
+        io.acc_a = a.acc_a;
+        io.acc_b = a.acc_b;
+        io.wa = ac->wa[k - 1];
+        io.wb = ac->wb[k - 1];
+        io.wa0 = ac->wa0;
+        io.wb0 = ac->wb0;
+        io.ma = ac->ma[k - 1];
+        io.mb = ac->mb[k - 1];
+    } else {
+        io.in = (k == 1) ? a.in0 : a.Y + (size_t)(k - 2) * stride;
+        io.prev = (k == 1) ? a.inm1 : (k == 2 ? a.in0 : a.Y + (size_t)(k - 3) * stride);
+        io.out = a.Y + (size_t)(k - 1) * stride;
+    }
     io.recur = a.recur;
     io.alpha = cf.alpha[k - 1];
     io.beta = cf.beta[k - 1];
@@ -326,14 +402,14 @@ __device__ __forceinline__ PowerIO power_io(const SegArgs &a, const Coefs &cf, i
 // ------------------------------------------------------------------ baseline
 
 // One power: workgroup b walks slices [b*per, min((b+1)*per, n_slices)).
-template <typename V, int RC>
+template <typename V, int RC, bool ACC>
 __global__ __launch_bounds__(kBlock, 2) void spmv_power_kernel(DevMatrix m, PowerIO io, int32_t R,
                                                            DevSlices sl, int32_t n_slices,
                                                            int32_t per) {
     __shared__ RowSmem<Staging<RC, kSpmvKP>::value> sm;
     const int32_t s0 = blockIdx.x * per;
     const int32_t s1 = min(n_slices, s0 + per);
-    run_slices<V, RC, Staging<RC, kSpmvKP>::value, false>(m, io, R, sl, s0, s1, sm);
+    run_slices<V, RC, Staging<RC, kSpmvKP>::value, false, ACC>(m, io, R, sl, s0, s1, sm);
 }
 
 // ------------------------------------------------------------------ level-blocked
@@ -341,15 +417,32 @@ __global__ __launch_bounds__(kBlock, 2) void spmv_power_kernel(DevMatrix m, Powe
 // One diagonal of the STEPS schedule: workgroup b computes task tasks[b] =
 // (chunk c, power k).  All tasks of a diagonal are independent; the previous
 // diagonals' results are visible because they ran in earlier launches.
+template <typename V, int RC, bool ACC>
+__device__ __forceinline__ void step_body(const DevMatrix &m, DevSlices sl,
+                                          const int32_t *chunk_sptr, const int32_t *tasks,
+                                          const SegArgs &a, const Coefs &cf, const AccCoefs *ac) {
+    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
+    const int32_t c = tasks[2 * blockIdx.x];
+    const int32_t k = tasks[2 * blockIdx.x + 1];
+    run_slices<V, RC, Staging<RC, kTaskKP>::value, false, ACC>(
+        m, power_io<ACC>(a, cf, ac, k, m.n), a.R, sl, chunk_sptr[c], chunk_sptr[c + 1], sm);
+}
+
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void step_kernel(DevMatrix m, DevSlices sl,
                                                      const int32_t *chunk_sptr,
                                                      const int32_t *tasks, SegArgs a, Coefs cf) {
-    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
-    const int32_t c = tasks[2 * blockIdx.x];
-    const int32_t k = tasks[2 * blockIdx.x + 1];
-    run_slices<V, RC, Staging<RC, kTaskKP>::value, false>(m, power_io(a, cf, k, m.n), a.R, sl, chunk_sptr[c], chunk_sptr[c + 1],
-                               sm);
+    step_body<V, RC, false>(m, sl, chunk_sptr, tasks, a, cf, nullptr);
+}
+
+// The same with weighted sums (a separate kernel, so that the plain one
+// carries no trace of them).
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void step_acc_kernel(DevMatrix m, DevSlices sl,
+                                                         const int32_t *chunk_sptr,
+                                                         const int32_t *tasks, SegArgs a,
+                                                         Coefs cf, AccCoefs ac) {
+    step_body<V, RC, true>(m, sl, chunk_sptr, tasks, a, cf, &ac);
 }
 
 struct LBParams {
@@ -383,8 +476,8 @@ __device__ __forceinline__ bool inputs_ready(const LBParams &P, int32_t t) {
 // unfinished ticket can always proceed; every wait is also bounded by
 // spin_limit, after which the run is flagged as failed and all workgroups
 // leave.
-template <typename V, int RC>
-__global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coefs cf) {
+template <typename V, int RC, bool ACC>
+__device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, const AccCoefs *ac) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
@@ -431,8 +524,9 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coef
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
-        run_slices<V, RC, Staging<RC, kTaskKP>::value, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
-                                   P.s.chunk_sptr[c + 1], sm);
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
+            P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+            P.s.chunk_sptr[c + 1], sm);
         // The results were stored write-through; every wave waits until its
         // stores have completed (vmcnt = 0) before the barrier, so the chunk
         // is visible device-wide when the flag below is published and the
@@ -451,6 +545,17 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coef
         __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coefs cf) {
+    lb_body<V, RC, false>(P, cf, nullptr);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void lb_acc_kernel(LBParams P, Coefs cf,
+                                                                    AccCoefs ac) {
+    lb_body<V, RC, true>(P, cf, &ac);
+}
+
 constexpr int kMaxPending = 8;
 
 // Persistent kernel with skip-ahead: when the inputs of a workgroup's task
@@ -463,8 +568,8 @@ constexpr int kMaxPending = 8;
 // task held, either runs it when retrying or blocks on it; every wait is
 // bounded by spin_limit as in lb_kernel.  Wavefront 0 makes every choice and
 // the other wavefronts learn it through LDS, so control stays uniform.
-template <typename V, int RC>
-__global__ __launch_bounds__(kBlock, kTaskWaves) void lbs_kernel(LBParams P, Coefs cf) {
+template <typename V, int RC, bool ACC>
+__device__ __forceinline__ void lbs_body(const LBParams &P, const Coefs &cf, const AccCoefs *ac) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_task;
     const int tid = threadIdx.x;
@@ -529,9 +634,9 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void lbs_kernel(LBParams P, Coe
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int32_t c = P.s.tasks[2 * t];
         const int32_t k = P.s.tasks[2 * t + 1];
-        run_slices<V, RC, Staging<RC, kTaskKP>::value, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R,
-                                                           P.s.sl, P.s.chunk_sptr[c],
-                                                           P.s.chunk_sptr[c + 1], sm);
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
+            P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+            P.s.chunk_sptr[c + 1], sm);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): write-through results completed
         __syncthreads();
         if (tid == 0)
@@ -539,6 +644,17 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void lbs_kernel(LBParams P, Coe
     }
     if (failed && tid == 0)
         __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void lbs_kernel(LBParams P, Coefs cf) {
+    lbs_body<V, RC, false>(P, cf, nullptr);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void lbs_acc_kernel(LBParams P, Coefs cf,
+                                                                     AccCoefs ac) {
+    lbs_body<V, RC, true>(P, cf, &ac);
 }
 
 // XCD this wave runs on: hardware register XCC_ID (20), bits [3:0].
@@ -554,6 +670,12 @@ struct XcdParams {
     int64_t spin_limit;   // wall-clock ticks
 };
 
+// Kernel arguments stay well inside the 4 KiB argument segment.
+static_assert(sizeof(LBParams) + sizeof(Coefs) + sizeof(AccCoefs) <= 3584,
+              "level-blocked kernel arguments");
+static_assert(sizeof(XcdParams) + sizeof(Coefs) + sizeof(AccCoefs) <= 3584,
+              "XCD kernel arguments");
+
 // Persistent kernel of the XCD schedule.  Queue q holds the tasks of the
 // chunks owned by XCD q, in global dependency order; a workgroup serves the
 // queue of the XCD it runs on (read from the hardware, so the binding holds
@@ -562,8 +684,8 @@ struct XcdParams {
 // unfinished task in the global order is always held by a workgroup of its
 // queue (all earlier tasks of that queue are done), and its dependencies are
 // earlier still, so it can run; waits are bounded by spin_limit in any case.
-template <typename V, int RC>
-__global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_kernel(XcdParams P, Coefs cf) {
+template <typename V, int RC, bool ACC>
+__device__ __forceinline__ void xcd_body(const XcdParams &P, const Coefs &cf, const AccCoefs *ac) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
@@ -605,8 +727,9 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_kernel(XcdParams P, Co
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (!ok) break;
-        run_slices<V, RC, Staging<RC, kTaskKP>::value, true>(P.m, power_io(P.a, cf, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
-                                   P.s.chunk_sptr[c + 1], sm);
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
+            P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
+            P.s.chunk_sptr[c + 1], sm);
         // write-through results, completed (vmcnt = 0) before the barrier
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
@@ -619,6 +742,17 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_kernel(XcdParams P, Co
     }
     if (t < qn && tid == 0)
         __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_kernel(XcdParams P, Coefs cf) {
+    xcd_body<V, RC, false>(P, cf, nullptr);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_acc_kernel(XcdParams P, Coefs cf,
+                                                                     AccCoefs ac) {
+    xcd_body<V, RC, true>(P, cf, &ac);
 }
 
 __global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks) {
@@ -648,6 +782,22 @@ __global__ void permute_kernel(const int32_t *perm, int64_t n, int to_plan, cons
     }
 }
 
+// Complex states from the two weighted sums, on column pairs (column 2j the
+// real, 2j+1 the imaginary part): with weights wa + i wb and a real matrix
+// the real part is a[2j] - b[2j+1] and the imaginary part a[2j+1] + b[2j].
+__global__ void combine_complex_kernel(const double *a, const double *b, int64_t pairs,
+                                       double *out) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < pairs;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const double2 va = reinterpret_cast<const double2 *>(a)[g];
+        const double2 vb = reinterpret_cast<const double2 *>(b)[g];
+        double2 o;
+        o.x = va.x - vb.y;
+        o.y = va.y + vb.x;
+        reinterpret_cast<double2 *>(out)[g] = o;
+    }
+}
+
 // Load-only bandwidth probe: each workgroup sums its share of the buffer
 // `passes` times with 16-byte loads; one double per workgroup is written.
 __global__ __launch_bounds__(kBlock) void load_probe_kernel(const double2 *buf, int64_t n2,
@@ -673,8 +823,12 @@ __global__ __launch_bounds__(kBlock) void load_probe_kernel(const double2 *buf, 
 
 using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, DevSlices, int32_t, int32_t);
 using LbFn = void (*)(LBParams, Coefs);
+using LbAccFn = void (*)(LBParams, Coefs, AccCoefs);
 using StepFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *, SegArgs, Coefs);
+using StepAccFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *, SegArgs, Coefs,
+                           AccCoefs);
 using XcdFn = void (*)(XcdParams, Coefs);
+using XcdAccFn = void (*)(XcdParams, Coefs, AccCoefs);
 
 int r_index(int R) {
     switch (R) {
@@ -687,59 +841,75 @@ int r_index(int R) {
     return 5;  // any other count: generic instantiation
 }
 
+// Kernels by value type and right-hand-side count: R = 1, 2, 4, 8, 16 are
+// specialised, every other count uses the generic instantiation (RC = 0).
 template <typename V>
 struct VTable {
-    SpmvFn spmv[6];
-    LbFn lb[6];
-    LbFn lbs[6];
+    SpmvFn spmv[6], spmv_acc[6];
+    LbFn lb[6], lbs[6];
+    LbAccFn lb_acc[6], lbs_acc[6];
     StepFn step[6];
+    StepAccFn step_acc[6];
     XcdFn xcd[6];
+    XcdAccFn xcd_acc[6];
+    template <int RC>
+    void fill(int i) {
+        spmv[i] = spmv_power_kernel<V, RC, false>;
+        spmv_acc[i] = spmv_power_kernel<V, RC, true>;
+        lb[i] = lb_kernel<V, RC>;
+        lb_acc[i] = lb_acc_kernel<V, RC>;
+        lbs[i] = lbs_kernel<V, RC>;
+        lbs_acc[i] = lbs_acc_kernel<V, RC>;
+        step[i] = step_kernel<V, RC>;
+        step_acc[i] = step_acc_kernel<V, RC>;
+        xcd[i] = xcd_kernel<V, RC>;
+        xcd_acc[i] = xcd_acc_kernel<V, RC>;
+    }
     VTable() {
-        lbs[0] = lbs_kernel<V, 1>;
-        lbs[1] = lbs_kernel<V, 2>;
-        lbs[2] = lbs_kernel<V, 4>;
-        lbs[3] = lbs_kernel<V, 8>;
-        lbs[4] = lbs_kernel<V, 16>;
-        lbs[5] = lbs_kernel<V, 0>;
-        xcd[0] = xcd_kernel<V, 1>;
-        xcd[1] = xcd_kernel<V, 2>;
-        xcd[2] = xcd_kernel<V, 4>;
-        xcd[3] = xcd_kernel<V, 8>;
-        xcd[4] = xcd_kernel<V, 16>;
-        xcd[5] = xcd_kernel<V, 0>;
-        spmv[0] = spmv_power_kernel<V, 1>;  lb[0] = lb_kernel<V, 1>;  step[0] = step_kernel<V, 1>;
-        spmv[1] = spmv_power_kernel<V, 2>;  lb[1] = lb_kernel<V, 2>;  step[1] = step_kernel<V, 2>;
-        spmv[2] = spmv_power_kernel<V, 4>;  lb[2] = lb_kernel<V, 4>;  step[2] = step_kernel<V, 4>;
-        spmv[3] = spmv_power_kernel<V, 8>;  lb[3] = lb_kernel<V, 8>;  step[3] = step_kernel<V, 8>;
-        spmv[4] = spmv_power_kernel<V, 16>; lb[4] = lb_kernel<V, 16>; step[4] = step_kernel<V, 16>;
-        spmv[5] = spmv_power_kernel<V, 0>;  lb[5] = lb_kernel<V, 0>;  step[5] = step_kernel<V, 0>;
+        fill<1>(0);
+        fill<2>(1);
+        fill<4>(2);
+        fill<8>(3);
+        fill<16>(4);
+        fill<0>(5);
     }
 };
 
-const VTable<double> &t64() {
-    static VTable<double> t;
-    return t;
-}
-const VTable<float> &t32() {
-    static VTable<float> t;
+template <typename V>
+const VTable<V> &vt() {
+    static VTable<V> t;
     return t;
 }
 
-SpmvFn spmv_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().spmv[r_index(R)] : t64().spmv[r_index(R)];
+const VTable<double> &t64() { return vt<double>(); }
+const VTable<float> &t32() { return vt<float>(); }
+
+SpmvFn spmv_fn(int value_bits, int R, bool acc) {
+    const int i = r_index(R);
+    if (value_bits == 32) return acc ? t32().spmv_acc[i] : t32().spmv[i];
+    return acc ? t64().spmv_acc[i] : t64().spmv[i];
 }
-LbFn lbs_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().lbs[r_index(R)] : t64().lbs[r_index(R)];
+LbFn lb_fn(int value_bits, int R, bool skip) {
+    const int i = r_index(R);
+    if (value_bits == 32) return skip ? t32().lbs[i] : t32().lb[i];
+    return skip ? t64().lbs[i] : t64().lb[i];
 }
-LbFn lb_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().lb[r_index(R)] : t64().lb[r_index(R)];
+LbAccFn lb_acc_fn(int value_bits, int R, bool skip) {
+    const int i = r_index(R);
+    if (value_bits == 32) return skip ? t32().lbs_acc[i] : t32().lb_acc[i];
+    return skip ? t64().lbs_acc[i] : t64().lb_acc[i];
 }
 StepFn step_fn(int value_bits, int R) {
     return value_bits == 32 ? t32().step[r_index(R)] : t64().step[r_index(R)];
 }
-
+StepAccFn step_acc_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().step_acc[r_index(R)] : t64().step_acc[r_index(R)];
+}
 XcdFn xcd_fn(int value_bits, int R) {
     return value_bits == 32 ? t32().xcd[r_index(R)] : t64().xcd[r_index(R)];
+}
+XcdAccFn xcd_acc_fn(int value_bits, int R) {
+    return value_bits == 32 ? t32().xcd_acc[r_index(R)] : t64().xcd_acc[r_index(R)];
 }
 
 }  // namespace
@@ -753,31 +923,41 @@ int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream) {
 
 int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_t per,
                       const double *in, const double *inm1, double *out, int32_t R, int recur,
-                      double alpha, double beta, double gamma, void *stream) {
+                      double alpha, double beta, double gamma, const AccStep *acc,
+                      void *stream) {
     if (R < 1 || R > 16 || per < 1) return (int)hipErrorInvalidValue;
     if (m.n == 0 || n_slices == 0) return 0;
-    PowerIO io{in, inm1, out, alpha, beta, gamma, recur};
+    PowerIO io{in, inm1, out, alpha, beta, gamma, recur,
+               acc ? acc->acc_a : nullptr, acc ? acc->acc_b : nullptr,
+               acc ? acc->wa : 0.0, acc ? acc->wb : 0.0, acc ? acc->wa0 : 0.0,
+               acc ? acc->wb0 : 0.0, acc ? acc->ma : 0, acc ? acc->mb : 0};
     const int32_t grid = (n_slices + per - 1) / per;
-    hipLaunchKernelGGL(spmv_fn(m.value_bits, R), dim3((unsigned)grid), dim3(kBlock), 0,
+    hipLaunchKernelGGL(spmv_fn(m.value_bits, R, acc != nullptr), dim3((unsigned)grid), dim3(kBlock), 0,
                        (hipStream_t)stream, m, io, R, sl, n_slices, per);
     return (int)hipGetLastError();
 }
 
 int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
-                int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream) {
+                int32_t n_tasks, const SegArgs &a, const Coefs *cf, const AccCoefs *acc,
+                void *stream) {
     if (a.R < 1 || a.R > 16 || a.p < 1 || a.p > kMaxSegPowers) return (int)hipErrorInvalidValue;
     if (n_tasks <= 0) return 0;
     Coefs c{};
     if (cf) c = *cf;
-    hipLaunchKernelGGL(step_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock), 0,
-                       (hipStream_t)stream, m, sl, chunk_sptr, tasks, a, c);
+    if (acc)
+        hipLaunchKernelGGL(step_acc_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock),
+                           0, (hipStream_t)stream, m, sl, chunk_sptr, tasks, a, c, *acc);
+    else
+        hipLaunchKernelGGL(step_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock), 0,
+                           (hipStream_t)stream, m, sl, chunk_sptr, tasks, a, c);
     return (int)hipGetLastError();
 }
 
 int lb_max_workgroups(int value_bits, int R, int device) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(lb_fn(value_bits, R)), kBlock, 0) != hipSuccess)
+            &per_cu, reinterpret_cast<const void *>(lb_fn(value_bits, R, false)), kBlock, 0) !=
+        hipSuccess)
         return 0;
     // At most kTaskWaves workgroups per CU even where registers and LDS would
     // allow more (the unstaged path for R >= 4): more persistent workgroups
@@ -789,8 +969,8 @@ int lb_max_workgroups(int value_bits, int R, int device) {
 }
 
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
-              const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
-              int pending, void *stream) {
+              const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
+              int64_t spin_limit, int pending, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (pending < 0 || pending > kMaxPending) return (int)hipErrorInvalidValue;
@@ -798,14 +978,18 @@ int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
     LBParams P{m, s, ws, a, spin_limit, pending};
     Coefs c{};
     if (cf) c = *cf;
-    hipLaunchKernelGGL(pending > 0 ? lbs_fn(m.value_bits, a.R) : lb_fn(m.value_bits, a.R),
-                       dim3(workgroups), dim3(kBlock), 0, (hipStream_t)stream, P, c);
+    if (acc)
+        hipLaunchKernelGGL(lb_acc_fn(m.value_bits, a.R, pending > 0), dim3(workgroups),
+                           dim3(kBlock), 0, (hipStream_t)stream, P, c, *acc);
+    else
+        hipLaunchKernelGGL(lb_fn(m.value_bits, a.R, pending > 0), dim3(workgroups), dim3(kBlock),
+                           0, (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
 }
 
 int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
-               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
-               void *stream) {
+               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
+               int64_t spin_limit, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (s.n_queues < 1 || s.n_queues > kMaxQueues) return (int)hipErrorInvalidValue;
@@ -813,8 +997,12 @@ int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &
     XcdParams P{m, s, ws, a, spin_limit};
     Coefs c{};
     if (cf) c = *cf;
-    hipLaunchKernelGGL(xcd_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
-                       (hipStream_t)stream, P, c);
+    if (acc)
+        hipLaunchKernelGGL(xcd_acc_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
+                           (hipStream_t)stream, P, c, *acc);
+    else
+        hipLaunchKernelGGL(xcd_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
+                           (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
 }
 
@@ -849,6 +1037,18 @@ int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in
     if (grid > 65536) grid = 65536;
     hipLaunchKernelGGL(permute_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
                        perm, n, to_plan, in, out, nvec, R);
+    return (int)hipGetLastError();
+}
+
+int launch_combine_complex(const double *a, const double *b, int64_t n, int R, double *out,
+                           void *stream) {
+    if (R < 2 || (R & 1)) return (int)hipErrorInvalidValue;
+    const int64_t pairs = n * (R / 2);
+    if (pairs == 0) return 0;
+    int64_t grid = (pairs + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(combine_complex_kernel, dim3((unsigned)grid), dim3(256), 0,
+                       (hipStream_t)stream, a, b, pairs, out);
     return (int)hipGetLastError();
 }
 

@@ -117,21 +117,56 @@ struct DevSlices {
     const int32_t *snz;    // n_slices + 1 nonzero offsets (rowptr at srow)
 };
 
+// Weighted sums of the powers (polynomial evaluation): what the task that
+// computes y_k does with one sum.  The host derives the modes from the
+// weights w_0..w_p so that the sum runs in increasing k and skips zero
+// weights: the first nonzero term sets the sum, later ones add to it.
+enum AccMode : int8_t {
+    kAccNone = 0,      // weight zero: leave the sum alone
+    kAccSet = 1,       // acc = w*y_k
+    kAccAdd = 2,       // acc = acc + w*y_k
+    kAccSetWithX = 3,  // acc = w_0*y_0 + w*y_1  (first power only)
+    kAccSetX = 4,      // acc = w_0*y_0          (first power only, w_1 = 0)
+    kAccZero = 5,      // acc = 0                (last power, all weights zero)
+};
+
 struct Coefs {
     double alpha[kMaxSegPowers];
     double beta[kMaxSegPowers];
     double gamma[kMaxSegPowers];
 };
 
+// Weights of the segment's powers for the two weighted sums (the kernels
+// that take these are separate from the plain ones).
+struct AccCoefs {
+    double wa[kMaxSegPowers];    // weight of the segment's power k (index k-1), sum a
+    double wb[kMaxSegPowers];    // the same for sum b
+    double wa0, wb0;             // weights of y_0 (first segment)
+    int8_t ma[kMaxSegPowers];    // AccMode per power, sum a
+    int8_t mb[kMaxSegPowers];
+};
+
 // One launch covers powers 1..p of a segment: y_0 = in0, y_{-1} = inm1
-// (recurrence only, may be null), outputs Y[(k-1)*n*R ...].
+// (recurrence only, may be null).  Plain kernels: outputs Y[(k-1)*n*R ...].
+// Weighted-sum kernels: Y is a ring of two vectors, the segment's power k
+// (the sequence's power g = k0 + k) goes to slot (g-1) mod 2, and acc_a /
+// acc_b are the sums (acc_b may be null).
 struct SegArgs {
     const double *in0;
     const double *inm1;
     double *Y;
+    double *acc_a, *acc_b;
     int32_t p;
     int32_t R;
     int32_t recur;
+    int32_t k0;
+};
+
+// The weighted-sum work of one power of the p x SpMV kernel.
+struct AccStep {
+    double *acc_a, *acc_b;
+    double wa, wb, wa0, wb0;
+    int32_t ma, mb;
 };
 
 struct DevSchedule {
@@ -162,23 +197,31 @@ struct DevXcdSchedule {
 // Launchers (kernels.hip).  All return hipError_t as int.
 int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);  // also clears the queue tickets
 // pending > 0 selects the skip-ahead kernel with that many parked tasks (<= 8).
+// acc != null: the ring / weighted-sum kernels (SegArgs ring, acc_a, acc_b).
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
-              const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
-              int pending, void *stream);
+              const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
+              int64_t spin_limit, int pending, void *stream);
 // One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
 int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
-                int32_t n_tasks, const SegArgs &a, const Coefs *cf, void *stream);
+                int32_t n_tasks, const SegArgs &a, const Coefs *cf, const AccCoefs *acc,
+                void *stream);
 // One power over all rows; workgroup b walks slices [b*per, (b+1)*per).
+// acc may be null (no weighted sums).
 int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_t per,
                       const double *in, const double *inm1, double *out, int32_t R, int recur,
-                      double alpha, double beta, double gamma, void *stream);
+                      double alpha, double beta, double gamma, const AccStep *acc,
+                      void *stream);
+// out[i][2j] = a[i][2j] - b[i][2j+1], out[i][2j+1] = a[i][2j+1] + b[i][2j]
+// for the n rows of R (even) columns.
+int launch_combine_complex(const double *a, const double *b, int64_t n, int R, double *out,
+                           void *stream);
 int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in, double *out,
                    int nvec, int R, void *stream);
 int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int workgroups,
                       double *sink, void *stream);
 int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
-               const SegArgs &a, const Coefs *cf, int workgroups, int64_t spin_limit,
-               void *stream);
+               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
+               int64_t spin_limit, void *stream);
 // XCDs of the device when workgroup i runs on XCD i mod n (checked with a probe
 // kernel), else 1.
 int detect_xcds(int device);

@@ -39,7 +39,9 @@ def asm(tmp_path_factory):
 
 
 def kernels(asm_text, name):
-    """{symbol: [lines]} for every kernel whose mangled name contains `name`."""
+    """{symbol: [lines]} for every kernel whose mangled name contains `name`:
+    the lines from its label to the end-of-function marker (a kernel may
+    hold several s_endpgm, e.g. an early return placed first)."""
     out = {}
     cur = None
     for line in asm_text.splitlines():
@@ -49,9 +51,10 @@ def kernels(asm_text, name):
             out[cur] = []
             continue
         if cur is not None:
-            out[cur].append(line)
-            if "s_endpgm" in line:
+            if line.startswith(".Lfunc_end"):
                 cur = None
+                continue
+            out[cur].append(line)
     return out
 
 
@@ -93,15 +96,16 @@ def loops_with_barrier_and_divergent_exit(lines):
     return bad
 
 
-def test_task_loop_has_uniform_exit(asm):
-    ks = kernels(asm, "lb_kernel")
+@pytest.mark.parametrize("name", ["lb_kernel", "lb_acc_kernel"])
+def test_task_loop_has_uniform_exit(asm, name):
+    ks = kernels(asm, name)
     assert len(ks) == 12  # 6 right-hand-side variants x 2 value types
     for sym, lines in ks.items():
         assert any("s_barrier" in l for l in lines)
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
 
 
-@pytest.mark.parametrize("name", ["xcd_kernel", "lbs_kernel"])
+@pytest.mark.parametrize("name", ["xcd_kernel", "lbs_kernel", "xcd_acc_kernel", "lbs_acc_kernel"])
 def test_other_task_loops_have_uniform_exit(asm, name):
     ks = kernels(asm, name)
     assert len(ks) == 12
@@ -111,7 +115,7 @@ def test_other_task_loops_have_uniform_exit(asm, name):
 
 def test_baseline_row_loop_has_uniform_exit(asm):
     ks = kernels(asm, "spmv_power_kernel")
-    assert len(ks) == 12
+    assert len(ks) == 24  # with and without the weighted sums
     for sym, lines in ks.items():
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
 
@@ -154,7 +158,8 @@ def _publish_ok(lines):
     assert n_checked >= 1
 
 
-@pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel", "lbs_kernel"])
+@pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel", "lbs_kernel", "lb_acc_kernel",
+                                  "xcd_acc_kernel", "lbs_acc_kernel"])
 def test_results_write_through_and_publish_after_completion(asm, name):
     for sym, lines in kernels(asm, name).items():
         body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
