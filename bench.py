@@ -226,6 +226,84 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
     return out
 
 
+def time_step(torch, mpk, w, steps, warmup, stream):
+    """One Chebyshev time step exp(-i dt H) psi on the Anderson lattice (160^3,
+    FP32 values, 4 complex states as 8 real columns, M = 16, dt = 1): the
+    weighted sums accumulated in the kernels over a two-vector ring, level-
+    blocked and as p x SpMV, against the recurrence that writes all M vectors
+    (without even summing them).  The result is checked bit for bit against
+    the oracle's sums with the same weights."""
+    import numpy as np
+    import oracle
+    A, x, _, _ = w.config("anderson160_cheb16_r8")
+    M, dt = 16, 1.0
+    n, R = A.n, x.shape[1]
+    xd = torch.from_numpy(x).cuda()
+    al, be, ga, wa, wb = mpk.cheb_time_coefficients(M, dt)
+    # the lattice's own order: faster than BFS order for both forms here
+    P = mpk.Plan(A, value_bits=32, reorder="none")
+    Y = torch.empty((M, n, R), dtype=torch.float64, device="cuda")
+    tq = P.autotune(xd, M, Y, reps=3, recur=True, stream=stream)
+    out = torch.empty_like(xd)
+    acc = torch.empty((2, n, R), dtype=torch.float64, device="cuda")
+    work = torch.empty((2, n, R), dtype=torch.float64, device="cuda")
+
+    def fused(baseline):
+        run = P.run_baseline_poly if baseline else P.run_poly
+        run(xd, wa, wb, al, be, ga, acc=acc, work=work, stream=stream)
+        P.combine_complex(acc, out, stream=stream)
+    lb = time_calls(lambda: fused(False), steps, warmup, torch, stream)["median_ms"]
+    P.sync()
+    got_lb = out.cpu().numpy()
+    tr = time_calls(lambda: fused(True), steps, warmup, torch, stream)["median_ms"]
+    P.sync()
+    got_tr = out.cpu().numpy()
+    full = time_calls(lambda: P.run_recur(xd, al, be, ga, Y=Y, stream=stream), steps, warmup,
+                      torch, stream)["median_ms"]
+    full_tr = time_calls(lambda: P.run_baseline_recur(xd, al, be, ga, Y=Y, stream=stream), steps,
+                         warmup, torch, stream)["median_ms"]
+    P.sync()
+    ra, rb = oracle.poly_sums(A, x, al, be, ga, wa, wb, value_bits=32)
+    ref = oracle.combine_complex(ra, rb)
+    exact = bool(np.array_equal(got_lb, ref) and np.array_equal(got_tr, ref))
+    def norms(v):  # per complex state, with an exactly rounded sum of squares
+        import math
+        sq = v[:, 0::2] ** 2 + v[:, 1::2] ** 2
+        return np.array([math.sqrt(math.fsum(sq[:, j])) for j in range(sq.shape[1])])
+    norm_drift = float(np.max(np.abs(norms(got_lb) / norms(x) - 1.0)))
+    P.close()
+    del Y, acc, work, out, xd
+    V = 8 * n * R
+    Ab = 4 * (n + 1) + 8 * A.nnz
+    flop = mpk.flops(A.nnz, n, M, R, recur=True) + 2.0 * n * R * (M + 1) + n * R
+    # p x SpMV: A and y_{k-1} per power, y_{k-2} read and y_k written from the
+    # second power on, one sum read and written per power after the first
+    # (the weights alternate between the real and imaginary sums), two sums
+    # set at the first power, then the combination (2 V read, V written)
+    trad_b = M * Ab + V + 2 * V + (M - 1) * 5 * V + 3 * V
+    # level-blocked ideal: A, x, the two ring slots and the two sums once
+    lb_b = Ab + V + 2 * V + 2 * V + 3 * V
+    res = {"n": n, "nnz": A.nnz, "M": M, "dt": dt, "states": R // 2, "real_columns": R,
+           "values": "fp32", "schedule": tq["schedule"], "gflops_flop_count": flop,
+           "lb_fused_ms": round(lb, 4), "lb_fused_gflops": round(flop / lb / 1e6, 1),
+           "pxspmv_fused_ms": round(tr, 4), "pxspmv_fused_gflops": round(flop / tr / 1e6, 1),
+           "recurrence_writing_all_M_vectors_ms": {"level_blocked": round(full, 4),
+                                                   "pxspmv": round(full_tr, 4)},
+           "reorder": "none",
+           "device_vectors_fused": 4, "device_vectors_unfused": M,
+           "bit_identical_to_oracle_sums": exact, "norm_drift": norm_drift,
+           "pxspmv_roofline": {"bound": "hbm", "algorithmic_bytes": trad_b,
+                               "achieved_GBs": round(trad_b / tr / 1e6, 1),
+                               "frac": round(trad_b / tr / 1e6 / HBM_PEAK_GBS, 4)},
+           "lb_roofline": {"bound": "hbm", "algorithmic_bytes": lb_b,
+                           "achieved_GBs": round(lb_b / lb / 1e6, 1),
+                           "frac": round(lb_b / lb / 1e6 / HBM_PEAK_GBS, 4)}}
+    log(f"[bench] time step: level-blocked fused {lb:.3f} ms ({tq['schedule']}), "
+        f"p x SpMV fused {tr:.3f} ms, recurrence writing all vectors {full:.3f} / {full_tr:.3f} ms, "
+        f"exact {exact}")
+    return res
+
+
 def cpu_baseline(A, x, p, budget_s=20.0):
     """The CPU oracle on all host cores: whole runs of the workload, bounded in time."""
     import oracle
@@ -274,6 +352,8 @@ def main():
                     help="headline workload (default: the 128^3 stencil; others for profiling)")
     ap.add_argument("--value-bits", type=int, default=None, choices=[32, 64],
                     help="matrix value precision (default: the workload's)")
+    ap.add_argument("--time-step-only", action="store_true",
+                    help="print only the Chebyshev time-step measurement (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
@@ -295,6 +375,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each": a.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.time_step_only:
+        print(json.dumps(time_step(torch, mpk, w, args.steps, args.warmup, stream)), flush=True)
         return
     t0 = time.perf_counter()
     A, x, p, kind = w.config(args.workload)
@@ -413,6 +496,8 @@ def main():
     del Y, B
     if not args.no_configs and args.schedule is None and args.workload == WORKLOAD:
         out["other_configs"] = other_configs(torch, mpk, w, args.steps, args.warmup, stream)
+        out["other_configs"]["cheb_time_step_anderson160_m16_s4_fp32"] = time_step(
+            torch, mpk, w, args.steps, args.warmup, stream)
     if not args.no_serve and args.workload == WORKLOAD:
         out["serving"] = serving(torch, mpk, w)
     if not args.no_cpu and args.workload == WORKLOAD:
