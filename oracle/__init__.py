@@ -23,6 +23,9 @@ Distributed-Memory Parallel Matrix Power Kernels", that it follows):
 * :func:`bfs_levels` -- the level sets of Sec. "RACE Applied to the Matrix
   Power Kernel" (the case equation for L(i)), computed literally with set
   operations on the symmetrised graph G(A).
+* :func:`pseudo_peripheral_root` -- a BFS root far from the rest of the
+  graph (the root choice the paper leaves open when it roots the levels at
+  row 0), by the George-Liu iteration.
 * :func:`lp_diagonal_order` -- the LB-MPK traversal of the Lp diagram: the
   diagonals i + p = const in increasing order, each walked from bottom-right
   (largest level) to top-left (Fig. lp_basic).
@@ -301,6 +304,45 @@ def bfs_levels(n: int, rowptr, col, root: int = 0):
     iperm = np.empty(n, dtype=np.int64)
     iperm[perm] = np.arange(n)
     return levels, perm, iperm
+
+
+def pseudo_peripheral_root(n: int, rowptr, col, start: int = 0) -> int:
+    """A pseudo-peripheral vertex of start's component of G(A) (George-Liu).
+
+    Take x = start.  Repeatedly run a breadth-first search from x and pick,
+    in its last distance layer, the vertex y of smallest degree (number of
+    distinct neighbours other than itself; ties to the smaller index).  If
+    y's eccentricity exceeds x's, continue from y; otherwise x is the
+    result.  The levels of the paper rooted at this vertex are as many and
+    as thin as this heuristic can make them.
+    """
+    if n == 0:
+        return 0
+    N = neighbour_sets(n, rowptr, col)
+
+    def layers(r):
+        dist = {r: 0}
+        front = [r]
+        out = [front]
+        while True:
+            nxt = sorted({v for u in front for v in N[u] if v not in dist})
+            if not nxt:
+                return out
+            for v in nxt:
+                dist[v] = len(out)
+            out.append(nxt)
+            front = nxt
+
+    x = start
+    Lx = layers(x)
+    while True:
+        last = Lx[-1]
+        y = min(last, key=lambda v: (len(N[v]), v))
+        Ly = layers(y)
+        if len(Ly) > len(Lx):
+            x, Lx = y, Ly
+        else:
+            return x
 
 
 def lp_diagonal_order(n_levels: int, p_m: int):

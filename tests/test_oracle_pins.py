@@ -323,3 +323,54 @@ def test_time_step_dense_matches_matrix_exponential():
     # a unitary step keeps the norm
     z = out[:, 0] + 1j * out[:, 1]
     assert abs(np.linalg.norm(z) - np.linalg.norm(psi)) < 1e-12
+
+
+# ------------------------------------------------------------ root selection
+
+def _ecc(N, r):
+    seen, front, depth = {r}, {r}, 0
+    while True:
+        nxt = {v for u in front for v in N[u]} - seen
+        if not nxt:
+            return depth
+        seen |= nxt
+        front = nxt
+        depth += 1
+
+
+def _csr_from_edges(n, edges):
+    d = np.zeros((n, n))
+    for a, b in edges:
+        d[a, b] = d[b, a] = 1.0
+    for i in range(n):
+        d[i, i] = 4.0
+    return w.from_dense(d)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_peripheral_root_of_a_tree_ends_a_diameter(seed):
+    # on a tree, a farthest vertex from any vertex ends a longest path, so
+    # the root's eccentricity is the tree's diameter (brute force over all)
+    g = np.random.default_rng(300 + seed)
+    n = int(g.integers(5, 60))
+    edges = [(i, int(g.integers(0, i))) for i in range(1, n)]
+    A = _csr_from_edges(n, edges)
+    r = oracle.pseudo_peripheral_root(n, A.rowptr, A.col)
+    N = oracle.neighbour_sets(n, A.rowptr, A.col)
+    assert _ecc(N, r) == max(_ecc(N, v) for v in range(n))
+
+
+def test_peripheral_root_of_a_scrambled_path_is_an_end():
+    n = 31
+    order = np.random.default_rng(9).permutation(n)      # path visits order[0], order[1], ...
+    edges = [(int(order[i]), int(order[i + 1])) for i in range(n - 1)]
+    A = _csr_from_edges(n, edges)
+    r = oracle.pseudo_peripheral_root(n, A.rowptr, A.col)
+    assert r in (int(order[0]), int(order[-1]))
+
+
+def test_peripheral_root_of_a_grid_is_a_corner():
+    A = w.stencil_2d5(9)      # 9 x 9 grid, row 0 is a corner
+    for start in (40, 13, 0):
+        r = oracle.pseudo_peripheral_root(A.n, A.rowptr, A.col, start=start)
+        assert r in (0, 8, 72, 80), (start, r)
