@@ -92,12 +92,20 @@ typedef struct {
     const double *val;       /* nnz entries                                    */
 } mpk_csr_t;
 
+/* opts.root: a pseudo-peripheral row of row 0's component, found by the
+ * George-Liu iteration (repeated BFS from a least-degree vertex of the
+ * previous search's last level while the eccentricity grows).  The paper
+ * roots the levels at row 0 as a rule; a peripheral root gives as many and
+ * as thin levels as the heuristic finds.  Costs a few extra BFS sweeps. */
+#define MPK_ROOT_PERIPHERAL (-1)
+
 typedef struct {
     int value_bits;          /* 64 (default) or 32: values stored as float,
                                 promoted to double before each product        */
     int reorder;             /* MPK_REORDER_BFS (default) or MPK_REORDER_NONE   */
     int order;               /* MPK_ORDER_ORIGINAL (default) or MPK_ORDER_PLAN  */
-    int root;                /* BFS root row (default 0)                       */
+    int root;                /* BFS root row (default 0), or
+                                MPK_ROOT_PERIPHERAL                           */
     int device;              /* HIP device, MPK_DEVICE_CURRENT or MPK_DEVICE_NONE */
 } mpk_plan_opts_t;
 

@@ -149,7 +149,7 @@ class Plan:
     """
 
     def __init__(self, A, value_bits: int = 64, reorder: str = "bfs", order: str = "original",
-                 root: int = 0, device=MPK_DEVICE_CURRENT):
+                 root=0, device=MPK_DEVICE_CURRENT):
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
@@ -164,7 +164,7 @@ class Plan:
         opts.value_bits = int(value_bits)
         opts.reorder = {"bfs": MPK_REORDER_BFS, "none": MPK_REORDER_NONE}[reorder]
         opts.order = {"original": MPK_ORDER_ORIGINAL, "plan": MPK_ORDER_PLAN}[order]
-        opts.root = int(root)
+        opts.root = -1 if root == "peripheral" else int(root)   # MPK_ROOT_PERIPHERAL
         if device is None or device == "none":
             device = MPK_DEVICE_NONE
         opts.device = int(device)
@@ -424,15 +424,28 @@ class Plan:
         al, be, ga, wa, wb = cheb_time_coefficients(M, dt)
         run = self.run_baseline_poly if baseline else self.run_poly
         acc, work = run(psi, wa, wb, al, be, ga, stream=stream)
-        if out is None:
-            out = torch.empty_like(psi)
-        check(self._lib.mpk_combine_complex(self._h, ctypes.c_void_p(acc.data_ptr()), R,
-                                            ctypes.c_void_p(out.data_ptr()),
-                                            _stream_handle(stream)))
+        out = self.combine_complex(acc, out, stream=stream)
         if stream is not None:
             # the temporaries stay reserved until the work queued on `stream` is done
             acc.record_stream(stream)
             work.record_stream(stream)
+        return out
+
+    def combine_complex(self, acc, out=None, stream=None):
+        """Complex states from the two sums of run_poly (mpk_combine_complex):
+        acc (2, n, 2m) -> out (n, 2m) with column pairs (real, imaginary)."""
+        torch = _torch()
+        if acc.dim() != 3 or acc.shape[0] != 2 or acc.shape[1] != self.n or \
+                acc.dtype != torch.float64 or not acc.is_contiguous() or not acc.is_cuda:
+            raise ValueError("acc must be a contiguous float64 device tensor (2, n, nrhs)")
+        R = int(acc.shape[2])
+        if out is None:
+            out = torch.empty((self.n, R), dtype=torch.float64, device=acc.device)
+        elif out.numel() != self.n * R or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of n x nrhs values")
+        check(self._lib.mpk_combine_complex(self._h, ctypes.c_void_p(acc.data_ptr()), R,
+                                            ctypes.c_void_p(out.data_ptr()),
+                                            _stream_handle(stream)))
         return out
 
     def permute(self, v, to_plan: bool, out=None, stream=None):

@@ -694,7 +694,8 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
     std::string err;
     mpk_status_t st = validate_csr(A, !host_only, err);
     if (st) return fail(st, err);
-    if (A->n > 0 && (o.root < 0 || o.root >= A->n)) return fail(MPK_EINVAL, "root out of range");
+    if (A->n > 0 && o.root != MPK_ROOT_PERIPHERAL && (o.root < 0 || o.root >= A->n))
+        return fail(MPK_EINVAL, "root out of range");
 
     const double t0 = now_ms();
     std::unique_ptr<mpk_plan_s> plan;

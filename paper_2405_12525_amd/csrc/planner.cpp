@@ -8,6 +8,7 @@
 // schedule generalises the Lp-diagram traversal of the same section (Fig.
 // lp_basic) from whole levels to chunks of rows.
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -58,6 +59,74 @@ mpk_status_t validate_csr(const mpk_csr_t *A, bool need_values, std::string &err
     return MPK_OK;
 }
 
+// Breadth-first search over the symmetrised graph (stored entries and their
+// mirrors, self-loops ignored) from r: returns the eccentricity of r within
+// its component and leaves the last distance layer in `last` (ascending).
+// mark[] holds a stamp per visited vertex; `stamp` must be new for each call.
+static int bfs_last_layer(const int32_t *rowptr, const int32_t *col, const int32_t *tptr,
+                          const int32_t *tcol, int32_t r, std::vector<int32_t> &mark,
+                          int32_t stamp, std::vector<int32_t> &last) {
+    std::vector<int32_t> front{r}, next;
+    mark[r] = stamp;
+    int depth = 0;
+    for (;;) {
+        next.clear();
+        for (int32_t u : front) {
+            for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
+                if (mark[col[e]] != stamp) {
+                    mark[col[e]] = stamp;
+                    next.push_back(col[e]);
+                }
+            for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e)
+                if (mark[tcol[e]] != stamp) {
+                    mark[tcol[e]] = stamp;
+                    next.push_back(tcol[e]);
+                }
+        }
+        if (next.empty()) break;
+        front.swap(next);
+        ++depth;
+    }
+    std::sort(front.begin(), front.end());
+    last.swap(front);
+    return depth;
+}
+
+// George-Liu pseudo-peripheral vertex of start's component: from x, take the
+// vertex y of least degree (distinct neighbours other than itself, ties to
+// the smaller index) in the last BFS layer; move to y while that increases
+// the eccentricity.
+static int32_t pseudo_peripheral(int64_t n, const int32_t *rowptr, const int32_t *col,
+                                 const int32_t *tptr, const int32_t *tcol, int32_t start) {
+    std::vector<int32_t> mark(n, -1), last, nb;
+    int32_t stamp = 0;
+    int32_t x = start;
+    int ex = bfs_last_layer(rowptr, col, tptr, tcol, x, mark, stamp++, last);
+    for (;;) {
+        int32_t y = -1;
+        size_t best = SIZE_MAX;
+        for (int32_t v : last) {
+            nb.clear();
+            for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e)
+                if (col[e] != v) nb.push_back(col[e]);
+            for (int32_t e = tptr[v]; e < tptr[v + 1]; ++e)
+                if (tcol[e] != v) nb.push_back(tcol[e]);
+            std::sort(nb.begin(), nb.end());
+            const size_t deg = (size_t)(std::unique(nb.begin(), nb.end()) - nb.begin());
+            if (deg < best) {  // `last` is ascending: ties keep the smaller index
+                best = deg;
+                y = v;
+            }
+        }
+        std::vector<int32_t> ylast;
+        const int ey = bfs_last_layer(rowptr, col, tptr, tcol, y, mark, stamp++, ylast);
+        if (ey <= ex) return x;
+        x = y;
+        ex = ey;
+        last.swap(ylast);
+    }
+}
+
 Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t root) {
     Levels lv;
     lv.perm.reserve(n);
@@ -82,6 +151,8 @@ Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t 
     int64_t lowest = 0;  // every row below this index is already levelled
     int64_t visited = 0;
     int32_t start = (root >= 0 && root < n) ? root : 0;
+    if (root == MPK_ROOT_PERIPHERAL)
+        start = pseudo_peripheral(n, rowptr, col, tptr.data(), tcol.data(), 0);
     // claim v for the next level (several threads may find it at once)
     auto claim = [&seen](int32_t v) {
         return __atomic_load_n(&seen[v], __ATOMIC_RELAXED) == 0 &&

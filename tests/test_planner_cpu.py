@@ -71,6 +71,29 @@ def test_planner_root_option():
     assert np.array_equal(perm, perm_o)
 
 
+@pytest.mark.parametrize("seed,sym", [(4, True), (5, False), (6, True)])
+def test_planner_peripheral_root_matches_oracle(seed, sym):
+    # the same George-Liu choice (an integer: exact), then the same levels
+    A = w.random_sparse(300, 0.008, seed, symmetric_pattern=sym)
+    r = oracle.pseudo_peripheral_root(A.n, A.rowptr, A.col)
+    lv, perm_o, _ = oracle.bfs_levels(A.n, A.rowptr, A.col, root=r)
+    lp, perm = host_plan(A, root="peripheral").levels()
+    assert perm[0] == r
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(np.diff(lp), [len(L) for L in lv])
+
+
+def test_planner_peripheral_root_on_lattices():
+    # a corner of the 3D 27-point stencil, and an end of a banded matrix
+    A = w.stencil_3d27(7)
+    lp, perm = host_plan(A, root="peripheral").levels()
+    corners = {x + 7 * (y + 7 * z) for x in (0, 6) for y in (0, 6) for z in (0, 6)}
+    assert perm[0] in corners and len(lp) - 1 == 7
+    B = w.tridiag_1d(50)
+    _, permb = host_plan(B, root="peripheral").levels()
+    assert permb[0] in (0, 49)
+
+
 def _level_of(lp, n):
     lev = np.empty(n, dtype=np.int64)
     for i in range(len(lp) - 1):
