@@ -226,6 +226,22 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
     return out
 
 
+def flush_bytes(wts, V):
+    """HBM bytes of one weighted sum: the kernels flush its pending nonzero
+    terms k..min(k+2, p) at power min(k+2, p), the first flush writing the
+    sum (V) and each later one reading and writing it (2 V)."""
+    p = len(wts) - 1
+    k, n_flush = 0, 0
+    while True:
+        while k <= p and wts[k] == 0.0:
+            k += 1
+        if k > p:
+            break
+        n_flush += 1
+        k = min(k + 2, p) + 1
+    return V if n_flush == 0 else V + 2 * V * (n_flush - 1)
+
+
 def time_step(torch, mpk, w, steps, warmup, stream):
     """One Chebyshev time step exp(-i dt H) psi on the Anderson lattice (160^3,
     FP32 values, 4 complex states as 8 real columns, M = 16, dt = 1): the
@@ -276,11 +292,12 @@ def time_step(torch, mpk, w, steps, warmup, stream):
     V = 8 * n * R
     Ab = 4 * (n + 1) + 8 * A.nnz
     flop = mpk.flops(A.nnz, n, M, R, recur=True) + 2.0 * n * R * (M + 1) + n * R
-    # p x SpMV: A and y_{k-1} per power, y_{k-2} read and y_k written from the
-    # second power on, one sum read and written per power after the first
-    # (the weights alternate between the real and imaginary sums), two sums
-    # set at the first power, then the combination (2 V read, V written)
-    trad_b = M * Ab + V + 2 * V + (M - 1) * 5 * V + 3 * V
+    # p x SpMV: A, the gathered y_{k-1} and the written y_k per power, y_{k-2}
+    # read from the second power on, the sums' flushes (a sum's first flush
+    # writes it, every later one reads and writes it), then the combination
+    # (2 V read, V written)
+    trad_b = M * Ab + M * V + (M - 1) * V + M * V + flush_bytes(wa, V) + flush_bytes(wb, V) \
+        + 3 * V
     # level-blocked ideal: A, x, the two ring slots and the two sums once
     lb_b = Ab + V + 2 * V + 2 * V + 3 * V
     res = {"n": n, "nnz": A.nnz, "M": M, "dt": dt, "states": R // 2, "real_columns": R,

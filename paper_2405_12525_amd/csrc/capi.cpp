@@ -365,27 +365,38 @@ mpk_status_t task_slices(mpk_plan_t plan, SchedEntry *se, int R, SliceSet **out)
 }
 
 // Weighted sums of the powers (mpk_run_poly): host weights, device sums and
-// the AccMode of each power 1..p (index k) per sum.
+// the AccFlags of each power 1..p (index m) per sum.
 struct Poly {
     const double *wa, *wb;
     double *acc_a, *acc_b;
-    std::vector<int8_t> ma, mb;
+    std::vector<uint8_t> fa, fb;
+    int p;
+    double w(const double *v, int k) const { return v && k >= 0 && k <= p ? v[k] : 0.0; }
 };
 
-// Modes that make the device sum equal sum_{k=0..p} w[k] y_k taken in
-// increasing k with zero weights skipped (all zero: the sum is zero).
-void acc_modes(const double *w, int p, std::vector<int8_t> &mode) {
-    mode.assign((size_t)p + 1, kAccNone);
+// Flushes that make the device sum equal sum_{k=0..p} w[k] y_k taken in
+// increasing k with zero weights skipped (all zero: the sum is zero).  The
+// earliest pending term k is flushed as late as it can be, at power
+// m = min(k+2, p), together with every nonzero term in k..m; the task at
+// power m holds y_{m-2}, y_{m-1} and y_m.  With the Chebyshev weights, which
+// alternate between the two sums, each sum is flushed every fourth power.
+void acc_flushes(const double *w, int p, std::vector<uint8_t> &f) {
+    f.assign((size_t)p + 1, 0);
     if (!w) return;
-    const bool h0 = w[0] != 0.0, h1 = w[1] != 0.0;
-    mode[1] = h0 && h1 ? kAccSetWithX : (h0 ? kAccSetX : (h1 ? kAccSet : kAccNone));
-    bool started = h0 || h1;
-    for (int k = 2; k <= p; ++k)
-        if (w[k] != 0.0) {
-            mode[k] = started ? kAccAdd : kAccSet;
-            started = true;
-        }
-    if (!started) mode[p] = kAccZero;
+    bool started = false;
+    int k = 0;
+    for (;;) {
+        while (k <= p && w[k] == 0.0) ++k;
+        if (k > p) break;
+        const int m = std::min(k + 2, p);
+        uint8_t bits = started ? 0 : kAccStart;
+        for (int j = k; j <= m; ++j)
+            if (w[j] != 0.0) bits |= j == m ? kAccT0 : (j == m - 1 ? kAccT1 : kAccT2);
+        f[(size_t)m] = bits;
+        started = true;
+        k = m + 1;
+    }
+    if (!started) f[(size_t)p] = kAccZero;
 }
 
 // Y is the output (p vectors), or with poly the two-slot ring.
@@ -445,16 +456,14 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                 cf.gamma[j] = gamma[base + j];
             }
         AccCoefs ac{};
-        if (poly) {  // y_0's weights matter at the first power only
-            ac.wa0 = poly->wa[0];
-            ac.wb0 = poly->wb ? poly->wb[0] : 0.0;
+        if (poly) {  // weights of the sequence's powers base-1 .. base+ps
+            for (int i = 0; i < ps + 2; ++i) {
+                ac.wa[i] = poly->w(poly->wa, base - 1 + i);
+                ac.wb[i] = poly->w(poly->wb, base - 1 + i);
+            }
             for (int j = 0; j < ps; ++j) {
-                ac.wa[j] = poly->wa[base + j + 1];
-                ac.ma[j] = poly->ma[base + j + 1];
-                if (poly->wb) {
-                    ac.wb[j] = poly->wb[base + j + 1];
-                    ac.mb[j] = poly->mb[base + j + 1];
-                }
+                ac.fa[j] = poly->fa[(size_t)(base + j + 1)];
+                ac.fb[j] = poly->fb[(size_t)(base + j + 1)];
             }
         }
         const AccCoefs *acp = poly ? &ac : nullptr;
@@ -546,14 +555,12 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
         if (poly) {
             as.acc_a = poly->acc_a;
             as.acc_b = poly->acc_b;
-            as.wa = poly->wa[k];
-            as.wa0 = poly->wa[0];
-            as.ma = poly->ma[k];
-            if (poly->wb) {
-                as.wb = poly->wb[k];
-                as.wb0 = poly->wb[0];
-                as.mb = poly->mb[k];
+            for (int i = 0; i < 3; ++i) {  // powers k-2, k-1, k
+                as.wa[i] = poly->w(poly->wa, k - 2 + i);
+                as.wb[i] = poly->w(poly->wb, k - 2 + i);
             }
+            as.fa = poly->fa[(size_t)k];
+            as.fb = poly->fb[(size_t)k];
         }
         int rc = launch_spmv_power(m, sl->view(), sl->n_slices, kSpmvSlicesPerWG, in, prev, out,
                                    nrhs, recur ? 1 : 0, recur ? alpha[k - 1] : 1.0,
@@ -590,8 +597,9 @@ mpk_status_t run_poly(mpk_plan_t plan, const double *x, int p, int nrhs, const d
     poly.wb = wb;
     poly.acc_a = acc;
     poly.acc_b = wb ? acc + (size_t)plan->n * nrhs : nullptr;
-    acc_modes(wa, p, poly.ma);
-    acc_modes(wb, p, poly.mb);
+    poly.p = p;
+    acc_flushes(wa, p, poly.fa);
+    acc_flushes(wb, p, poly.fb);
     return baseline ? run_baseline(plan, x, p, nrhs, alpha, beta, gamma, work, stream, &poly)
                     : run_lb(plan, x, p, nrhs, alpha, beta, gamma, work, stream, &poly);
 }

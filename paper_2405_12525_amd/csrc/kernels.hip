@@ -48,10 +48,11 @@ struct PowerIO {
     double *out;          // y_k
     double alpha, beta, gamma;
     int recur;
-    // weighted sums of the powers (AccMode per sum; both kAccNone: none)
+    // weighted sums of the powers: weights of y_{k-2}, y_{k-1}, y_k and the
+    // AccFlags of each sum (kernels with the sums only)
     double *acc_a, *acc_b;
-    double wa, wb, wa0, wb0;
-    int ma, mb;
+    double wa2, wa1, wa0, wb2, wb1, wb0;
+    int fa, fb;
 };
 
 // y = alpha*s + beta*y_{k-1} + gamma*y_{k-2} evaluated left to right, or s.
@@ -74,36 +75,32 @@ __device__ __forceinline__ double epilogue(const PowerIO &io, double s, size_t i
 template <bool WT>
 __device__ __forceinline__ void store_out(double *p, double v);
 
-// One weighted sum at one element, after y_k = v has been computed (y_0 is
-// io.in at the first power).  Terms are formed and added left to right
-// without contraction, as the host-side definition of the sum states.
+// One weighted sum at one element: the flush of this power (AccFlags f)
+// adds w2*y_{k-2} (value y2), w1*y_{k-1} (the input row) and w0*y_k (v), as
+// flagged and in that order, each product rounded and then added without
+// contraction; the sum's first term starts it.
 template <bool WT>
-__device__ __forceinline__ void accumulate(double *acc, int mode, double w, double w0,
-                                           const PowerIO &io, double v, size_t idx) {
-    double r;
-    switch (mode) {
-    case kAccSet:
-        r = w * v;
-        break;
-    case kAccAdd: {
-        const double t = w * v;
-        r = acc[idx] + t;
-        break;
-    }
-    case kAccSetWithX: {
-        const double t0 = w0 * io.in[idx];
-        const double t = w * v;
-        r = t0 + t;
-        break;
-    }
-    case kAccSetX:
-        r = w0 * io.in[idx];
-        break;
-    case kAccZero:
-        r = 0.0;
-        break;
-    default:
-        return;
+__device__ __forceinline__ void accumulate(double *acc, int f, double w2, double w1, double w0,
+                                           double y2, const PowerIO &io, double v, size_t idx) {
+    if (!f) return;
+    double r = 0.0;
+    if (!(f & kAccZero)) {
+        bool have = !(f & kAccStart);
+        if (have) r = acc[idx];
+        if (f & kAccT2) {
+            const double t = w2 * y2;
+            r = have ? r + t : t;
+            have = true;
+        }
+        if (f & kAccT1) {
+            const double t = w1 * io.in[idx];
+            r = have ? r + t : t;
+            have = true;
+        }
+        if (f & kAccT0) {
+            const double t = w0 * v;
+            r = have ? r + t : t;
+        }
     }
     store_out<WT>(acc + idx, r);
 }
@@ -128,12 +125,30 @@ __device__ __forceinline__ void store_out(double *p, double v) {
 
 template <bool WT, bool ACC>
 __device__ __forceinline__ void finish(const PowerIO &io, double s, size_t idx) {
-    const double v = epilogue(io, s, idx);
-    store_out<WT>(io.out + idx, v);
-    if (ACC) {
-        accumulate<WT>(io.acc_a, io.ma, io.wa, io.wa0, io, v, idx);
-        accumulate<WT>(io.acc_b, io.mb, io.wb, io.wb0, io, v, idx);
+    if (!ACC) {
+        store_out<WT>(io.out + idx, epilogue(io, s, idx));
+        return;
     }
+    // y_{k-2} is read once, for the recurrence and for the sums, and before
+    // y_k is stored: in the two-vector ring both share this element
+    const bool g = io.recur && io.prev && io.gamma != 0.0;
+    const bool need2 = g || ((io.fa | io.fb) & kAccT2);
+    const double y2 = need2 ? io.prev[idx] : 0.0;
+    double v = s;
+    if (io.recur) {
+        v = io.alpha * s;
+        if (io.beta != 0.0) {
+            const double b = io.beta * io.in[idx];
+            v = v + b;
+        }
+        if (g) {
+            const double t = io.gamma * y2;
+            v = v + t;
+        }
+    }
+    store_out<WT>(io.out + idx, v);
+    accumulate<WT>(io.acc_a, io.fa, io.wa2, io.wa1, io.wa0, y2, io, v, idx);
+    accumulate<WT>(io.acc_b, io.fb, io.wb2, io.wb1, io.wb0, y2, io, v, idx);
 }
 
 // Loads of a slice with 1 <= nz nonzeros starting at nb, rows [rb, re):
@@ -381,12 +396,14 @@ __device__ __forceinline__ PowerIO power_io(const SegArgs &a, const Coefs &cf,
         io.out = a.Y + (size_t)((g - 1) & 1) * stride;
         io.acc_a = a.acc_a;
         io.acc_b = a.acc_b;
-        io.wa = ac->wa[k - 1];
-        io.wb = ac->wb[k - 1];
-        io.wa0 = ac->wa0;
-        io.wb0 = ac->wb0;
-        io.ma = ac->ma[k - 1];
-        io.mb = ac->mb[k - 1];
+        io.wa2 = ac->wa[k - 1];  // weights of the sequence's powers g-2, g-1, g
+        io.wa1 = ac->wa[k];
+        io.wa0 = ac->wa[k + 1];
+        io.wb2 = ac->wb[k - 1];
+        io.wb1 = ac->wb[k];
+        io.wb0 = ac->wb[k + 1];
+        io.fa = ac->fa[k - 1];
+        io.fb = ac->fb[k - 1];
     } else {
         io.in = (k == 1) ? a.in0 : a.Y + (size_t)(k - 2) * stride;
         io.prev = (k == 1) ? a.inm1 : (k == 2 ? a.in0 : a.Y + (size_t)(k - 3) * stride);
@@ -927,10 +944,22 @@ int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_
                       void *stream) {
     if (R < 1 || R > 16 || per < 1) return (int)hipErrorInvalidValue;
     if (m.n == 0 || n_slices == 0) return 0;
-    PowerIO io{in, inm1, out, alpha, beta, gamma, recur,
-               acc ? acc->acc_a : nullptr, acc ? acc->acc_b : nullptr,
-               acc ? acc->wa : 0.0, acc ? acc->wb : 0.0, acc ? acc->wa0 : 0.0,
-               acc ? acc->wb0 : 0.0, acc ? acc->ma : 0, acc ? acc->mb : 0};
+    PowerIO io{in, inm1, out, alpha, beta, gamma, recur};
+    io.acc_a = io.acc_b = nullptr;
+    io.wa2 = io.wa1 = io.wa0 = io.wb2 = io.wb1 = io.wb0 = 0.0;
+    io.fa = io.fb = 0;
+    if (acc) {
+        io.acc_a = acc->acc_a;
+        io.acc_b = acc->acc_b;
+        io.wa2 = acc->wa[0];
+        io.wa1 = acc->wa[1];
+        io.wa0 = acc->wa[2];
+        io.wb2 = acc->wb[0];
+        io.wb1 = acc->wb[1];
+        io.wb0 = acc->wb[2];
+        io.fa = acc->fa;
+        io.fb = acc->fb;
+    }
     const int32_t grid = (n_slices + per - 1) / per;
     hipLaunchKernelGGL(spmv_fn(m.value_bits, R, acc != nullptr), dim3((unsigned)grid), dim3(kBlock), 0,
                        (hipStream_t)stream, m, io, R, sl, n_slices, per);

@@ -117,17 +117,18 @@ struct DevSlices {
     const int32_t *snz;    // n_slices + 1 nonzero offsets (rowptr at srow)
 };
 
-// Weighted sums of the powers (polynomial evaluation): what the task that
-// computes y_k does with one sum.  The host derives the modes from the
-// weights w_0..w_p so that the sum runs in increasing k and skips zero
-// weights: the first nonzero term sets the sum, later ones add to it.
-enum AccMode : int8_t {
-    kAccNone = 0,      // weight zero: leave the sum alone
-    kAccSet = 1,       // acc = w*y_k
-    kAccAdd = 2,       // acc = acc + w*y_k
-    kAccSetWithX = 3,  // acc = w_0*y_0 + w*y_1  (first power only)
-    kAccSetX = 4,      // acc = w_0*y_0          (first power only, w_1 = 0)
-    kAccZero = 5,      // acc = 0                (last power, all weights zero)
+// Weighted sums of the powers (polynomial evaluation).  The task that
+// computes y_m also holds y_{m-1} (its own input row) and y_{m-2} (read by the
+// recurrence anyway), so the host groups each sum's nonzero terms into
+// flushes: at power m the flagged terms among k = m-2, m-1, m are added in
+// that order, either starting the sum or adding to it.  Each flush is one
+// read-modify-write of the sum instead of one per term.
+enum AccFlags : uint8_t {
+    kAccT2 = 1,       // add w_{m-2} y_{m-2}
+    kAccT1 = 2,       // add w_{m-1} y_{m-1}
+    kAccT0 = 4,       // add w_m y_m
+    kAccStart = 8,    // the sum's first flush: it starts with its first term
+    kAccZero = 16,    // last power of a sum whose weights are all zero: store 0
 };
 
 struct Coefs {
@@ -136,14 +137,15 @@ struct Coefs {
     double gamma[kMaxSegPowers];
 };
 
-// Weights of the segment's powers for the two weighted sums (the kernels
-// that take these are separate from the plain ones).
+// Weights and flushes of the two weighted sums for one segment: w[i] is the
+// weight of the sequence's power k0 - 1 + i (0 outside 0..p), f[k-1] the
+// AccFlags of the segment's power k.  (Kernels that take these are separate
+// from the plain ones.)
 struct AccCoefs {
-    double wa[kMaxSegPowers];    // weight of the segment's power k (index k-1), sum a
-    double wb[kMaxSegPowers];    // the same for sum b
-    double wa0, wb0;             // weights of y_0 (first segment)
-    int8_t ma[kMaxSegPowers];    // AccMode per power, sum a
-    int8_t mb[kMaxSegPowers];
+    double wa[kMaxSegPowers + 2];
+    double wb[kMaxSegPowers + 2];
+    uint8_t fa[kMaxSegPowers];
+    uint8_t fb[kMaxSegPowers];
 };
 
 // One launch covers powers 1..p of a segment: y_0 = in0, y_{-1} = inm1
@@ -162,11 +164,12 @@ struct SegArgs {
     int32_t k0;
 };
 
-// The weighted-sum work of one power of the p x SpMV kernel.
+// The weighted-sum work of one power m of the p x SpMV kernel: weights of
+// y_{m-2}, y_{m-1}, y_m and the AccFlags of each sum.
 struct AccStep {
     double *acc_a, *acc_b;
-    double wa, wb, wa0, wb0;
-    int32_t ma, mb;
+    double wa[3], wb[3];
+    int32_t fa, fb;
 };
 
 struct DevSchedule {

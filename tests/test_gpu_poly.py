@@ -189,3 +189,24 @@ def test_argument_checks():
     with pytest.raises(ValueError):
         P.cheb_time_step(dev(w.uniform_vectors(A.n, 3, 2)), 1.0, 8)   # odd column count
     P.close()
+
+
+@pytest.mark.parametrize("seg", [0, 1, 2, 3])
+def test_flush_patterns_across_segments(seg):
+    # each sum is flushed at most every third power and takes y_{m-2} and
+    # y_{m-1} from the task at power m; segments of 1-3 powers put those
+    # terms in the previous launch's outputs
+    A = w.stencil_2d5(20)
+    A = w.CSR(A.n, A.rowptr, A.col, A.val / 8.0, "scaled")
+    P = mpk.Plan(A)
+    P.tune(schedule="wave", chunk_nnz=300, seg_powers=seg)
+    g = np.random.default_rng(500 + seg)
+    for case in range(12):
+        p = int(g.integers(1, 8))
+        R = int(g.choice([1, 2, 4]))
+        x = w.uniform_vectors(A.n, R, 600 + case)
+        wa = g.uniform(-1, 1, p + 1) * (g.random(p + 1) < g.uniform(0.2, 0.9))
+        wb = g.uniform(-1, 1, p + 1) * (g.random(p + 1) < g.uniform(0.2, 0.9))
+        coefs = oracle.chebyshev_coefficients(p) if case % 2 else None
+        check_poly(P, A, x, wa, wb, coefs, 64)
+    P.close()
