@@ -258,11 +258,13 @@ mpk_status_t mpk_run_baseline_recur(mpk_plan_t plan, const double *x, int p, int
  * gamma all NULL: plain powers y_k = A^k x).  The sequence itself is not
  * kept: y_k lives in the ring `work` at work + ((k-1) mod 2)*n*nrhs, so on
  * return work holds y_p and (p >= 2) y_{p-1}.
- * Each sum is updated in the epilogue of the task that computes y_k, in
- * increasing k: its first term with a nonzero weight sets it to w[k]*y_k,
- * each later one adds w[k]*y_k (no fused multiply-add), a weight that is
- * exactly zero omits its term and its vector traffic, and a sum whose
- * weights are all zero is written as zeros.  The results are therefore the
+ * The sums are formed in the kernels' epilogues, in increasing k: a sum's
+ * first term with a nonzero weight sets it to w[k]*y_k, each later one adds
+ * w[k]*y_k (no fused multiply-add), a weight that is exactly zero omits its
+ * term, and a sum whose weights are all zero is written as zeros.  The task
+ * that computes y_m holds y_{m-2} and y_{m-1} as well, so up to three
+ * consecutive terms are added in one read-modify-write of the sum (the
+ * Chebyshev weights touch each sum every fourth power).  The results are therefore the
  * same bit for bit as mpk_run_baseline_poly, and as forming these sums
  * from the output of mpk_run_recur.
  * alpha, beta, gamma: HOST arrays of p doubles (or all NULL); wa, wb: HOST
