@@ -210,3 +210,52 @@ def test_flush_patterns_across_segments(seg):
         coefs = oracle.chebyshev_coefficients(p) if case % 2 else None
         check_poly(P, A, x, wa, wb, coefs, 64)
     P.close()
+
+
+@pytest.mark.parametrize("R", [3, 5, 16])
+def test_sums_generic_rhs_counts(R):
+    # R = 3 and 5 run the generic instantiation; 16 the widest specialised one
+    A = w.anderson_3d(10)
+    x = w.uniform_vectors(A.n, R, 80 + R)
+    P = mpk.Plan(A, value_bits=32)
+    P.tune(schedule="wave", chunk_nnz=900)
+    p = 7
+    check_poly(P, A, x, weights(p, 90 + R), weights(p, 91 + R), oracle.chebyshev_coefficients(p), 32)
+    P.close()
+
+
+def test_sums_in_plan_order():
+    # vectors in the BFS numbering: the same sums as the oracle on P A P^T
+    A = w.stencil_3d27(14)
+    P = mpk.Plan(A, order="plan")
+    _, perm = P.levels()
+    Ap = oracle.permute_csr(A, perm)
+    x = w.uniform_vectors(A.n, 2, 95)
+    p = 6
+    check_poly(P, Ap, x, weights(p, 96), weights(p, 97), oracle.chebyshev_coefficients(p), 64)
+    P.close()
+
+
+def test_sums_on_concurrent_streams():
+    # runs on one plan from several streams draw separate dependency
+    # workspaces; each call has its own ring and sums
+    A = w.stencil_3d27(20)
+    P = mpk.Plan(A)
+    P.tune(schedule="wave", chunk_nnz=1500)
+    p = 8
+    coefs = oracle.chebyshev_coefficients(p)
+    xs = [w.uniform_vectors(A.n, 2, 120 + i) for i in range(3)]
+    ws = [(weights(p, 130 + i), weights(p, 140 + i)) for i in range(3)]
+    streams = [torch.cuda.Stream() for _ in xs]
+    xds = [dev(x) for x in xs]
+    torch.cuda.synchronize()
+    outs = []
+    for xd, (wa, wb), s in zip(xds, ws, streams):
+        with torch.cuda.stream(s):
+            outs.append(P.run_poly(xd, wa, wb, *coefs, stream=s))
+    P.sync()
+    for x, (wa, wb), (acc, _) in zip(xs, ws, outs):
+        ra, rb = oracle.poly_sums(A, x, *coefs, wa, wb)
+        got = host(acc)
+        assert np.array_equal(got[0], ra) and np.array_equal(got[1], rb)
+    P.close()
