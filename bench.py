@@ -274,6 +274,15 @@ def time_step(torch, mpk, w, steps, warmup, stream):
     tr = time_calls(lambda: fused(True), steps, warmup, torch, stream)["median_ms"]
     P.sync()
     got_tr = out.cpu().numpy()
+    graphs = {}
+    for name, base in (("level_blocked", False), ("pxspmv", True)):
+        gout = torch.empty_like(xd)
+        G = P.capture_time_step(xd, dt, M, gout, baseline=base)
+        graphs[name] = round(time_calls(lambda: G.launch(stream=stream), steps, warmup, torch,
+                                        stream)["median_ms"], 4)
+        stream.synchronize()
+        graphs[name + "_equal"] = bool(np.array_equal(gout.cpu().numpy(), got_lb))
+        G.close()
     full = time_calls(lambda: P.run_recur(xd, al, be, ga, Y=Y, stream=stream), steps, warmup,
                       torch, stream)["median_ms"]
     full_tr = time_calls(lambda: P.run_baseline_recur(xd, al, be, ga, Y=Y, stream=stream), steps,
@@ -304,6 +313,7 @@ def time_step(torch, mpk, w, steps, warmup, stream):
            "values": "fp32", "schedule": tq["schedule"], "gflops_flop_count": flop,
            "lb_fused_ms": round(lb, 4), "lb_fused_gflops": round(flop / lb / 1e6, 1),
            "pxspmv_fused_ms": round(tr, 4), "pxspmv_fused_gflops": round(flop / tr / 1e6, 1),
+           "hip_graph_ms": graphs,
            "recurrence_writing_all_M_vectors_ms": {"level_blocked": round(full, 4),
                                                    "pxspmv": round(full_tr, 4)},
            "reorder": "none",
@@ -316,7 +326,8 @@ def time_step(torch, mpk, w, steps, warmup, stream):
                            "achieved_GBs": round(lb_b / lb / 1e6, 1),
                            "frac": round(lb_b / lb / 1e6 / HBM_PEAK_GBS, 4)}}
     log(f"[bench] time step: level-blocked fused {lb:.3f} ms ({tq['schedule']}), "
-        f"p x SpMV fused {tr:.3f} ms, recurrence writing all vectors {full:.3f} / {full_tr:.3f} ms, "
+        f"p x SpMV fused {tr:.3f} ms, graphs {graphs}, "
+        f"recurrence writing all vectors {full:.3f} / {full_tr:.3f} ms, "
         f"exact {exact}")
     return res
 

@@ -364,6 +364,23 @@ typedef struct mpk_graph_s *mpk_graph_t;
 mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs,
                                const double *alpha, const double *beta, const double *gamma,
                                double *Y, mpk_graph_t *out);
+
+/*
+ * Capture one Chebyshev time step (Sec. "Application: Chebyshev Time
+ * Propagation"): the weights of mpk_cheb_time_coefficients(M, dt), the
+ * weighted sums of mpk_run_poly (baseline != 0: mpk_run_baseline_poly) and
+ * mpk_combine_complex into out, as one graph for repeated launches.
+ * psi, out: device, n*nrhs doubles (nrhs even, 2..16: real and imaginary
+ * columns); acc, work: device scratch, 2*n*nrhs doubles each.  out must not
+ * overlap psi, acc or work; acc and out are 16-byte aligned.  A propagation
+ * loop captures two graphs (psi -> out and out -> psi) and alternates them.
+ * The graph keeps these pointers and the plan's tuning at capture time.
+ * Errors: as mpk_run_poly and mpk_graph_capture; MPK_EINVAL (odd nrhs, M,
+ * dt, NULL, overlap, alignment).
+ */
+mpk_status_t mpk_graph_capture_time_step(mpk_plan_t plan, const double *psi, int nrhs, double dt,
+                                         int M, int baseline, double *out, double *acc,
+                                         double *work, mpk_graph_t *graph);
 mpk_status_t mpk_graph_launch(mpk_graph_t graph, void *hip_stream);
 void mpk_graph_destroy(mpk_graph_t graph);
 

@@ -301,6 +301,26 @@ class Plan:
                                           ctypes.c_void_p(Y.data_ptr()), ctypes.byref(h)))
         return Graph(h, self, (x, Y))
 
+    def capture_time_step(self, psi, dt: float, M: int, out=None, baseline: bool = False) -> "Graph":
+        """Capture one Chebyshev time step psi -> out (mpk_graph_capture_time_step);
+        Graph.launch() returns out.  Scratch for the ring and the sums is
+        allocated here and kept by the graph."""
+        torch = _torch()
+        _vec_check(psi, self.n, "psi")
+        if psi.dim() != 2 or psi.shape[1] % 2:
+            raise ValueError("psi must be (n, 2m): real and imaginary columns")
+        R = int(psi.shape[1])
+        if out is None:
+            out = torch.empty_like(psi)
+        acc = torch.empty((2, self.n, R), dtype=torch.float64, device=psi.device)
+        work = torch.empty((2, self.n, R), dtype=torch.float64, device=psi.device)
+        h = ctypes.c_void_p()
+        check(self._lib.mpk_graph_capture_time_step(
+            self._h, ctypes.c_void_p(psi.data_ptr()), R, float(dt), int(M), int(bool(baseline)),
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(acc.data_ptr()),
+            ctypes.c_void_p(work.data_ptr()), ctypes.byref(h)))
+        return Graph(h, self, (psi, out, acc, work))
+
     # ------------------------------------------------------------ runs
     def _prep(self, x, p, Y):
         torch = _torch()

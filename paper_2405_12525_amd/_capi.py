@@ -25,6 +25,7 @@ EXPORTS = [
     "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
     "mpk_plan_autotune", "mpk_graph_capture", "mpk_graph_launch", "mpk_graph_destroy",
     "mpk_run_poly", "mpk_run_baseline_poly", "mpk_cheb_time_coefficients", "mpk_combine_complex",
+    "mpk_graph_capture_time_step",
 ]
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -111,6 +112,9 @@ def load():
         f.restype = st
     lib.mpk_cheb_time_coefficients.argtypes = [ctypes.c_int, ctypes.c_double, P, P, P, P, P]
     lib.mpk_cheb_time_coefficients.restype = st
+    lib.mpk_graph_capture_time_step.argtypes = [P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                                ctypes.c_int, P, P, P, ctypes.POINTER(P)]
+    lib.mpk_graph_capture_time_step.restype = st
     lib.mpk_combine_complex.argtypes = [P, P, ctypes.c_int, P, P]
     lib.mpk_combine_complex.restype = st
     lib.mpk_permute.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P]

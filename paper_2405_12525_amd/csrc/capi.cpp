@@ -513,6 +513,21 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     return MPK_OK;
 }
 
+// Slice table of the p x SpMV kernel for R right-hand sides, built once
+// (plan->mu held).
+mpk_status_t spmv_slices(mpk_plan_t plan, int R, SliceSet **out) {
+    auto it = plan->spmv_slices.find(R);
+    if (it == plan->spmv_slices.end()) {
+        auto ss = std::make_unique<SliceSet>();
+        const std::vector<int32_t> whole{0, (int32_t)plan->n};
+        mpk_status_t st = make_slices(plan->rowptr, whole, slice_nnz(kSpmvKP, R), false, *ss);
+        if (st) return st;
+        it = plan->spmv_slices.emplace(R, std::move(ss)).first;
+    }
+    *out = it->second.get();
+    return MPK_OK;
+}
+
 mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
                           const double *beta, const double *gamma, double *Y, void *stream_v,
                           const Poly *poly = nullptr) {
@@ -530,16 +545,9 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     SliceSet *sl = nullptr;
     {
         std::lock_guard<std::mutex> g(plan->mu);
-        auto it = plan->spmv_slices.find(nrhs);
-        if (it == plan->spmv_slices.end()) {
-            if (cap == hipStreamCaptureStatusActive)
-                return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
-            auto ss = std::make_unique<SliceSet>();
-            const std::vector<int32_t> whole{0, (int32_t)plan->n};
-            if ((st = make_slices(plan->rowptr, whole, slice_nnz(kSpmvKP, nrhs), false, *ss))) return st;
-            it = plan->spmv_slices.emplace(nrhs, std::move(ss)).first;
-        }
-        sl = it->second.get();
+        if (cap == hipStreamCaptureStatusActive && !plan->spmv_slices.count(nrhs))
+            return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
+        if ((st = spmv_slices(plan, nrhs, &sl))) return st;
     }
     const size_t stride = (size_t)plan->n * nrhs;
     const DevMatrix m = plan->matrix();
@@ -1188,6 +1196,82 @@ mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs
     e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     *out = g.release();
+    return MPK_OK;
+}
+
+mpk_status_t mpk_graph_capture_time_step(mpk_plan_t plan, const double *psi, int nrhs, double dt,
+                                         int M, int baseline, double *out, double *acc,
+                                         double *work, mpk_graph_t *graph) {
+    if (!graph) return fail(MPK_EINVAL, "graph is NULL");
+    *graph = nullptr;
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    if (nrhs < 2 || nrhs > MPK_MAX_RHS || (nrhs & 1))
+        return fail(MPK_EINVAL, "nrhs must be even, 2..16 (real and imaginary columns)");
+    if (M < 1 || M > 100000) return fail(MPK_EINVAL, "M must be in [1, 100000]");
+    std::vector<double> al((size_t)M), be((size_t)M), ga((size_t)M), wa((size_t)M + 1),
+        wb((size_t)M + 1);
+    if ((st = mpk_cheb_time_coefficients(M, dt, al.data(), be.data(), ga.data(), wa.data(),
+                                         wb.data())))
+        return st;
+    if (plan->n > 0 && (!psi || !out || !acc || !work)) return fail(MPK_EINVAL, "NULL vector");
+    const size_t vb = (size_t)plan->n * nrhs * sizeof(double);
+    const char *o = reinterpret_cast<const char *>(out);
+    const char *ranges[3][2] = {{reinterpret_cast<const char *>(psi), nullptr},
+                                {reinterpret_cast<const char *>(acc), nullptr},
+                                {reinterpret_cast<const char *>(work), nullptr}};
+    const size_t lens[3] = {vb, 2 * vb, 2 * vb};
+    for (int i = 0; i < 3 && plan->n > 0; ++i)
+        if (o < ranges[i][0] + lens[i] && ranges[i][0] < o + vb)
+            return fail(MPK_EINVAL, "out overlaps psi, acc or work");
+    if (plan->n > 0 && ((reinterpret_cast<uintptr_t>(acc) | reinterpret_cast<uintptr_t>(out)) & 15))
+        return fail(MPK_EINVAL, "acc and out must be 16-byte aligned");
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::unique_ptr<mpk_graph_s> g(new mpk_graph_s());
+    e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    if (plan->n > 0) {
+        // everything a run allocates or uploads is prepared before the capture
+        std::lock_guard<std::mutex> lk(plan->mu);
+        if (baseline) {
+            SliceSet *ss = nullptr;
+            if ((st = spmv_slices(plan, nrhs, &ss))) return st;
+        } else {
+            if (!pattern_symmetric(plan))
+                return fail(MPK_EUNSUPPORTED,
+                            "the level-blocked weighted sums need a structurally symmetric pattern "
+                            "(use the p x SpMV form)");
+            const int wg_default = default_workgroups(plan, nrhs);
+            const int seg = plan->tune.seg_powers > 0 ? plan->tune.seg_powers : kMaxSegPowers;
+            for (int base = 0; base < M; base += seg) {
+                SchedEntry *se = nullptr;
+                if ((st = get_schedule(plan, std::min(seg, M - base), &se, wg_default))) return st;
+                SliceSet *ss = nullptr;
+                if ((st = task_slices(plan, se, nrhs, &ss))) return st;
+                if (se->host.step_ptr.empty()) {
+                    Workspace *ws = nullptr;
+                    if ((st = get_workspace(plan, se->host.n_chunks(), g->stream, false, &ws, true)))
+                        return st;
+                }
+            }
+        }
+    }
+    e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    st = run_poly(plan, psi, M, nrhs, al.data(), be.data(), ga.data(), wa.data(), wb.data(), acc,
+                  work, g->stream, baseline != 0);
+    if (!st && plan->n > 0) {
+        const int rc = launch_combine_complex(acc, acc + (size_t)plan->n * nrhs, plan->n, nrhs,
+                                              out, g->stream);
+        if (rc) st = hip_fail((hipError_t)rc, "combine kernel launch");
+    }
+    e = hipStreamEndCapture(g->stream, &g->graph);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    *graph = g.release();
     return MPK_OK;
 }
 

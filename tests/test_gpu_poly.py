@@ -259,3 +259,38 @@ def test_sums_on_concurrent_streams():
         got = host(acc)
         assert np.array_equal(got[0], ra) and np.array_equal(got[1], rb)
     P.close()
+
+
+@pytest.mark.parametrize("sched,baseline", [("steps", False), ("wave", False), ("xcd", False),
+                                            ("wave", True)])
+def test_time_step_graph_replays_match_eager(sched, baseline):
+    A = w.anderson_3d(14)
+    P = mpk.Plan(A)
+    P.tune(schedule=sched, chunk_nnz=1500)
+    g = np.random.default_rng(150)
+    psi = dev(g.standard_normal((A.n, 4)))
+    dt, M = 0.7, 12
+    eager = host(P.cheb_time_step(psi, dt, M, baseline=baseline))
+    out = torch.empty_like(psi)
+    G = P.capture_time_step(psi, dt, M, out, baseline=baseline)
+    for i in range(3):
+        out.fill_(np.nan)
+        torch.cuda.synchronize()
+        G.launch()
+        assert np.array_equal(host(out), eager), f"replay {i}"
+        # unrelated eager work on the same plan between replays
+        other = P.run(dev(w.uniform_vectors(A.n, 1, 160 + i)), 3)
+        P.sync()
+        del other
+    # two steps by alternating two graphs equal two eager steps
+    back = torch.empty_like(psi)
+    G2 = P.capture_time_step(out, dt, M, back, baseline=baseline)
+    G.launch()
+    G2.launch()
+    two = host(P.cheb_time_step(P.cheb_time_step(psi, dt, M, baseline=baseline), dt, M,
+                                baseline=baseline))
+    assert np.array_equal(host(back), two)
+    G.close()
+    G2.close()
+    P.sync()
+    P.close()
