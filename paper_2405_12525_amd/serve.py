@@ -10,6 +10,10 @@ the loop admits them as stream slots and memory free up:
   ran alone (the kernels' per-column arithmetic does not depend on the
   right-hand-side count) and powers are prefix-consistent, so request i takes
   the first p_i powers of its own columns;
+* a Chebyshev time step (kind "time_step": one step exp(-i dt H) psi with
+  M = p terms, psi as real and imaginary column pairs) batches only with
+  steps of the same dt and M, since those fix the weights; each request
+  takes its own columns of the stepped states;
 * batches for different matrices run concurrently on separate HIP streams;
 * a batch is admitted only while the device memory held by running batches
   (stacked inputs plus outputs) stays within the budget.
@@ -37,7 +41,8 @@ class Request:
     matrix: int               # index into the server's plans
     p: int
     x: object                 # device tensor (n, R), float64
-    kind: str = "powers"      # "powers" or "chebyshev"
+    kind: str = "powers"      # "powers", "chebyshev" or "time_step"
+    dt: float = 0.0           # time step (kind "time_step"; p is the expansion order M)
 
     @property
     def R(self) -> int:
@@ -47,7 +52,7 @@ class Request:
 @dataclasses.dataclass
 class Result:
     id: int
-    Y: object                 # device tensor view (p, n, R)
+    Y: object                 # device tensor view (p, n, R); (n, R) for a time step
     arrival: float
     start: float              # batch launch time
     done: float               # completion observed by the loop
@@ -58,9 +63,16 @@ class Result:
         return self.done - self.arrival
 
 
-def batch_bytes(n: int, p: int, R: int) -> int:
-    """Device bytes a batch holds while running: stacked x plus Y."""
-    return 8 * n * R * (p + 1)
+def batch_bytes(n: int, p: int, R: int, kind: str = "powers") -> int:
+    """Device bytes a batch holds while running: stacked x plus Y, or for a
+    time step x, the stepped states, the two sums and the two-vector ring."""
+    return 8 * n * R * (6 if kind == "time_step" else p + 1)
+
+
+def _same_batch(a: Request, b: Request) -> bool:
+    if a.kind != b.kind:
+        return False
+    return a.kind != "time_step" or (a.p == b.p and a.dt == b.dt)
 
 
 def form_batch(queue: collections.deque, max_rhs: int = MAX_RHS) -> List[Request]:
@@ -71,7 +83,7 @@ def form_batch(queue: collections.deque, max_rhs: int = MAX_RHS) -> List[Request
     keep = collections.deque()
     while queue:
         r = queue.popleft()
-        if r.kind == head.kind and total + r.R <= max_rhs:
+        if _same_batch(r, head) and total + r.R <= max_rhs:
             batch.append(r)
             total += r.R
         else:
@@ -111,6 +123,8 @@ class Server:
             X = xs[0] if len(xs) == 1 else torch.cat(xs, dim=1).contiguous()
             if batch[0].kind == "chebyshev":
                 Y = P.run_recur(X, *chebyshev_coefficients(p), stream=stream)
+            elif batch[0].kind == "time_step":
+                Y = P.cheb_time_step(X, batch[0].dt, p, stream=stream)
             else:
                 Y = P.run(X, p, stream=stream)
             ev = torch.cuda.Event()
@@ -131,7 +145,11 @@ class Server:
                 raise ValueError(f"request {r.id}: no matrix {r.matrix}")
             if r.R > self.max_rhs or r.p < 1:
                 raise ValueError(f"request {r.id}: bad p or R")
-            need = batch_bytes(self.plans[r.matrix].n, r.p, r.R)
+            if r.kind not in ("powers", "chebyshev", "time_step"):
+                raise ValueError(f"request {r.id}: unknown kind {r.kind}")
+            if r.kind == "time_step" and r.R % 2:
+                raise ValueError(f"request {r.id}: a time step needs real and imaginary columns")
+            need = batch_bytes(self.plans[r.matrix].n, r.p, r.R, r.kind)
             if need > self.mem_budget:
                 raise ValueError(f"request {r.id} needs {need} bytes, above the budget")
         order = sorted(requests, key=lambda r: r.arrival)
@@ -156,7 +174,12 @@ class Server:
                     done = time.perf_counter() - t0
                     c0 = 0
                     for r in batch:
-                        view = Y[:r.p, :, c0:c0 + r.R] if keep else None
+                        if not keep:
+                            view = None
+                        elif r.kind == "time_step":
+                            view = Y[:, c0:c0 + r.R]
+                        else:
+                            view = Y[:r.p, :, c0:c0 + r.R]
                         c0 += r.R
                         arr = r.arrival if realtime else 0.0
                         results[r.id] = Result(r.id, view, arr, start, done, len(batch))
@@ -174,7 +197,7 @@ class Server:
                 q = pending[m]
                 batch = form_batch(q, self.max_rhs)
                 p = max(r.p for r in batch)
-                nbytes = batch_bytes(self.plans[m].n, p, sum(r.R for r in batch))
+                nbytes = batch_bytes(self.plans[m].n, p, sum(r.R for r in batch), batch[0].kind)
                 if in_use + nbytes > self.mem_budget and running:
                     for r in reversed(batch):
                         q.appendleft(r)
@@ -203,7 +226,9 @@ def summarize(results: Sequence[Result], requests: Sequence[Request], plans: Seq
     for res in results:
         rq = by_id[res.id]
         P = plans[rq.matrix]
-        fl += flops(P.nnz, P.n, rq.p, rq.R, recur=rq.kind == "chebyshev")
+        fl += flops(P.nnz, P.n, rq.p, rq.R, recur=rq.kind != "powers")
+        if rq.kind == "time_step":   # the weighted sums and the complex combination
+            fl += 2.0 * P.n * rq.R * (rq.p + 1) + P.n * rq.R
     first = min(r.arrival for r in results)
     last = max(r.done for r in results)
     span = max(last - first, 1e-9)

@@ -59,3 +59,31 @@ def test_mix_equals_alone(realtime):
     assert st["requests"] == 60 and st["p99_ms"] >= st["p50_ms"] > 0
     for P in plans:
         P.close()
+
+
+def test_time_step_requests_equal_alone():
+    torch.cuda.set_device(0)
+    mats = [w.anderson_3d(12), w.stencil_3d27(12)]
+    plans = [mpk.Plan(A) for A in mats]
+    g = np.random.default_rng(5)
+    reqs = []
+    for i in range(24):
+        m = i % 2
+        kind = "time_step" if i % 3 else "powers"
+        R = int(g.choice([2, 4])) if kind == "time_step" else int(g.choice([1, 2]))
+        reqs.append(serve.Request(id=i, arrival=0.0005 * i, matrix=m,
+                                  p=12 if kind == "time_step" else int(g.integers(2, 6)),
+                                  x=device_x(mats[m].n, R, 300 + i), kind=kind,
+                                  dt=(0.5 if i % 4 else 0.75) if kind == "time_step" else 0.0))
+    srv = serve.Server(plans, n_streams=2, mem_budget=64 << 20)
+    res = srv.serve(reqs, realtime=False)
+    assert max(r.batch_size for q, r in zip(reqs, res) if q.kind == "time_step") > 1
+    for q, r in zip(reqs, res):
+        P = plans[q.matrix]
+        alone = P.cheb_time_step(q.x, q.dt, q.p) if q.kind == "time_step" else P.run(q.x, q.p)
+        torch.cuda.synchronize()
+        assert r.Y.shape == alone.shape and torch.equal(r.Y, alone), q.id
+    st = serve.summarize(res, reqs, plans)
+    assert st["requests"] == 24 and st["gflops"] > 0
+    for P in plans:
+        P.close()

@@ -41,3 +41,21 @@ def test_batch_respects_a_smaller_cap():
 
 def test_batch_bytes():
     assert serve.batch_bytes(1000, 8, 4) == 8 * 1000 * 4 * 9
+
+
+def test_time_steps_batch_only_with_equal_dt_and_order():
+    def ts(i, R, p, dt):
+        r = req(i, R, "time_step", p)
+        r.dt = dt
+        return r
+    q = collections.deque([ts(0, 2, 16, 0.5), ts(1, 2, 16, 0.25), ts(2, 4, 16, 0.5),
+                           ts(3, 2, 12, 0.5), req(4, 2)])
+    assert [r.id for r in serve.form_batch(q)] == [0, 2]
+    assert [r.id for r in serve.form_batch(q)] == [1]
+    assert [r.id for r in serve.form_batch(q)] == [3]
+    assert [r.id for r in serve.form_batch(q)] == [4]
+
+
+def test_time_step_batch_bytes():
+    # x, the stepped states, two sums and the two-vector ring
+    assert serve.batch_bytes(1000, 16, 4, "time_step") == 8 * 1000 * 4 * 6
