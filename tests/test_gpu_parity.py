@@ -361,3 +361,24 @@ def test_full_anderson160_chebyshev16_r8_fp32():
     assert np.array_equal(Y, B)
     assert np.array_equal(Y, oracle.recur(A, x, *coefs, value_bits=32))
     assert rel_err_per_power(Y, oracle.recur(A, x, *coefs)).max() <= TOL32
+
+
+# the launch configuration the benchmark times: the workloads' own order and
+# the autotuner's choice (whichever it picks, the result is the oracle's)
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,vb", [("stencil3d27_128_p8", 64), ("banded_4m_p6", 64),
+                                     ("banded_4m_p6", 32), ("stencil3d27_64_p16_r16", 64),
+                                     ("anderson160_cheb16_r8", 32)])
+def test_full_size_autotuned_original_order(name, vb):
+    A, x, p, kind = w.config(name)
+    cheb = kind == "chebyshev"
+    coefs = oracle.chebyshev_coefficients(p) if cheb else None
+    xd = dev(x)
+    P = mpk.Plan(A, reorder="none", value_bits=vb)
+    P.autotune(xd, p, reps=1, recur=cheb, force=True)
+    Y, B = run_both(P, x, p, recur=coefs)
+    ref = (oracle.recur(A, x, *coefs, value_bits=vb) if cheb
+           else oracle.powers(A, x, p, value_bits=vb))
+    assert np.array_equal(Y, ref) and np.array_equal(B, ref)
+    P.close()

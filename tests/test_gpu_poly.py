@@ -294,3 +294,20 @@ def test_time_step_graph_replays_match_eager(sched, baseline):
     G2.close()
     P.sync()
     P.close()
+
+
+@pytest.mark.slow
+def test_full_size_time_step_anderson160():
+    # the benchmark's time step: 160^3 lattice, FP32 values, 4 complex states,
+    # M = 16, dt = 1, original order, autotuned level-blocked and p x SpMV forms
+    A, x, _, _ = w.config("anderson160_cheb16_r8")
+    M, dt = 16, 1.0
+    P = mpk.Plan(A, value_bits=32, reorder="none")
+    xd = dev(x)
+    P.autotune(xd, M, reps=1, recur=True, force=True)
+    al, be, ga, wa, wb = mpk.cheb_time_coefficients(M, dt)
+    ref = oracle.combine_complex(*oracle.poly_sums(A, x, al, be, ga, wa, wb, value_bits=32))
+    for base in (False, True):
+        out = host(P.cheb_time_step(xd, dt, M, baseline=base))
+        assert np.array_equal(out, ref), base
+    P.close()
