@@ -201,11 +201,24 @@ mpk_status_t check_device_plan(mpk_plan_t plan) {
     return MPK_OK;
 }
 
-// Schedule for p powers with the plan's current tuning (plan->mu held).
 // Stored columns in plan numbering (built once when the plan keeps the
-// caller's numbering; plan->mu held).
-const std::vector<int32_t> &plan_columns(mpk_plan_t plan) {
-    if (plan->plan_cols) return plan->col;
+// caller's numbering; plan->mu held).  A device plan in the caller's own
+// order keeps its columns on the device only; they are copied back here on
+// first use.  Returns nullptr on failure.
+const std::vector<int32_t> *plan_columns(mpk_plan_t plan) {
+    if (plan->col.size() != (size_t)plan->nnz) {
+        plan->col.resize((size_t)plan->nnz);
+        hipError_t e = hipSetDevice(plan->device);
+        if (e == hipSuccess)
+            e = hipMemcpy(plan->col.data(), plan->d_col.ptr, (size_t)plan->nnz * 4,
+                          hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            plan->col.clear();
+            hip_fail(e, "hipMemcpy (columns)");
+            return nullptr;
+        }
+    }
+    if (plan->plan_cols) return &plan->col;
     if (plan->pcol.size() != (size_t)plan->nnz) {
         plan->pcol.resize((size_t)plan->nnz);
         const int32_t *inv = plan->lv.iperm.data(), *c = plan->col.data();
@@ -214,15 +227,18 @@ const std::vector<int32_t> &plan_columns(mpk_plan_t plan) {
 #pragma omp parallel for schedule(static)
         for (int64_t e = 0; e < nz; ++e) out[e] = inv[c[e]];
     }
-    return plan->pcol;
+    return &plan->pcol;
 }
 
 // Whether every stored off-diagonal entry (i, j) has a stored mirror (j, i).
 // A symmetric permutation keeps this property, so the plan-order copy is
 // checked.  Computed once (plan->mu held).
-bool pattern_symmetric(mpk_plan_t plan) {
-    if (plan->pattern_sym >= 0) return plan->pattern_sym == 1;
-    const std::vector<int32_t> &pc = plan_columns(plan);
+// Returns 1 or 0, or -1 when the columns could not be read back.
+int pattern_symmetric(mpk_plan_t plan) {
+    if (plan->pattern_sym >= 0) return plan->pattern_sym;
+    const std::vector<int32_t> *pcp = plan_columns(plan);
+    if (!pcp) return -1;
+    const std::vector<int32_t> &pc = *pcp;
     const int32_t *rp = plan->rowptr.data();
     const int64_t n = plan->n;
     std::vector<int32_t> sorted(pc);
@@ -242,7 +258,7 @@ bool pattern_symmetric(mpk_plan_t plan) {
         }
     }
     plan->pattern_sym = ok;
-    return ok == 1;
+    return ok;
 }
 
 mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_wg) {
@@ -256,7 +272,10 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
     int n_xcd = plan->xcd_bound ? plan->n_xcd : 1;
     if (plan->tune.workgroups > 0 && plan->tune.workgroups < n_xcd) n_xcd = 1;
     const std::vector<int32_t> *pcol = &plan->col;
-    if (plan->tune.schedule == MPK_SCHED_XCD) pcol = &plan_columns(plan);  // exact dependency lists
+    if (plan->tune.schedule == MPK_SCHED_XCD) {  // exact dependency lists
+        pcol = plan_columns(plan);
+        if (!pcol) return MPK_EHIP;
+    }
     PlanShape sh{plan->n, plan->nnz, plan->value_bits / 8, &plan->lv.level_ptr, &plan->rowptr,
                  &plan->row_lo, &plan->row_hi, pcol, n_xcd,
                  plan->xcd_bound && n_xcd > 1};
@@ -417,10 +436,14 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     const bool capturing = cap == hipStreamCaptureStatusActive;
 
     std::lock_guard<std::mutex> g(plan->mu);
-    if (poly && !pattern_symmetric(plan))
-        return fail(MPK_EUNSUPPORTED,
-                    "the level-blocked weighted sums need a structurally symmetric pattern "
-                    "(use the p x SpMV form)");
+    if (poly) {
+        const int sym = pattern_symmetric(plan);
+        if (sym < 0) return MPK_EHIP;
+        if (!sym)
+            return fail(MPK_EUNSUPPORTED,
+                        "the level-blocked weighted sums need a structurally symmetric pattern "
+                        "(use the p x SpMV form)");
+    }
     const int wg_default = default_workgroups(plan, nrhs);
     const int wg = plan->tune.workgroups > 0 ? plan->tune.workgroups : wg_default;
     const int64_t limit_us = plan->tune.spin_limit_us > 0 ? plan->tune.spin_limit_us : 2000000;
@@ -749,12 +772,13 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                 plan->wall_khz = khz;
             const size_t nnz = (size_t)A->nnz;
             if ((st = plan->d_rowptr.upload(pc.rowptr.data(), pc.rowptr.size() * 4))) return st;
-            if ((st = plan->d_col.upload(pc.col.data(), nnz * 4))) return st;
+            if ((st = plan->d_col.upload(pc.identity ? A->col : pc.col.data(), nnz * 4)))
+                return st;
+            const double *v64 = pc.identity ? A->val : pc.val.data();
             if (o.value_bits == 64) {
-                if ((st = plan->d_val.upload(pc.val.data(), nnz * 8))) return st;
+                if ((st = plan->d_val.upload(v64, nnz * 8))) return st;
             } else {
                 std::vector<float> v32(nnz);
-                const double *v64 = pc.val.data();
 #pragma omp parallel for schedule(static)
                 for (int64_t i = 0; i < (int64_t)nnz; ++i) v32[i] = (float)v64[i];
                 if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
@@ -767,7 +791,10 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                     if ((st = plan->d_outrow.upload(plan->lv.perm.data(), (size_t)A->n * 4))) return st;
             }
         }
-        plan->col.swap(pc.col);  // kept for the schedules' dependency lists
+        // kept on the host for the schedules' dependency lists (a device plan
+        // in the caller's order reads them back from the device when needed)
+        if (!pc.identity) plan->col.swap(pc.col);
+        else if (host_only) plan->col.assign(A->col, A->col + A->nnz);
     } catch (const std::bad_alloc &) {
         return fail(MPK_ENOMEM, "host allocation failed");
     } catch (const std::exception &ex) {
@@ -1238,7 +1265,9 @@ mpk_status_t mpk_graph_capture_time_step(mpk_plan_t plan, const double *psi, int
             SliceSet *ss = nullptr;
             if ((st = spmv_slices(plan, nrhs, &ss))) return st;
         } else {
-            if (!pattern_symmetric(plan))
+            const int sym = pattern_symmetric(plan);
+            if (sym < 0) return MPK_EHIP;
+            if (!sym)
                 return fail(MPK_EUNSUPPORTED,
                             "the level-blocked weighted sums need a structurally symmetric pattern "
                             "(use the p x SpMV form)");

@@ -36,7 +36,8 @@ Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col);
 // row's smallest / largest column in PLAN numbering (the dependency extent).
 struct PermutedCSR {
     std::vector<int32_t> rowptr, col, row_lo, row_hi;
-    std::vector<double> val;
+    std::vector<double> val;   // col and val are empty when identity: the
+    bool identity = false;     // caller's arrays are in plan order already
 };
 void permute_csr(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                  const Levels &lv, bool plan_cols, PermutedCSR &out);

@@ -222,11 +222,14 @@ Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col) {
         }
     };
 #pragma omp parallel for schedule(dynamic, 4096)
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t hi = (int32_t)i;  // row i's own farthest column, raised once
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-            raise((int32_t)i, col[e]);
-            raise(col[e], (int32_t)i);
+            hi = std::max(hi, col[e]);
+            raise(col[e], (int32_t)i);  // and i as a neighbour of that column
         }
+        raise((int32_t)i, hi);
+    }
     // level 0 = row 0; level j+1 ends just past the farthest neighbour of level j
     int64_t b_prev = 0, b = 1;
     lv.level_ptr.push_back(1);
@@ -243,6 +246,29 @@ Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col) {
 
 void permute_csr(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                  const Levels &lv, bool plan_cols, PermutedCSR &out) {
+    bool identity = true;
+    for (int64_t r = 0; r < n && identity; ++r) identity = lv.perm[r] == r;
+    out.identity = identity;
+    if (identity) {
+        // the caller's arrays are already in plan order: leave columns and
+        // values to be read in place and only find each row's column extent
+        out.rowptr.assign(rowptr, rowptr + n + 1);
+        out.col.clear();
+        out.val.clear();
+        out.row_lo.resize(n);
+        out.row_hi.resize(n);
+#pragma omp parallel for schedule(static)
+        for (int64_t r = 0; r < n; ++r) {
+            int32_t lo = (int32_t)r, hi = (int32_t)r;
+            for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+                lo = std::min(lo, col[e]);
+                hi = std::max(hi, col[e]);
+            }
+            out.row_lo[r] = lo;
+            out.row_hi[r] = hi;
+        }
+        return;
+    }
     out.rowptr.assign(n + 1, 0);
     for (int64_t r = 0; r < n; ++r) {
         int32_t old = lv.perm[r];
