@@ -339,8 +339,10 @@ mpk_status_t mpk_plan_sync(mpk_plan_t plan);
  * Autotuner (the counterpart of the paper's parameter study over the cache
  * size C and the RACE safety factor, Sec. "Parameter Study"): times the
  * level-blocked run for p powers and nrhs right-hand sides under a fixed list
- * of candidate tunings (schedule x cache budget x chunk size), keeps the
- * fastest and sets it on the plan.  Each candidate runs once untimed, then
+ * of candidate tunings (schedule x cache budget x chunk size, and for the
+ * persistent schedules one or two workgroups per compute unit, p split into
+ * two segments, skip-ahead parking), keeps the fastest and sets it on the
+ * plan.  Each candidate runs once untimed, then
  * `reps` timed runs on `stream` (mean).  Results are cached per (matrix
  * fingerprint, value precision, p, nrhs, recurrence): a later call with the
  * same key applies the cached tuning without timing unless force != 0.

@@ -1082,17 +1082,21 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
             return MPK_OK;
         }
     }
-    // candidates: the paper's study varies the cache size C; here C, the
-    // chunk size and the schedule
+    // candidates: the paper's study varies the cache size C (and p x C by
+    // splitting p); here C, the chunk size, the schedule, the number of
+    // persistent workgroups, segments of p and skip-ahead parking
     std::vector<mpk_tune_t> cands;
-    auto add = [&](int sched, int64_t cache_mib, int chunk, int lag) {
+    auto add = [&](int sched, int64_t cache_mib, int chunk, int lag, int wg = 0, int seg = 0,
+                   int skip = 0) {
         mpk_tune_t t = base;
         t.schedule = sched;
         t.cache_bytes = cache_mib << 20;
         t.cache_safety = 1.0;
         t.chunk_nnz = chunk;
         t.lag = lag;
-        t.seg_powers = 0;
+        t.workgroups = wg;
+        t.seg_powers = seg;
+        t.skip_ahead = skip;
         cands.push_back(t);
     };
     for (int64_t c : {32, 64, 128})
@@ -1100,6 +1104,16 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     for (int chunk : {8192, 16384, 32768}) add(MPK_SCHED_WAVE, 64, chunk, 0);
     add(MPK_SCHED_XCD, 64, 16384, 0);
     add(MPK_SCHED_POWERS, 64, 8192, 0);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plan->device) !=
+            hipSuccess || cus < 1)
+        cus = 0;
+    if (cus > 0) {  // one persistent workgroup per compute unit instead of two
+        add(MPK_SCHED_WAVE, 64, 32768, 0, cus);
+        add(MPK_SCHED_POWERS, 64, 8192, 0, cus);
+    }
+    if (p >= 4) add(MPK_SCHED_WAVE, 64, 32768, 0, 0, (p + 1) / 2);  // two segments
+    add(MPK_SCHED_WAVE, 64, 16384, 0, 0, 0, 2);                     // park up to two tasks
     // Chebyshev coefficients for timing the recurrence (values do not change the time)
     std::vector<double> al(p), be(p, 0.0), ga(p, -1.0);
     for (int k = 0; k < p; ++k) al[k] = k == 0 ? 1.0 : 2.0;
