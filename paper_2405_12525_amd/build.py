@@ -43,9 +43,10 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)
-    ko = os.path.join(OUT_DIR, "kernels.o")
-    _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", ko], verbose)
-    objs.append(ko)
+    for src in ("kernels.hip", "gpu_plan.hip"):
+        o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
+        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
+        objs.append(o)
     tmp = LIB + f".tmp{os.getpid()}"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lgomp",
           f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"], verbose)

@@ -747,15 +747,15 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         plan->order = o.order;
         plan->host_only = host_only;
         mpk_tune_default(&plan->tune);
-        plan->lv = o.reorder == MPK_REORDER_BFS ? bfs_levels(A->n, A->rowptr, A->col, o.root)
-                                                : order_levels(A->n, A->rowptr, A->col);
-        PermutedCSR pc;
         const bool plan_cols = o.order == MPK_ORDER_PLAN;
-        permute_csr(A->n, A->rowptr, A->col, host_only ? nullptr : A->val, plan->lv, plan_cols, pc);
-        plan->rowptr = pc.rowptr;
-        plan->row_lo.swap(pc.row_lo);
-        plan->row_hi.swap(pc.row_hi);
         plan->plan_cols = plan_cols;
+        const size_t nnz = (size_t)A->nnz;
+        // BFS order on a device: levels and permutation on the GPU (the host
+        // path below computes the same; the pseudo-peripheral root and
+        // host-only plans take the host path)
+        bool gpu_levels = !host_only && o.reorder == MPK_REORDER_BFS &&
+                          o.root != MPK_ROOT_PERIPHERAL && A->n > 0;
+        PermutedCSR pc;
         if (!host_only) {
             int dev = o.device;
             if (dev == MPK_DEVICE_CURRENT) {
@@ -770,19 +770,57 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
             int khz = 0;
             if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
                 plan->wall_khz = khz;
-            const size_t nnz = (size_t)A->nnz;
-            if ((st = plan->d_rowptr.upload(pc.rowptr.data(), pc.rowptr.size() * 4))) return st;
-            if ((st = plan->d_col.upload(pc.identity ? A->col : pc.col.data(), nnz * 4)))
-                return st;
-            const double *v64 = pc.identity ? A->val : pc.val.data();
-            if (o.value_bits == 64) {
-                if ((st = plan->d_val.upload(v64, nnz * 8))) return st;
+        }
+        if (gpu_levels) {
+            DevBuf rp0, c0, v0;  // the caller's CSR in its own order
+            if ((st = rp0.upload(A->rowptr, ((size_t)A->n + 1) * 4))) return st;
+            if ((st = c0.upload(A->col, nnz * 4))) return st;
+            if ((st = v0.upload(A->val, nnz * 8))) return st;
+            if ((st = plan->d_rowptr.alloc(((size_t)A->n + 1) * 4))) return st;
+            if ((st = plan->d_col.alloc(nnz * 4))) return st;
+            if ((st = plan->d_val.alloc(nnz * (size_t)(o.value_bits / 8)))) return st;
+            GpuLevels g;
+            const int rc = gpu_levels_permute(A->n, A->nnz, rp0.as<int32_t>(), c0.as<int32_t>(),
+                                              v0.as<double>(), o.root, plan_cols, o.value_bits,
+                                              plan->d_rowptr.as<int32_t>(),
+                                              plan->d_col.as<int32_t>(), plan->d_val.ptr, g);
+            if (rc == kTooManyLevels) {
+                gpu_levels = false;  // many levels or components: the host planner
+            } else if (rc) {
+                return hip_fail((hipError_t)rc, "device level construction");
             } else {
-                std::vector<float> v32(nnz);
-#pragma omp parallel for schedule(static)
-                for (int64_t i = 0; i < (int64_t)nnz; ++i) v32[i] = (float)v64[i];
-                if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
+                plan->lv.level_ptr.swap(g.level_ptr);
+                plan->lv.perm.swap(g.perm);
+                plan->lv.iperm.swap(g.iperm);
+                plan->rowptr.swap(g.rowptr);
+                plan->row_lo.swap(g.row_lo);
+                plan->row_hi.swap(g.row_hi);
             }
+        }
+        if (!gpu_levels) {
+            plan->lv = o.reorder == MPK_REORDER_BFS ? bfs_levels(A->n, A->rowptr, A->col, o.root)
+                                                    : order_levels(A->n, A->rowptr, A->col);
+            permute_csr(A->n, A->rowptr, A->col, host_only ? nullptr : A->val, plan->lv,
+                        plan_cols, pc);
+            plan->rowptr = pc.rowptr;
+            plan->row_lo.swap(pc.row_lo);
+            plan->row_hi.swap(pc.row_hi);
+            if (!host_only) {
+                if ((st = plan->d_rowptr.upload(pc.rowptr.data(), pc.rowptr.size() * 4))) return st;
+                if ((st = plan->d_col.upload(pc.identity ? A->col : pc.col.data(), nnz * 4)))
+                    return st;
+                const double *v64 = pc.identity ? A->val : pc.val.data();
+                if (o.value_bits == 64) {
+                    if ((st = plan->d_val.upload(v64, nnz * 8))) return st;
+                } else {
+                    std::vector<float> v32(nnz);
+#pragma omp parallel for schedule(static)
+                    for (int64_t i = 0; i < (int64_t)nnz; ++i) v32[i] = (float)v64[i];
+                    if ((st = plan->d_val.upload(v32.data(), nnz * 4))) return st;
+                }
+            }
+        }
+        if (!host_only) {
             bool identity = true;
             for (int64_t i = 0; i < A->n && identity; ++i) identity = plan->lv.perm[i] == i;
             if (!identity) {
@@ -791,10 +829,14 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
                     if ((st = plan->d_outrow.upload(plan->lv.perm.data(), (size_t)A->n * 4))) return st;
             }
         }
-        // kept on the host for the schedules' dependency lists (a device plan
-        // in the caller's order reads them back from the device when needed)
-        if (!pc.identity) plan->col.swap(pc.col);
-        else if (host_only) plan->col.assign(A->col, A->col + A->nnz);
+        // kept on the host for the schedules' dependency lists (device plans
+        // built in place or on the GPU read them back when needed)
+        if (host_only) {
+            if (pc.identity) plan->col.assign(A->col, A->col + A->nnz);
+            else plan->col.swap(pc.col);
+        } else if (!gpu_levels && !pc.identity) {
+            plan->col.swap(pc.col);
+        }
     } catch (const std::bad_alloc &) {
         return fail(MPK_ENOMEM, "host allocation failed");
     } catch (const std::exception &ex) {

@@ -1,0 +1,306 @@
+// Device-side preprocessing for BFS-ordered plans: the level construction and
+// the symmetric permutation of Sec. "RACE Applied to the Matrix Power Kernel"
+// (level equation, BFS reordering; the endnote on non-symmetric patterns),
+// computed on the GPU from the caller's CSR already uploaded in its own order.
+// The result is the one the host planner (bfs_levels + permute_csr) produces:
+//
+//   * the graph is the stored pattern plus its mirror, self-loops ignored;
+//   * level 0 is the root; level L+1 holds the unvisited neighbours of level
+//     L; when a level comes out empty while rows remain, the next level
+//     starts at the lowest unvisited row;
+//   * inside a level rows keep ascending original index (a stable radix
+//     sort of the rows by level);
+//   * row r' of the permuted matrix is old row perm[r'] with its entries in
+//     stored order, columns renumbered when the plan keeps plan numbering.
+//
+// All level membership is decided by one compare-and-swap per vertex, so the
+// level of every row is unique whatever order the threads run in.
+
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "mpk_internal.h"
+
+namespace mpk {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int32_t kMaxDeviceLevels = 16384;
+constexpr int kMaxDeviceRestarts = 64;
+
+inline unsigned grid_for(int64_t work) {
+    const int64_t g = (work + kThreads - 1) / kThreads;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+__global__ void fill_kernel(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void iota_kernel(int32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// cnt[c + 1] = number of stored entries in column c (cnt zeroed, n + 1 long)
+__global__ void count_cols_kernel(const int32_t *col, int64_t nnz, int32_t *cnt) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[col[e] + 1], 1);
+}
+
+// in-neighbours: tcol[fill[c]++] = i for every stored (i, c); the order inside
+// a transposed row does not matter (levels are sets)
+__global__ void transpose_kernel(const int32_t *rowptr, const int32_t *col, int64_t n,
+                                 int32_t *fill, int32_t *tcol) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            tcol[atomicAdd(&fill[col[e]], 1)] = (int32_t)i;
+}
+
+// One BFS level: every unvisited neighbour v of the frontier gets level L
+// (claimed by compare-and-swap, so once) and is appended to `next`.
+__global__ void expand_kernel(const int32_t *rowptr, const int32_t *col, const int32_t *tptr,
+                              const int32_t *tcol, const int32_t *front, int32_t nf,
+                              int32_t *lev, int32_t L, int32_t *next, int32_t *cnt) {
+    for (int32_t f = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); f < nf;
+         f += (int32_t)(gridDim.x * blockDim.x)) {
+        const int32_t u = front[f];
+        for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+            const int32_t v = col[e];
+            if (lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1) next[atomicAdd(cnt, 1)] = v;
+        }
+        for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e) {
+            const int32_t v = tcol[e];
+            if (lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1) next[atomicAdd(cnt, 1)] = v;
+        }
+    }
+}
+
+// out = the lowest row without a level (out preset to n)
+__global__ void first_unvisited_kernel(const int32_t *lev, int64_t n, int32_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (lev[i] < 0) atomicMin(out, (int32_t)i);
+}
+
+// level_ptr[key] = first position of each level in the sorted keys
+__global__ void level_starts_kernel(const int32_t *keys, int64_t n, int32_t *level_ptr) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (i == 0 || keys[i] != keys[i - 1]) level_ptr[keys[i]] = (int32_t)i;
+}
+
+// iperm[perm[r]] = r, and the permuted row lengths len[r] (len[n] = 0)
+__global__ void inverse_kernel(const int32_t *perm, const int32_t *rowptr, int64_t n,
+                               int32_t *iperm, int32_t *len) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        if (r == n) {
+            len[n] = 0;
+            continue;
+        }
+        const int32_t old = perm[r];
+        iperm[old] = (int32_t)r;
+        len[r] = rowptr[old + 1] - rowptr[old];
+    }
+}
+
+// Row r of the permuted matrix: old row perm[r] in stored order, columns in
+// plan numbering when plan_cols, values as double or float; row_lo / row_hi
+// are the smallest / largest plan-numbered column (the row itself included).
+template <typename V>
+__global__ void permute_kernel(const int32_t *rowptr, const int32_t *col, const double *val,
+                               const int32_t *perm, const int32_t *iperm, const int32_t *nrp,
+                               int64_t n, int plan_cols, int32_t *ncol, V *nval, int32_t *row_lo,
+                               int32_t *row_hi) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t old = perm[r];
+        int32_t lo = (int32_t)r, hi = (int32_t)r;
+        int32_t d = nrp[r];
+        for (int32_t e = rowptr[old]; e < rowptr[old + 1]; ++e, ++d) {
+            const int32_t c = col[e];
+            const int32_t cp = iperm[c];
+            ncol[d] = plan_cols ? cp : c;
+            nval[d] = static_cast<V>(val[e]);
+            lo = min(lo, cp);
+            hi = max(hi, cp);
+        }
+        row_lo[r] = lo;
+        row_hi[r] = hi;
+    }
+}
+
+// Device scratch freed on every exit path.
+struct Scratch {
+    std::vector<void *> ptrs;
+    ~Scratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t get(T **p, size_t count) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) return e;
+        ptrs.push_back(q);
+        *p = static_cast<T *>(q);
+        return hipSuccess;
+    }
+};
+
+#define MPK_TRY(x)                          \
+    do {                                    \
+        hipError_t e_ = (x);                \
+        if (e_ != hipSuccess) return (int)e_; \
+    } while (0)
+
+}  // namespace
+
+int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                       const double *val, int32_t root, bool plan_cols, int value_bits,
+                       int32_t *out_rowptr, int32_t *out_col, void *out_val, GpuLevels &res) {
+    res = GpuLevels{};
+    res.level_ptr.push_back(0);
+    if (n == 0) return 0;
+    Scratch s;
+    int32_t *tptr, *fill, *tcol, *lev, *front, *next, *cnt, *perm_in, *perm, *keys, *iperm,
+        *len, *level_ptr, *lo, *hi, *start;
+    MPK_TRY(s.get(&tptr, n + 1));
+    MPK_TRY(s.get(&fill, n + 1));
+    MPK_TRY(s.get(&tcol, nnz));
+    MPK_TRY(s.get(&lev, n));
+    MPK_TRY(s.get(&front, n));
+    MPK_TRY(s.get(&next, n));
+    MPK_TRY(s.get(&cnt, 2));
+    MPK_TRY(s.get(&perm_in, n));
+    MPK_TRY(s.get(&perm, n));
+    MPK_TRY(s.get(&keys, n));
+    MPK_TRY(s.get(&iperm, n));
+    MPK_TRY(s.get(&len, n + 1));
+    MPK_TRY(s.get(&lo, n));
+    MPK_TRY(s.get(&hi, n));
+    MPK_TRY(s.get(&start, 1));
+
+    // 1. transpose pattern (in-neighbours): counts, exclusive sums, scatter
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n + 1)), dim3(kThreads), 0, 0, tptr, n + 1, 0);
+    hipLaunchKernelGGL(count_cols_kernel, dim3(grid_for(nnz)), dim3(kThreads), 0, 0, col, nnz,
+                       tptr);
+    {
+        size_t tmp_bytes = 0;
+        MPK_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, tptr, fill, (int)(n + 1)));
+        void *tmp = nullptr;
+        MPK_TRY(s.get(reinterpret_cast<char **>(&tmp), tmp_bytes));
+        MPK_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, tptr, fill, (int)(n + 1)));
+    }
+    // fill = running insert positions (a copy of the column starts)
+    MPK_TRY(hipMemcpy(tptr, fill, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice));
+    hipLaunchKernelGGL(transpose_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr, col, n,
+                       fill, tcol);
+    MPK_TRY(hipGetLastError());
+
+    // 2. levels, one launch per level; a restart at the lowest unvisited row
+    //    when the frontier empties
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, lev, n, -1);
+    int64_t visited = 0;
+    int32_t L = 0;
+    int32_t nf = 0;
+    int restarts = 0;
+    int32_t first = (root >= 0 && root < n) ? root : 0;
+    while (visited < n) {
+        // each level costs a launch and a round trip: graphs with very many
+        // levels or components are left to the host planner
+        if (L > kMaxDeviceLevels || restarts > kMaxDeviceRestarts) return kTooManyLevels;
+        if (nf == 0) {
+            if (visited > 0) {
+                ++restarts;
+                const int32_t nn = (int32_t)n;
+                MPK_TRY(hipMemcpy(start, &nn, 4, hipMemcpyHostToDevice));
+                hipLaunchKernelGGL(first_unvisited_kernel, dim3(grid_for(n)), dim3(kThreads), 0,
+                                   0, lev, n, start);
+                MPK_TRY(hipMemcpy(&first, start, 4, hipMemcpyDeviceToHost));
+                if (first < 0 || first >= n) return (int)hipErrorUnknown;
+            }
+            MPK_TRY(hipMemcpy(lev + first, &L, 4, hipMemcpyHostToDevice));
+            MPK_TRY(hipMemcpy(front, &first, 4, hipMemcpyHostToDevice));
+            nf = 1;
+        }
+        visited += nf;
+        ++L;
+        const int32_t zero = 0;
+        MPK_TRY(hipMemcpy(cnt, &zero, 4, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(expand_kernel, dim3(grid_for(nf)), dim3(kThreads), 0, 0, rowptr, col,
+                           tptr, tcol, front, nf, lev, L, next, cnt);
+        MPK_TRY(hipGetLastError());
+        MPK_TRY(hipMemcpy(&nf, cnt, 4, hipMemcpyDeviceToHost));
+        if (nf < 0 || visited + nf > n) return (int)hipErrorUnknown;
+        std::swap(front, next);
+    }
+    const int32_t n_levels = L;
+
+    // 3. rows by level, ascending original index inside a level (the radix
+    //    sort is stable and its input is in index order)
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, perm_in, n);
+    {
+        int bits = 1;
+        while ((1ll << bits) <= n_levels) ++bits;
+        size_t tmp_bytes = 0;
+        MPK_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, lev, keys, perm_in, perm,
+                                                   (int)n, 0, bits));
+        void *tmp = nullptr;
+        MPK_TRY(s.get(reinterpret_cast<char **>(&tmp), tmp_bytes));
+        MPK_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, lev, keys, perm_in, perm,
+                                                   (int)n, 0, bits));
+    }
+    MPK_TRY(s.get(&level_ptr, (size_t)n_levels + 1));
+    hipLaunchKernelGGL(level_starts_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, keys, n,
+                       level_ptr);
+
+    // 4. inverse permutation, permuted row pointer, permuted rows
+    hipLaunchKernelGGL(inverse_kernel, dim3(grid_for(n + 1)), dim3(kThreads), 0, 0, perm, rowptr,
+                       n, iperm, len);
+    {
+        size_t tmp_bytes = 0;
+        MPK_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, len, out_rowptr, (int)(n + 1)));
+        void *tmp = nullptr;
+        MPK_TRY(s.get(reinterpret_cast<char **>(&tmp), tmp_bytes));
+        MPK_TRY(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, len, out_rowptr, (int)(n + 1)));
+    }
+    if (value_bits == 32)
+        hipLaunchKernelGGL(permute_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr,
+                           col, val, perm, iperm, out_rowptr, n, plan_cols ? 1 : 0, out_col,
+                           static_cast<float *>(out_val), lo, hi);
+    else
+        hipLaunchKernelGGL(permute_kernel<double>, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+                           rowptr, col, val, perm, iperm, out_rowptr, n, plan_cols ? 1 : 0,
+                           out_col, static_cast<double *>(out_val), lo, hi);
+    MPK_TRY(hipGetLastError());
+
+    // 5. what the host scheduler needs
+    res.level_ptr.assign((size_t)n_levels + 1, 0);
+    res.perm.resize((size_t)n);
+    res.iperm.resize((size_t)n);
+    res.rowptr.resize((size_t)n + 1);
+    res.row_lo.resize((size_t)n);
+    res.row_hi.resize((size_t)n);
+    MPK_TRY(hipMemcpy(res.level_ptr.data(), level_ptr, (size_t)n_levels * 4,
+                      hipMemcpyDeviceToHost));
+    res.level_ptr[(size_t)n_levels] = (int32_t)n;
+    MPK_TRY(hipMemcpy(res.perm.data(), perm, (size_t)n * 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(res.iperm.data(), iperm, (size_t)n * 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(res.rowptr.data(), out_rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(res.row_lo.data(), lo, (size_t)n * 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(res.row_hi.data(), hi, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (res.rowptr[(size_t)n] != nnz) return (int)hipErrorUnknown;
+    return 0;
+}
+
+}  // namespace mpk

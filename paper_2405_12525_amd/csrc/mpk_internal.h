@@ -42,6 +42,22 @@ struct PermutedCSR {
 void permute_csr(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                  const Levels &lv, bool plan_cols, PermutedCSR &out);
 
+// Levels and the permuted CSR computed on the device (gpu_plan.hip): the
+// same result as bfs_levels + permute_csr.  rowptr / col / val are the
+// caller's CSR on the device in its own order; out_rowptr (n + 1), out_col
+// (nnz) and out_val (nnz doubles or floats, by value_bits) receive the
+// permuted matrix; `res` the host copies the scheduler needs.  Returns a
+// hipError_t (0 on success), or kTooManyLevels when the graph has more
+// levels or components than a level-by-level device search handles well
+// (the caller then uses the host planner).
+constexpr int kTooManyLevels = -1;
+struct GpuLevels {
+    std::vector<int32_t> level_ptr, perm, iperm, rowptr, row_lo, row_hi;
+};
+int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                       const double *val, int32_t root, bool plan_cols, int value_bits,
+                       int32_t *out_rowptr, int32_t *out_col, void *out_val, GpuLevels &res);
+
 // Schedule of (chunk, power) tasks for p powers.
 struct Schedule {
     int p = 0;

@@ -382,3 +382,60 @@ def test_full_size_autotuned_original_order(name, vb):
            else oracle.powers(A, x, p, value_bits=vb))
     assert np.array_equal(Y, ref) and np.array_equal(B, ref)
     P.close()
+
+
+# ------------------------------------------------------------------ device-built plans
+
+def _host_levels(A, **kw):
+    return mpk.Plan(A, device=mpk.MPK_DEVICE_NONE, **kw).levels()
+
+
+@pytest.mark.parametrize("case", ["stencil", "random_sym", "random_nonsym", "disconnected",
+                                  "empty_rows", "anderson"])
+@pytest.mark.parametrize("order", ["original", "plan"])
+def test_device_levels_equal_host_levels(case, order):
+    # BFS levels and the permutation computed on the GPU are the host
+    # planner's exactly (integers), and runs on the device-built plan match
+    # the oracle bit for bit
+    A = {"stencil": lambda: w.stencil_3d27(16),
+         "random_sym": lambda: w.random_sparse(3000, 0.002, 41, symmetric_pattern=True),
+         "random_nonsym": lambda: w.random_sparse(3000, 0.0015, 42),
+         "disconnected": lambda: w.random_sparse(2500, 0.0004, 43, symmetric_pattern=True),
+         "empty_rows": lambda: w.CSR(6, np.array([0, 0, 2, 2, 3, 3, 3], np.int32),
+                                     np.array([4, 1, 2], np.int32), np.array([1.0, 2.0, 3.0])),
+         "anderson": lambda: w.anderson_3d(12)}[case]()
+    for root in (0, A.n // 2):
+        P = mpk.Plan(A, order=order, root=root)
+        lp, perm = P.levels()
+        lh, permh = _host_levels(A, order=order, root=root)
+        assert np.array_equal(lp, lh) and np.array_equal(perm, permh), (case, root)
+        x = w.uniform_vectors(A.n, 2, 7)
+        if order == "plan":
+            Ap = oracle.permute_csr(A, perm)
+            Y, B = run_both(P, x[perm], 4)
+            ref = oracle.powers(Ap, x[perm], 4)
+        else:
+            Y, B = run_both(P, x, 4)
+            ref = oracle.powers(A, x, 4)
+        assert np.array_equal(Y, ref) and np.array_equal(B, ref)
+        P.close()
+
+
+def test_device_levels_fp32_and_many_components():
+    # FP32 values are converted by the device permutation; a graph with more
+    # components than the device search takes goes through the host planner
+    A = w.anderson_3d(10)
+    P = mpk.Plan(A, value_bits=32)
+    x = w.uniform_vectors(A.n, 1, 8)
+    Y, B = run_both(P, x, 3)
+    assert np.array_equal(Y, oracle.powers(A, x, 3, value_bits=32))
+    n = 500   # a diagonal matrix: 500 components
+    D = w.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+              np.linspace(0.5, 1.5, n))
+    Q = mpk.Plan(D)
+    lp, perm = Q.levels()
+    assert len(lp) - 1 == n and np.array_equal(perm, np.arange(n))
+    Y, B = run_both(Q, np.ones((n, 1)), 2)
+    assert np.array_equal(Y, oracle.powers(D, np.ones((n, 1)), 2))
+    P.close()
+    Q.close()
