@@ -461,6 +461,23 @@ def main():
             Q.close()
     info = P.info()
     sched = P.schedule(p)
+    # the same plan from a CSR already in device memory (mpk_plan_device)
+    import types
+    dcsr = types.SimpleNamespace(n=A.n, rowptr=torch.from_numpy(A.rowptr).cuda(),
+                                 col=torch.from_numpy(A.col).cuda(),
+                                 val=torch.from_numpy(A.val).cuda())
+    dev_ms = {}
+    for ro in ("none", "bfs"):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Pd = mpk.Plan(dcsr, reorder=ro, value_bits=vb)
+            ts.append((time.perf_counter() - t0) * 1e3)
+            Pd.close()
+        dev_ms[ro] = round(statistics.median(ts), 1)
+    del dcsr
+    log(f"[bench] plans from a device CSR: {dev_ms} ms")
     run_base(P, B)
     run_lb(P, Y)
     stream.synchronize()
@@ -518,7 +535,10 @@ def main():
         "bit_identical_to_pxspmv": same,
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
                  "chunks": sched["n_chunks"], "launches_per_run": sched["n_steps"],
-                 "spmv_equivalents": round(info["plan_ms"] / (bmed / p), 1)},
+                 "spmv_equivalents": round(info["plan_ms"] / (bmed / p), 1),
+                 "from_device_csr_ms": dev_ms,
+                 "from_device_csr_spmv_equivalents": {k: round(v / (bmed / p), 1)
+                                                      for k, v in dev_ms.items()}},
     }
     P.close()
     del Y, B

@@ -175,6 +175,19 @@ void mpk_tune_default(mpk_tune_t *tune);
  */
 mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out);
 
+/*
+ * The same plan from a CSR whose rowptr, col and val are DEVICE pointers (on
+ * opts->device, or the current device when MPK_DEVICE_CURRENT).  Validation,
+ * the levels and the permutation run on the device, so no matrix crosses the
+ * host link.  The pseudo-peripheral root and graphs beyond the device level
+ * search (more than 16384 levels or 64 components) are copied to the host
+ * and planned as by mpk_plan.  The result, including the autotuner's
+ * fingerprint, equals mpk_plan's for the same matrix and options.  The plan
+ * copies the matrix: the caller may free its arrays when the call returns.
+ * Errors: as mpk_plan; MPK_EINVAL for opts->device == MPK_DEVICE_NONE.
+ */
+mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out);
+
 /* Release the plan and all device memory it owns (waits for its runs). */
 void mpk_plan_destroy(mpk_plan_t plan);
 

@@ -145,7 +145,8 @@ class Plan:
     """A preprocessed matrix resident on one device (or host-only).
 
     ``A`` is any object with ``n``, ``rowptr`` (int32), ``col`` (int32) and
-    ``val`` (float64) attributes, e.g. :class:`workloads.CSR`.
+    ``val`` (float64) attributes, e.g. :class:`workloads.CSR`.  When they are
+    device tensors the plan is built on the device (mpk_plan_device).
     """
 
     def __init__(self, A, value_bits: int = 64, reorder: str = "bfs", order: str = "original",
@@ -153,12 +154,24 @@ class Plan:
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
-        rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
-        col = np.ascontiguousarray(A.col, dtype=np.int32)
-        val = None if A.val is None else np.ascontiguousarray(A.val, dtype=np.float64)
-        csr = _capi.CSRStruct(int(A.n), int(rowptr[-1]) if rowptr.size else 0,
-                              rowptr.ctypes.data, col.ctypes.data if col.size else None,
-                              val.ctypes.data if (val is not None and val.size) else None)
+        on_device = getattr(A.rowptr, "is_cuda", False)
+        if on_device:
+            torch = _torch()
+            rowptr, col, val = A.rowptr, A.col, A.val
+            for t, dt, name in ((rowptr, torch.int32, "rowptr"), (col, torch.int32, "col"),
+                                (val, torch.float64, "val")):
+                if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                    raise TypeError(f"{name} must be a contiguous {dt} device tensor")
+            nnz = int(col.numel())
+            csr = _capi.CSRStruct(int(A.n), nnz, rowptr.data_ptr(),
+                                  col.data_ptr() if nnz else None, val.data_ptr() if nnz else None)
+        else:
+            rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+            col = np.ascontiguousarray(A.col, dtype=np.int32)
+            val = None if A.val is None else np.ascontiguousarray(A.val, dtype=np.float64)
+            csr = _capi.CSRStruct(int(A.n), int(rowptr[-1]) if rowptr.size else 0,
+                                  rowptr.ctypes.data, col.ctypes.data if col.size else None,
+                                  val.ctypes.data if (val is not None and val.size) else None)
         opts = _capi.PlanOpts()
         L.mpk_plan_opts_default(ctypes.byref(opts))
         opts.value_bits = int(value_bits)
@@ -168,7 +181,8 @@ class Plan:
         if device is None or device == "none":
             device = MPK_DEVICE_NONE
         opts.device = int(device)
-        check(L.mpk_plan(ctypes.byref(csr), ctypes.byref(opts), ctypes.byref(self._h)))
+        make = L.mpk_plan_device if on_device else L.mpk_plan
+        check(make(ctypes.byref(csr), ctypes.byref(opts), ctypes.byref(self._h)))
         self.n = int(A.n)
         self.nnz = int(csr.nnz)
         self.order = order

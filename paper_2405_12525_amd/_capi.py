@@ -25,7 +25,7 @@ EXPORTS = [
     "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
     "mpk_plan_autotune", "mpk_graph_capture", "mpk_graph_launch", "mpk_graph_destroy",
     "mpk_run_poly", "mpk_run_baseline_poly", "mpk_cheb_time_coefficients", "mpk_combine_complex",
-    "mpk_graph_capture_time_step",
+    "mpk_graph_capture_time_step", "mpk_plan_device",
 ]
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -87,6 +87,9 @@ def load():
     lib.mpk_plan.argtypes = [ctypes.POINTER(CSRStruct), ctypes.POINTER(PlanOpts),
                              ctypes.POINTER(ctypes.c_void_p)]
     lib.mpk_plan.restype = st
+    lib.mpk_plan_device.argtypes = [ctypes.POINTER(CSRStruct), ctypes.POINTER(PlanOpts),
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    lib.mpk_plan_device.restype = st
     lib.mpk_plan_destroy.argtypes = [P]
     lib.mpk_plan_destroy.restype = None
     lib.mpk_plan_tune.argtypes = [P, ctypes.POINTER(Tune)]

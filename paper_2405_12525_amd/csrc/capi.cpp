@@ -606,6 +606,40 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     return MPK_OK;
 }
 
+// An FNV-style hash (one xor and multiply per 32-bit word) over the shape,
+// the options, every row pointer and a sample of the columns (every step-th
+// entry): the key of the autotuner's cache.  The row pointers are hashed in
+// 64 fixed pieces in parallel and the piece hashes folded in order, so the
+// key does not depend on the thread count.
+int64_t fingerprint_step(int64_t nnz) { return std::max<int64_t>(1, nnz / 65536); }
+uint64_t fingerprint(int64_t n, int64_t nnz, const mpk_plan_opts_t &o, const int32_t *rowptr,
+                     const std::vector<int32_t> &sample) {
+    constexpr uint64_t kBasis = 1469598103934665603ull, kPrime = 1099511628211ull;
+    uint64_t h = kBasis;
+    auto mix = [&h](uint64_t v) {
+        h ^= v;
+        h *= kPrime;
+    };
+    mix((uint64_t)n);
+    mix((uint64_t)nnz);
+    mix((uint64_t)o.reorder * 1000 + o.order * 100 + (uint64_t)o.root);
+    constexpr int kPieces = 64;
+    uint64_t piece[kPieces];
+    const int64_t len = n + 1;
+#pragma omp parallel for schedule(static)
+    for (int b = 0; b < kPieces; ++b) {
+        uint64_t g = kBasis;
+        for (int64_t i = len * b / kPieces; i < len * (b + 1) / kPieces; ++i) {
+            g ^= (uint64_t)(uint32_t)rowptr[i];
+            g *= kPrime;
+        }
+        piece[b] = g;
+    }
+    for (int b = 0; b < kPieces; ++b) mix(piece[b]);
+    for (int32_t c : sample) mix((uint64_t)(uint32_t)c);
+    return h;
+}
+
 // Weighted sums: argument checks shared by both forms.
 mpk_status_t run_poly(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
                       const double *beta, const double *gamma, const double *wa,
@@ -843,22 +877,138 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         return fail(MPK_EINVAL, ex.what());
     }
     {
-        // FNV-1a over the shape, the options, every row pointer and a sample
-        // of the columns: the key of the autotuner's cache
-        uint64_t h = 1469598103934665603ull;
-        auto mix = [&h](uint64_t v) {
-            for (int b = 0; b < 8; ++b) {
-                h ^= (v >> (8 * b)) & 0xff;
-                h *= 1099511628211ull;
+        const int64_t step = fingerprint_step(A->nnz);
+        std::vector<int32_t> sample;
+        for (int64_t e2 = 0; e2 < A->nnz; e2 += step) sample.push_back(A->col[e2]);
+        plan->fingerprint = fingerprint(A->n, A->nnz, o, A->rowptr, sample);
+    }
+    plan->plan_ms = now_ms() - t0;
+    *out = plan.release();
+    return MPK_OK;
+}
+
+mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out) {
+    if (!out) return fail(MPK_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A) return fail(MPK_EINVAL, "A is NULL");
+    mpk_plan_opts_t o;
+    mpk_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.device == MPK_DEVICE_NONE) return fail(MPK_EINVAL, "a device CSR needs a device plan");
+    if (o.value_bits != 64 && o.value_bits != 32) return fail(MPK_EINVAL, "value_bits must be 32 or 64");
+    if (o.reorder != MPK_REORDER_BFS && o.reorder != MPK_REORDER_NONE) return fail(MPK_EINVAL, "bad reorder");
+    if (o.order != MPK_ORDER_ORIGINAL && o.order != MPK_ORDER_PLAN) return fail(MPK_EINVAL, "bad order");
+    if (A->n < 0 || A->nnz < 0) return fail(MPK_EBADCSR, "negative n or nnz");
+    if (A->n >= (int64_t)INT32_MAX) return fail(MPK_EUNSUPPORTED, "n >= 2^31 is not supported");
+    if (A->nnz >= (int64_t)INT32_MAX) return fail(MPK_EUNSUPPORTED, "nnz >= 2^31 is not supported");
+    if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val))) return fail(MPK_EINVAL, "NULL array");
+    if (A->n > 0 && o.root != MPK_ROOT_PERIPHERAL && (o.root < 0 || o.root >= A->n))
+        return fail(MPK_EINVAL, "root out of range");
+    const double t0 = now_ms();
+    int dev = o.device;
+    if (dev == MPK_DEVICE_CURRENT) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    }
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int64_t n = A->n, nnz = A->nnz;
+    // validation on the device
+    int bad_rows = 0, bad_cols = 0;
+    int32_t ends[2] = {0, 0};
+    int rc = gpu_validate(n, nnz, A->rowptr, A->col, &bad_rows, &bad_cols, ends);
+    if (rc) return hip_fail((hipError_t)rc, "device validation");
+    if (ends[0] != 0) return fail(MPK_EBADCSR, "rowptr[0] != 0");
+    if (bad_rows) return fail(MPK_EBADCSR, "rowptr decreases");
+    if ((int64_t)ends[1] != nnz) return fail(MPK_EBADCSR, "rowptr[n] != nnz");
+    if (bad_cols) return fail(MPK_EBADCSR, "column index out of range");
+    const bool plan_cols = o.order == MPK_ORDER_PLAN;
+    // the pseudo-peripheral root, and graphs beyond the device level search,
+    // are planned from a host copy
+    auto via_host = [&]() -> mpk_status_t {
+        std::vector<int32_t> rp((size_t)n + 1), cl((size_t)nnz);
+        std::vector<double> vl((size_t)nnz);
+        hipError_t e2 = hipMemcpy(rp.data(), A->rowptr, rp.size() * 4, hipMemcpyDeviceToHost);
+        if (e2 == hipSuccess && nnz)
+            e2 = hipMemcpy(cl.data(), A->col, cl.size() * 4, hipMemcpyDeviceToHost);
+        if (e2 == hipSuccess && nnz)
+            e2 = hipMemcpy(vl.data(), A->val, vl.size() * 8, hipMemcpyDeviceToHost);
+        if (e2 != hipSuccess) return hip_fail(e2, "hipMemcpy (device CSR to host)");
+        mpk_csr_t H{n, nnz, rp.data(), cl.data(), vl.data()};
+        mpk_plan_opts_t o2 = o;
+        o2.device = dev;
+        return mpk_plan(&H, &o2, out);
+    };
+    if (o.reorder == MPK_REORDER_BFS && o.root == MPK_ROOT_PERIPHERAL) return via_host();
+    std::unique_ptr<mpk_plan_s> plan;
+    try {
+        plan.reset(new mpk_plan_s());
+        plan->n = n;
+        plan->nnz = nnz;
+        plan->value_bits = o.value_bits;
+        plan->reorder = o.reorder;
+        plan->order = o.order;
+        plan->host_only = false;
+        plan->plan_cols = plan_cols;
+        mpk_tune_default(&plan->tune);
+        plan->device = dev;
+        plan->n_xcd = detect_xcds(dev);
+        plan->xcd_bound = plan->n_xcd > 1;
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            plan->wall_khz = khz;
+        mpk_status_t st;
+        if ((st = plan->d_rowptr.alloc(((size_t)n + 1) * 4))) return st;
+        if ((st = plan->d_col.alloc((size_t)nnz * 4))) return st;
+        if ((st = plan->d_val.alloc((size_t)nnz * (size_t)(o.value_bits / 8)))) return st;
+        if (o.reorder == MPK_REORDER_BFS && n > 0) {
+            GpuLevels g;
+            rc = gpu_levels_permute(n, nnz, A->rowptr, A->col, A->val, o.root, plan_cols,
+                                    o.value_bits, plan->d_rowptr.as<int32_t>(),
+                                    plan->d_col.as<int32_t>(), plan->d_val.ptr, g);
+            if (rc == kTooManyLevels) {
+                plan.reset();
+                return via_host();
             }
-        };
-        mix((uint64_t)A->n);
-        mix((uint64_t)A->nnz);
-        mix((uint64_t)o.reorder * 1000 + o.order * 100 + (uint64_t)o.root);
-        for (int64_t i = 0; i <= A->n; ++i) mix((uint64_t)(uint32_t)A->rowptr[i]);
-        const int64_t step = std::max<int64_t>(1, A->nnz / 65536);
-        for (int64_t e2 = 0; e2 < A->nnz; e2 += step) mix((uint64_t)(uint32_t)A->col[e2]);
-        plan->fingerprint = h;
+            if (rc) return hip_fail((hipError_t)rc, "device level construction");
+            plan->lv.level_ptr.swap(g.level_ptr);
+            plan->lv.perm.swap(g.perm);
+            plan->lv.iperm.swap(g.iperm);
+            plan->rowptr.swap(g.rowptr);
+            plan->row_lo.swap(g.row_lo);
+            plan->row_hi.swap(g.row_hi);
+        } else {
+            // the caller's order: order-derived levels from the device's far[]
+            std::vector<int32_t> far;
+            if (n > 0 && (rc = gpu_order_far(n, A->rowptr, A->col, far)))
+                return hip_fail((hipError_t)rc, "device level extents");
+            plan->lv = levels_from_far(n, far);
+            rc = gpu_copy_in_place_order(n, nnz, A->rowptr, A->col, A->val, o.value_bits,
+                                         plan->d_rowptr.as<int32_t>(), plan->d_col.as<int32_t>(),
+                                         plan->d_val.ptr, plan->rowptr, plan->row_lo,
+                                         plan->row_hi);
+            if (rc) return hip_fail((hipError_t)rc, "device copy of the matrix");
+        }
+        bool identity = true;
+        for (int64_t i = 0; i < n && identity; ++i) identity = plan->lv.perm[i] == i;
+        if (!identity) {
+            if ((st = plan->d_perm.upload(plan->lv.perm.data(), (size_t)n * 4))) return st;
+            if (o.order == MPK_ORDER_ORIGINAL)
+                if ((st = plan->d_outrow.upload(plan->lv.perm.data(), (size_t)n * 4))) return st;
+        }
+        // the same fingerprint as a plan of the same matrix from host arrays
+        const int64_t step = fingerprint_step(nnz);
+        std::vector<int32_t> sample, rp0;
+        if ((rc = gpu_sample_cols(A->col, step, nnz ? (nnz + step - 1) / step : 0, sample)))
+            return hip_fail((hipError_t)rc, "hipMemcpy (column sample)");
+        rp0.resize((size_t)n + 1);
+        e = hipMemcpy(rp0.data(), A->rowptr, rp0.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy (row pointer)");
+        plan->fingerprint = fingerprint(n, nnz, o, rp0.data(), sample);
+    } catch (const std::bad_alloc &) {
+        return fail(MPK_ENOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(MPK_EINVAL, ex.what());
     }
     plan->plan_ms = now_ms() - t0;
     *out = plan.release();

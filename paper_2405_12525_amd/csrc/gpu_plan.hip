@@ -140,6 +140,61 @@ __global__ void permute_kernel(const int32_t *rowptr, const int32_t *col, const 
     }
 }
 
+// flags[0] |= a row pointer that decreases, flags[1] |= a column out of range
+__global__ void validate_kernel(const int32_t *rowptr, const int32_t *col, int64_t n,
+                                int64_t nnz, int32_t *flags) {
+    int bad_rows = 0, bad_cols = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad_rows |= rowptr[i + 1] < rowptr[i];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        bad_cols |= col[e] < 0 || (int64_t)col[e] >= n;
+    if (bad_rows) atomicOr(&flags[0], 1);
+    if (bad_cols) atomicOr(&flags[1], 1);
+}
+
+// far[i] = the largest row joined to row i in the symmetrised pattern (or i)
+__global__ void far_kernel(const int32_t *rowptr, const int32_t *col, int64_t n, int32_t *far) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t hi = (int32_t)i;
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            hi = max(hi, col[e]);
+            atomicMax(&far[col[e]], (int32_t)i);
+        }
+        atomicMax(&far[i], hi);
+    }
+}
+
+// each row's smallest / largest column, the row itself included
+__global__ void extent_kernel(const int32_t *rowptr, const int32_t *col, int64_t n, int32_t *lo,
+                              int32_t *hi) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t a = (int32_t)i, b = (int32_t)i;
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            a = min(a, col[e]);
+            b = max(b, col[e]);
+        }
+        lo[i] = a;
+        hi[i] = b;
+    }
+}
+
+__global__ void to_float_kernel(const double *in, int64_t n, float *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = static_cast<float>(in[i]);
+}
+
+// out[k] = col[k * step] for k < count
+__global__ void gather_kernel(const int32_t *col, int64_t step, int64_t count, int32_t *out) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = col[k * step];
+}
+
 // Device scratch freed on every exit path.
 struct Scratch {
     std::vector<void *> ptrs;
@@ -300,6 +355,78 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
     MPK_TRY(hipMemcpy(res.row_lo.data(), lo, (size_t)n * 4, hipMemcpyDeviceToHost));
     MPK_TRY(hipMemcpy(res.row_hi.data(), hi, (size_t)n * 4, hipMemcpyDeviceToHost));
     if (res.rowptr[(size_t)n] != nnz) return (int)hipErrorUnknown;
+    return 0;
+}
+
+int gpu_validate(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                 int *bad_rows, int *bad_cols, int32_t *first_last) {
+    Scratch s;
+    int32_t *flags;
+    MPK_TRY(s.get(&flags, 2));
+    MPK_TRY(hipMemset(flags, 0, 8));
+    hipLaunchKernelGGL(validate_kernel, dim3(grid_for(std::max(n, nnz))), dim3(kThreads), 0, 0,
+                       rowptr, col, n, nnz, flags);
+    MPK_TRY(hipGetLastError());
+    int32_t f[2];
+    MPK_TRY(hipMemcpy(f, flags, 8, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(&first_last[0], rowptr, 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(&first_last[1], rowptr + n, 4, hipMemcpyDeviceToHost));
+    *bad_rows = f[0];
+    *bad_cols = f[1];
+    return 0;
+}
+
+int gpu_order_far(int64_t n, const int32_t *rowptr, const int32_t *col, std::vector<int32_t> &far) {
+    Scratch s;
+    int32_t *d;
+    MPK_TRY(s.get(&d, n));
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, d, n);
+    hipLaunchKernelGGL(far_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr, col, n, d);
+    MPK_TRY(hipGetLastError());
+    far.resize((size_t)n);
+    MPK_TRY(hipMemcpy(far.data(), d, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int gpu_copy_in_place_order(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                            const double *val, int value_bits, int32_t *out_rowptr,
+                            int32_t *out_col, void *out_val, std::vector<int32_t> &h_rowptr,
+                            std::vector<int32_t> &row_lo, std::vector<int32_t> &row_hi) {
+    Scratch s;
+    int32_t *lo, *hi;
+    MPK_TRY(s.get(&lo, n));
+    MPK_TRY(s.get(&hi, n));
+    MPK_TRY(hipMemcpy(out_rowptr, rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice));
+    if (nnz > 0) {
+        MPK_TRY(hipMemcpy(out_col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice));
+        if (value_bits == 32)
+            hipLaunchKernelGGL(to_float_kernel, dim3(grid_for(nnz)), dim3(kThreads), 0, 0, val,
+                               nnz, static_cast<float *>(out_val));
+        else
+            MPK_TRY(hipMemcpy(out_val, val, (size_t)nnz * 8, hipMemcpyDeviceToDevice));
+    }
+    hipLaunchKernelGGL(extent_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr, col, n, lo,
+                       hi);
+    MPK_TRY(hipGetLastError());
+    h_rowptr.resize((size_t)n + 1);
+    row_lo.resize((size_t)n);
+    row_hi.resize((size_t)n);
+    MPK_TRY(hipMemcpy(h_rowptr.data(), rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(row_lo.data(), lo, (size_t)n * 4, hipMemcpyDeviceToHost));
+    MPK_TRY(hipMemcpy(row_hi.data(), hi, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int gpu_sample_cols(const int32_t *col, int64_t step, int64_t count, std::vector<int32_t> &out) {
+    out.assign((size_t)count, 0);
+    if (count == 0) return 0;
+    Scratch s;
+    int32_t *d;
+    MPK_TRY(s.get(&d, count));
+    hipLaunchKernelGGL(gather_kernel, dim3(grid_for(count)), dim3(kThreads), 0, 0, col, step,
+                       count, d);
+    MPK_TRY(hipGetLastError());
+    MPK_TRY(hipMemcpy(out.data(), d, (size_t)count * 4, hipMemcpyDeviceToHost));
     return 0;
 }
 

@@ -58,6 +58,25 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
                        const double *val, int32_t root, bool plan_cols, int value_bits,
                        int32_t *out_rowptr, int32_t *out_col, void *out_val, GpuLevels &res);
 
+// Helpers for plans built from a device CSR (gpu_plan.hip; hipError_t
+// results).  gpu_validate: flags for a decreasing row pointer and for a
+// column out of range, and rowptr[0], rowptr[n].  gpu_order_far: far[i] of
+// the order-derived levels (the largest row joined to row i).
+// gpu_copy_in_place_order: the plan's copy of a CSR kept in the caller's
+// order (values converted for FP32) plus the host row pointer and row
+// extents.  gpu_sample_cols: col[k * step] for k < count.
+int gpu_validate(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                 int *bad_rows, int *bad_cols, int32_t *first_last);
+int gpu_order_far(int64_t n, const int32_t *rowptr, const int32_t *col, std::vector<int32_t> &far);
+int gpu_copy_in_place_order(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                            const double *val, int value_bits, int32_t *out_rowptr,
+                            int32_t *out_col, void *out_val, std::vector<int32_t> &h_rowptr,
+                            std::vector<int32_t> &row_lo, std::vector<int32_t> &row_hi);
+int gpu_sample_cols(const int32_t *col, int64_t step, int64_t count, std::vector<int32_t> &out);
+// Levels from far[] (order_levels' rule): level 0 = row 0, level j+1 ends
+// just past the farthest neighbour of level j.
+Levels levels_from_far(int64_t n, const std::vector<int32_t> &far);
+
 // Schedule of (chunk, power) tasks for p powers.
 struct Schedule {
     int p = 0;

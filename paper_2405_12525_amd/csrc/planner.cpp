@@ -230,6 +230,19 @@ Levels order_levels(int64_t n, const int32_t *rowptr, const int32_t *col) {
         }
         raise((int32_t)i, hi);
     }
+    Levels from = levels_from_far(n, far);
+    lv.level_ptr.swap(from.level_ptr);
+    return lv;
+}
+
+Levels levels_from_far(int64_t n, const std::vector<int32_t> &far) {
+    Levels lv;
+    lv.perm.resize(n);
+    lv.iperm.resize(n);
+    std::iota(lv.perm.begin(), lv.perm.end(), 0);
+    std::iota(lv.iperm.begin(), lv.iperm.end(), 0);
+    lv.level_ptr.push_back(0);
+    if (n == 0) return lv;
     // level 0 = row 0; level j+1 ends just past the farthest neighbour of level j
     int64_t b_prev = 0, b = 1;
     lv.level_ptr.push_back(1);

@@ -439,3 +439,71 @@ def test_device_levels_fp32_and_many_components():
     assert np.array_equal(Y, oracle.powers(D, np.ones((n, 1)), 2))
     P.close()
     Q.close()
+
+
+def _device_csr(A):
+    import types
+    return types.SimpleNamespace(
+        n=A.n, rowptr=torch.from_numpy(np.ascontiguousarray(A.rowptr, np.int32)).cuda(),
+        col=torch.from_numpy(np.ascontiguousarray(A.col, np.int32)).cuda(),
+        val=torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).cuda())
+
+
+@pytest.mark.parametrize("reorder,order,vb", [("bfs", "original", 64), ("none", "original", 64),
+                                              ("bfs", "plan", 32), ("none", "plan", 32)])
+@pytest.mark.parametrize("case", ["stencil", "random_nonsym", "disconnected"])
+def test_plan_from_device_csr_equals_host_plan(reorder, order, vb, case):
+    A = {"stencil": lambda: w.stencil_3d27(14),
+         "random_nonsym": lambda: w.random_sparse(2000, 0.002, 44),
+         "disconnected": lambda: w.random_sparse(1500, 0.0005, 45, symmetric_pattern=True)}[case]()
+    P = mpk.Plan(_device_csr(A), reorder=reorder, order=order, value_bits=vb)
+    Q = mpk.Plan(A, reorder=reorder, order=order, value_bits=vb)
+    lp, perm = P.levels()
+    lq, permq = Q.levels()
+    assert np.array_equal(lp, lq) and np.array_equal(perm, permq)
+    ip, iq = P.info(), Q.info()
+    assert {k: ip[k] for k in ("n", "nnz", "n_levels", "max_level_rows", "matrix_bytes")} == \
+        {k: iq[k] for k in ("n", "nnz", "n_levels", "max_level_rows", "matrix_bytes")}
+    x = w.uniform_vectors(A.n, 2, 9)
+    xs = x[perm] if order == "plan" else x
+    Y, B = run_both(P, xs, 4)
+    Yq, _ = run_both(Q, xs, 4)
+    assert np.array_equal(Y, Yq) and np.array_equal(B, Yq)
+    P.tune(schedule="xcd", chunk_nnz=800)   # exact dependency lists: columns read back
+    Yx, _ = run_both(P, xs, 4)
+    assert np.array_equal(Yx, Yq)
+    P.close()
+    Q.close()
+
+
+def test_plan_from_device_csr_checks_and_fallbacks():
+    A = w.stencil_2d5(12)
+    D = _device_csr(A)
+    bad = _device_csr(A)
+    bad.col[5] = A.n                      # a column out of range
+    with pytest.raises(mpk.MPKError):
+        mpk.Plan(bad)
+    bad = _device_csr(A)
+    bad.rowptr[3] = bad.rowptr[2] - 1     # a row pointer that decreases
+    with pytest.raises(mpk.MPKError):
+        mpk.Plan(bad)
+    # the pseudo-peripheral root and a 400-component graph go through the host
+    P = mpk.Plan(D, root="peripheral")
+    Q = mpk.Plan(A, root="peripheral")
+    assert np.array_equal(P.levels()[1], Q.levels()[1])
+    n = 400
+    Dg = w.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+               np.linspace(0.5, 1.5, n))
+    R = mpk.Plan(_device_csr(Dg))
+    assert len(R.levels()[0]) - 1 == n
+    Y, B = run_both(R, np.ones((n, 1)), 2)
+    assert np.array_equal(Y, oracle.powers(Dg, np.ones((n, 1)), 2))
+    # the autotuner's cache key is the same for both constructions
+    xd = dev(w.uniform_vectors(A.n, 1, 3))
+    t = Q.autotune(xd, 4, reps=1, force=True)
+    import time
+    t0 = time.perf_counter()
+    t2 = mpk.Plan(D, root="peripheral").autotune(xd, 4)
+    assert time.perf_counter() - t0 < 0.5 and t2["schedule"] == t["schedule"]
+    for X in (P, Q, R):
+        X.close()
