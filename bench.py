@@ -45,6 +45,8 @@ WORKLOAD_TEXT = {
                      "permutation), {vb} CSR, x U[-1,1) seed 1003, p=6, 1 RHS", 64),
     "anderson160_cheb16_r8": ("Anderson 160^3 periodic (W=16.5, /14.25), {vb} CSR, Chebyshev "
                               "recurrence p=16, 8 random-sign RHS seed 1004", 32),
+    "stencil3d27_64_p16_r16": ("3D 27-point stencil 64^3 (truncated), {vb} CSR, x U[-1,1) seed "
+                               "1006, p=16, 16 RHS", 64),
 }
 KERNEL_SRC = os.path.join(_ROOT, "paper_2405_12525_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(_ROOT, "profiles", "traffic_{workload}_fp{vb}.json")
