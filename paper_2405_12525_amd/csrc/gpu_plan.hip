@@ -67,20 +67,34 @@ __global__ void transpose_kernel(const int32_t *rowptr, const int32_t *col, int6
 }
 
 // One BFS level: every unvisited neighbour v of the frontier gets level L
-// (claimed by compare-and-swap, so once) and is appended to `next`.
+// (claimed by compare-and-swap, so once) and is appended to `next`.  One
+// wavefront per frontier vertex: its lanes check the out- and in-neighbours
+// together, and the wave appends all its claims with one atomic add.
 __global__ void expand_kernel(const int32_t *rowptr, const int32_t *col, const int32_t *tptr,
                               const int32_t *tcol, const int32_t *front, int32_t nf,
                               int32_t *lev, int32_t L, int32_t *next, int32_t *cnt) {
-    for (int32_t f = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); f < nf;
-         f += (int32_t)(gridDim.x * blockDim.x)) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < nf; f += nwaves) {
         const int32_t u = front[f];
-        for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
-            const int32_t v = col[e];
-            if (lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1) next[atomicAdd(cnt, 1)] = v;
-        }
-        for (int32_t e = tptr[u]; e < tptr[u + 1]; ++e) {
-            const int32_t v = tcol[e];
-            if (lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1) next[atomicAdd(cnt, 1)] = v;
+        const int32_t a0 = rowptr[u], na = rowptr[u + 1] - a0;
+        const int32_t b0 = tptr[u], total = na + (tptr[u + 1] - b0);
+        for (int32_t base = 0; base < total; base += 64) {  // uniform over the wave
+            const int32_t k = base + lane;
+            int32_t v = 0;
+            bool claim = false;
+            if (k < total) {
+                v = k < na ? col[a0 + k] : tcol[b0 + (k - na)];
+                claim = lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1;
+            }
+            const unsigned long long m = __ballot(claim);
+            if (m) {
+                const int first = __ffsll((long long)m) - 1;
+                int32_t pos = 0;
+                if (lane == first) pos = atomicAdd(cnt, (int32_t)__popcll(m));
+                pos = __shfl(pos, first);
+                if (claim) next[pos + (int32_t)__popcll(m & ((1ull << lane) - 1ull))] = v;
+            }
         }
     }
 }
@@ -117,26 +131,35 @@ __global__ void inverse_kernel(const int32_t *perm, const int32_t *rowptr, int64
 // Row r of the permuted matrix: old row perm[r] in stored order, columns in
 // plan numbering when plan_cols, values as double or float; row_lo / row_hi
 // are the smallest / largest plan-numbered column (the row itself included).
+// One wavefront per row: lanes copy consecutive entries (coalesced) and the
+// extent is reduced across the wave.
 template <typename V>
 __global__ void permute_kernel(const int32_t *rowptr, const int32_t *col, const double *val,
                                const int32_t *perm, const int32_t *iperm, const int32_t *nrp,
                                int64_t n, int plan_cols, int32_t *ncol, V *nval, int32_t *row_lo,
                                int32_t *row_hi) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nwaves) {
         const int32_t old = perm[r];
+        const int32_t e0 = rowptr[old], len = rowptr[old + 1] - e0, d0 = nrp[r];
         int32_t lo = (int32_t)r, hi = (int32_t)r;
-        int32_t d = nrp[r];
-        for (int32_t e = rowptr[old]; e < rowptr[old + 1]; ++e, ++d) {
-            const int32_t c = col[e];
+        for (int32_t k = lane; k < len; k += 64) {
+            const int32_t c = col[e0 + k];
             const int32_t cp = iperm[c];
-            ncol[d] = plan_cols ? cp : c;
-            nval[d] = static_cast<V>(val[e]);
+            ncol[d0 + k] = plan_cols ? cp : c;
+            nval[d0 + k] = static_cast<V>(val[e0 + k]);
             lo = min(lo, cp);
             hi = max(hi, cp);
         }
-        row_lo[r] = lo;
-        row_hi[r] = hi;
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        if (lane == 0) {
+            row_lo[r] = lo;
+            row_hi[r] = hi;
+        }
     }
 }
 
@@ -235,7 +258,7 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
     MPK_TRY(s.get(&lev, n));
     MPK_TRY(s.get(&front, n));
     MPK_TRY(s.get(&next, n));
-    MPK_TRY(s.get(&cnt, 2));
+    MPK_TRY(s.get(&cnt, (size_t)kMaxDeviceLevels + 2));  // one counter per level
     MPK_TRY(s.get(&perm_in, n));
     MPK_TRY(s.get(&perm, n));
     MPK_TRY(s.get(&keys, n));
@@ -265,6 +288,8 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
     // 2. levels, one launch per level; a restart at the lowest unvisited row
     //    when the frontier empties
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, lev, n, -1);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(kMaxDeviceLevels + 2)), dim3(kThreads), 0, 0,
+                       cnt, (int64_t)kMaxDeviceLevels + 2, 0);
     int64_t visited = 0;
     int32_t L = 0;
     int32_t nf = 0;
@@ -290,12 +315,10 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
         }
         visited += nf;
         ++L;
-        const int32_t zero = 0;
-        MPK_TRY(hipMemcpy(cnt, &zero, 4, hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(expand_kernel, dim3(grid_for(nf)), dim3(kThreads), 0, 0, rowptr, col,
-                           tptr, tcol, front, nf, lev, L, next, cnt);
+        hipLaunchKernelGGL(expand_kernel, dim3(grid_for((int64_t)nf * 64)), dim3(kThreads), 0, 0,
+                           rowptr, col, tptr, tcol, front, nf, lev, L, next, cnt + L);
         MPK_TRY(hipGetLastError());
-        MPK_TRY(hipMemcpy(&nf, cnt, 4, hipMemcpyDeviceToHost));
+        MPK_TRY(hipMemcpy(&nf, cnt + L, 4, hipMemcpyDeviceToHost));
         if (nf < 0 || visited + nf > n) return (int)hipErrorUnknown;
         std::swap(front, next);
     }
@@ -330,11 +353,11 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
         MPK_TRY(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, len, out_rowptr, (int)(n + 1)));
     }
     if (value_bits == 32)
-        hipLaunchKernelGGL(permute_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr,
+        hipLaunchKernelGGL(permute_kernel<float>, dim3(grid_for(n * 64)), dim3(kThreads), 0, 0, rowptr,
                            col, val, perm, iperm, out_rowptr, n, plan_cols ? 1 : 0, out_col,
                            static_cast<float *>(out_val), lo, hi);
     else
-        hipLaunchKernelGGL(permute_kernel<double>, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+        hipLaunchKernelGGL(permute_kernel<double>, dim3(grid_for(n * 64)), dim3(kThreads), 0, 0,
                            rowptr, col, val, perm, iperm, out_rowptr, n, plan_cols ? 1 : 0,
                            out_col, static_cast<double *>(out_val), lo, hi);
     MPK_TRY(hipGetLastError());
