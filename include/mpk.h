@@ -170,7 +170,11 @@ void mpk_tune_default(mpk_tune_t *tune);
  * preserved), and upload the matrix.  (Sec. "RACE Applied to the Matrix Power
  * Kernel": level equation, BFS reordering, and the endnote on non-symmetric
  * patterns.)  Disconnected graphs restart a new level at the lowest unvisited
- * row.  Errors: MPK_EINVAL (NULL, bad opts), MPK_EBADCSR, MPK_EUNSUPPORTED
+ * row.  A device plan in BFS order uploads the CSR as given and builds the
+ * levels and the permutation on the GPU (the same result; graphs with more
+ * than 16384 levels or 64 components, and MPK_ROOT_PERIPHERAL, are handled
+ * on the host); host-only plans always use the host planner.
+ * Errors: MPK_EINVAL (NULL, bad opts), MPK_EBADCSR, MPK_EUNSUPPORTED
  * (nnz >= 2^31 or n >= 2^31), MPK_ENOMEM, MPK_EHIP.
  */
 mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out);
