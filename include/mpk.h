@@ -306,6 +306,23 @@ mpk_status_t mpk_run_baseline_poly(mpk_plan_t plan, const double *x, int p, int 
                                    void *hip_stream);
 
 /*
+ * Build and upload, ahead of time, what runs with p powers and nrhs
+ * right-hand sides fetch from the plan's caches on first use: the
+ * schedule of every segment (Sec. "RACE Applied to the Matrix Power
+ * Kernel": the (level group, power) tasks of the Lp diagram), its row
+ * slices for nrhs, an idle dependency workspace, and the p x SpMV slices
+ * for nrhs.  No kernel runs.  Later calls of mpk_run, mpk_run_recur,
+ * mpk_run_poly and the baseline forms with the same p and nrhs then do no
+ * host planning and allocate nothing on the plan's side, so that their
+ * first call does not pay for it.  Slice tables depend only on whether nrhs
+ * is 1, 2, 3 or at least 4, so preparing every nrhs costs four tables per
+ * schedule.  Valid until mpk_plan_tune changes the tuning.
+ * Errors: MPK_EINVAL (p < 1, NULL plan), MPK_EUNSUPPORTED (nrhs outside
+ * [1, 16]), MPK_ENODEVICE (host-only plan), MPK_ENOMEM.
+ */
+mpk_status_t mpk_plan_prepare(mpk_plan_t plan, int p, int nrhs);
+
+/*
  * Coefficients of one Chebyshev time step (Sec. "Application: Chebyshev
  * Time Propagation"): exp(-i dt H) psi is approximated by
  * J_0(dt) v_0 + 2 sum_{k=1..M} (-i)^k J_k(dt) v_k with v_0 = psi,

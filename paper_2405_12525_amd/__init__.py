@@ -350,6 +350,16 @@ class Plan:
                 raise TypeError("Y must be a contiguous float64 device tensor")
         return R, Y
 
+    def prepare(self, ps, rhs=range(1, 17)):
+        """Build and upload ahead of time the schedules, slice tables and
+        workspace that runs with each p in ps and each R in rhs fetch on
+        first use, so that those runs do no host planning."""
+        ps = [int(ps)] if isinstance(ps, (int, np.integer)) else [int(p) for p in ps]
+        rhs = [int(rhs)] if isinstance(rhs, (int, np.integer)) else [int(r) for r in rhs]
+        for p in ps:
+            for R in rhs:
+                check(self._lib.mpk_plan_prepare(self._h, p, R))
+
     def run(self, x, p: int, Y=None, stream=None):
         """Level-blocked MPK: returns Y with Y[k-1] = A^k x."""
         R, Y = self._prep(x, p, Y)

@@ -25,7 +25,7 @@ EXPORTS = [
     "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load",
     "mpk_plan_autotune", "mpk_graph_capture", "mpk_graph_launch", "mpk_graph_destroy",
     "mpk_run_poly", "mpk_run_baseline_poly", "mpk_cheb_time_coefficients", "mpk_combine_complex",
-    "mpk_graph_capture_time_step", "mpk_plan_device",
+    "mpk_graph_capture_time_step", "mpk_plan_device", "mpk_plan_prepare",
 ]
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -102,6 +102,8 @@ def load():
     lib.mpk_plan_schedule.restype = st
     lib.mpk_plan_schedule_xcd.argtypes = [P, ctypes.c_int, P, P, P, P, P]
     lib.mpk_plan_schedule_xcd.restype = st
+    lib.mpk_plan_prepare.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    lib.mpk_plan_prepare.restype = st
     lib.mpk_run.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P]
     lib.mpk_run.restype = st
     lib.mpk_run_recur.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]

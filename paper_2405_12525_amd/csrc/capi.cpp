@@ -116,7 +116,7 @@ mpk_status_t make_slices(const std::vector<int32_t> &rowptr, const std::vector<i
 
 struct SchedEntry {
     Schedule host;
-    std::map<int, std::unique_ptr<SliceSet>> slices;  // by right-hand-side count
+    std::map<int, std::unique_ptr<SliceSet>> slices;  // by slice size (slice_nnz of the RHS count)
     DevBuf dep_lo, dep_hi, tasks;
     DevBuf dep_ptr, dep_idx, qptr;  // XCD schedule
     int workgroups = 0;
@@ -160,7 +160,7 @@ struct mpk_plan_s {
     bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
     // device data
     DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
-    std::map<int, std::unique_ptr<SliceSet>> spmv_slices;  // p x SpMV, by RHS count
+    std::map<int, std::unique_ptr<SliceSet>> spmv_slices;  // p x SpMV, by slice size
     // schedules and workspaces
     std::mutex mu;
     mpk_tune_t tune{};
@@ -371,13 +371,13 @@ mpk_status_t note_stream(mpk_plan_t plan, hipStream_t stream) {
 
 // Slices of a schedule's chunks for R right-hand sides (plan->mu held).
 mpk_status_t task_slices(mpk_plan_t plan, SchedEntry *se, int R, SliceSet **out) {
-    auto it = se->slices.find(R);
+    const int key = slice_nnz(kTaskKP, R);  // the same table for every R >= 4
+    auto it = se->slices.find(key);
     if (it == se->slices.end()) {
         auto ss = std::make_unique<SliceSet>();
-        mpk_status_t st = make_slices(plan->rowptr, se->host.chunk_ptr, slice_nnz(kTaskKP, R), true,
-                                      *ss);
+        mpk_status_t st = make_slices(plan->rowptr, se->host.chunk_ptr, key, true, *ss);
         if (st) return st;
-        it = se->slices.emplace(R, std::move(ss)).first;
+        it = se->slices.emplace(key, std::move(ss)).first;
     }
     *out = it->second.get();
     return MPK_OK;
@@ -491,7 +491,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         }
         const AccCoefs *acp = poly ? &ac : nullptr;
         SliceSet *ss = nullptr;
-        if (capturing && !se->slices.count(nrhs))
+        if (capturing && !se->slices.count(slice_nnz(kTaskKP, nrhs)))
             return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
         if ((st = task_slices(plan, se, nrhs, &ss))) return st;
         if (!se->host.step_ptr.empty()) {
@@ -539,13 +539,14 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
 // Slice table of the p x SpMV kernel for R right-hand sides, built once
 // (plan->mu held).
 mpk_status_t spmv_slices(mpk_plan_t plan, int R, SliceSet **out) {
-    auto it = plan->spmv_slices.find(R);
+    const int key = slice_nnz(kSpmvKP, R);
+    auto it = plan->spmv_slices.find(key);
     if (it == plan->spmv_slices.end()) {
         auto ss = std::make_unique<SliceSet>();
         const std::vector<int32_t> whole{0, (int32_t)plan->n};
-        mpk_status_t st = make_slices(plan->rowptr, whole, slice_nnz(kSpmvKP, R), false, *ss);
+        mpk_status_t st = make_slices(plan->rowptr, whole, key, false, *ss);
         if (st) return st;
-        it = plan->spmv_slices.emplace(R, std::move(ss)).first;
+        it = plan->spmv_slices.emplace(key, std::move(ss)).first;
     }
     *out = it->second.get();
     return MPK_OK;
@@ -568,7 +569,7 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     SliceSet *sl = nullptr;
     {
         std::lock_guard<std::mutex> g(plan->mu);
-        if (cap == hipStreamCaptureStatusActive && !plan->spmv_slices.count(nrhs))
+        if (cap == hipStreamCaptureStatusActive && !plan->spmv_slices.count(slice_nnz(kSpmvKP, nrhs)))
             return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
         if ((st = spmv_slices(plan, nrhs, &sl))) return st;
     }
@@ -1157,6 +1158,33 @@ mpk_status_t mpk_run_baseline_poly(mpk_plan_t plan, const double *x, int p, int 
                                    const double *wa, const double *wb, double *acc, double *work,
                                    void *stream) {
     return run_poly(plan, x, p, nrhs, alpha, beta, gamma, wa, wb, acc, work, stream, true);
+}
+
+mpk_status_t mpk_plan_prepare(mpk_plan_t plan, int p, int nrhs) {
+    if (!plan) return fail(MPK_EINVAL, "plan is NULL");
+    if (p < 1) return fail(MPK_EINVAL, "p must be >= 1");
+    if (nrhs < 1 || nrhs > MPK_MAX_RHS) return fail(MPK_EUNSUPPORTED, "nrhs must be in [1, 16]");
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    if (plan->n == 0) return MPK_OK;
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::lock_guard<std::mutex> g(plan->mu);
+    // the same schedules, slice tables and workspace a run would fetch first
+    const int wg_default = default_workgroups(plan, nrhs);
+    const int seg = plan->tune.seg_powers > 0 ? plan->tune.seg_powers : kMaxSegPowers;
+    for (int base = 0; base < p; base += seg) {
+        SchedEntry *se = nullptr;
+        if ((st = get_schedule(plan, std::min(seg, p - base), &se, wg_default))) return st;
+        SliceSet *ss = nullptr;
+        if ((st = task_slices(plan, se, nrhs, &ss))) return st;
+        if (se->host.step_ptr.empty()) {
+            Workspace *ws = nullptr;
+            if ((st = get_workspace(plan, se->host.n_chunks(), nullptr, false, &ws))) return st;
+        }
+    }
+    SliceSet *sl = nullptr;
+    return spmv_slices(plan, nrhs, &sl);
 }
 
 mpk_status_t mpk_cheb_time_coefficients(int M, double dt, double *alpha, double *beta,

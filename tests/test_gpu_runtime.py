@@ -31,6 +31,37 @@ def host(t):
     return t.cpu().numpy()
 
 
+@pytest.mark.parametrize("sched", ["wave", "steps", "xcd"])
+def test_prepare_then_run_is_exact(sched):
+    """Runs after mpk_plan_prepare (schedules and slice tables built ahead,
+    the slice tables shared by every R >= 4) equal the oracle bit for bit,
+    as do runs on a plan that builds them lazily."""
+    A = w.stencil_3d27(14)
+    P = mpk.Plan(A)
+    Q = mpk.Plan(A)
+    for plan in (P, Q):
+        plan.tune(schedule=sched, chunk_nnz=3000)
+    P.prepare(range(1, 7))        # every R in 1..16
+    g = np.random.default_rng(9)
+    for p, R in [(1, 1), (5, 3), (6, 16), (4, 7), (6, 4)]:
+        x = dev(g.uniform(-1, 1, (A.n, R)))
+        ref = oracle.powers(A, host(x), p)
+        assert np.array_equal(host(P.run(x, p)), ref), (p, R)
+        assert np.array_equal(host(Q.run(x, p)), ref), (p, R)
+        assert np.array_equal(host(P.run_baseline(x, p)), ref), (p, R)
+    # p above the segment length: every segment's schedule is prepared
+    P.tune(schedule=sched, chunk_nnz=3000, seg_powers=3)
+    P.prepare(7, 2)
+    x = dev(g.uniform(-1, 1, (A.n, 2)))
+    assert np.array_equal(host(P.run(x, 7)), oracle.powers(A, host(x), 7))
+    with pytest.raises(mpk.MPKError):
+        P.prepare(0, 1)
+    with pytest.raises(mpk.MPKError):
+        P.prepare(3, 17)
+    P.close()
+    Q.close()
+
+
 def test_autotune_choice_is_exact_and_cached():
     A = w.stencil_3d27(32)
     x = w.uniform_vectors(A.n, 2, 11)

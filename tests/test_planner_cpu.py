@@ -350,6 +350,10 @@ def test_run_argument_errors_without_device():
     assert L.mpk_run_baseline(P._h, None, -1, 1, None, None) == _capi.MPK_EINVAL
     assert L.mpk_run(None, None, 3, 1, None, None) == _capi.MPK_EINVAL
     assert L.mpk_plan_sync(P._h) == _capi.MPK_ENODEVICE
+    assert L.mpk_plan_prepare(P._h, 0, 1) == _capi.MPK_EINVAL
+    assert L.mpk_plan_prepare(P._h, 3, 17) == _capi.MPK_EUNSUPPORTED
+    assert L.mpk_plan_prepare(P._h, 3, 1) == _capi.MPK_ENODEVICE
+    assert L.mpk_plan_prepare(None, 3, 1) == _capi.MPK_EINVAL
 
 
 def test_tune_validation():
