@@ -25,7 +25,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import time
-from typing import Dict, List, Optional, Sequence
+from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -112,33 +112,73 @@ class Server:
             mem_budget = int(free * 0.6)
         self.mem_budget = int(mem_budget)
         self.streams = [torch.cuda.Stream() for _ in range(max(1, int(n_streams)))]
+        # per-stream buffers reused by serve(keep=False): stacked inputs, outputs
+        self._stage = [None] * len(self.streams)
+        self._out = [None] * len(self.streams)
 
-    # one batch on one stream
-    def _launch(self, batch: List[Request], stream):
+    def _scratch(self, store: list, si: int, numel: int, device):
+        """Stream si's reusable buffer of at least numel doubles.  Only the
+        batch on that stream uses it, and a stream is handed out again only
+        once its batch has finished, so no copy is in flight when it is
+        reused or grown."""
         torch = _torch()
+        b = store[si]
+        if b is None or b.numel() < numel:
+            store[si] = None
+            with torch.cuda.stream(self.streams[si]):
+                b = torch.empty(numel, dtype=torch.float64, device=device)
+            store[si] = b
+        return b[:numel]
+
+    # one batch on stream si; keep=False takes the stacked inputs and the
+    # outputs from the stream's reused buffers instead of new allocations
+    def _launch(self, batch: List[Request], si: int, keep: bool):
+        torch = _torch()
+        stream = self.streams[si]
         P = self.plans[batch[0].matrix]
         p = max(r.p for r in batch)
+        kind = batch[0].kind
         with torch.cuda.stream(stream):
             xs = [r.x.reshape(P.n, -1) for r in batch]
-            X = xs[0] if len(xs) == 1 else torch.cat(xs, dim=1).contiguous()
-            if batch[0].kind == "chebyshev":
-                Y = P.run_recur(X, *chebyshev_coefficients(p), stream=stream)
-            elif batch[0].kind == "time_step":
-                Y = P.cheb_time_step(X, batch[0].dt, p, stream=stream)
+            R = sum(int(x.shape[1]) for x in xs)
+            dev = xs[0].device
+            if len(xs) == 1:
+                X = xs[0]
+            elif keep:
+                X = torch.cat(xs, dim=1).contiguous()
             else:
-                Y = P.run(X, p, stream=stream)
+                X = torch.cat(xs, dim=1,
+                              out=self._scratch(self._stage, si, P.n * R, dev).view(P.n, R))
+            Yo = None
+            if not keep:
+                nvec = 1 if kind == "time_step" else p
+                Yo = self._scratch(self._out, si, nvec * P.n * R, dev)
+                Yo = Yo.view(P.n, R) if kind == "time_step" else Yo.view(p, P.n, R)
+            if kind == "chebyshev":
+                Y = P.run_recur(X, *chebyshev_coefficients(p), Y=Yo, stream=stream)
+            elif kind == "time_step":
+                Y = P.cheb_time_step(X, batch[0].dt, p, out=Yo, stream=stream)
+            else:
+                Y = P.run(X, p, Y=Yo, stream=stream)
             ev = torch.cuda.Event()
             ev.record(stream)
         return Y, ev, p
 
     def serve(self, requests: Sequence[Request], realtime: bool = True,
-              keep: bool = True) -> List[Result]:
+              keep: bool = True,
+              on_result: Optional[Callable[[Request, object], None]] = None) -> List[Result]:
         """Serve the requests (sorted by arrival); returns results by id.
 
         realtime=True replays the arrival times against the wall clock;
         realtime=False makes every request available at once (saturation).
         keep=False drops each output once its batch has finished (Result.Y is
-        None): for measuring streams whose outputs would not fit at once."""
+        None): for measuring streams whose outputs would not fit at once.
+        The batches then write into one output buffer per stream, reused and
+        kept for the server's lifetime, so that the device allocator does not
+        fill with freed outputs of every size.
+        on_result(request, Y) is called when a request's batch has finished,
+        with the request's own output view; with keep=False the view is only
+        valid during the call."""
         torch = _torch()
         for r in requests:
             if not 0 <= r.matrix < len(self.plans):
@@ -174,15 +214,16 @@ class Server:
                     done = time.perf_counter() - t0
                     c0 = 0
                     for r in batch:
-                        if not keep:
-                            view = None
-                        elif r.kind == "time_step":
+                        if r.kind == "time_step":
                             view = Y[:, c0:c0 + r.R]
                         else:
                             view = Y[:r.p, :, c0:c0 + r.R]
                         c0 += r.R
+                        if on_result is not None:
+                            on_result(r, view)
                         arr = r.arrival if realtime else 0.0
-                        results[r.id] = Result(r.id, view, arr, start, done, len(batch))
+                        results[r.id] = Result(r.id, view if keep else None, arr, start, done,
+                                               len(batch))
                     in_use -= nbytes
                     free_streams.append(si)
                 else:
@@ -204,7 +245,7 @@ class Server:
                     break
                 si = free_streams.pop()
                 start = time.perf_counter() - t0
-                Y, ev, p = self._launch(batch, self.streams[si])
+                Y, ev, p = self._launch(batch, si, keep)
                 in_use += nbytes
                 running.append((si, ev, batch, Y, p, nbytes, start))
             # idle until the next arrival or a completion can be observed

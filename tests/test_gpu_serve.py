@@ -87,3 +87,53 @@ def test_time_step_requests_equal_alone():
     assert st["requests"] == 24 and st["gflops"] > 0
     for P in plans:
         P.close()
+
+
+def test_unkept_outputs_equal_alone():
+    """keep=False reuses one output and one staging buffer per stream; every
+    output, seen through on_result before its buffer is reused, equals the
+    request run alone, bit for bit, in a saturated and a paced pass."""
+    torch.cuda.set_device(0)
+    mats = [w.stencil_2d5(40), w.stencil_3d27(14), w.anderson_3d(10)]
+    plans = [mpk.Plan(A) for A in mats]
+    plans[2].tune(schedule="steps")
+    specs = w.serving_requests(80, rate_per_s=4000.0, seed=91, pool_size=3, p_range=(1, 12),
+                               rhs_choices=(1, 2, 3, 4, 8, 16))
+    reqs = []
+    for i, s in enumerate(specs):
+        if i % 7 == 3 and s["R"] % 2 == 0:
+            kind, p, dt = "time_step", 12, 0.5
+        else:
+            kind, p, dt = ("chebyshev" if i % 5 == 0 else "powers"), s["p"], 0.0
+        reqs.append(serve.Request(id=s["id"], arrival=s["t"], matrix=s["matrix"], p=p,
+                                  x=device_x(mats[s["matrix"]].n, s["R"], s["x_seed"]),
+                                  kind=kind, dt=dt))
+    assert {q.kind for q in reqs} == {"powers", "chebyshev", "time_step"}
+    alone = {}
+    for q in reqs:
+        P = plans[q.matrix]
+        if q.kind == "chebyshev":
+            Y = P.run_recur(q.x, *mpk.chebyshev_coefficients(q.p))
+        elif q.kind == "time_step":
+            Y = P.cheb_time_step(q.x, q.dt, q.p)
+        else:
+            Y = P.run(q.x, q.p)
+        alone[q.id] = Y.cpu().numpy()
+    srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20)
+    got = {}
+
+    def grab(q, Y):   # copy now: the buffer behind Y is reused by a later batch
+        got[q.id] = Y.cpu().numpy()
+
+    for realtime in (False, True):
+        got.clear()
+        res = srv.serve(reqs, realtime=realtime, keep=False, on_result=grab)
+        assert all(r.Y is None for r in res)
+        if not realtime:
+            assert max(r.batch_size for r in res) > 1
+        assert sorted(got) == sorted(q.id for q in reqs)
+        for q in reqs:
+            assert got[q.id].shape == alone[q.id].shape, q.id
+            assert np.array_equal(got[q.id], alone[q.id]), (realtime, q.id, q.kind)
+    for P in plans:
+        P.close()
