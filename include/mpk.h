@@ -314,7 +314,10 @@ mpk_status_t mpk_run_baseline_poly(mpk_plan_t plan, const double *x, int p, int 
  * for nrhs.  No kernel runs.  Later calls of mpk_run, mpk_run_recur,
  * mpk_run_poly and the baseline forms with the same p and nrhs then do no
  * host planning and allocate nothing on the plan's side, so that their
- * first call does not pay for it.  Slice tables depend only on whether nrhs
+ * first call does not pay for it, and so that the caller may capture them
+ * into its own HIP graph (stream capture) without a run beforehand; a
+ * captured level-blocked run keeps its workspace until the plan is destroyed.
+ * Slice tables depend only on whether nrhs
  * is 1, 2, 3 or at least 4, so preparing every nrhs costs four tables per
  * schedule.  Valid until mpk_plan_tune changes the tuning.
  * Errors: MPK_EINVAL (p < 1, NULL plan), MPK_EUNSUPPORTED (nrhs outside

@@ -314,7 +314,7 @@ mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream
     }
     if (capturing) {
         // allocation is not allowed while a stream is being captured
-        return fail(MPK_EINVAL, "no idle workspace: run once outside capture first");
+        return fail(MPK_EINVAL, "no idle workspace: call mpk_plan_prepare or run once outside capture first");
     }
     auto w = std::make_unique<Workspace>();
     w->cap = std::max<int32_t>(n_chunks, 1024);
@@ -453,6 +453,9 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     const int seg = plan->tune.seg_powers > 0 ? plan->tune.seg_powers : kMaxSegPowers;
     for (int base = 0; base < p; base += seg) {
         const int ps = std::min(seg, p - base);
+        if (capturing && !plan->scheds.count(ps))  // building one would copy synchronously
+            return fail(MPK_EINVAL,
+                        "no schedule for this p: call mpk_plan_prepare or run once outside capture first");
         SchedEntry *se = nullptr;
         if ((st = get_schedule(plan, ps, &se, wg_default))) return st;
         SegArgs a{};
@@ -492,7 +495,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         const AccCoefs *acp = poly ? &ac : nullptr;
         SliceSet *ss = nullptr;
         if (capturing && !se->slices.count(slice_nnz(kTaskKP, nrhs)))
-            return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
+            return fail(MPK_EINVAL, "no slice table for this RHS count: call mpk_plan_prepare or run once outside capture first");
         if ((st = task_slices(plan, se, nrhs, &ss))) return st;
         if (!se->host.step_ptr.empty()) {
             // one launch per diagonal; stream order separates the diagonals
@@ -570,7 +573,7 @@ mpk_status_t run_baseline(mpk_plan_t plan, const double *x, int p, int nrhs, con
     {
         std::lock_guard<std::mutex> g(plan->mu);
         if (cap == hipStreamCaptureStatusActive && !plan->spmv_slices.count(slice_nnz(kSpmvKP, nrhs)))
-            return fail(MPK_EINVAL, "no slice table for this RHS count: run once outside capture first");
+            return fail(MPK_EINVAL, "no slice table for this RHS count: call mpk_plan_prepare or run once outside capture first");
         if ((st = spmv_slices(plan, nrhs, &sl))) return st;
     }
     const size_t stride = (size_t)plan->n * nrhs;

@@ -62,6 +62,40 @@ def test_prepare_then_run_is_exact(sched):
     Q.close()
 
 
+@pytest.mark.parametrize("sched", ["wave", "steps"])
+def test_prepare_allows_stream_capture_without_a_run(sched):
+    """After mpk_plan_prepare alone, mpk_run can be captured into the
+    caller's own graph; every replay equals the oracle.  Without it the
+    capture is refused with a clear error instead of planning inside it."""
+    A = w.stencil_3d27(12)
+    P = mpk.Plan(A)
+    P.tune(schedule=sched, chunk_nnz=3000)
+    x = dev(np.random.default_rng(4).uniform(-1, 1, (A.n, 2)))
+    Y = torch.empty((5, A.n, 2), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    P.prepare(3, 2)      # another p: the refused capture below launches nothing
+    torch.cuda.synchronize()
+    with pytest.raises(mpk.MPKError, match="mpk_plan_prepare"):
+        g0 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g0, stream=s):
+            P.run(x, 5, Y=Y, stream=s)
+    torch.cuda.synchronize()
+    P.prepare(5, 2)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        P.run(x, 5, Y=Y, stream=s)
+    torch.cuda.synchronize()
+    ref = oracle.powers(A, host(x), 5)
+    for _ in range(3):
+        Y.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(Y), ref)
+    del g
+    P.close()
+
+
 def test_autotune_choice_is_exact_and_cached():
     A = w.stencil_3d27(32)
     x = w.uniform_vectors(A.n, 2, 11)
