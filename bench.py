@@ -335,9 +335,16 @@ def time_step(torch, mpk, w, steps, warmup, stream):
 
 
 def cpu_baseline(A, x, p, budget_s=20.0):
-    """The CPU oracle on all host cores: whole runs of the workload, bounded in time."""
+    """The CPU oracle on all host cores: whole runs of the workload, bounded in
+    time; also one core, for reference (3 runs)."""
     import oracle
     nthreads = oracle.threads()
+    t1 = []
+    for _ in range(3):   # first: the thread count set here holds until the next call sets it
+        t0 = time.perf_counter()
+        oracle.powers(A, x, p, nthreads=1)
+        t1.append(time.perf_counter() - t0)
+    gflops1 = 2.0 * A.nnz * x.shape[1] * p / statistics.median(t1) / 1e9
     times = []
     t_start = time.perf_counter()
     while True:
@@ -359,7 +366,8 @@ def cpu_baseline(A, x, p, budget_s=20.0):
         pass
     return {"value": round(gflops, 3), "unit": "Gflop/s", "cores": nthreads, "kind": "oracle",
             "sample": f"the full workload (all {p} powers), median of {len(times)} runs "
-                      f"({med * 1e3:.0f} ms each), OpenMP over rows on {nthreads} threads of {cpu}"}
+                      f"({med * 1e3:.0f} ms each), OpenMP over rows on {nthreads} threads of {cpu}",
+            "single_thread_value": round(gflops1, 3)}
 
 
 def main():
