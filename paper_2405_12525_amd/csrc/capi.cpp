@@ -1324,7 +1324,10 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     };
     for (int64_t c : {32, 64, 128})
         for (int chunk : {4096, 8192}) add(MPK_SCHED_STEPS, c, chunk, 0);
-    for (int chunk : {8192, 16384, 32768}) add(MPK_SCHED_WAVE, 64, chunk, 0);
+    // (chunks are capped so that each running workgroup gets two per power:
+    // 65536 means "as large as that allows", e.g. ~54K nonzeros for 2^21 rows
+    // of a 27-point stencil)
+    for (int chunk : {8192, 16384, 32768, 65536}) add(MPK_SCHED_WAVE, 64, chunk, 0);
     add(MPK_SCHED_XCD, 64, 16384, 0);
     add(MPK_SCHED_POWERS, 64, 8192, 0);
     int cus = 0;
