@@ -370,6 +370,43 @@ def cpu_baseline(A, x, p, budget_s=20.0):
             "single_thread_value": round(gflops1, 3)}
 
 
+def bandwidth_sweep(torch, mpk, stream, reps=5):
+    """Load-only bandwidth against the working-set size (1 MiB .. 4 GiB), the
+    MI355X counterpart of the paper's load-bandwidth curves: 'global' lets
+    every workgroup stride over the whole buffer (each XCD's L2 sees all of
+    it); 'xcd_local' gives each XCD its own eighth (its L2 sees 1/8).  Each
+    point reads at least ~4 GB in one launch; median of `reps` launches timed
+    with events on the launch stream."""
+    wg = 4096
+    buf = torch.ones(1 << 29, dtype=torch.float64, device="cuda")   # 4 GiB
+    sink = torch.empty(wg, dtype=torch.float64, device="cuda")
+    xcc = torch.empty(wg, dtype=torch.int32, device="cuda")
+    rows = []
+    for lg in range(20, 33):
+        nbytes = 1 << lg
+        view = buf[: nbytes // 8]
+        passes = max(1, (4 << 30) // nbytes)
+        for mode in ("global", "xcd_local"):
+            if mode == "global":
+                fn = lambda: mpk.probe_load(view, passes=passes, workgroups=wg, sink=sink,
+                                            stream=stream)
+            else:
+                fn = lambda: mpk.probe_load_xcd(view, regions=8, passes=passes, workgroups=wg,
+                                                sink=sink, xcc=xcc, stream=stream)
+            t = time_calls(fn, reps, 1, torch, stream)
+            gbs = nbytes * passes / (t["median_ms"] * 1e-3) / 1e9
+            rows.append({"bytes": nbytes, "mode": mode, "passes": passes,
+                         "ms": round(t["median_ms"], 4), "GBs": round(gbs, 1)})
+            log(f"[bench] probe {mode:9s} {nbytes / 2**20:8.0f} MiB x{passes}: {gbs:8.0f} GB/s")
+    ids = xcc.cpu().numpy()
+    import numpy as np
+    placement = bool(np.array_equal(ids, np.arange(wg) % 8))
+    del buf
+    return {"workgroups": wg, "threads_per_workgroup": 256, "load_bytes": 16,
+            "round_robin_placement": placement, "xcc_ids_seen": sorted(set(int(v) for v in ids)),
+            "points": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +429,8 @@ def main():
                     help="matrix value precision (default: the workload's)")
     ap.add_argument("--time-step-only", action="store_true",
                     help="print only the Chebyshev time-step measurement (for profiling)")
+    ap.add_argument("--bandwidth-sweep", action="store_true",
+                    help="only run the load-bandwidth probe over 1 MiB .. 4 GiB working sets")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
@@ -413,6 +452,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each": a.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.bandwidth_sweep:
+        print(json.dumps(bandwidth_sweep(torch, mpk, stream)), flush=True)
         return
     if args.time_step_only:
         print(json.dumps(time_step(torch, mpk, w, args.steps, args.warmup, stream)), flush=True)

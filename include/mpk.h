@@ -132,6 +132,11 @@ typedef struct {
     int skip_ahead;          /* WAVE, DIAG, POWERS: tasks a workgroup may park
                                 while their inputs are not ready, taking newer
                                 tickets meanwhile (0..8; 0 = wait in order)     */
+    int acquire_always;      /* persistent schedules: 1 = every task invalidates
+                                its XCD's caches before reading its inputs;
+                                0 (default) = only where a cache line of an
+                                output could have been read before it was
+                                complete (see mpk_run)                          */
 } mpk_tune_t;
 
 typedef struct {
@@ -365,12 +370,29 @@ mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double 
                          int nrhs, void *hip_stream);
 
 /* Wait for every run issued on this plan (all streams it was given) and
- * report device-side failures (MPK_ETIMEOUT when a dependency wait hit its
- * limit; the results of that run are invalid).  The failure is sticky: runs
- * issued after it on the same dependency workspace are abandoned as well
- * (their results are invalid too) until this call has reported and cleared
- * it. */
+ * report device-side failures: MPK_ETIMEOUT when a dependency wait of any
+ * run since the previous call hit its limit (the results of that run are
+ * invalid), and clear the report.  A failure affects only its own run: every
+ * run starts with its abort flag cleared. */
 mpk_status_t mpk_plan_sync(mpk_plan_t plan);
+
+/*
+ * Per-run failure status without a host synchronisation: enqueue on
+ * hip_stream a copy into *status of the failure word of this plan's runs
+ * issued on that stream since the previous mpk_run_status call for it
+ * (0 = every one completed, 1 = a dependency wait hit its limit, so the
+ * outputs of a run among them are invalid), and clear the word.  status is
+ * device memory or pinned host memory (e.g. hipHostMalloc); it holds the
+ * value once the stream has reached this point, so a caller that records an
+ * event after this call can read it as soon as the event has completed, and
+ * must not hand out that stream's outputs before.  The kernel abandons a
+ * run whose wait hits tune.spin_limit_us (Alg. 2's dependencies cannot
+ * deadlock; the limit guards against a stalled device).  p x SpMV and STEPS
+ * runs never fail this way.  Plans keep 256 words; beyond 256 streams,
+ * streams share words (a failure then shows on each of them).
+ * Errors: MPK_EINVAL (NULL), MPK_ENODEVICE, MPK_EHIP.
+ */
+mpk_status_t mpk_run_status(mpk_plan_t plan, void *hip_stream, int32_t *status);
 
 /*
  * Autotuner (the counterpart of the paper's parameter study over the cache
@@ -432,6 +454,19 @@ void mpk_graph_destroy(mpk_graph_t graph);
  */
 mpk_status_t mpk_probe_load(const double *buf, int64_t n, int passes, int workgroups,
                             double *sink, void *hip_stream);
+
+/*
+ * XCD-local form of the same probe: buf[n] is cut into `regions` equal parts
+ * (n a multiple of 2 x regions) and each workgroup reads, `passes` times, the
+ * part of the XCD it runs on (hardware XCC_ID mod regions), so that the
+ * working set of each XCD's L2 is n/regions doubles.  sink[workgroups] as
+ * above; xcc[workgroups] (device int32) receives the XCC_ID of each
+ * workgroup, to check the placement the probe assumes (workgroup b on XCD
+ * b mod regions).  regions in [1, 16].
+ * Errors: MPK_EINVAL (NULL, n or regions out of range), MPK_EHIP.
+ */
+mpk_status_t mpk_probe_load_xcd(const double *buf, int64_t n, int regions, int passes,
+                                int workgroups, double *sink, int32_t *xcc, void *hip_stream);
 
 /* Device allocator used for plan data (NULL, NULL restores hipMalloc/hipFree). */
 mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx),

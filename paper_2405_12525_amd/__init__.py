@@ -24,7 +24,7 @@ __all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN"
            "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
            "MPK_SCHED_POWERS", "MPK_SCHED_XCD", "use_torch_allocator", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
            "cheb_time_coefficients",
-           "flops", "lib", "probe_load"]
+           "flops", "lib", "probe_load", "probe_load_xcd"]
 
 _SCHED = {"steps": MPK_SCHED_STEPS, "wave": MPK_SCHED_WAVE, "diag": MPK_SCHED_DIAG,
           "powers": MPK_SCHED_POWERS, "xcd": MPK_SCHED_XCD}
@@ -77,6 +77,23 @@ def probe_load(buf, passes: int = 1, workgroups: int = 2048, sink=None, stream=N
                                int(workgroups), ctypes.c_void_p(sink.data_ptr()),
                                _stream_handle(stream)))
     return sink
+
+
+def probe_load_xcd(buf, regions: int = 8, passes: int = 1, workgroups: int = 2048, sink=None,
+                   xcc=None, stream=None):
+    """XCD-local load probe (mpk_probe_load_xcd): each workgroup reads the
+    part of buf belonging to the XCD it runs on.  Returns (sink, xcc)."""
+    torch = _torch()
+    if buf.dtype != torch.float64 or not buf.is_contiguous() or not buf.is_cuda:
+        raise TypeError("buf must be a contiguous float64 device tensor")
+    if sink is None:
+        sink = torch.empty(workgroups, dtype=torch.float64, device=buf.device)
+    if xcc is None:
+        xcc = torch.empty(workgroups, dtype=torch.int32, device=buf.device)
+    check(lib().mpk_probe_load_xcd(ctypes.c_void_p(buf.data_ptr()), buf.numel(), int(regions),
+                                   int(passes), int(workgroups), ctypes.c_void_p(sink.data_ptr()),
+                                   ctypes.c_void_p(xcc.data_ptr()), _stream_handle(stream)))
+    return sink, xcc
 
 
 def _torch():
@@ -513,6 +530,20 @@ class Plan:
     def sync(self):
         """Wait for this plan's runs; raises MPKError(MPK_ETIMEOUT) on a failed wait."""
         check(self._lib.mpk_plan_sync(self._h))
+
+    def run_status(self, out, stream=None):
+        """Enqueue on `stream` a copy of the failure word of this plan's runs
+        issued there since the last call (mpk_run_status) into out[0]: an
+        int32 tensor in device memory or pinned host memory.  0 = all
+        completed, 1 = a wait hit its limit (those outputs are invalid)."""
+        torch = _torch()
+        if out.dtype != torch.int32 or out.numel() < 1:
+            raise TypeError("out must be an int32 tensor with at least one element")
+        if not (out.is_cuda or out.is_pinned()):
+            raise TypeError("out must be device memory or pinned host memory")
+        check(self._lib.mpk_run_status(self._h, _stream_handle(stream),
+                                       ctypes.c_void_p(out.data_ptr())))
+        return out
 
 
 class Graph:

@@ -123,15 +123,15 @@ struct SchedEntry {
 };
 
 struct Workspace {
-    DevBuf buf;          // done[cap] | ticket[kMaxQueues] | err
+    DevBuf buf;          // done[cap] | ticket[kMaxQueues] | err | fail
     int32_t cap = 0;
     hipEvent_t ev = nullptr;
     hipStream_t last_stream = nullptr;
     bool recorded = false;
     bool reserved = false;  // owned by a captured graph
-    DevWorkspace view() const {
+    DevWorkspace view(int32_t *status = nullptr) const {
         int32_t *b = buf.as<int32_t>();
-        return DevWorkspace{b, b + cap, b + cap + kMaxQueues};
+        return DevWorkspace{b, b + cap, b + cap + kMaxQueues, b + cap + kMaxQueues + 1, status};
     }
 };
 
@@ -169,6 +169,8 @@ struct mpk_plan_s {
     std::vector<std::unique_ptr<Workspace>> pool;
     std::map<long long, int> wg_cache;
     std::map<hipStream_t, hipEvent_t> stream_ev;  // last run issued per stream
+    DevBuf status_words;                          // kStatusSlots failure words
+    std::map<hipStream_t, int> status_slot;       // stream -> its word
     uint64_t fingerprint = 0;                     // of the input CSR and options
 
     DevMatrix matrix() const {
@@ -318,7 +320,7 @@ mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream
     }
     auto w = std::make_unique<Workspace>();
     w->cap = std::max<int32_t>(n_chunks, 1024);
-    const size_t words = (size_t)w->cap + kMaxQueues + 1;
+    const size_t words = (size_t)w->cap + kMaxQueues + 2;
     mpk_status_t st = w->buf.alloc(words * sizeof(int32_t));
     if (st) return st;
     hipError_t e = hipMemset(w->buf.ptr, 0, words * sizeof(int32_t));
@@ -328,6 +330,29 @@ mpk_status_t get_workspace(mpk_plan_t plan, int32_t n_chunks, hipStream_t stream
     *out = w.get();
     plan->pool.push_back(std::move(w));
     return MPK_OK;
+}
+
+// The failure word of runs issued on `stream` (plan->mu held).  Streams get
+// words in the order they are first seen; past kStatusSlots they share.
+int32_t *status_word(mpk_plan_t plan, hipStream_t stream) {
+    auto it = plan->status_slot.find(stream);
+    int slot;
+    if (it != plan->status_slot.end()) {
+        slot = it->second;
+    } else {
+        slot = (int)(plan->status_slot.size() % kStatusSlots);
+        plan->status_slot.emplace(stream, slot);
+    }
+    return plan->status_words.as<int32_t>() + slot;
+}
+
+// Device-side state every device plan holds from the start (allocated
+// outside any capture): the zeroed failure words.
+mpk_status_t init_device_state(mpk_plan_t plan) {
+    mpk_status_t st = plan->status_words.alloc(kStatusSlots * sizeof(int32_t));
+    if (st) return st;
+    hipError_t e = hipMemset(plan->status_words.ptr, 0, kStatusSlots * sizeof(int32_t));
+    return e == hipSuccess ? MPK_OK : hip_fail(e, "hipMemset");
 }
 
 int default_workgroups(mpk_plan_t plan, int R) {
@@ -513,17 +538,29 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         DevSchedule ds{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
                        se->dep_hi.as<int32_t>(), se->tasks.as<int32_t>(), se->host.n_tasks(),
                        se->host.n_chunks()};
-        int rc = launch_reset(ws->view(), se->host.n_chunks(), stream);
+        const DevWorkspace wv = ws->view(status_word(plan, stream));
+        int rc = launch_reset(wv, se->host.n_chunks(), stream);
         if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
+        // Without an invalidating acquire per task, an output line must
+        // never be read before it is complete: the chunks must own whole
+        // 128-byte lines of every output vector (line-closed schedule, plan
+        // row order, 128-byte aligned outputs with n*R a multiple of 16) and
+        // no address may be written twice in a run (not so for the ring of
+        // the weighted-sum kernels).
+        const bool lines_own = se->host.line_closed && !poly && !plan->d_outrow.ptr &&
+                               ((size_t)plan->n * nrhs) % kLineRows == 0 &&
+                               reinterpret_cast<uintptr_t>(Y) % 128 == 0;
+        const int acquire = (plan->tune.acquire_always || !lines_own) ? 1 : 0;
         if (!se->host.qptr.empty()) {
             DevXcdSchedule xs{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_ptr.as<int32_t>(),
                               se->dep_idx.as<int32_t>(),
                               se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
                               se->host.n_queues, se->host.n_chunks()};
-            rc = launch_xcd(m, xs, ws->view(), a, &cf, acp, wg, spin_ticks, stream);
+            const int64_t steal_ticks = 20 * (int64_t)plan->wall_khz / 1000;  // 20 us
+            rc = launch_xcd(m, xs, wv, a, &cf, acp, wg, spin_ticks, steal_ticks, stream);
         } else {
-            rc = launch_lb(m, ds, ws->view(), a, &cf, acp, wg, spin_ticks, plan->tune.skip_ahead,
-                           stream);
+            rc = launch_lb(m, ds, wv, a, &cf, acp, wg, spin_ticks, plan->tune.skip_ahead,
+                           acquire, stream);
         }
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
         if (capturing) {
@@ -747,6 +784,7 @@ void mpk_tune_default(mpk_tune_t *t) {
     t->spin_limit_us = 0;
     t->seg_powers = 0;
     t->skip_ahead = 0;
+    t->acquire_always = 0;
 }
 
 mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
@@ -808,6 +846,7 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
             int khz = 0;
             if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
                 plan->wall_khz = khz;
+            if ((st = init_device_state(plan.get()))) return st;
         }
         if (gpu_levels) {
             DevBuf rp0, c0, v0;  // the caller's CSR in its own order
@@ -962,6 +1001,7 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
             plan->wall_khz = khz;
         mpk_status_t st;
+        if ((st = init_device_state(plan.get()))) return st;
         if ((st = plan->d_rowptr.alloc(((size_t)n + 1) * 4))) return st;
         if ((st = plan->d_col.alloc((size_t)nnz * 4))) return st;
         if ((st = plan->d_val.alloc((size_t)nnz * (size_t)(o.value_bits / 8)))) return st;
@@ -1034,6 +1074,8 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
         return fail(MPK_EINVAL, "seg_powers must be in [0, 64]");
     if (t.chunk_nnz < 1 || t.lag < 0 || t.workgroups < 0 || t.spin_limit_us < 0)
         return fail(MPK_EINVAL, "negative tuning value");
+    if (t.acquire_always != 0 && t.acquire_always != 1)
+        return fail(MPK_EINVAL, "acquire_always must be 0 or 1");
     std::lock_guard<std::mutex> g(plan->mu);
     plan->tune = t;
     // schedules may still be read by queued kernels: keep them until destroy
@@ -1261,6 +1303,16 @@ mpk_status_t mpk_probe_load(const double *buf, int64_t n, int passes, int workgr
     if (!buf || !sink || n < 2 || (n & 1) || passes < 1 || workgroups < 1)
         return fail(MPK_EINVAL, "probe needs buf, sink, an even n >= 2, passes and workgroups >= 1");
     int rc = launch_load_probe(buf, n, passes, workgroups, sink, stream);
+    return rc ? hip_fail((hipError_t)rc, "probe kernel launch") : MPK_OK;
+}
+
+mpk_status_t mpk_probe_load_xcd(const double *buf, int64_t n, int regions, int passes,
+                                int workgroups, double *sink, int32_t *xcc, void *stream) {
+    if (!buf || !sink || !xcc || regions < 1 || regions > kMaxQueues || passes < 1 ||
+        workgroups < 1 || n < 2 * (int64_t)regions || n % (2 * (int64_t)regions))
+        return fail(MPK_EINVAL, "probe needs buf, sink, xcc, 1 <= regions <= 16, n a multiple of "
+                                "2 x regions, passes and workgroups >= 1");
+    int rc = launch_load_probe_xcd(buf, n, regions, passes, workgroups, sink, xcc, stream);
     return rc ? hip_fail((hipError_t)rc, "probe kernel launch") : MPK_OK;
 }
 
@@ -1553,6 +1605,22 @@ mpk_status_t mpk_graph_launch(mpk_graph_t graph, void *stream) {
 
 void mpk_graph_destroy(mpk_graph_t graph) { delete graph; }
 
+mpk_status_t mpk_run_status(mpk_plan_t plan, void *stream_v, int32_t *status) {
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    if (!status) return fail(MPK_EINVAL, "status is NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int32_t *word;
+    {
+        std::lock_guard<std::mutex> g(plan->mu);
+        word = status_word(plan, stream);
+    }
+    int rc = launch_status_copy(word, status, stream);
+    return rc ? hip_fail((hipError_t)rc, "status kernel launch") : MPK_OK;
+}
+
 mpk_status_t mpk_plan_sync(mpk_plan_t plan) {
     mpk_status_t st = check_device_plan(plan);
     if (st) return st;
@@ -1570,12 +1638,12 @@ mpk_status_t mpk_plan_sync(mpk_plan_t plan) {
             if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
         }
         int32_t flag = 0;
-        e = hipMemcpy(&flag, w->view().err, sizeof(int32_t), hipMemcpyDeviceToHost);
+        e = hipMemcpy(&flag, w->view().fail, sizeof(int32_t), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
         if (flag) {
             timeout = true;
             const int32_t zero = 0;
-            e = hipMemcpy(w->view().err, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
+            e = hipMemcpy(w->view().fail, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
         }
     }

@@ -42,6 +42,13 @@ __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A wait hit its limit: abandon the run and record the failure.
+__device__ __forceinline__ void record_failure(const DevWorkspace &ws) {
+    __hip_atomic_store(ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ws.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ws.status) __hip_atomic_store(ws.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 struct PowerIO {
     const double *in;     // y_{k-1}
     const double *prev;   // y_{k-2} (recurrence; null at the very first power)
@@ -469,6 +476,7 @@ struct LBParams {
     SegArgs a;
     int64_t spin_limit;   // wall-clock ticks
     int32_t pending;      // skip-ahead slots (lbs_kernel)
+    int32_t acquire;      // invalidate caches before a task reads its inputs
 };
 
 // One non-blocking look at task t's inputs by wavefront 0 (all 64 lanes):
@@ -537,8 +545,16 @@ __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, cons
             }
             __syncthreads();
             ok = __builtin_amdgcn_readfirstlane(s_ok);
-            // the producers' rows are visible to every wave of this workgroup
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // The producers' rows are visible to every wave of this
+            // workgroup.  With a line-closed schedule no cache holds a copy
+            // of any line they wrote (nobody read it before it was
+            // complete), so the loads below miss down to the level their
+            // write-through stores reached, and the caches stay warm; else
+            // this XCD's caches are invalidated first.
+            if (P.acquire)
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            else
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
         if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
         run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
@@ -558,8 +574,7 @@ __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, cons
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
-    if (t < P.s.n_tasks && tid == 0)
-        __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t < P.s.n_tasks && tid == 0) record_failure(P.ws);
 }
 
 template <typename V, int RC>
@@ -648,7 +663,10 @@ __device__ __forceinline__ void lbs_body(const LBParams &P, const Coefs &cf, con
         __syncthreads();
         const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
         if (t < 0) break;  // uniform: no work left (or a wait failed)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (P.acquire)  // as in lb_body
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        else
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         const int32_t c = P.s.tasks[2 * t];
         const int32_t k = P.s.tasks[2 * t + 1];
         run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
@@ -659,8 +677,7 @@ __device__ __forceinline__ void lbs_body(const LBParams &P, const Coefs &cf, con
         if (tid == 0)
             __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (failed && tid == 0)
-        __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (failed && tid == 0) record_failure(P.ws);
 }
 
 template <typename V, int RC>
@@ -685,6 +702,7 @@ struct XcdParams {
     DevWorkspace ws;
     SegArgs a;
     int64_t spin_limit;   // wall-clock ticks
+    int64_t steal_ticks;  // wait on the own queue's head before serving others
 };
 
 // Kernel arguments stay well inside the 4 KiB argument segment.
@@ -693,72 +711,113 @@ static_assert(sizeof(LBParams) + sizeof(Coefs) + sizeof(AccCoefs) <= 3584,
 static_assert(sizeof(XcdParams) + sizeof(Coefs) + sizeof(AccCoefs) <= 3584,
               "XCD kernel arguments");
 
+// Whether task t of the XCD schedule can run: every chunk it reads has
+// completed the previous power.  Wavefront 0 only (all 64 lanes).
+__device__ __forceinline__ bool xcd_task_ready(const XcdParams &P, int32_t t) {
+    const int32_t c = P.s.tasks[2 * t];
+    const int32_t k = P.s.tasks[2 * t + 1];
+    if (k == 1) return true;
+    const int32_t lo = P.s.dep_ptr[c], hi = P.s.dep_ptr[c + 1];
+    int ready = 1;
+    for (int32_t j = lo + (int)threadIdx.x; j < hi; j += kWave)
+        ready &= ld_relaxed(P.ws.done + P.s.dep_idx[j]) >= k - 1;
+    return __all(ready);
+}
+
+// Claims the head of queue j if its inputs are done: returns the global task
+// index, -1 when the head is not ready, -2 when the queue is exhausted.
+// Wavefront 0 only; lane 0 does the atomics and broadcasts.
+__device__ __forceinline__ int32_t xcd_claim_head(const XcdParams &P, int j) {
+    const int32_t q0 = P.s.qptr[j];
+    const int32_t qn = P.s.qptr[j + 1] - q0;
+    int32_t *head = P.ws.ticket + j;
+    for (;;) {
+        int32_t h = 0;
+        if (threadIdx.x == 0) h = ld_relaxed(head);
+        h = __shfl(h, 0);
+        if (h >= qn) return -2;
+        if (!xcd_task_ready(P, q0 + h)) return -1;
+        int won = 0;
+        if (threadIdx.x == 0) {
+            int32_t expect = h;
+            won = __hip_atomic_compare_exchange_strong(head, &expect, h + 1, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
+        }
+        if (__shfl(won, 0)) return q0 + h;
+        // another workgroup took this head: look at the next one
+    }
+}
+
 // Persistent kernel of the XCD schedule.  Queue q holds the tasks of the
-// chunks owned by XCD q, in global dependency order; a workgroup serves the
-// queue of the XCD it runs on (read from the hardware, so the binding holds
-// whatever the dispatcher does).  Dependencies are exact chunk lists;
-// results are published as in lb_kernel.  Deadlock freedom: the earliest
-// unfinished task in the global order is always held by a workgroup of its
-// queue (all earlier tasks of that queue are done), and its dependencies are
-// earlier still, so it can run; waits are bounded by spin_limit in any case.
+// chunks owned by XCD q, in the global dependency order the queues were cut
+// from.  A workgroup only ever claims a task whose inputs are done (the head
+// of a queue, by compare-and-swap), so it never holds a task while waiting.
+// It serves the queue of the XCD it runs on (read from the hardware) first;
+// when that head stays unready for steal_ticks, or the queue is exhausted, it
+// claims ready heads of the other queues as well.  Deadlock freedom, whatever
+// the dispatcher does and whatever else runs on the device: the earliest
+// unfinished task of the global order has all its inputs done and every
+// earlier task of its queue finished, so it is either running or the ready
+// head of its queue, which any workgroup not holding a task will claim.
+// Waits for a ready head are bounded by spin_limit in any case.  Results are
+// published as in lb_kernel.
 template <typename V, int RC, bool ACC>
 __device__ __forceinline__ void xcd_body(const XcdParams &P, const Coefs &cf, const AccCoefs *ac) {
     __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
-    __shared__ int32_t s_ticket;
-    __shared__ int s_ok;
+    __shared__ int32_t s_task;
     const int tid = threadIdx.x;
-    const int q = P.s.n_queues == 1 ? 0 : __builtin_amdgcn_readfirstlane(xcc_id());
-    if (q >= P.s.n_queues) return;  // uniform: no queue for this XCD
-    const int32_t q0 = P.s.qptr[q];
-    const int32_t qn = P.s.qptr[q + 1] - q0;
-    int32_t *ticket = P.ws.ticket + q;
-    if (tid == 0)
-        s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    int32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
-    while (t < qn) {
-        const int32_t c = P.s.tasks[2 * (q0 + t)];
-        const int32_t k = P.s.tasks[2 * (q0 + t) + 1];
-        int ok = 1;
-        if (k > 1) {
-            if (tid < kWave) {
-                const int32_t lo = P.s.dep_ptr[c], hi = P.s.dep_ptr[c + 1];
-                uint64_t t0 = 0;
-                for (int round = 0;; ++round) {
-                    int ready = 1;
-                    for (int32_t j = lo + tid; j < hi; j += kWave)
-                        ready &= ld_relaxed(P.ws.done + P.s.dep_idx[j]) >= k - 1;
-                    if (__all(ready)) break;
-                    if (round == 0) t0 = wall_clock64();
-                    if (ld_relaxed(P.ws.err) != 0 ||
-                        (int64_t)(wall_clock64() - t0) > P.spin_limit) {
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
+    const int nq = P.s.n_queues;
+    const int home = nq == 1 ? 0 : __builtin_amdgcn_readfirstlane(xcc_id()) % nq;
+    bool failed = false;  // wavefront 0: a wait hit its limit (reported after the loop)
+    for (;;) {
+        if (tid < kWave) {
+            int32_t chosen = -1;
+            uint64_t t0 = wall_clock64();
+            for (;;) {
+                const int32_t own = xcd_claim_head(P, home);
+                if (own >= 0) {
+                    chosen = own;
+                    break;
                 }
-                if (tid == 0) s_ok = ok;
+                const int64_t waited = (int64_t)(wall_clock64() - t0);
+                bool left = own == -1;
+                if (own == -2 || waited > P.steal_ticks) {
+                    for (int i = 1; i < nq; ++i) {
+                        const int32_t t = xcd_claim_head(P, (home + i) % nq);
+                        if (t >= 0) {
+                            chosen = t;
+                            break;
+                        }
+                        left |= t == -1;
+                    }
+                    if (chosen >= 0) break;
+                }
+                if (!left) break;  // every queue exhausted
+                if (ld_relaxed(P.ws.err) != 0 || waited > P.spin_limit) {
+                    failed = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
-            __syncthreads();
-            ok = __builtin_amdgcn_readfirstlane(s_ok);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (tid == 0) s_task = chosen;
         }
-        if (!ok) break;
+        __syncthreads();
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
+        if (t < 0) break;  // uniform: no work left (or a wait failed)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int32_t c = P.s.tasks[2 * t];
+        const int32_t k = P.s.tasks[2 * t + 1];
         run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
             P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
             P.s.chunk_sptr[c + 1], sm);
         // write-through results, completed (vmcnt = 0) before the barrier
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0)
             __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
-    if (t < qn && tid == 0)
-        __hip_atomic_store(P.ws.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (failed && tid == 0) record_failure(P.ws);
 }
 
 template <typename V, int RC>
@@ -776,6 +835,12 @@ __global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_chunks) ws.done[i] = 0;
     if (i < kMaxQueues) ws.ticket[i] = 0;
+    if (i == 0) *ws.err = 0;
+}
+
+__global__ void status_copy_kernel(int32_t *word, int32_t *out) {
+    const int32_t v = __hip_atomic_exchange(word, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(out, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Each workgroup records the XCD it ran on.
@@ -834,6 +899,39 @@ __global__ __launch_bounds__(kBlock) void load_probe_kernel(const double2 *buf, 
         __syncthreads();
     }
     if (threadIdx.x == 0) sink[blockIdx.x] = red[0];
+}
+
+// XCD-local variant: the buffer is cut into `regions` equal parts and every
+// workgroup reads the part of the XCD it runs on (XCC_ID mod regions), so each
+// XCD's L2 sees only its own part.  Workgroups are numbered within an XCD by
+// blockIdx / regions (the dispatcher deals workgroups to XCDs round robin);
+// were it otherwise, parts would be read unevenly but every load stays inside
+// the buffer.  xcc[b] records where workgroup b ran.
+__global__ __launch_bounds__(kBlock) void load_probe_local_kernel(const double2 *buf, int64_t n2,
+                                                                int regions, int passes,
+                                                                double *sink, int32_t *xcc) {
+    const int x = __builtin_amdgcn_readfirstlane(xcc_id()) % regions;
+    const int64_t per = n2 / regions;
+    const double2 *part = buf + (int64_t)x * per;
+    const int64_t idx = blockIdx.x / regions;
+    const int64_t stride = (int64_t)((gridDim.x + regions - 1) / regions) * kBlock;
+    double acc = 0.0;
+    for (int p = 0; p < passes; ++p)
+        for (int64_t i = idx * kBlock + threadIdx.x; i < per; i += stride) {
+            const double2 v = part[i];
+            acc += v.x + v.y;
+        }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sink[blockIdx.x] = red[0];
+        xcc[blockIdx.x] = xcc_id();
+    }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -938,6 +1036,12 @@ int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream) {
     return (int)hipGetLastError();
 }
 
+int launch_status_copy(int32_t *status_word, int32_t *out, void *stream) {
+    hipLaunchKernelGGL(status_copy_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, status_word,
+                       out);
+    return (int)hipGetLastError();
+}
+
 int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_t per,
                       const double *in, const double *inm1, double *out, int32_t R, int recur,
                       double alpha, double beta, double gamma, const AccStep *acc,
@@ -999,12 +1103,12 @@ int lb_max_workgroups(int value_bits, int R, int device) {
 
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-              int64_t spin_limit, int pending, void *stream) {
+              int64_t spin_limit, int pending, int acquire, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (pending < 0 || pending > kMaxPending) return (int)hipErrorInvalidValue;
     if (s.n_tasks == 0) return 0;
-    LBParams P{m, s, ws, a, spin_limit, pending};
+    LBParams P{m, s, ws, a, spin_limit, pending, acquire ? 1 : 0};
     Coefs c{};
     if (cf) c = *cf;
     if (acc)
@@ -1018,12 +1122,12 @@ int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
 
 int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
                const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-               int64_t spin_limit, void *stream) {
+               int64_t spin_limit, int64_t steal_ticks, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (s.n_queues < 1 || s.n_queues > kMaxQueues) return (int)hipErrorInvalidValue;
     if (s.n_chunks == 0) return 0;
-    XcdParams P{m, s, ws, a, spin_limit};
+    XcdParams P{m, s, ws, a, spin_limit, steal_ticks};
     Coefs c{};
     if (cf) c = *cf;
     if (acc)
@@ -1086,6 +1190,17 @@ int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int work
     if (n_doubles < 2 || passes < 1 || workgroups < 1) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(load_probe_kernel, dim3(workgroups), dim3(kBlock), 0, (hipStream_t)stream,
                        reinterpret_cast<const double2 *>(buf), n_doubles / 2, passes, sink);
+    return (int)hipGetLastError();
+}
+
+int launch_load_probe_xcd(const double *buf, int64_t n_doubles, int regions, int passes,
+                          int workgroups, double *sink, int32_t *xcc, void *stream) {
+    if (n_doubles < 2 * (int64_t)regions || regions < 1 || regions > kMaxQueues || passes < 1 ||
+        workgroups < 1)
+        return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(load_probe_local_kernel, dim3(workgroups), dim3(kBlock), 0,
+                       (hipStream_t)stream, reinterpret_cast<const double2 *>(buf),
+                       n_doubles / 2, regions, passes, sink, xcc);
     return (int)hipGetLastError();
 }
 

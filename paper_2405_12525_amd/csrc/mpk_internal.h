@@ -94,6 +94,12 @@ struct Schedule {
     int32_t n_queues = 0;
     int32_t n_groups = 0, lag = 0, max_reach = 0;
     double window_bytes = 0.0, build_ms = 0.0;
+    // Every chunk boundary except n is a multiple of kLineRows: a 128-byte
+    // line of an output vector (128-byte aligned, n*R a multiple of 16) then
+    // holds rows of one chunk only.  Tasks read rows of done chunks only, so
+    // no cache can hold a copy of an output line from before the line was
+    // complete, and tasks need no cache invalidation before their reads.
+    bool line_closed = false;
     int32_t n_chunks() const { return (int32_t)chunk_group.size(); }
     int32_t n_tasks() const { return (int32_t)(tasks.size() / 2); }
     int32_t n_steps() const { return step_ptr.empty() ? 1 : (int32_t)step_ptr.size() - 1; }
@@ -138,6 +144,9 @@ constexpr int kMaxSegPowers = 64;   // powers per kernel launch
 constexpr int kSpmvKP = 16;   // products per thread and buffer, p x SpMV kernel
 constexpr int kTaskKP = 16;   // the same for the level-blocked kernels
 constexpr int kSliceRows = 256;
+// Rows per 128-byte cache line of a single-RHS double vector; 16 rows of R
+// right-hand sides are exactly R lines for any R.
+constexpr int kLineRows = 16;
 inline int slice_nnz(int kp, int R) { return R >= 4 ? kp * 256 : kp * 256 / R; }
 
 // Cuts rows [bounds.front(), bounds.back()) into slices of at most E
@@ -221,8 +230,14 @@ constexpr int kMaxQueues = 16;
 struct DevWorkspace {
     int32_t *done;      // n_chunks completion powers
     int32_t *ticket;    // next task (kMaxQueues counters for the XCD schedule)
-    int32_t *err;       // sticky failure flag
+    int32_t *err;       // this run failed: every workgroup leaves (cleared per run)
+    int32_t *fail;      // a run on this workspace failed (kept until mpk_plan_sync)
+    int32_t *status;    // the launch stream's status word (may be null)
 };
+
+// A failed wait: the run is abandoned (err), the failure is kept for
+// mpk_plan_sync (fail) and for mpk_run_status on the launch stream (status).
+constexpr int kStatusSlots = 256;  // status words per plan (streams share a slot beyond that)
 
 struct DevXcdSchedule {
     DevSlices sl;
@@ -234,12 +249,19 @@ struct DevXcdSchedule {
 };
 
 // Launchers (kernels.hip).  All return hipError_t as int.
-int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);  // also clears the queue tickets
+// Clears done[], the queue tickets and err before a run (fail and status stay).
+int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);
+// *out = *status_word, then *status_word = 0 (one thread; out may be pinned
+// host memory).
+int launch_status_copy(int32_t *status_word, int32_t *out, void *stream);
 // pending > 0 selects the skip-ahead kernel with that many parked tasks (<= 8).
 // acc != null: the ring / weighted-sum kernels (SegArgs ring, acc_a, acc_b).
+// acquire = 0: tasks read their inputs without invalidating caches first
+// (only valid for a line-closed schedule whose outputs are written in plan
+// order into 128-byte aligned vectors, see Schedule::line_closed).
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-              int64_t spin_limit, int pending, void *stream);
+              int64_t spin_limit, int pending, int acquire, void *stream);
 // One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
 int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
                 int32_t n_tasks, const SegArgs &a, const Coefs *cf, const AccCoefs *acc,
@@ -258,9 +280,14 @@ int launch_permute(const int32_t *perm, int64_t n, int to_plan, const double *in
                    int nvec, int R, void *stream);
 int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int workgroups,
                       double *sink, void *stream);
+int launch_load_probe_xcd(const double *buf, int64_t n_doubles, int regions, int passes,
+                          int workgroups, double *sink, int32_t *xcc, void *stream);
+// The XCD schedule's persistent kernel: workgroups claim ready queue heads,
+// their own XCD's queue first and, after steal_ticks of waiting (wall-clock
+// ticks) or once it is exhausted, any queue's.
 int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
                const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-               int64_t spin_limit, void *stream);
+               int64_t spin_limit, int64_t steal_ticks, void *stream);
 // XCDs of the device when workgroup i runs on XCD i mod n (checked with a probe
 // kernel), else 1.
 int detect_xcds(int device);

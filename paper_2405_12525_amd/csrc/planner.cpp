@@ -568,9 +568,37 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
     }
     s.n_groups = (int32_t)group_ptr.size() - 1;
 
-    // 2. chunks: rows of one group cut at about chunk_nnz nonzeros (never split a row)
+    // 2. chunks.  The persistent wavefront and power-order schedules track
+    // dependencies per chunk and need no group structure: their chunks are
+    // cut at about chunk_nnz nonzeros on multiples of kLineRows rows (a chunk
+    // may span a group boundary; chunk_group is the group of its first row),
+    // so that each 128-byte line of an output vector belongs to one chunk
+    // (line_closed).  The diagonal schedules cut every group on its own.
     s.chunk_ptr.push_back(0);
-    for (int32_t g = 0; g < s.n_groups; ++g) {
+    const bool aligned = tune.schedule == MPK_SCHED_WAVE || tune.schedule == MPK_SCHED_POWERS;
+    if (aligned) {
+        std::vector<int32_t> level_group(n_levels);
+        for (int32_t g = 0; g < s.n_groups; ++g)
+            for (int32_t l = group_ptr[g]; l < group_ptr[g + 1]; ++l) level_group[l] = g;
+        int32_t lev = 0;
+        int64_t r = 0;
+        while (r < n) {
+            const int64_t lim = std::min<int64_t>((int64_t)rp[r] + chunk_nnz, INT32_MAX);
+            // last row end within the nonzero target, at most 65536 rows
+            int64_t e = std::upper_bound(rp.begin() + r + 1, rp.begin() + n + 1, (int32_t)lim) -
+                        rp.begin() - 1;
+            e = std::min<int64_t>(e, r + 65536);
+            e -= e % kLineRows;
+            if (e <= r) e = r + kLineRows;  // at least one block of lines
+            e = std::min<int64_t>(e, n);
+            while (lev + 1 < n_levels && lp[lev + 1] <= r) ++lev;
+            s.chunk_ptr.push_back((int32_t)e);
+            s.chunk_group.push_back(level_group[lev]);
+            r = e;
+        }
+        s.line_closed = true;
+    }
+    for (int32_t g = 0; g < s.n_groups && !aligned; ++g) {
         const int64_t r0 = lp[group_ptr[g]], r1 = lp[group_ptr[g + 1]];
         const int64_t nz0 = rp[r0], nz = (int64_t)rp[r1] - nz0;
         const int64_t rows = r1 - r0;
@@ -714,6 +742,12 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
 bool validate_schedule(const Schedule &s, std::string &err) {
     const int32_t nc = s.n_chunks();
     const int p = s.p;
+    if (s.line_closed)
+        for (int32_t c = 0; c + 1 < nc; ++c)
+            if (s.chunk_ptr[c + 1] % kLineRows != 0) {
+                err = "line-closed schedule with a chunk boundary off the line grid";
+                return false;
+            }
     if (!s.qptr.empty()) {
         // XCD queues: every (chunk, power) once, in the owning XCD's queue, and
         // within a queue a chunk's powers in increasing order

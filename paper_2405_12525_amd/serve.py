@@ -16,7 +16,11 @@ the loop admits them as stream slots and memory free up:
   takes its own columns of the stepped states;
 * batches for different matrices run concurrently on separate HIP streams;
 * a batch is admitted only while the device memory held by running batches
-  (stacked inputs plus outputs) stays within the budget.
+  (stacked inputs plus outputs) stays within the budget;
+* each batch's device status (mpk_run_status, copied into pinned host memory
+  on the batch's stream) is read when the batch completes and before any of
+  its outputs is handed out: a batch whose dependency wait hit its limit
+  delivers nothing, and its requests are reported as failed.
 
 All arithmetic runs in the library's kernels; this module only schedules.
 """
@@ -29,7 +33,8 @@ from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 
-from . import Plan, chebyshev_coefficients, flops, _torch
+from . import MPKError, Plan, chebyshev_coefficients, flops, _torch
+from ._capi import MPK_ETIMEOUT
 
 MAX_RHS = 16
 
@@ -57,6 +62,7 @@ class Result:
     start: float              # batch launch time
     done: float               # completion observed by the loop
     batch_size: int
+    error: Optional[str] = None   # the batch failed on the device (Y is None)
 
     @property
     def latency(self) -> float:
@@ -112,6 +118,10 @@ class Server:
             mem_budget = int(free * 0.6)
         self.mem_budget = int(mem_budget)
         self.streams = [torch.cuda.Stream() for _ in range(max(1, int(n_streams)))]
+        # per-stream device status of the batch last launched there, written by
+        # the stream itself into pinned host memory (mpk_run_status)
+        self._status = [torch.zeros(1, dtype=torch.int32, pin_memory=True)
+                        for _ in self.streams]
         # per-stream buffers reused by serve(keep=False): stacked inputs, outputs
         self._stage = [None] * len(self.streams)
         self._out = [None] * len(self.streams)
@@ -160,13 +170,16 @@ class Server:
                 Y = P.cheb_time_step(X, batch[0].dt, p, out=Yo, stream=stream)
             else:
                 Y = P.run(X, p, Y=Yo, stream=stream)
+            # the batch's failure word, ready when the event below completes
+            P.run_status(self._status[si], stream=stream)
             ev = torch.cuda.Event()
             ev.record(stream)
         return Y, ev, p
 
     def serve(self, requests: Sequence[Request], realtime: bool = True,
               keep: bool = True,
-              on_result: Optional[Callable[[Request, object], None]] = None) -> List[Result]:
+              on_result: Optional[Callable[[Request, object], None]] = None,
+              raise_on_error: bool = True) -> List[Result]:
         """Serve the requests (sorted by arrival); returns results by id.
 
         realtime=True replays the arrival times against the wall clock;
@@ -178,7 +191,12 @@ class Server:
         fill with freed outputs of every size.
         on_result(request, Y) is called when a request's batch has finished,
         with the request's own output view; with keep=False the view is only
-        valid during the call."""
+        valid during the call.
+        A batch whose run failed on the device (a dependency wait hit its
+        limit) hands out nothing: on_result is not called for its requests and
+        their Results carry `error` and no output.  The other batches are
+        unaffected.  raise_on_error=True then raises MPKError(MPK_ETIMEOUT)
+        once the stream has been served."""
         torch = _torch()
         for r in requests:
             if not 0 <= r.matrix < len(self.plans):
@@ -212,8 +230,14 @@ class Server:
                 si, ev, batch, Y, p, nbytes, start = item
                 if ev.query():
                     done = time.perf_counter() - t0
+                    failed = int(self._status[si][0]) != 0
                     c0 = 0
                     for r in batch:
+                        arr = r.arrival if realtime else 0.0
+                        if failed:
+                            results[r.id] = Result(r.id, None, arr, start, done, len(batch),
+                                                   error="a dependency wait hit its limit")
+                            continue
                         if r.kind == "time_step":
                             view = Y[:, c0:c0 + r.R]
                         else:
@@ -221,7 +245,6 @@ class Server:
                         c0 += r.R
                         if on_result is not None:
                             on_result(r, view)
-                        arr = r.arrival if realtime else 0.0
                         results[r.id] = Result(r.id, view if keep else None, arr, start, done,
                                                len(batch))
                     in_use -= nbytes
@@ -254,13 +277,25 @@ class Server:
                 wait = 20e-6 if running else (order[i].arrival - now if i < len(order) else 0.0)
                 if wait > 0:
                     time.sleep(min(wait, 1e-3))
+        failed = [i for i, r in results.items() if r.error is not None]
         for P in self.plans:
-            P.sync()
-        return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
+            try:
+                P.sync()
+            except MPKError as e:
+                # a failed run is already reported per batch above
+                if e.status != MPK_ETIMEOUT or not failed:
+                    raise
+        out = [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
+        if failed and raise_on_error:
+            raise MPKError(MPK_ETIMEOUT, f"{len(failed)} requests failed on the device "
+                                         f"(first ids {sorted(failed)[:8]}); nothing was "
+                                         "delivered for them")
+        return out
 
 
 def summarize(results: Sequence[Result], requests: Sequence[Request], plans: Sequence[Plan]) -> dict:
     """Latency percentiles, throughput and delivered Gflop/s of a served stream."""
+    results = [r for r in results if r.error is None]
     lat = np.array([r.latency for r in results])
     by_id = {r.id: r for r in requests}
     fl = 0.0
