@@ -247,6 +247,29 @@ mpk_status_t mpk_run(mpk_plan_t plan, const double *x, int p, int nrhs, double *
                      void *hip_stream);
 
 /*
+ * mpk_run for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same
+ * level-blocked run with the same results, whose dependency workspace is a
+ * file-scope device array of the library (1 MiB per GPU, held until the
+ * process ends) instead of a workspace from the plan's pool.  The call
+ * allocates nothing, builds nothing and records no event: the schedule, slice
+ * tables and workgroup count for (p, nrhs) must exist, so call
+ * mpk_plan_prepare(plan, p, nrhs) (or run mpk_run once with them) first.
+ * status: device or pinned host int32, or NULL; set to 0 when the run starts
+ * on the stream and to 1 if a dependency wait hits tune.spin_limit_us (the
+ * outputs are then invalid).  Not reported by mpk_plan_sync or
+ * mpk_run_status.
+ * Every call on one GPU shares that array, which keeps the last call's
+ * contents (each run clears what it uses): calls that overlap on one GPU
+ * race and give wrong results, so issue them on one stream or order them.
+ * Errors: as mpk_run; MPK_EINVAL when (p, nrhs) was not prepared;
+ * MPK_EUNSUPPORTED when the schedule has more than 262126 chunks (raise
+ * tune.chunk_nnz).
+ */
+mpk_status_t mpk_run_noalloc(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                             int32_t *status, void *hip_stream);
+
+/*
  * Three-term recurrence, Eq. (anderson_spmv) generalised:
  *   y_1     = alpha[0] A x   + beta[0] x
  *   y_{j+1} = alpha[j] A y_j + beta[j] y_j + gamma[j] y_{j-1},  j = 1..p-1

@@ -384,6 +384,23 @@ class Plan:
                                 ctypes.c_void_p(Y.data_ptr()), _stream_handle(stream)))
         return Y
 
+    def run_noalloc(self, x, p: int, Y, status=None, stream=None):
+        """mpk_run_noalloc: the level-blocked run with the library's static
+        device workspace; allocates nothing (Y must be given, and (p, nrhs)
+        prepared).  status: optional int32 tensor (device or pinned host)
+        that receives 0, or 1 when a dependency wait hit its limit."""
+        R, Y = self._prep(x, p, Y)
+        sp = None
+        if status is not None:
+            torch = _torch()
+            if status.dtype != torch.int32 or status.numel() < 1:
+                raise TypeError("status must be an int32 tensor")
+            sp = ctypes.c_void_p(status.data_ptr())
+        check(self._lib.mpk_run_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), int(p), R,
+                                        ctypes.c_void_p(Y.data_ptr()), sp,
+                                        _stream_handle(stream)))
+        return Y
+
     def run_baseline(self, x, p: int, Y=None, stream=None):
         """p back-to-back SpMVs (one launch per power); bit-identical to run()."""
         R, Y = self._prep(x, p, Y)

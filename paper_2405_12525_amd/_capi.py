@@ -22,7 +22,7 @@ EXPORTS = [
     "mpk_plan_opts_default", "mpk_tune_default", "mpk_plan", "mpk_plan_destroy", "mpk_plan_tune",
     "mpk_plan_info", "mpk_plan_levels", "mpk_plan_schedule", "mpk_plan_schedule_xcd", "mpk_run", "mpk_run_recur",
     "mpk_run_baseline", "mpk_run_baseline_recur", "mpk_permute", "mpk_plan_sync",
-    "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load", "mpk_probe_load_xcd", "mpk_run_status",
+    "mpk_set_allocator", "mpk_last_error", "mpk_version", "mpk_probe_load", "mpk_probe_load_xcd", "mpk_run_status", "mpk_run_noalloc",
     "mpk_plan_autotune", "mpk_graph_capture", "mpk_graph_launch", "mpk_graph_destroy",
     "mpk_run_poly", "mpk_run_baseline_poly", "mpk_cheb_time_coefficients", "mpk_combine_complex",
     "mpk_graph_capture_time_step", "mpk_plan_device", "mpk_plan_prepare",
@@ -133,6 +133,8 @@ def load():
     lib.mpk_probe_load_xcd.restype = st
     lib.mpk_run_status.argtypes = [P, P, P]
     lib.mpk_run_status.restype = st
+    lib.mpk_run_noalloc.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, P]
+    lib.mpk_run_noalloc.restype = st
     lib.mpk_plan_autotune.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(Tune),
                                       ctypes.POINTER(ctypes.c_double)]

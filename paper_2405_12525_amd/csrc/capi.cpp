@@ -443,10 +443,19 @@ void acc_flushes(const double *w, int p, std::vector<uint8_t> &f) {
     if (!started) f[(size_t)p] = kAccZero;
 }
 
-// Y is the output (p vectors), or with poly the two-slot ring.
+// The run of mpk_run_noalloc: the device's scratch workspace and the
+// caller's status word instead of a pooled workspace and the stream's word.
+struct NoAlloc {
+    int32_t *scratch;
+    int32_t *status;
+};
+
+// Y is the output (p vectors), or with poly the two-slot ring.  With `na`
+// nothing is built, allocated or recorded: schedules, slice tables and the
+// workgroup count must exist already.
 mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,
                     const double *beta, const double *gamma, double *Y, void *stream_v,
-                    const Poly *poly = nullptr) {
+                    const Poly *poly = nullptr, const NoAlloc *na = nullptr) {
     mpk_status_t st = check_run_args(plan, x, poly ? 2 : p, nrhs, Y);
     if (st) return st;
     if (p < 1) return fail(MPK_EINVAL, "p must be >= 1");
@@ -469,6 +478,8 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                         "the level-blocked weighted sums need a structurally symmetric pattern "
                         "(use the p x SpMV form)");
     }
+    if (na && !plan->wg_cache.count((long long)plan->value_bits * 1000 + nrhs))
+        return fail(MPK_EINVAL, "not prepared for this nrhs: call mpk_plan_prepare(plan, p, nrhs) first");
     const int wg_default = default_workgroups(plan, nrhs);
     const int wg = plan->tune.workgroups > 0 ? plan->tune.workgroups : wg_default;
     const int64_t limit_us = plan->tune.spin_limit_us > 0 ? plan->tune.spin_limit_us : 2000000;
@@ -476,8 +487,20 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
     const size_t stride = (size_t)plan->n * nrhs;
     const DevMatrix m = plan->matrix();
     const int seg = plan->tune.seg_powers > 0 ? plan->tune.seg_powers : kMaxSegPowers;
+    if (na) {  // the caller's status word reports this run only: 0 until a wait fails
+        for (int base = 0; base < p; base += seg)
+            if (!plan->scheds.count(std::min(seg, p - base)))
+                return fail(MPK_EINVAL,
+                            "no schedule for this p: call mpk_plan_prepare(plan, p, nrhs) first");
+        int32_t *b = na->scratch;
+        const DevWorkspace w0{b, b, b + kMaxQueues, b + kMaxQueues + 1, na->status};
+        int rc = launch_reset(w0, 0, stream, true);
+        if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
+    }
     for (int base = 0; base < p; base += seg) {
         const int ps = std::min(seg, p - base);
+        if (na && !plan->scheds.count(ps))
+            return fail(MPK_EINVAL, "no schedule for this p: call mpk_plan_prepare(plan, p, nrhs) first");
         if (capturing && !plan->scheds.count(ps))  // building one would copy synchronously
             return fail(MPK_EINVAL,
                         "no schedule for this p: call mpk_plan_prepare or run once outside capture first");
@@ -519,8 +542,8 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
         }
         const AccCoefs *acp = poly ? &ac : nullptr;
         SliceSet *ss = nullptr;
-        if (capturing && !se->slices.count(slice_nnz(kTaskKP, nrhs)))
-            return fail(MPK_EINVAL, "no slice table for this RHS count: call mpk_plan_prepare or run once outside capture first");
+        if ((capturing || na) && !se->slices.count(slice_nnz(kTaskKP, nrhs)))
+            return fail(MPK_EINVAL, "no slice table for this RHS count: call mpk_plan_prepare first");
         if ((st = task_slices(plan, se, nrhs, &ss))) return st;
         if (!se->host.step_ptr.empty()) {
             // one launch per diagonal; stream order separates the diagonals
@@ -533,13 +556,26 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
             }
             continue;
         }
+        const int32_t nc = se->host.n_chunks();
         Workspace *ws = nullptr;
-        if ((st = get_workspace(plan, se->host.n_chunks(), stream, capturing, &ws))) return st;
+        DevWorkspace wv;
+        if (na) {
+            if ((int64_t)nc + kMaxQueues + 2 > kScratchWords)
+                return fail(MPK_EUNSUPPORTED,
+                            "the schedule has " + std::to_string(nc) +
+                                " chunks; the no-allocation run holds at most " +
+                                std::to_string(kScratchWords - kMaxQueues - 2) +
+                                " (raise tune.chunk_nnz)");
+            int32_t *b = na->scratch;
+            wv = DevWorkspace{b, b + nc, b + nc + kMaxQueues, b + nc + kMaxQueues + 1, na->status};
+        } else {
+            if ((st = get_workspace(plan, nc, stream, capturing, &ws))) return st;
+            wv = ws->view(status_word(plan, stream));
+        }
         DevSchedule ds{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
                        se->dep_hi.as<int32_t>(), se->tasks.as<int32_t>(), se->host.n_tasks(),
                        se->host.n_chunks()};
-        const DevWorkspace wv = ws->view(status_word(plan, stream));
-        int rc = launch_reset(wv, se->host.n_chunks(), stream);
+        int rc = launch_reset(wv, nc, stream);
         if (rc) return hip_fail((hipError_t)rc, "reset kernel launch");
         // Without an invalidating acquire per task, an output line must
         // never be read before it is complete: the chunks must own whole
@@ -563,6 +599,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                            acquire, stream);
         }
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
+        if (na) continue;
         if (capturing) {
             ws->reserved = true;
         } else {
@@ -572,7 +609,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
             ws->last_stream = stream;
         }
     }
-    if (!capturing && (st = note_stream(plan, stream))) return st;
+    if (!capturing && !na && (st = note_stream(plan, stream))) return st;
     return MPK_OK;
 }
 
@@ -1172,6 +1209,17 @@ mpk_status_t mpk_plan_schedule_xcd(mpk_plan_t plan, int p, int32_t *dep_ptr, int
 
 mpk_status_t mpk_run(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y, void *stream) {
     return run_lb(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream);
+}
+
+mpk_status_t mpk_run_noalloc(mpk_plan_t plan, const double *x, int p, int nrhs, double *Y,
+                             int32_t *status, void *stream) {
+    mpk_status_t st = check_device_plan(plan);
+    if (st) return st;
+    int32_t *scratch = nullptr;
+    int rc = scratch_workspace(plan->device, &scratch);
+    if (rc) return hip_fail((hipError_t)rc, "hipGetSymbolAddress (scratch workspace)");
+    const NoAlloc na{scratch, status};
+    return run_lb(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream, nullptr, &na);
 }
 
 mpk_status_t mpk_run_recur(mpk_plan_t plan, const double *x, int p, int nrhs, const double *alpha,

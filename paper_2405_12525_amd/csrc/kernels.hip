@@ -24,10 +24,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "mpk_internal.h"
 
 namespace mpk {
+
+// Dependency workspace of mpk_run_noalloc (done[] | tickets | err | fail),
+// for callers that cannot allocate.  Every GPU holds its own copy until the
+// process ends; host code uses the address from scratch_workspace, never
+// this name.
+static __device__ __align__(256) int32_t scratch[kScratchWords];
 
 namespace {
 
@@ -831,11 +838,15 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_acc_kernel(XcdParams P
     xcd_body<V, RC, true>(P, cf, &ac);
 }
 
-__global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks) {
+__global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks, int clear_status) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_chunks) ws.done[i] = 0;
     if (i < kMaxQueues) ws.ticket[i] = 0;
-    if (i == 0) *ws.err = 0;
+    if (i == 0) {
+        *ws.err = 0;
+        if (clear_status && ws.status)
+            __hip_atomic_store(ws.status, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 __global__ void status_copy_kernel(int32_t *word, int32_t *out) {
@@ -1029,11 +1040,33 @@ XcdAccFn xcd_acc_fn(int value_bits, int R) {
 
 }  // namespace
 
-int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream) {
+int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream, bool clear_status) {
     const int32_t n = n_chunks > 0 ? n_chunks : 1;
     hipLaunchKernelGGL(reset_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, ws,
-                       n_chunks);
+                       n_chunks, clear_status ? 1 : 0);
     return (int)hipGetLastError();
+}
+
+int scratch_workspace(int device, int32_t **out) {
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static int32_t *addr[kDevices] = {};
+    if (device < 0 || device >= kDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return (int)e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return (int)e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        addr[device] = static_cast<int32_t *>(p);
+    }
+    *out = addr[device];
+    return 0;
 }
 
 int launch_status_copy(int32_t *status_word, int32_t *out, void *stream) {

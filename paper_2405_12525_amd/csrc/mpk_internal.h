@@ -249,8 +249,16 @@ struct DevXcdSchedule {
 };
 
 // Launchers (kernels.hip).  All return hipError_t as int.
-// Clears done[], the queue tickets and err before a run (fail and status stay).
-int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream);
+// Clears done[], the queue tickets and err before a run (fail stays; the
+// status word too unless clear_status).
+int launch_reset(const DevWorkspace &ws, int32_t n_chunks, void *stream, bool clear_status = false);
+
+// The no-allocation run's dependency workspace: a file-scope device array of
+// kScratchWords int32 (kernels.hip), one per device.  scratch_workspace
+// returns its device address on `device` (looked up once per device, with
+// that device current) as a hipError_t.
+constexpr int64_t kScratchWords = 1 << 18;   // 1 MiB: done[] of up to 262126 chunks
+int scratch_workspace(int device, int32_t **out);
 // *out = *status_word, then *status_word = 0 (one thread; out may be pinned
 // host memory).
 int launch_status_copy(int32_t *status_word, int32_t *out, void *stream);
