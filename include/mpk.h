@@ -147,6 +147,12 @@ typedef struct {
     int64_t matrix_bytes;    /* device CSR bytes: 4(n+1) + (4 + value bytes) nnz */
     double plan_ms;          /* host preprocessing time                         */
     int32_t device;
+    int32_t sliced_layout;   /* 1: the kernels read the matrix in slices of 64
+                                rows stored slot by slot (one coalesced access
+                                per slot for the 64 rows); 0: CSR rows staged
+                                through LDS (chosen when padding every slice
+                                to its longest row would add more than 25%)  */
+    int64_t sliced_entries;  /* stored slots of the sliced layout (0 if none)  */
 } mpk_plan_info_t;
 
 typedef struct {

@@ -55,7 +55,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_level_rows", ctypes.c_int32), ("value_bits", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("matrix_bytes", ctypes.c_int64),
-                ("plan_ms", ctypes.c_double), ("device", ctypes.c_int32)]
+                ("plan_ms", ctypes.c_double), ("device", ctypes.c_int32),
+                ("sliced_layout", ctypes.c_int32), ("sliced_entries", ctypes.c_int64)]
 
 
 class SchedInfo(ctypes.Structure):

@@ -117,7 +117,7 @@ mpk_status_t make_slices(const std::vector<int32_t> &rowptr, const std::vector<i
 struct SchedEntry {
     Schedule host;
     std::map<int, std::unique_ptr<SliceSet>> slices;  // by slice size (slice_nnz of the RHS count)
-    DevBuf dep_lo, dep_hi, tasks;
+    DevBuf dep_lo, dep_hi, tasks, chunk_row;
     DevBuf dep_ptr, dep_idx, qptr;  // XCD schedule
     int workgroups = 0;
 };
@@ -160,6 +160,8 @@ struct mpk_plan_s {
     bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
     // device data
     DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
+    DevBuf d_soff, d_rlen, d_scol, d_sval;   // sliced layout (empty if not built)
+    int64_t sell_entries = 0;
     std::map<int, std::unique_ptr<SliceSet>> spmv_slices;  // p x SpMV, by slice size
     // schedules and workspaces
     std::mutex mu;
@@ -175,7 +177,9 @@ struct mpk_plan_s {
 
     DevMatrix matrix() const {
         return DevMatrix{d_rowptr.as<int32_t>(), d_col.as<int32_t>(), d_val.ptr,
-                         d_outrow.as<int32_t>(), (int32_t)n, value_bits};
+                         d_outrow.as<int32_t>(), (int32_t)n, value_bits,
+                         d_soff.as<const int64_t>(), d_rlen.as<int32_t>(), d_scol.as<int32_t>(),
+                         d_sval.ptr};
     }
     ~mpk_plan_s() {
         if (!host_only) {
@@ -290,6 +294,7 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
         if ((st = e->dep_lo.upload(s.dep_lo.data(), s.dep_lo.size() * 4))) return st;
         if ((st = e->dep_hi.upload(s.dep_hi.data(), s.dep_hi.size() * 4))) return st;
         if ((st = e->tasks.upload(s.tasks.data(), s.tasks.size() * 4))) return st;
+        if ((st = e->chunk_row.upload(s.chunk_ptr.data(), s.chunk_ptr.size() * 4))) return st;
         if (!s.qptr.empty()) {
             if ((st = e->dep_ptr.upload(s.dep_ptr.data(), s.dep_ptr.size() * 4))) return st;
             if ((st = e->dep_idx.upload(s.dep_idx.data(), s.dep_idx.size() * 4))) return st;
@@ -346,6 +351,32 @@ int32_t *status_word(mpk_plan_t plan, hipStream_t stream) {
     return plan->status_words.as<int32_t>() + slot;
 }
 
+// The sliced layout of the plan's matrix, built on the device from its CSR
+// (plan row order), unless padding each slice to its longest row would add
+// more than a quarter to the stored entries (rows of uneven length: there
+// the LDS-staged slices of the CSR were measured faster).
+mpk_status_t build_sell(mpk_plan_t plan) {
+    if (plan->n == 0 || plan->nnz == 0) return MPK_OK;
+    std::vector<int32_t> width;
+    int rc = gpu_sell_widths(plan->n, plan->d_rowptr.as<int32_t>(), width);
+    if (rc) return hip_fail((hipError_t)rc, "slice widths");
+    std::vector<int64_t> off(width.size() + 1, 0);
+    for (size_t s = 0; s < width.size(); ++s) off[s + 1] = off[s] + (int64_t)width[s] * kSellRows;
+    const int64_t entries = off.back();
+    if (entries > plan->nnz + plan->nnz / 4 + (int64_t)kSellRows) return MPK_OK;
+    mpk_status_t st;
+    if ((st = plan->d_soff.upload(off.data(), off.size() * 8))) return st;
+    if ((st = plan->d_rlen.alloc((size_t)plan->n * 4))) return st;
+    if ((st = plan->d_scol.alloc((size_t)entries * 4))) return st;
+    if ((st = plan->d_sval.alloc((size_t)entries * (plan->value_bits / 8)))) return st;
+    rc = gpu_sell_fill(plan->n, plan->d_rowptr.as<int32_t>(), plan->d_col.as<int32_t>(),
+                       plan->d_val.ptr, plan->value_bits, plan->d_soff.as<const int64_t>(), entries,
+                       plan->d_rlen.as<int32_t>(), plan->d_scol.as<int32_t>(), plan->d_sval.ptr);
+    if (rc) return hip_fail((hipError_t)rc, "sliced layout");
+    plan->sell_entries = entries;
+    return MPK_OK;
+}
+
 // Device-side state every device plan holds from the start (allocated
 // outside any capture): the zeroed failure words.
 mpk_status_t init_device_state(mpk_plan_t plan) {
@@ -359,7 +390,7 @@ int default_workgroups(mpk_plan_t plan, int R) {
     const long long key = (long long)plan->value_bits * 1000 + R;
     auto it = plan->wg_cache.find(key);
     if (it != plan->wg_cache.end()) return it->second;
-    int wg = lb_max_workgroups(plan->value_bits, R, plan->device);
+    int wg = lb_max_workgroups(plan->value_bits, R, plan->device, plan->d_scol.ptr != nullptr);
     if (wg <= 0) wg = 1024;
     plan->wg_cache[key] = wg;
     return wg;
@@ -550,6 +581,7 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
             const auto &sp = se->host.step_ptr;
             for (size_t d = 0; d + 1 < sp.size(); ++d) {
                 int rc = launch_step(m, ss->view(), ss->bound_sptr.as<int32_t>(),
+                                     se->chunk_row.as<int32_t>(),
                                      se->tasks.as<int32_t>() + 2 * (size_t)sp[d], sp[d + 1] - sp[d],
                                      a, &cf, acp, stream);
                 if (rc) return hip_fail((hipError_t)rc, "step kernel launch");
@@ -572,7 +604,8 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
             if ((st = get_workspace(plan, nc, stream, capturing, &ws))) return st;
             wv = ws->view(status_word(plan, stream));
         }
-        DevSchedule ds{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_lo.as<int32_t>(),
+        DevSchedule ds{ss->view(), ss->bound_sptr.as<int32_t>(), se->chunk_row.as<int32_t>(),
+                       se->dep_lo.as<int32_t>(),
                        se->dep_hi.as<int32_t>(), se->tasks.as<int32_t>(), se->host.n_tasks(),
                        se->host.n_chunks()};
         int rc = launch_reset(wv, nc, stream);
@@ -962,6 +995,7 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         for (int64_t e2 = 0; e2 < A->nnz; e2 += step) sample.push_back(A->col[e2]);
         plan->fingerprint = fingerprint(A->n, A->nnz, o, A->rowptr, sample);
     }
+    if (!host_only && (st = build_sell(plan.get()))) return st;
     plan->plan_ms = now_ms() - t0;
     *out = plan.release();
     return MPK_OK;
@@ -1086,6 +1120,8 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
         e = hipMemcpy(rp0.data(), A->rowptr, rp0.size() * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy (row pointer)");
         plan->fingerprint = fingerprint(n, nnz, o, rp0.data(), sample);
+        mpk_status_t st2 = build_sell(plan.get());
+        if (st2) return st2;
     } catch (const std::bad_alloc &) {
         return fail(MPK_ENOMEM, "host allocation failed");
     } catch (const std::exception &ex) {
@@ -1136,6 +1172,8 @@ mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info) {
     info->matrix_bytes = 4 * (plan->n + 1) + (4 + plan->value_bits / 8) * plan->nnz;
     info->plan_ms = plan->plan_ms;
     info->device = plan->device;
+    info->sliced_layout = plan->d_scol.ptr ? 1 : 0;
+    info->sliced_entries = plan->sell_entries;
     return MPK_OK;
 }
 
@@ -1437,6 +1475,18 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     if (cus > 0) {  // one persistent workgroup per compute unit instead of two
         add(MPK_SCHED_WAVE, 64, 32768, 0, cus);
         add(MPK_SCHED_POWERS, 64, 8192, 0, cus);
+    }
+    if (cus > 0 && plan->d_scol.ptr) {
+        // sliced layout: two or four workgroups per compute unit, and a
+        // wavefront slack of 2-5 times the running workgroups per power
+        // (the default is 8 times: no waits, but a window far beyond the
+        // fast cache; smaller slack keeps the window smaller and the
+        // inputs cached, at the risk of waits that cascade)
+        for (int wpc : {2, 4})
+            for (int m : {2, 3, 5})
+                for (int chunk : {8192, 16384})
+                    add(MPK_SCHED_WAVE, 64, chunk, std::max(1, m * wpc * cus / p), wpc * cus);
+        add(MPK_SCHED_POWERS, 64, 8192, 0, 2 * cus);
     }
     if (p >= 4) add(MPK_SCHED_WAVE, 64, 32768, 0, 0, (p + 1) / 2);  // two segments
     add(MPK_SCHED_WAVE, 64, 16384, 0, 0, 0, 2);                     // park up to two tasks

@@ -453,4 +453,68 @@ int gpu_sample_cols(const int32_t *col, int64_t step, int64_t count, std::vector
     return 0;
 }
 
+namespace {
+
+// Width (longest row) of each 64-row slice.
+__global__ void sell_width_kernel(const int32_t *rowptr, int64_t n, int32_t *width) {
+    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_sl;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r1 = std::min<int64_t>(n, (s + 1) * kSellRows);
+        int32_t w = 0;
+        for (int64_t r = s * kSellRows; r < r1; ++r) w = max(w, rowptr[r + 1] - rowptr[r]);
+        width[s] = w;
+    }
+}
+
+// Entry j of row r goes to soff[r / 64] + j * 64 + r % 64; rlen[r] = length.
+template <typename V>
+__global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, const V *val,
+                                 int64_t n, const int64_t *soff, int32_t *rlen, int32_t *scol,
+                                 V *sval) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e0 = rowptr[r], L = rowptr[r + 1] - e0;
+        rlen[r] = L;
+        const int64_t base = soff[r / kSellRows] + r % kSellRows;
+        for (int32_t j = 0; j < L; ++j) {
+            scol[base + (int64_t)j * kSellRows] = col[e0 + j];
+            sval[base + (int64_t)j * kSellRows] = val[e0 + j];
+        }
+    }
+}
+
+}  // namespace
+
+int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width) {
+    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
+    width.assign((size_t)n_sl, 0);
+    if (n_sl == 0) return 0;
+    Scratch s;
+    int32_t *d;
+    MPK_TRY(s.get(&d, n_sl));
+    hipLaunchKernelGGL(sell_width_kernel, dim3(grid_for(n_sl)), dim3(kThreads), 0, 0, rowptr, n, d);
+    MPK_TRY(hipGetLastError());
+    MPK_TRY(hipMemcpy(width.data(), d, (size_t)n_sl * 4, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
+                  int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
+                  int32_t *scol, void *sval) {
+    if (n == 0) return 0;
+    MPK_TRY(hipMemset(scol, 0, (size_t)entries * 4));
+    MPK_TRY(hipMemset(sval, 0, (size_t)entries * (value_bits / 8)));
+    if (value_bits == 32)
+        hipLaunchKernelGGL(sell_fill_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+                           rowptr, col, static_cast<const float *>(val), n, soff, rlen, scol,
+                           static_cast<float *>(sval));
+    else
+        hipLaunchKernelGGL(sell_fill_kernel<double>, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+                           rowptr, col, static_cast<const double *>(val), n, soff, rlen, scol,
+                           static_cast<double *>(sval));
+    MPK_TRY(hipGetLastError());
+    return (int)hipDeviceSynchronize();
+}
+
 }  // namespace mpk

@@ -298,6 +298,55 @@ __device__ void run_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_
     }
 }
 
+// Rows [r0, r1) of one power in the sliced layout: one thread per (row,
+// right-hand side) sums its row sequentially in stored order from 0.0, U
+// slots at a time (the loads of a group are issued before its products; a
+// slot past the row end reloads the row's last entry and adds nothing).  The
+// 64 rows of a slice read each slot with one coalesced access, and the R
+// threads of a row share it.  No LDS, no barrier: idle lanes (R not dividing
+// the block) just skip.  U = 4: more waves in flight won over fewer round
+// trips per row (8 and 16 were measured slower, also for 4 to 16
+// right-hand sides).
+template <int RC>
+struct SellU {
+    static constexpr int value = 4;
+};
+constexpr int64_t kSpmvSellGrid = 4096;   // baseline workgroups per power (sliced layout)
+template <typename V, int RC, bool WT, bool ACC>
+__device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, int R_rt,
+                                         int32_t r0, int32_t r1) {
+    const int R = RC ? RC : R_rt;
+    const int rows_per_step = kBlock / R;
+    const int tid = threadIdx.x;
+    const int li = tid / R;
+    const int rr = tid - li * R;
+    if (li >= rows_per_step) return;
+    constexpr int U = SellU<RC>::value;
+    const V *sval = static_cast<const V *>(m.sval);
+    for (int32_t row = r0 + li; row < r1; row += rows_per_step) {
+        const int32_t L = m.rlen[row];
+        const int64_t base = m.soff[row / kSellRows] + row % kSellRows;
+        double s = 0.0;
+        for (int32_t j = 0; j < L; j += U) {
+            int32_t c[U];
+            double a[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = base + (int64_t)min(j + u, L - 1) * kSellRows;
+                c[u] = m.scol[q];
+                a[u] = static_cast<double>(sval[q]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = io.in[(size_t)c[u] * R + rr];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j + u < L) s = s + a[u] * xv[u];
+        }
+        const int32_t o = m.out_row ? m.out_row[row] : row;
+        finish<WT, ACC>(io, s, (size_t)o * R + rr);
+    }
+}
+
 // Products staged per thread and buffer: the slice path for R < 4 (R = 0 is
 // the generic instantiation, which takes either path at run time).
 template <int RC, int KP>
@@ -443,27 +492,52 @@ __global__ __launch_bounds__(kBlock, 2) void spmv_power_kernel(DevMatrix m, Powe
     run_slices<V, RC, Staging<RC, kSpmvKP>::value, false, ACC>(m, io, R, sl, s0, s1, sm);
 }
 
+// One power in the sliced layout: workgroup b walks row blocks b, b + grid,
+// ... of 256/R rows each.
+template <typename V, int RC, bool ACC>
+__global__ __launch_bounds__(kBlock) void spmv_sell_kernel(DevMatrix m, PowerIO io, int32_t R) {
+    const int32_t step = kBlock / (RC ? RC : R);
+    for (int32_t r0 = blockIdx.x * step; r0 < m.n; r0 += gridDim.x * step)
+        run_sell<V, RC, false, ACC>(m, io, R, r0, min(m.n, r0 + step));
+}
+
 // ------------------------------------------------------------------ level-blocked
 
 // One diagonal of the STEPS schedule: workgroup b computes task tasks[b] =
 // (chunk c, power k).  All tasks of a diagonal are independent; the previous
 // diagonals' results are visible because they ran in earlier launches.
-template <typename V, int RC, bool ACC>
+// Chunk c of one power: its slices staged through LDS, or (SELL) its rows in
+// the sliced layout.  WT: write-through result stores.
+template <typename V, int RC, bool WT, bool ACC, bool SELL>
+__device__ __forceinline__ void run_chunk(const DevMatrix &m, const PowerIO &io, int R,
+                                          DevSlices sl, const int32_t *chunk_sptr,
+                                          const int32_t *chunk_row, int32_t c) {
+    if constexpr (SELL) {
+        run_sell<V, RC, WT, ACC>(m, io, R, chunk_row[c], chunk_row[c + 1]);
+    } else {
+        __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
+        run_slices<V, RC, Staging<RC, kTaskKP>::value, WT, ACC>(m, io, R, sl, chunk_sptr[c],
+                                                                chunk_sptr[c + 1], sm);
+    }
+}
+
+template <typename V, int RC, bool ACC, bool SELL>
 __device__ __forceinline__ void step_body(const DevMatrix &m, DevSlices sl,
-                                          const int32_t *chunk_sptr, const int32_t *tasks,
-                                          const SegArgs &a, const Coefs &cf, const AccCoefs *ac) {
-    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
+                                          const int32_t *chunk_sptr, const int32_t *chunk_row,
+                                          const int32_t *tasks, const SegArgs &a, const Coefs &cf,
+                                          const AccCoefs *ac) {
     const int32_t c = tasks[2 * blockIdx.x];
     const int32_t k = tasks[2 * blockIdx.x + 1];
-    run_slices<V, RC, Staging<RC, kTaskKP>::value, false, ACC>(
-        m, power_io<ACC>(a, cf, ac, k, m.n), a.R, sl, chunk_sptr[c], chunk_sptr[c + 1], sm);
+    run_chunk<V, RC, false, ACC, SELL>(m, power_io<ACC>(a, cf, ac, k, m.n), a.R, sl, chunk_sptr,
+                                       chunk_row, c);
 }
 
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void step_kernel(DevMatrix m, DevSlices sl,
                                                      const int32_t *chunk_sptr,
+                                                     const int32_t *chunk_row,
                                                      const int32_t *tasks, SegArgs a, Coefs cf) {
-    step_body<V, RC, false>(m, sl, chunk_sptr, tasks, a, cf, nullptr);
+    step_body<V, RC, false, false>(m, sl, chunk_sptr, chunk_row, tasks, a, cf, nullptr);
 }
 
 // The same with weighted sums (a separate kernel, so that the plain one
@@ -471,9 +545,29 @@ __global__ __launch_bounds__(kBlock, kTaskWaves) void step_kernel(DevMatrix m, D
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void step_acc_kernel(DevMatrix m, DevSlices sl,
                                                          const int32_t *chunk_sptr,
+                                                         const int32_t *chunk_row,
                                                          const int32_t *tasks, SegArgs a,
                                                          Coefs cf, AccCoefs ac) {
-    step_body<V, RC, true>(m, sl, chunk_sptr, tasks, a, cf, &ac);
+    step_body<V, RC, true, false>(m, sl, chunk_sptr, chunk_row, tasks, a, cf, &ac);
+}
+
+// Sliced-layout forms (no LDS, so more workgroups fit a compute unit).
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock) void step_sell_kernel(DevMatrix m, DevSlices sl,
+                                                           const int32_t *chunk_sptr,
+                                                           const int32_t *chunk_row,
+                                                           const int32_t *tasks, SegArgs a,
+                                                           Coefs cf) {
+    step_body<V, RC, false, true>(m, sl, chunk_sptr, chunk_row, tasks, a, cf, nullptr);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock) void step_sell_acc_kernel(DevMatrix m, DevSlices sl,
+                                                               const int32_t *chunk_sptr,
+                                                               const int32_t *chunk_row,
+                                                               const int32_t *tasks, SegArgs a,
+                                                               Coefs cf, AccCoefs ac) {
+    step_body<V, RC, true, true>(m, sl, chunk_sptr, chunk_row, tasks, a, cf, &ac);
 }
 
 struct LBParams {
@@ -502,15 +596,14 @@ __device__ __forceinline__ bool inputs_ready(const LBParams &P, int32_t t) {
 // Persistent kernel: workgroups take tasks (chunk c, power k) in schedule
 // order from a shared ticket counter.  Before computing, a task waits until
 // every chunk in [dep_lo[c], dep_hi[c]] has completed power k-1 and then
-// invalidates its caches (acquire); it computes with write-through stores and
-// publishes done[c] = k once they have completed.  Dependencies always carry smaller
-// tickets and a workgroup holds one ticket at a time, so the smallest
-// unfinished ticket can always proceed; every wait is also bounded by
-// spin_limit, after which the run is flagged as failed and all workgroups
-// leave.
-template <typename V, int RC, bool ACC>
+// invalidates its caches (acquire) where needed; it computes with
+// write-through stores and publishes done[c] = k once they have completed.
+// Dependencies always carry smaller tickets and a workgroup holds one ticket
+// at a time, so the smallest unfinished ticket can always proceed; every
+// wait is also bounded by spin_limit, after which the run is flagged as
+// failed and all workgroups leave.
+template <typename V, int RC, bool ACC, bool SELL>
 __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, const AccCoefs *ac) {
-    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
@@ -564,13 +657,15 @@ __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, cons
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
         if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
-        run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
-            P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
-            P.s.chunk_sptr[c + 1], sm);
+        run_chunk<V, RC, true, ACC, SELL>(P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R,
+                                          P.s.sl, P.s.chunk_sptr, P.s.chunk_row, c);
         // The results were stored write-through; every wave waits until its
         // stores have completed (vmcnt = 0) before the barrier, so the chunk
         // is visible device-wide when the flag below is published and the
-        // next ticket is taken.  No L2 write-back is needed.
+        // next ticket is taken.  No L2 write-back is needed.  (Taking the
+        // next ticket before computing, to overlap its round trip, was
+        // measured slower: it doubles the tickets in flight, and tasks then
+        // wait more often on inputs that are still being computed.)
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters untouched
         __syncthreads();
         if (tid == 0) {
@@ -586,13 +681,27 @@ __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, cons
 
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void lb_kernel(LBParams P, Coefs cf) {
-    lb_body<V, RC, false>(P, cf, nullptr);
+    lb_body<V, RC, false, false>(P, cf, nullptr);
 }
 
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void lb_acc_kernel(LBParams P, Coefs cf,
                                                                     AccCoefs ac) {
-    lb_body<V, RC, true>(P, cf, &ac);
+    lb_body<V, RC, true, false>(P, cf, &ac);
+}
+
+// Sliced-layout forms: no LDS, built for up to kSellWaves workgroups per
+// compute unit.
+constexpr int kSellWaves = 8;
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kSellWaves) void lb_sell_kernel(LBParams P, Coefs cf) {
+    lb_body<V, RC, false, true>(P, cf, nullptr);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kSellWaves) void lb_sell_acc_kernel(LBParams P, Coefs cf,
+                                                                         AccCoefs ac) {
+    lb_body<V, RC, true, true>(P, cf, &ac);
 }
 
 constexpr int kMaxPending = 8;
@@ -948,11 +1057,13 @@ __global__ __launch_bounds__(kBlock) void load_probe_local_kernel(const double2 
 // ------------------------------------------------------------------ dispatch
 
 using SpmvFn = void (*)(DevMatrix, PowerIO, int32_t, DevSlices, int32_t, int32_t);
+using SpmvSellFn = void (*)(DevMatrix, PowerIO, int32_t);
 using LbFn = void (*)(LBParams, Coefs);
 using LbAccFn = void (*)(LBParams, Coefs, AccCoefs);
-using StepFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *, SegArgs, Coefs);
-using StepAccFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *, SegArgs, Coefs,
-                           AccCoefs);
+using StepFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *, const int32_t *,
+                        SegArgs, Coefs);
+using StepAccFn = void (*)(DevMatrix, DevSlices, const int32_t *, const int32_t *,
+                           const int32_t *, SegArgs, Coefs, AccCoefs);
 using XcdFn = void (*)(XcdParams, Coefs);
 using XcdAccFn = void (*)(XcdParams, Coefs, AccCoefs);
 
@@ -972,22 +1083,29 @@ int r_index(int R) {
 template <typename V>
 struct VTable {
     SpmvFn spmv[6], spmv_acc[6];
-    LbFn lb[6], lbs[6];
-    LbAccFn lb_acc[6], lbs_acc[6];
-    StepFn step[6];
-    StepAccFn step_acc[6];
+    SpmvSellFn spmv_sell[6], spmv_sell_acc[6];
+    LbFn lb[6], lbs[6], lb_sell[6];
+    LbAccFn lb_acc[6], lbs_acc[6], lb_sell_acc[6];
+    StepFn step[6], step_sell[6];
+    StepAccFn step_acc[6], step_sell_acc[6];
     XcdFn xcd[6];
     XcdAccFn xcd_acc[6];
     template <int RC>
     void fill(int i) {
         spmv[i] = spmv_power_kernel<V, RC, false>;
         spmv_acc[i] = spmv_power_kernel<V, RC, true>;
+        spmv_sell[i] = spmv_sell_kernel<V, RC, false>;
+        spmv_sell_acc[i] = spmv_sell_kernel<V, RC, true>;
         lb[i] = lb_kernel<V, RC>;
         lb_acc[i] = lb_acc_kernel<V, RC>;
+        lb_sell[i] = lb_sell_kernel<V, RC>;
+        lb_sell_acc[i] = lb_sell_acc_kernel<V, RC>;
         lbs[i] = lbs_kernel<V, RC>;
         lbs_acc[i] = lbs_acc_kernel<V, RC>;
         step[i] = step_kernel<V, RC>;
         step_acc[i] = step_acc_kernel<V, RC>;
+        step_sell[i] = step_sell_kernel<V, RC>;
+        step_sell_acc[i] = step_sell_acc_kernel<V, RC>;
         xcd[i] = xcd_kernel<V, RC>;
         xcd_acc[i] = xcd_acc_kernel<V, RC>;
     }
@@ -1015,21 +1133,38 @@ SpmvFn spmv_fn(int value_bits, int R, bool acc) {
     if (value_bits == 32) return acc ? t32().spmv_acc[i] : t32().spmv[i];
     return acc ? t64().spmv_acc[i] : t64().spmv[i];
 }
-LbFn lb_fn(int value_bits, int R, bool skip) {
+SpmvSellFn spmv_sell_fn(int value_bits, int R, bool acc) {
     const int i = r_index(R);
-    if (value_bits == 32) return skip ? t32().lbs[i] : t32().lb[i];
-    return skip ? t64().lbs[i] : t64().lb[i];
+    if (value_bits == 32) return acc ? t32().spmv_sell_acc[i] : t32().spmv_sell[i];
+    return acc ? t64().spmv_sell_acc[i] : t64().spmv_sell[i];
 }
-LbAccFn lb_acc_fn(int value_bits, int R, bool skip) {
+// skip: the skip-ahead kernel (LDS-staged rows); else sell picks the
+// sliced-layout kernel
+LbFn lb_fn(int value_bits, int R, bool skip, bool sell) {
+    const VTable<double> &a = t64();
+    const VTable<float> &b = t32();
     const int i = r_index(R);
-    if (value_bits == 32) return skip ? t32().lbs_acc[i] : t32().lb_acc[i];
-    return skip ? t64().lbs_acc[i] : t64().lb_acc[i];
+    if (skip) return value_bits == 32 ? b.lbs[i] : a.lbs[i];
+    if (sell) return value_bits == 32 ? b.lb_sell[i] : a.lb_sell[i];
+    return value_bits == 32 ? b.lb[i] : a.lb[i];
 }
-StepFn step_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().step[r_index(R)] : t64().step[r_index(R)];
+LbAccFn lb_acc_fn(int value_bits, int R, bool skip, bool sell) {
+    const VTable<double> &a = t64();
+    const VTable<float> &b = t32();
+    const int i = r_index(R);
+    if (skip) return value_bits == 32 ? b.lbs_acc[i] : a.lbs_acc[i];
+    if (sell) return value_bits == 32 ? b.lb_sell_acc[i] : a.lb_sell_acc[i];
+    return value_bits == 32 ? b.lb_acc[i] : a.lb_acc[i];
 }
-StepAccFn step_acc_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().step_acc[r_index(R)] : t64().step_acc[r_index(R)];
+StepFn step_fn(int value_bits, int R, bool sell) {
+    const int i = r_index(R);
+    if (sell) return value_bits == 32 ? t32().step_sell[i] : t64().step_sell[i];
+    return value_bits == 32 ? t32().step[i] : t64().step[i];
+}
+StepAccFn step_acc_fn(int value_bits, int R, bool sell) {
+    const int i = r_index(R);
+    if (sell) return value_bits == 32 ? t32().step_sell_acc[i] : t64().step_sell_acc[i];
+    return value_bits == 32 ? t32().step_acc[i] : t64().step_acc[i];
 }
 XcdFn xcd_fn(int value_bits, int R) {
     return value_bits == 32 ? t32().xcd[r_index(R)] : t64().xcd[r_index(R)];
@@ -1097,38 +1232,48 @@ int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_
         io.fa = acc->fa;
         io.fb = acc->fb;
     }
+    if (m.scol) {  // sliced layout: row blocks of 256 / R rows, grid-stride
+        const int64_t nblk = ((int64_t)m.n + kBlock / R - 1) / (kBlock / R);
+        const int64_t grid = std::min<int64_t>(nblk, kSpmvSellGrid);
+        hipLaunchKernelGGL(spmv_sell_fn(m.value_bits, R, acc != nullptr), dim3((unsigned)grid),
+                           dim3(kBlock), 0, (hipStream_t)stream, m, io, R);
+        return (int)hipGetLastError();
+    }
     const int32_t grid = (n_slices + per - 1) / per;
     hipLaunchKernelGGL(spmv_fn(m.value_bits, R, acc != nullptr), dim3((unsigned)grid), dim3(kBlock), 0,
                        (hipStream_t)stream, m, io, R, sl, n_slices, per);
     return (int)hipGetLastError();
 }
 
-int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
-                int32_t n_tasks, const SegArgs &a, const Coefs *cf, const AccCoefs *acc,
-                void *stream) {
+int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr,
+                const int32_t *chunk_row, const int32_t *tasks, int32_t n_tasks,
+                const SegArgs &a, const Coefs *cf, const AccCoefs *acc, void *stream) {
     if (a.R < 1 || a.R > 16 || a.p < 1 || a.p > kMaxSegPowers) return (int)hipErrorInvalidValue;
     if (n_tasks <= 0) return 0;
     Coefs c{};
     if (cf) c = *cf;
+    const bool sell = m.scol != nullptr;
     if (acc)
-        hipLaunchKernelGGL(step_acc_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock),
-                           0, (hipStream_t)stream, m, sl, chunk_sptr, tasks, a, c, *acc);
+        hipLaunchKernelGGL(step_acc_fn(m.value_bits, a.R, sell), dim3((unsigned)n_tasks),
+                           dim3(kBlock), 0, (hipStream_t)stream, m, sl, chunk_sptr, chunk_row,
+                           tasks, a, c, *acc);
     else
-        hipLaunchKernelGGL(step_fn(m.value_bits, a.R), dim3((unsigned)n_tasks), dim3(kBlock), 0,
-                           (hipStream_t)stream, m, sl, chunk_sptr, tasks, a, c);
+        hipLaunchKernelGGL(step_fn(m.value_bits, a.R, sell), dim3((unsigned)n_tasks), dim3(kBlock),
+                           0, (hipStream_t)stream, m, sl, chunk_sptr, chunk_row, tasks, a, c);
     return (int)hipGetLastError();
 }
 
-int lb_max_workgroups(int value_bits, int R, int device) {
+int lb_max_workgroups(int value_bits, int R, int device, bool sell) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(lb_fn(value_bits, R, false)), kBlock, 0) !=
-        hipSuccess)
+            &per_cu, reinterpret_cast<const void *>(lb_fn(value_bits, R, false, sell)), kBlock,
+            0) != hipSuccess)
         return 0;
-    // At most kTaskWaves workgroups per CU even where registers and LDS would
-    // allow more (the unstaged path for R >= 4): more persistent workgroups
-    // only add ticket and flag traffic and were measured 2-3x slower.
-    per_cu = std::min(per_cu, kTaskWaves);
+    // LDS-staged rows: at most kTaskWaves workgroups per CU even where
+    // registers and LDS would allow more (the unstaged path for R >= 4): more
+    // persistent workgroups only added ticket and flag traffic and were
+    // measured 2-3x slower.  Sliced layout: at most four.
+    per_cu = std::min(per_cu, sell ? 4 : kTaskWaves);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
     return per_cu * prop.multiProcessorCount;
@@ -1144,12 +1289,13 @@ int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
     LBParams P{m, s, ws, a, spin_limit, pending, acquire ? 1 : 0};
     Coefs c{};
     if (cf) c = *cf;
+    const bool sell = m.scol != nullptr;
     if (acc)
-        hipLaunchKernelGGL(lb_acc_fn(m.value_bits, a.R, pending > 0), dim3(workgroups),
+        hipLaunchKernelGGL(lb_acc_fn(m.value_bits, a.R, pending > 0, sell), dim3(workgroups),
                            dim3(kBlock), 0, (hipStream_t)stream, P, c, *acc);
     else
-        hipLaunchKernelGGL(lb_fn(m.value_bits, a.R, pending > 0), dim3(workgroups), dim3(kBlock),
-                           0, (hipStream_t)stream, P, c);
+        hipLaunchKernelGGL(lb_fn(m.value_bits, a.R, pending > 0, sell), dim3(workgroups),
+                           dim3(kBlock), 0, (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
 }
 

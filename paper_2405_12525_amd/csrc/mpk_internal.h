@@ -73,6 +73,20 @@ int gpu_copy_in_place_order(int64_t n, int64_t nnz, const int32_t *rowptr, const
                             int32_t *out_col, void *out_val, std::vector<int32_t> &h_rowptr,
                             std::vector<int32_t> &row_lo, std::vector<int32_t> &row_hi);
 int gpu_sample_cols(const int32_t *col, int64_t step, int64_t count, std::vector<int32_t> &out);
+
+// Sliced layout of the plan's matrix (the kernels' row routine for plain
+// rows): rows in slices of kSellRows; slice s holds width[s] slots (its
+// longest row) stored slot-major, entry j of row r at soff[r / 64] + j * 64 +
+// r % 64, so that the 64 rows of a slice read slot j with one coalesced
+// access.  Slots past a row's length are padding and never read.
+constexpr int kSellRows = 64;
+// gpu_sell_widths: width of every slice (host copy).  gpu_sell_fill: rlen[n]
+// and the slotted columns and values (value_bits 64 or 32, like val) into
+// buffers of `entries` = soff[n_slices] slots.
+int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width);
+int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
+                  int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
+                  int32_t *scol, void *sval);
 // Levels from far[] (order_levels' rule): level 0 = row 0, level j+1 ends
 // just past the farthest neighbour of level j.
 Levels levels_from_far(int64_t n, const std::vector<int32_t> &far);
@@ -132,6 +146,11 @@ struct DevMatrix {
     const int32_t *out_row;   // nullptr: output row = plan row
     int32_t n;
     int32_t value_bits;
+    // the sliced layout (null when the plan has none: too much padding)
+    const int64_t *soff;      // n_slices + 1 slot offsets
+    const int32_t *rlen;      // n row lengths
+    const int32_t *scol;      // slotted columns
+    const void *sval;         // slotted values (double or float)
 };
 
 constexpr int kMaxSegPowers = 64;   // powers per kernel launch
@@ -220,6 +239,7 @@ struct AccStep {
 struct DevSchedule {
     DevSlices sl;
     const int32_t *chunk_sptr;   // n_chunks + 1 slice offsets
+    const int32_t *chunk_row;    // n_chunks + 1 plan rows (sliced layout)
     const int32_t *dep_lo, *dep_hi;
     const int32_t *tasks;
     int32_t n_tasks, n_chunks;
@@ -271,9 +291,9 @@ int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
               int64_t spin_limit, int pending, int acquire, void *stream);
 // One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
-int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr, const int32_t *tasks,
-                int32_t n_tasks, const SegArgs &a, const Coefs *cf, const AccCoefs *acc,
-                void *stream);
+int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr,
+                const int32_t *chunk_row, const int32_t *tasks, int32_t n_tasks,
+                const SegArgs &a, const Coefs *cf, const AccCoefs *acc, void *stream);
 // One power over all rows; workgroup b walks slices [b*per, (b+1)*per).
 // acc may be null (no weighted sums).
 int launch_spmv_power(const DevMatrix &m, DevSlices sl, int32_t n_slices, int32_t per,
@@ -299,7 +319,9 @@ int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &
 // XCDs of the device when workgroup i runs on XCD i mod n (checked with a probe
 // kernel), else 1.
 int detect_xcds(int device);
-// Max co-resident persistent workgroups of the level-blocked kernel.
-int lb_max_workgroups(int value_bits, int R, int device);
+// Default persistent workgroups of the level-blocked kernel: what fits,
+// capped at two per compute unit for the LDS-staged routine and four for the
+// sliced layout (sell).
+int lb_max_workgroups(int value_bits, int R, int device, bool sell);
 
 }  // namespace mpk

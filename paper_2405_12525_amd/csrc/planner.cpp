@@ -570,10 +570,11 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
 
     // 2. chunks.  The persistent wavefront and power-order schedules track
     // dependencies per chunk and need no group structure: their chunks are
-    // cut at about chunk_nnz nonzeros on multiples of kLineRows rows (a chunk
+    // cut at about chunk_nnz nonzeros on multiples of kSellRows rows (a chunk
     // may span a group boundary; chunk_group is the group of its first row),
     // so that each 128-byte line of an output vector belongs to one chunk
-    // (line_closed).  The diagonal schedules cut every group on its own.
+    // (line_closed) and chunks hold whole slices of the sliced layout.  The
+    // diagonal schedules cut every group on its own.
     s.chunk_ptr.push_back(0);
     const bool aligned = tune.schedule == MPK_SCHED_WAVE || tune.schedule == MPK_SCHED_POWERS;
     if (aligned) {
@@ -588,8 +589,8 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
             int64_t e = std::upper_bound(rp.begin() + r + 1, rp.begin() + n + 1, (int32_t)lim) -
                         rp.begin() - 1;
             e = std::min<int64_t>(e, r + 65536);
-            e -= e % kLineRows;
-            if (e <= r) e = r + kLineRows;  // at least one block of lines
+            e -= e % kSellRows;
+            if (e <= r) e = r + kSellRows;  // at least one slice
             e = std::min<int64_t>(e, n);
             while (lev + 1 < n_levels && lp[lev + 1] <= r) ++lev;
             s.chunk_ptr.push_back((int32_t)e);

@@ -96,7 +96,8 @@ def loops_with_barrier_and_divergent_exit(lines):
     return bad
 
 
-@pytest.mark.parametrize("name", ["lb_kernel", "lb_acc_kernel"])
+@pytest.mark.parametrize("name", ["lb_kernel", "lb_acc_kernel", "lb_sell_kernel",
+                                  "lb_sell_acc_kernel"])
 def test_task_loop_has_uniform_exit(asm, name):
     ks = kernels(asm, name)
     assert len(ks) == 12  # 6 right-hand-side variants x 2 value types
@@ -118,6 +119,25 @@ def test_baseline_row_loop_has_uniform_exit(asm):
     assert len(ks) == 24  # with and without the weighted sums
     for sym, lines in ks.items():
         assert loops_with_barrier_and_divergent_exit(lines) == [], sym
+
+
+def test_sliced_layout_kernels_need_no_lds():
+    """The sliced-layout kernels hold no LDS, so that their occupancy is set
+    by registers alone (up to eight waves per SIMD)."""
+    import subprocess
+    out = subprocess.run(
+        [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+         "-target-feature", "-Xclang", "-packed-fp32-ops", "-c", f"-I{ROOT}/include",
+         f"-I{ROOT}/paper_2405_12525_amd/csrc", "-Rpass-analysis=kernel-resource-usage",
+         "--cuda-device-only", "-o", os.devnull, SRC], capture_output=True, text=True).stderr
+    names = re.findall(r"Function Name: (\S+)", out)
+    lds = re.findall(r"LDS Size \[bytes/block\]: (\d+)", out)
+    assert len(names) == len(lds) > 0
+    sell = [(n, int(b)) for n, b in zip(names, lds)
+            if "sell_kernel" in n or "sell_acc_kernel" in n]
+    assert len(sell) >= 4 * 12
+    for n, b in sell:
+        assert b <= 64, n   # the ticket and status words of the persistent kernels
 
 
 def _instructions_with_loop_flag(lines):
@@ -159,7 +179,8 @@ def _publish_ok(lines):
 
 
 @pytest.mark.parametrize("name", ["lb_kernel", "xcd_kernel", "lbs_kernel", "lb_acc_kernel",
-                                  "xcd_acc_kernel", "lbs_acc_kernel"])
+                                  "xcd_acc_kernel", "lbs_acc_kernel", "lb_sell_kernel",
+                                  "lb_sell_acc_kernel"])
 def test_results_write_through_and_publish_after_completion(asm, name):
     for sym, lines in kernels(asm, name).items():
         body = [l.strip() for l in lines if l.strip() and not l.strip().startswith(";")]
