@@ -11,15 +11,18 @@ resident in HBM.  Prints ONE JSON line on stdout (progress goes to stderr).
 The level-blocked run uses the plan's autotuned schedule (BFS and original
 order are both tried; the faster is reported).  A serving session on the
 six-matrix pool (2D/3D stencils and Anderson lattices, N from 1e4 to 4.1e6)
-replays 512 Poisson arrivals at 0.7 x the measured saturated request rate and
-reports p50/p99 latency next to throughput.
+measures the saturated request rate, then replays 512 Poisson arrivals at a
+fixed rate (--serve-rate) and reports p50/p99 latency overall and per matrix.
+With the CPU leg on, each power of the headline result is compared with the
+FP64 oracle.
 
 The roofline object describes the level-blocked run: algorithmic bytes
 (matrix once, x once, p output vectors; see algorithmic_bytes) divided by
 the mean duration of one run, measured with HIP events recorded on the
-stream the kernels are launched on.  Measured HBM traffic is taken from the
-committed counter summary when it was recorded for the current kernel
-source (same SHA-256), else reported as null.
+stream the kernels are launched on.  Measured traffic (bytes at L2 egress,
+which include Infinity Cache hits) is taken from the committed counter
+summary when it was recorded for the current kernel source (same SHA-256)
+and the same tuning, else reported as null.
 """
 from __future__ import annotations
 
@@ -72,6 +75,16 @@ def algorithmic_bytes(n, nnz, p, R, value_bytes, kind, perm_rows=0):
     return A + V + p * V + perm_rows * 4
 
 
+def per_power_rel_err(got, ref):
+    """Relative error of each power against the FP64 oracle: for power k the
+    largest, over right-hand sides, of ||got_k - ref_k||_2 / ||ref_k||_2."""
+    import numpy as np
+    p, R = ref.shape[0], ref.shape[-1]
+    num = np.linalg.norm((got - ref).reshape(p, -1, R), axis=1)
+    den = np.linalg.norm(ref.reshape(p, -1, R), axis=1)
+    return [float(v) for v in np.max(num / np.where(den > 0, den, 1.0), axis=1)]
+
+
 def time_calls(fn, steps, warmup, torch, stream):
     """Per-call durations from events recorded on `stream` (the launch stream)."""
     with torch.cuda.stream(stream):
@@ -94,10 +107,11 @@ def time_calls(fn, steps, warmup, torch, stream):
                 total_ms=sum(ms), wall_s=wall)
 
 
-def measured_traffic(workload, vb, kernel_key):
-    """HBM bytes per run from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE per dispatch, scaled by what the same counters read for a 1 GiB
-    copy), if it was taken for the current kernel source and this tuning."""
+def measured_traffic(workload, vb, run_key):
+    """Bytes per run at L2 egress from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same counters
+    read for a 1 GiB copy), if it was taken for the current kernel source and
+    this tuning; else None."""
     try:
         with open(TRAFFIC_FILE.format(workload=workload, vb=vb)) as f:
             t = json.load(f)
@@ -105,26 +119,36 @@ def measured_traffic(workload, vb, kernel_key):
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if t.get("kernels_sha256") != sha or kernel_key not in t.get("runs", {}):
+    run = t.get("runs", {}).get(run_key)
+    if t.get("kernels_sha256") != sha or not run:
         return None
-    return t["runs"][kernel_key]["hbm_bytes_per_run"]
+    return run.get("l2_egress_bytes_per_run")
 
 
-def serving(torch, mpk, w, n_requests=512):
-    """Saturated rate first (all requests at t=0), then Poisson arrivals at 0.7x it.
-    Each pool plan is autotuned once (p = 16, 4 RHS) before serving."""
+def serving(torch, mpk, w, rates, n_requests=512):
+    """The saturated rate first (all requests at t = 0), then Poisson arrivals
+    at each fixed rate in `rates` (the first is reported at the top level).
+    Each pool plan is autotuned once (p = 16, 4 RHS) and serves through the
+    level-blocked or the p x SpMV kernels, whichever was faster at that shape
+    (the results are the same bit for bit); one stream per matrix."""
     from paper_2405_12525_amd import serve
     t0 = time.perf_counter()
     specs = w.serving_pool_specs()
     mats = [w.build_pool_matrix(s) for s in specs]
     plans = [mpk.Plan(A) for A in mats]
-    # one autotuning per plan at a representative request shape (p = 16, 4 RHS)
+    use_base = []
+    stream = torch.cuda.Stream()
     for P in plans:
         xt = torch.rand((P.n, 4), device="cuda", dtype=torch.float64)
-        P.autotune(xt, 16, reps=2)
-        del xt
+        Yt = torch.empty((16, P.n, 4), device="cuda", dtype=torch.float64)
+        lb_ms = P.autotune(xt, 16, Yt, reps=2, stream=stream)["ms"]
+        tr_ms = time_calls(lambda: P.run_baseline(xt, 16, Yt, stream=stream), 3, 1, torch,
+                           stream)["mean_ms"]
+        use_base.append(tr_ms < lb_ms)
+        del xt, Yt
     log(f"[bench] serving pool ready in {time.perf_counter() - t0:.1f}s: "
         + ", ".join(f"{k}{sz} n={A.n}" for (k, sz), A in zip(specs, mats)))
+    names = [f"{k}{sz}" for k, sz in specs]
 
     def requests(rate):
         reqs = []
@@ -136,38 +160,54 @@ def serving(torch, mpk, w, n_requests=512):
             reqs.append(serve.Request(id=s["id"], arrival=s["t"], matrix=s["matrix"], p=s["p"], x=x))
         return reqs
 
-    srv = serve.Server(plans, n_streams=4)
+    def paced(st, rate):
+        return {"rate_rps": round(rate, 1), "p50_ms": round(st["p50_ms"], 3),
+                "p99_ms": round(st["p99_ms"], 3), "throughput_rps": round(st["throughput_rps"], 1),
+                "gflops": round(st["gflops"], 1), "mean_batch": round(st["mean_batch"], 2),
+                "by_matrix": {names[m]: {"n": v["n"], "requests": v["requests"],
+                                         "p50_ms": round(v["p50_ms"], 3),
+                                         "p99_ms": round(v["p99_ms"], 3)}
+                              for m, v in st["by_matrix"].items()}}
+
+    srv = serve.Server(plans, n_streams=len(plans), use_baseline=use_base)
     warm = requests(1000.0)[:24]
     srv.serve(warm, realtime=False, keep=False)
     reqs = requests(1000.0)
     sat = serve.summarize(srv.serve(reqs, realtime=False, keep=False), reqs, plans)
-    rate = 0.7 * sat["throughput_rps"]
     del reqs
-    reqs = requests(rate)
-    res = srv.serve(reqs, realtime=True, keep=False)
-    st = serve.summarize(res, reqs, plans)
-    del res, reqs
+    runs = []
+    for rate in rates:
+        reqs = requests(rate)
+        res = srv.serve(reqs, realtime=True, keep=False)
+        st = serve.summarize(res, reqs, plans)
+        del res, reqs
+        log(f"[bench] serving at {rate:.0f} req/s: p50 {st['p50_ms']:.2f} ms p99 "
+            f"{st['p99_ms']:.2f} ms, mean batch {st['mean_batch']:.2f}")
+        runs.append(paced(st, rate))
     for P in plans:
         P.close()
-    log(f"[bench] serving: saturated {sat['throughput_rps']:.0f} req/s; at {rate:.0f} req/s "
-        f"p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms")
-    return {"requests": n_requests, "rate_rps": round(rate, 1),
-            "rate_rule": "0.7 x saturated throughput", "p50_ms": round(st["p50_ms"], 3),
-            "p99_ms": round(st["p99_ms"], 3), "throughput_rps": round(st["throughput_rps"], 1),
-            "gflops": round(st["gflops"], 1), "mean_batch": round(st["mean_batch"], 2),
-            "saturated_rps": round(sat["throughput_rps"], 1),
-            "saturated_gflops": round(sat["gflops"], 1)}
+    log(f"[bench] serving: saturated {sat['throughput_rps']:.0f} req/s")
+    out = {"requests": n_requests, "rate_rule": "fixed (--serve-rate)", **runs[0],
+           "kernels": {names[m]: "p x SpMV" if b else "level-blocked"
+                       for m, b in enumerate(use_base)},
+           "streams": len(plans), "max_inflight_per_matrix": 1,
+           "saturated_rps": round(sat["throughput_rps"], 1),
+           "saturated_gflops": round(sat["gflops"], 1),
+           "saturated_mean_batch": round(sat["mean_batch"], 2)}
+    if len(runs) > 1:
+        out["other_rates"] = runs[1:]
+    return out
 
 
-def other_configs(torch, mpk, w, steps, warmup, stream):
+def other_configs(torch, mpk, w, steps, warmup, stream, with_oracle):
     """The banded random matrix (FP64 and FP32 values, p = 6), the Anderson
     lattice (Chebyshev p = 16, 8 RHS, FP32 values) and a 64^3 27-point
     stencil with 16 RHS (p = 16): autotuned level-blocked run vs p x SpMV in
-    the faster order, and the largest per-power relative error of the result
-    against the FP64 oracle."""
-    import numpy as np
-    import oracle
+    the faster order.  With the CPU leg on (with_oracle), also each power's
+    relative error against the FP64 oracle (the larger of the two orders)."""
     out = {}
+    if with_oracle:
+        import oracle
     for name, vbs in (("banded_4m_p6", (64, 32)), ("anderson160_cheb16_r8", (32,)),
                       ("stencil3d27_64_p16_r16", (64,))):
         A, x, p, kind = w.config(name)
@@ -175,7 +215,9 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
         xd = torch.from_numpy(x).cuda()
         cheb = kind == "chebyshev"
         coefs = mpk.chebyshev_coefficients(p) if cheb else None
-        ref = oracle.recur(A, x, *coefs) if cheb else oracle.powers(A, x, p)
+        ref = None
+        if with_oracle:
+            ref = oracle.recur(A, x, *coefs) if cheb else oracle.powers(A, x, p)
         flop = mpk.flops(A.nnz, A.n, p, R, recur=cheb)
         extra_v = p - 1 if cheb else 0   # y_{k-1} read again by the recurrence (powers 2..p)
         Y = torch.empty((p, A.n, R), dtype=torch.float64, device="cuda")
@@ -193,15 +235,12 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
                 tq = P.autotune(xd, p, Y, reps=3, recur=cheb, stream=stream)
                 lb = time_calls(lbf, steps, warmup, torch, stream)["median_ms"]
                 P.sync()
-                got = Y.cpu().numpy()
-                num = np.linalg.norm((got - ref).reshape(p, -1, R), axis=1)
-                den = np.linalg.norm(ref.reshape(p, -1, R), axis=1)
-                rel = float(np.max(num / np.where(den > 0, den, 1.0)))
+                if ref is not None:
+                    rel = per_power_rel_err(Y.cpu().numpy(), ref)
+                    best["rel"] = [max(a, b) for a, b in zip(best.get("rel", rel), rel)]
                 for key, ms in (("trad", tr), ("lb", lb)):
                     if key not in best or ms < best[key][0]:
                         best[key] = (ms, ro, tq["schedule"] if key == "lb" else None)
-                best.setdefault("rel", 0.0)
-                best["rel"] = max(best["rel"], rel)
                 P.close()
             tag = f"{name}_fp{vb}"
             vbytes = 8 * A.n * R
@@ -214,7 +253,7 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
                         "pxspmv_ms": round(best["trad"][0], 4), "pxspmv_reorder": best["trad"][1],
                         "pxspmv_gflops": round(flop / best["trad"][0] / 1e6, 1),
                         "speedup_vs_pxspmv": round(best["trad"][0] / best["lb"][0], 3),
-                        "max_rel_err_vs_fp64_oracle": rel,
+                        "rel_err_per_power_vs_fp64_oracle": best.get("rel"),
                         "pxspmv_roofline": {"bound": "hbm", "algorithmic_bytes": trad_b,
                                             "achieved_GBs": round(trad_b / best["trad"][0] / 1e6, 1),
                                             "frac": round(trad_b / best["trad"][0] / 1e6 / HBM_PEAK_GBS, 4)},
@@ -222,6 +261,7 @@ def other_configs(torch, mpk, w, steps, warmup, stream):
                                         "achieved_GBs": round(lb_b / best["lb"][0] / 1e6, 1),
                                         "frac": round(lb_b / best["lb"][0] / 1e6 / HBM_PEAK_GBS, 4)},
                         "tolerance": 1e-12 if vb == 64 else 1e-5}
+            rel = max(best["rel"]) if "rel" in best else float("nan")
             log(f"[bench] {tag}: level-blocked {best['lb'][0]:.3f} ms ({best['lb'][2]}, "
                 f"{best['lb'][1]}), p x SpMV {best['trad'][0]:.3f} ms, max rel err {rel:.2e}")
         del Y, xd
@@ -336,7 +376,8 @@ def time_step(torch, mpk, w, steps, warmup, stream):
 
 def cpu_baseline(A, x, p, budget_s=20.0):
     """The CPU oracle on all host cores: whole runs of the workload, bounded in
-    time; also one core, for reference (3 runs)."""
+    time; also one core, for reference (3 runs).  Returns the summary and the
+    oracle's powers (p, n, R) of the last run."""
     import oracle
     nthreads = oracle.threads()
     t1 = []
@@ -349,7 +390,7 @@ def cpu_baseline(A, x, p, budget_s=20.0):
     t_start = time.perf_counter()
     while True:
         t0 = time.perf_counter()
-        oracle.powers(A, x, p, nthreads=nthreads)
+        ref = oracle.powers(A, x, p, nthreads=nthreads)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s or len(times) >= 5:
             break
@@ -367,7 +408,7 @@ def cpu_baseline(A, x, p, budget_s=20.0):
     return {"value": round(gflops, 3), "unit": "Gflop/s", "cores": nthreads, "kind": "oracle",
             "sample": f"the full workload (all {p} powers), median of {len(times)} runs "
                       f"({med * 1e3:.0f} ms each), OpenMP over rows on {nthreads} threads of {cpu}",
-            "single_thread_value": round(gflops1, 3)}
+            "single_thread_value": round(gflops1, 3)}, ref
 
 
 def bandwidth_sweep(torch, mpk, stream, reps=5):
@@ -407,6 +448,114 @@ def bandwidth_sweep(torch, mpk, stream, reps=5):
             "points": rows}
 
 
+def _kernel_key(name):
+    """Readable kernel name of a rocprofv3 record (no namespaces or argument list)."""
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0].strip()
+
+
+def reduce_counters(d):
+    """Reduce the rocprofv3 output of one profiled bench configuration:
+    d/trace (--kernel-trace --stats), d/fetch (--pmc FETCH_SIZE), d/write
+    (--pmc WRITE_SIZE), d/tcc (--pmc TCC_HIT_sum TCC_MISS_sum) and the
+    copy-calibration runs d/cfetch, d/cwrite (a 1 GiB device copy, so that
+    the counters convert to bytes).  Per kernel: launches, mean duration,
+    FETCH/WRITE KiB per launch, the bytes they stand for at L2 egress (reads
+    into the L2 from the Infinity Cache or HBM, and writes out of it) and
+    the L2 hit rate."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def rows(sub, pattern):
+        out = []
+        for f in sorted(glob.glob(os.path.join(d, sub, "**", pattern), recursive=True)):
+            with open(f, newline="") as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def per_launch(sub):
+        acc = defaultdict(lambda: defaultdict(float))
+        for r in rows(sub, "*counter_collection.csv"):
+            acc[_kernel_key(r["Kernel_Name"])][(r["Dispatch_Id"], r["Counter_Name"])] += \
+                float(r["Counter_Value"])
+        res = {}
+        for k, v in acc.items():
+            per = defaultdict(list)
+            for (_, cname), val in v.items():
+                per[cname].append(val)
+            res[k] = {c: sum(x) / len(x) for c, x in per.items()}
+        return res
+
+    gib_kib = float(1 << 20)
+    cf = per_launch("cfetch").get("__amd_rocclr_copyBuffer", {}).get("FETCH_SIZE")
+    cw = per_launch("cwrite").get("__amd_rocclr_copyBuffer", {}).get("WRITE_SIZE")
+    fetch_scale = round(gib_kib / cf, 4) if cf else None
+    write_scale = round(gib_kib / cw, 4) if cw else None
+    stats = {}
+    for r in rows("trace", "*kernel_stats.csv"):
+        stats[_kernel_key(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3)
+    fetch, write, tcc = per_launch("fetch"), per_launch("write"), per_launch("tcc")
+    kernels = {}
+    for k in set(fetch) | set(write) | set(tcc):
+        if not k.startswith("mpk::") or k not in stats:
+            continue
+        e = {"launches": stats[k][0], "avg_us": round(stats[k][1], 2)}
+        if k in fetch and k in write and fetch_scale and write_scale:
+            fk, wk = fetch[k]["FETCH_SIZE"], write[k]["WRITE_SIZE"]
+            e.update(fetch_kib_per_launch=round(fk, 1), write_kib_per_launch=round(wk, 1),
+                     l2_egress_bytes_per_launch=int((fk * fetch_scale + wk * write_scale) * 1024))
+        if k in tcc:
+            h, m = tcc[k].get("TCC_HIT_sum", 0.0), tcc[k].get("TCC_MISS_sum", 0.0)
+            e.update(tcc_hits_per_launch=int(h), tcc_misses_per_launch=int(m),
+                     l2_hit_rate=round(h / (h + m), 4) if h + m else None)
+        kernels[k] = e
+    out = {"fetch_scale": fetch_scale, "write_scale": write_scale,
+           "calibration": "a 1 GiB device-to-device copy (bench.py --copy-calibration) under "
+                          "rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE",
+           "traffic_scope": "L2 egress: FETCH_SIZE x scale + WRITE_SIZE x scale; includes "
+                            "Infinity Cache hits (this GPU exposes no MALL hit counter)",
+           "kernels": kernels}
+    # the bench line of the traced run names the tuning: per-run bytes of its
+    # level-blocked kernel and of the p x SpMV kernel, keyed as bench.py looks
+    # them up
+    line = None
+    for f in sorted(glob.glob(os.path.join(d, "trace*.log"))):
+        with open(f) as fh:
+            for ln in fh:
+                if ln.startswith("{"):
+                    line = json.loads(ln)
+    if line is not None:
+        with open(KERNEL_SRC, "rb") as fh:
+            out["kernels_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+        out["command"] = line.get("command")
+        out["workload"] = line["config"]["workload"]
+        p = line["config"]["p"]
+
+        def run_entry(pred, launches):
+            ks = [k for k in kernels if pred(k.split("::")[-1]) and
+                  "l2_egress_bytes_per_launch" in kernels[k]]
+            if not ks:
+                return None
+            k = max(ks, key=lambda k: kernels[k]["launches"] * kernels[k]["avg_us"])
+            e = kernels[k]
+            return {"kernel": k, "launches_per_run": launches, "avg_launch_us": e["avg_us"],
+                    "l2_egress_bytes_per_run": e["l2_egress_bytes_per_launch"] * launches,
+                    "l2_hit_rate": e.get("l2_hit_rate")}
+
+        runs = {}
+        lbk = line["roofline"].get("run_key")
+        lbe = run_entry(lambda k: k.startswith(("lb_", "xcd_", "step_")),
+                        line["plan"]["launches_per_run"])
+        if lbk and lbe:
+            runs[lbk] = lbe
+        be = run_entry(lambda k: k.startswith("spmv_"), p)
+        if be:
+            runs["pxspmv:" + line["baseline_pxspmv"]["reorder"]] = be
+        out["runs"] = runs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,6 +563,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving session")
+    ap.add_argument("--serve-rate", default="190,250",
+                    help="Poisson arrival rates (requests/s, comma-separated) of the paced "
+                         "serving passes; the first is the headline")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the banded and Anderson workloads")
     ap.add_argument("--schedule", default=None,
@@ -421,6 +573,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=16384, help="chunk nonzeros with --schedule")
     ap.add_argument("--cache-mib", type=int, default=64, help="cache budget with --schedule")
     ap.add_argument("--lag", type=int, default=0, help="wavefront lag with --schedule")
+    ap.add_argument("--workgroups", type=int, default=0,
+                    help="persistent workgroups with --schedule (0: the library's default)")
+    ap.add_argument("--seg-powers", type=int, default=0,
+                    help="powers per launch with --schedule (0: all)")
     ap.add_argument("--reorder", default="bfs", choices=["bfs", "none"],
                     help="level construction with --schedule")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
@@ -431,6 +587,9 @@ def main():
                     help="print only the Chebyshev time-step measurement (for profiling)")
     ap.add_argument("--bandwidth-sweep", action="store_true",
                     help="only run the load-bandwidth probe over 1 MiB .. 4 GiB working sets")
+    ap.add_argument("--reduce-counters", metavar="DIR", default=None,
+                    help="reduce the rocprofv3 output of a profiled configuration (DIR/trace, "
+                         "fetch, write, tcc, cfetch, cwrite) to JSON on stdout and stop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
@@ -438,6 +597,10 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding the kernel over "
               "several GPUs is a design note, not a benchmark here.", file=sys.stderr)
         sys.exit(2)
+
+    if args.reduce_counters:
+        print(json.dumps(reduce_counters(args.reduce_counters), indent=1), flush=True)
+        return
 
     import torch
     import paper_2405_12525_amd as mpk
@@ -499,7 +662,8 @@ def main():
             tq = Q.autotune(xd, p, Y, reps=3, recur=cheb, stream=stream)
         else:
             tq = Q.tune(schedule=args.schedule, chunk_nnz=args.chunk,
-                        cache_bytes=args.cache_mib << 20, lag=args.lag)
+                        cache_bytes=args.cache_mib << 20, lag=args.lag,
+                        workgroups=args.workgroups, seg_powers=args.seg_powers)
         r = time_calls(lambda: run_lb(Q, Y), args.steps, args.warmup, torch, stream)
         Q.sync()
         log(f"[bench] level-blocked reorder={ro}: autotuned in {time.perf_counter() - t0:.1f}s "
@@ -544,11 +708,15 @@ def main():
     G.close()
     log(f"[bench] HIP graph replay: {gr['median_ms']:.3f} ms, equal: {graph_same}")
 
+    Yh = None if args.no_cpu else Y.cpu().numpy()   # for the per-power check on the CPU leg
     extra = (p - 1) * 8 * A.n * R if cheb else 0  # y_{k-1} read again by the recurrence
     lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "lb", A.n if reorder == "bfs" else 0)
     trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "trad",
                                    A.n if best_base == "bfs" else 0) + extra
     achieved = lb_bytes / (lb["mean_ms"] * 1e-3) / 1e9
+    effective = trad_bytes / (lb["mean_ms"] * 1e-3) / 1e9
+    run_key = "level_blocked:{schedule}:{chunk_nnz}:{cm}:{lag}:{ro}".format(
+        cm=tune["cache_bytes"] >> 20, ro=reorder, **tune)
     value = flop / (lb["median_ms"] * 1e-3) / 1e9
     bmed = base[best_base]["median_ms"]
     out = {
@@ -570,12 +738,14 @@ def main():
                    "chunk_nnz": tune["chunk_nnz"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, vb,
-                                                 "level_blocked:{schedule}:{chunk_nnz}:{cm}:{lag}:{ro}"
-                                                 .format(cm=tune["cache_bytes"] >> 20, ro=reorder,
-                                                         **tune)),
+                     "traffic": measured_traffic(args.workload, vb, run_key),
+                     "traffic_scope": "L2 egress bytes per run: FETCH_SIZE x 2.0 + WRITE_SIZE x "
+                                      "1.0 (copy-calibrated); Infinity Cache hits included",
                      "kernel": "level-blocked run (all launches of one mpk_run)",
-                     "algorithmic_bytes": lb_bytes},
+                     "run_key": run_key,
+                     "algorithmic_bytes": lb_bytes,
+                     "effective_GBs_vs_pxspmv_traffic": round(effective, 1),
+                     "effective_frac_vs_pxspmv_traffic": round(effective / HBM_PEAK_GBS, 4)},
         "baseline_pxspmv": {"gflops": round(flop / (bmed * 1e-3) / 1e9, 2), "ms": round(bmed, 4),
                             "reorder": best_base, "algorithmic_bytes": trad_bytes,
                             "achieved_GBs": round(trad_bytes / (base[best_base]["mean_ms"] * 1e-3)
@@ -587,20 +757,26 @@ def main():
         "bit_identical_to_pxspmv": same,
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
                  "chunks": sched["n_chunks"], "launches_per_run": sched["n_steps"],
+                 "window_bytes": int(sched["window_bytes"]), "max_reach": sched["max_reach"],
+                 "sliced_layout": bool(info["sliced_layout"]),
                  "spmv_equivalents": round(info["plan_ms"] / (bmed / p), 1),
                  "from_device_csr_ms": dev_ms,
                  "from_device_csr_spmv_equivalents": {k: round(v / (bmed / p), 1)
                                                       for k, v in dev_ms.items()}},
     }
+    if args.schedule is not None:
+        out["command"] = "python3 bench.py " + " ".join(sys.argv[1:])
     P.close()
     del Y, B
     if not args.no_configs and args.schedule is None and args.workload == WORKLOAD:
-        out["other_configs"] = other_configs(torch, mpk, w, args.steps, args.warmup, stream)
+        out["other_configs"] = other_configs(torch, mpk, w, args.steps, args.warmup, stream,
+                                             not args.no_cpu)
         out["other_configs"]["cheb_time_step_anderson160_m16_s4_fp32"] = time_step(
             torch, mpk, w, args.steps, args.warmup, stream)
     if not args.no_serve and args.workload == WORKLOAD:
         try:
-            out["serving"] = serving(torch, mpk, w)
+            out["serving"] = serving(torch, mpk, w,
+                                     [float(r) for r in args.serve_rate.split(",")])
         except mpk.MPKError as e:
             # a failed serving session is reported in the line, which still
             # carries the measured MPK runs above
@@ -608,7 +784,12 @@ def main():
             out["serving"] = {"error": str(e)}
     if not args.no_cpu and args.workload == WORKLOAD:
         log("[bench] timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(A, x, p)
+        out["cpu_baseline"], ref = cpu_baseline(A, x, p)
+        rel = per_power_rel_err(Yh, ref)
+        out["parity_vs_fp64_oracle"] = {"rel_err_per_power": rel, "tolerance": 1e-12,
+                                        "within_tolerance": max(rel) <= 1e-12}
+        log(f"[bench] per-power relative error vs the FP64 oracle: max {max(rel):.2e}")
+        del ref, Yh
     print(json.dumps(out), flush=True)
 
 

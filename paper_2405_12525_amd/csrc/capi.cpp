@@ -351,6 +351,22 @@ int32_t *status_word(mpk_plan_t plan, hipStream_t stream) {
     return plan->status_words.as<int32_t>() + slot;
 }
 
+// Per device: the event recorded after the latest launch of the XCD
+// schedule's kernel.  Its workgroups serve the queue of the XCD they run on,
+// so two overlapping launches could each fill the XCDs the other one's
+// queues need and wait for each other until their limits; every such launch
+// therefore waits for the previous one (other kernels may overlap it: they
+// finish on their own, after which its workgroups get every XCD).
+struct XcdGate {
+    std::mutex mu;
+    hipEvent_t ev = nullptr;
+    bool recorded = false;
+};
+XcdGate &xcd_gate(int device) {
+    static XcdGate gates[64];
+    return gates[device >= 0 && device < 64 ? device : 0];
+}
+
 // The sliced layout of the plan's matrix, built on the device from its CSR
 // (plan row order), unless padding each slice to its longest row would add
 // more than a quarter to the stored entries (rows of uneven length: there
@@ -380,6 +396,17 @@ mpk_status_t build_sell(mpk_plan_t plan) {
 // Device-side state every device plan holds from the start (allocated
 // outside any capture): the zeroed failure words.
 mpk_status_t init_device_state(mpk_plan_t plan) {
+    {
+        XcdGate &gate = xcd_gate(plan->device);
+        std::lock_guard<std::mutex> g(gate.mu);
+        if (!gate.ev) {
+            hipError_t e = hipEventCreateWithFlags(&gate.ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                gate.ev = nullptr;
+                return hip_fail(e, "hipEventCreate");
+            }
+        }
+    }
     mpk_status_t st = plan->status_words.alloc(kStatusSlots * sizeof(int32_t));
     if (st) return st;
     hipError_t e = hipMemset(plan->status_words.ptr, 0, kStatusSlots * sizeof(int32_t));
@@ -621,12 +648,27 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                                reinterpret_cast<uintptr_t>(Y) % 128 == 0;
         const int acquire = (plan->tune.acquire_always || !lines_own) ? 1 : 0;
         if (!se->host.qptr.empty()) {
-            DevXcdSchedule xs{ss->view(), ss->bound_sptr.as<int32_t>(), se->dep_ptr.as<int32_t>(),
+            DevXcdSchedule xs{ss->view(), ss->bound_sptr.as<int32_t>(), se->chunk_row.as<int32_t>(),
+                              se->dep_ptr.as<int32_t>(),
                               se->dep_idx.as<int32_t>(),
                               se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
                               se->host.n_queues, se->host.n_chunks()};
-            const int64_t steal_ticks = 20 * (int64_t)plan->wall_khz / 1000;  // 20 us
-            rc = launch_xcd(m, xs, wv, a, &cf, acp, wg, spin_ticks, steal_ticks, stream);
+            // at most one launch of this kernel in flight per device: wait for
+            // the previous one (any stream, any plan), then become the one to
+            // wait for (not under capture: a captured graph's launches are
+            // the caller's to order)
+            XcdGate &gate = xcd_gate(plan->device);
+            std::lock_guard<std::mutex> gg(gate.mu);
+            if (!capturing && gate.ev && gate.recorded) {
+                e = hipStreamWaitEvent(stream, gate.ev, 0);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+            }
+            rc = launch_xcd(m, xs, wv, a, &cf, acp, wg, spin_ticks, acquire, stream);
+            if (!rc && !capturing && gate.ev) {
+                e = hipEventRecord(gate.ev, stream);
+                if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+                gate.recorded = true;
+            }
         } else {
             rc = launch_lb(m, ds, wv, a, &cf, acp, wg, spin_ticks, plan->tune.skip_ahead,
                            acquire, stream);

@@ -468,18 +468,33 @@ __global__ void sell_width_kernel(const int32_t *rowptr, int64_t n, int32_t *wid
 }
 
 // Entry j of row r goes to soff[r / 64] + j * 64 + r % 64; rlen[r] = length.
+// One block per 64-row slice: the slice's nonzeros are contiguous in the CSR,
+// so the block reads them coalesced and finds each one's row by a binary
+// search over the slice's 65 row pointers held in LDS.  Padding is left
+// unwritten: the kernels never read past a row's length.
 template <typename V>
 __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, const V *val,
                                  int64_t n, const int64_t *soff, int32_t *rlen, int32_t *scol,
                                  V *sval) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t e0 = rowptr[r], L = rowptr[r + 1] - e0;
-        rlen[r] = L;
-        const int64_t base = soff[r / kSellRows] + r % kSellRows;
-        for (int32_t j = 0; j < L; ++j) {
-            scol[base + (int64_t)j * kSellRows] = col[e0 + j];
-            sval[base + (int64_t)j * kSellRows] = val[e0 + j];
+    __shared__ int32_t rp[kSellRows + 1];
+    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
+    for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
+        const int64_t r0 = s * kSellRows;
+        const int nr = (int)std::min<int64_t>(kSellRows, n - r0);
+        __syncthreads();
+        for (int i = threadIdx.x; i <= nr; i += blockDim.x) rp[i] = rowptr[r0 + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < nr; i += blockDim.x) rlen[r0 + i] = rp[i + 1] - rp[i];
+        const int64_t base = soff[s];
+        for (int32_t e = rp[0] + (int32_t)threadIdx.x; e < rp[nr]; e += blockDim.x) {
+            int lo = 0, hi = nr - 1;   // last row i with rp[i] <= e
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const int64_t dst = base + (int64_t)(e - rp[lo]) * kSellRows + lo;
+            scol[dst] = col[e];
+            sval[dst] = val[e];
         }
     }
 }
@@ -502,15 +517,16 @@ int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &widt
 int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                   int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
                   int32_t *scol, void *sval) {
+    (void)entries;
     if (n == 0) return 0;
-    MPK_TRY(hipMemset(scol, 0, (size_t)entries * 4));
-    MPK_TRY(hipMemset(sval, 0, (size_t)entries * (value_bits / 8)));
+    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
+    const dim3 grid((unsigned)std::min<int64_t>(n_sl, 65536));
     if (value_bits == 32)
-        hipLaunchKernelGGL(sell_fill_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+        hipLaunchKernelGGL(sell_fill_kernel<float>, grid, dim3(kThreads), 0, 0,
                            rowptr, col, static_cast<const float *>(val), n, soff, rlen, scol,
                            static_cast<float *>(sval));
     else
-        hipLaunchKernelGGL(sell_fill_kernel<double>, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+        hipLaunchKernelGGL(sell_fill_kernel<double>, grid, dim3(kThreads), 0, 0,
                            rowptr, col, static_cast<const double *>(val), n, soff, rlen, scol,
                            static_cast<double *>(sval));
     MPK_TRY(hipGetLastError());

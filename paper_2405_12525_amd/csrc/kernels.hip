@@ -818,7 +818,7 @@ struct XcdParams {
     DevWorkspace ws;
     SegArgs a;
     int64_t spin_limit;   // wall-clock ticks
-    int64_t steal_ticks;  // wait on the own queue's head before serving others
+    int32_t acquire;      // invalidate caches before a task reads its inputs
 };
 
 // Kernel arguments stay well inside the 4 KiB argument segment.
@@ -827,124 +827,100 @@ static_assert(sizeof(LBParams) + sizeof(Coefs) + sizeof(AccCoefs) <= 3584,
 static_assert(sizeof(XcdParams) + sizeof(Coefs) + sizeof(AccCoefs) <= 3584,
               "XCD kernel arguments");
 
-// Whether task t of the XCD schedule can run: every chunk it reads has
-// completed the previous power.  Wavefront 0 only (all 64 lanes).
-__device__ __forceinline__ bool xcd_task_ready(const XcdParams &P, int32_t t) {
-    const int32_t c = P.s.tasks[2 * t];
-    const int32_t k = P.s.tasks[2 * t + 1];
-    if (k == 1) return true;
-    const int32_t lo = P.s.dep_ptr[c], hi = P.s.dep_ptr[c + 1];
-    int ready = 1;
-    for (int32_t j = lo + (int)threadIdx.x; j < hi; j += kWave)
-        ready &= ld_relaxed(P.ws.done + P.s.dep_idx[j]) >= k - 1;
-    return __all(ready);
-}
-
-// Claims the head of queue j if its inputs are done: returns the global task
-// index, -1 when the head is not ready, -2 when the queue is exhausted.
-// Wavefront 0 only; lane 0 does the atomics and broadcasts.
-__device__ __forceinline__ int32_t xcd_claim_head(const XcdParams &P, int j) {
-    const int32_t q0 = P.s.qptr[j];
-    const int32_t qn = P.s.qptr[j + 1] - q0;
-    int32_t *head = P.ws.ticket + j;
-    for (;;) {
-        int32_t h = 0;
-        if (threadIdx.x == 0) h = ld_relaxed(head);
-        h = __shfl(h, 0);
-        if (h >= qn) return -2;
-        if (!xcd_task_ready(P, q0 + h)) return -1;
-        int won = 0;
-        if (threadIdx.x == 0) {
-            int32_t expect = h;
-            won = __hip_atomic_compare_exchange_strong(head, &expect, h + 1, __ATOMIC_RELAXED,
-                                                       __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
-        }
-        if (__shfl(won, 0)) return q0 + h;
-        // another workgroup took this head: look at the next one
-    }
-}
-
 // Persistent kernel of the XCD schedule.  Queue q holds the tasks of the
 // chunks owned by XCD q, in the global dependency order the queues were cut
-// from.  A workgroup only ever claims a task whose inputs are done (the head
-// of a queue, by compare-and-swap), so it never holds a task while waiting.
-// It serves the queue of the XCD it runs on (read from the hardware) first;
-// when that head stays unready for steal_ticks, or the queue is exhausted, it
-// claims ready heads of the other queues as well.  Deadlock freedom, whatever
-// the dispatcher does and whatever else runs on the device: the earliest
-// unfinished task of the global order has all its inputs done and every
-// earlier task of its queue finished, so it is either running or the ready
-// head of its queue, which any workgroup not holding a task will claim.
-// Waits for a ready head are bounded by spin_limit in any case.  Results are
-// published as in lb_kernel.
-template <typename V, int RC, bool ACC>
+// from; a workgroup serves the queue of the XCD it runs on (read from the
+// hardware, so the binding holds whatever the dispatcher does) and takes its
+// tickets in order.  Dependencies are exact chunk lists; results are
+// published as in lb_kernel.  Progress: the earliest unfinished task of the
+// global order has every earlier task of its queue finished, so it is the
+// next ticket of its queue or held by a workgroup, and its inputs are done;
+// it runs as soon as one workgroup of this launch runs on its XCD.  That
+// holds while nothing else stops this launch's workgroups from ever being
+// placed on an XCD: the library never lets two launches of this kernel run
+// at the same time on one device (two such launches could each fill the
+// XCDs the other one's queues need, and wait for each other), and any other
+// kernel finishes on its own.  Waits are bounded by spin_limit in any case.
+template <typename V, int RC, bool ACC, bool SELL>
 __device__ __forceinline__ void xcd_body(const XcdParams &P, const Coefs &cf, const AccCoefs *ac) {
-    __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
-    __shared__ int32_t s_task;
+    __shared__ int32_t s_ticket;
+    __shared__ int s_ok;
     const int tid = threadIdx.x;
-    const int nq = P.s.n_queues;
-    const int home = nq == 1 ? 0 : __builtin_amdgcn_readfirstlane(xcc_id()) % nq;
-    bool failed = false;  // wavefront 0: a wait hit its limit (reported after the loop)
-    for (;;) {
-        if (tid < kWave) {
-            int32_t chosen = -1;
-            uint64_t t0 = wall_clock64();
-            for (;;) {
-                const int32_t own = xcd_claim_head(P, home);
-                if (own >= 0) {
-                    chosen = own;
-                    break;
-                }
-                const int64_t waited = (int64_t)(wall_clock64() - t0);
-                bool left = own == -1;
-                if (own == -2 || waited > P.steal_ticks) {
-                    for (int i = 1; i < nq; ++i) {
-                        const int32_t t = xcd_claim_head(P, (home + i) % nq);
-                        if (t >= 0) {
-                            chosen = t;
-                            break;
-                        }
-                        left |= t == -1;
+    const int q = P.s.n_queues == 1 ? 0 : __builtin_amdgcn_readfirstlane(xcc_id());
+    if (q >= P.s.n_queues) return;  // uniform: no queue for this XCD
+    const int32_t q0 = P.s.qptr[q];
+    const int32_t qn = P.s.qptr[q + 1] - q0;
+    int32_t *ticket = P.ws.ticket + q;
+    if (tid == 0)
+        s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    int32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+    while (t < qn) {
+        const int32_t c = P.s.tasks[2 * (q0 + t)];
+        const int32_t k = P.s.tasks[2 * (q0 + t) + 1];
+        int ok = 1;
+        if (k > 1) {
+            if (tid < kWave) {
+                const int32_t lo = P.s.dep_ptr[c], hi = P.s.dep_ptr[c + 1];
+                uint64_t t0 = 0;
+                for (int round = 0;; ++round) {
+                    int ready = 1;
+                    for (int32_t j = lo + tid; j < hi; j += kWave)
+                        ready &= ld_relaxed(P.ws.done + P.s.dep_idx[j]) >= k - 1;
+                    if (__all(ready)) break;
+                    if (round == 0) t0 = wall_clock64();
+                    if (ld_relaxed(P.ws.err) != 0 ||
+                        (int64_t)(wall_clock64() - t0) > P.spin_limit) {
+                        ok = 0;
+                        break;
                     }
-                    if (chosen >= 0) break;
+                    __builtin_amdgcn_s_sleep(2);
                 }
-                if (!left) break;  // every queue exhausted
-                if (ld_relaxed(P.ws.err) != 0 || waited > P.spin_limit) {
-                    failed = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+                if (tid == 0) s_ok = ok;
             }
-            if (tid == 0) s_task = chosen;
+            __syncthreads();
+            ok = __builtin_amdgcn_readfirstlane(s_ok);
+            if (P.acquire)  // as in lb_body: a line-closed schedule needs no invalidation
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            else
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
-        __syncthreads();
-        const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
-        if (t < 0) break;  // uniform: no work left (or a wait failed)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int32_t c = P.s.tasks[2 * t];
-        const int32_t k = P.s.tasks[2 * t + 1];
-        run_slices<V, RC, Staging<RC, kTaskKP>::value, true, ACC>(
-            P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R, P.s.sl, P.s.chunk_sptr[c],
-            P.s.chunk_sptr[c + 1], sm);
+        if (!ok) break;
+        run_chunk<V, RC, true, ACC, SELL>(P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R,
+                                          P.s.sl, P.s.chunk_sptr, P.s.chunk_row, c);
         // write-through results, completed (vmcnt = 0) before the barrier
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
-        if (tid == 0)
+        if (tid == 0) {
             __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
-    if (failed && tid == 0) record_failure(P.ws);
+    if (t < qn && tid == 0) record_failure(P.ws);
 }
 
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_kernel(XcdParams P, Coefs cf) {
-    xcd_body<V, RC, false>(P, cf, nullptr);
+    xcd_body<V, RC, false, false>(P, cf, nullptr);
 }
 
 template <typename V, int RC>
 __global__ __launch_bounds__(kBlock, kTaskWaves) void xcd_acc_kernel(XcdParams P, Coefs cf,
                                                                      AccCoefs ac) {
-    xcd_body<V, RC, true>(P, cf, &ac);
+    xcd_body<V, RC, true, false>(P, cf, &ac);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kSellWaves) void xcd_sell_kernel(XcdParams P, Coefs cf) {
+    xcd_body<V, RC, false, true>(P, cf, nullptr);
+}
+
+template <typename V, int RC>
+__global__ __launch_bounds__(kBlock, kSellWaves) void xcd_sell_acc_kernel(XcdParams P, Coefs cf,
+                                                                          AccCoefs ac) {
+    xcd_body<V, RC, true, true>(P, cf, &ac);
 }
 
 __global__ void reset_kernel(DevWorkspace ws, int32_t n_chunks, int clear_status) {
@@ -1088,8 +1064,8 @@ struct VTable {
     LbAccFn lb_acc[6], lbs_acc[6], lb_sell_acc[6];
     StepFn step[6], step_sell[6];
     StepAccFn step_acc[6], step_sell_acc[6];
-    XcdFn xcd[6];
-    XcdAccFn xcd_acc[6];
+    XcdFn xcd[6], xcd_sell[6];
+    XcdAccFn xcd_acc[6], xcd_sell_acc[6];
     template <int RC>
     void fill(int i) {
         spmv[i] = spmv_power_kernel<V, RC, false>;
@@ -1108,6 +1084,8 @@ struct VTable {
         step_sell_acc[i] = step_sell_acc_kernel<V, RC>;
         xcd[i] = xcd_kernel<V, RC>;
         xcd_acc[i] = xcd_acc_kernel<V, RC>;
+        xcd_sell[i] = xcd_sell_kernel<V, RC>;
+        xcd_sell_acc[i] = xcd_sell_acc_kernel<V, RC>;
     }
     VTable() {
         fill<1>(0);
@@ -1166,11 +1144,15 @@ StepAccFn step_acc_fn(int value_bits, int R, bool sell) {
     if (sell) return value_bits == 32 ? t32().step_sell_acc[i] : t64().step_sell_acc[i];
     return value_bits == 32 ? t32().step_acc[i] : t64().step_acc[i];
 }
-XcdFn xcd_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().xcd[r_index(R)] : t64().xcd[r_index(R)];
+XcdFn xcd_fn(int value_bits, int R, bool sell) {
+    const int i = r_index(R);
+    if (sell) return value_bits == 32 ? t32().xcd_sell[i] : t64().xcd_sell[i];
+    return value_bits == 32 ? t32().xcd[i] : t64().xcd[i];
 }
-XcdAccFn xcd_acc_fn(int value_bits, int R) {
-    return value_bits == 32 ? t32().xcd_acc[r_index(R)] : t64().xcd_acc[r_index(R)];
+XcdAccFn xcd_acc_fn(int value_bits, int R, bool sell) {
+    const int i = r_index(R);
+    if (sell) return value_bits == 32 ? t32().xcd_sell_acc[i] : t64().xcd_sell_acc[i];
+    return value_bits == 32 ? t32().xcd_acc[i] : t64().xcd_acc[i];
 }
 
 }  // namespace
@@ -1301,19 +1283,20 @@ int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
 
 int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
                const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-               int64_t spin_limit, int64_t steal_ticks, void *stream) {
+               int64_t spin_limit, int acquire, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (s.n_queues < 1 || s.n_queues > kMaxQueues) return (int)hipErrorInvalidValue;
     if (s.n_chunks == 0) return 0;
-    XcdParams P{m, s, ws, a, spin_limit, steal_ticks};
+    XcdParams P{m, s, ws, a, spin_limit, acquire ? 1 : 0};
     Coefs c{};
     if (cf) c = *cf;
+    const bool sell = m.scol != nullptr;
     if (acc)
-        hipLaunchKernelGGL(xcd_acc_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
-                           (hipStream_t)stream, P, c, *acc);
+        hipLaunchKernelGGL(xcd_acc_fn(m.value_bits, a.R, sell), dim3(workgroups), dim3(kBlock),
+                           0, (hipStream_t)stream, P, c, *acc);
     else
-        hipLaunchKernelGGL(xcd_fn(m.value_bits, a.R), dim3(workgroups), dim3(kBlock), 0,
+        hipLaunchKernelGGL(xcd_fn(m.value_bits, a.R, sell), dim3(workgroups), dim3(kBlock), 0,
                            (hipStream_t)stream, P, c);
     return (int)hipGetLastError();
 }

@@ -262,6 +262,7 @@ constexpr int kStatusSlots = 256;  // status words per plan (streams share a slo
 struct DevXcdSchedule {
     DevSlices sl;
     const int32_t *chunk_sptr;
+    const int32_t *chunk_row;    // n_chunks + 1 plan rows (sliced layout)
     const int32_t *dep_ptr, *dep_idx;
     const int32_t *tasks;
     const int32_t *qptr;
@@ -310,12 +311,12 @@ int launch_load_probe(const double *buf, int64_t n_doubles, int passes, int work
                       double *sink, void *stream);
 int launch_load_probe_xcd(const double *buf, int64_t n_doubles, int regions, int passes,
                           int workgroups, double *sink, int32_t *xcc, void *stream);
-// The XCD schedule's persistent kernel: workgroups claim ready queue heads,
-// their own XCD's queue first and, after steal_ticks of waiting (wall-clock
-// ticks) or once it is exhausted, any queue's.
+// The XCD schedule's persistent kernel: each workgroup takes tickets of its
+// own XCD's queue.  Two launches must never overlap on one device (the
+// caller serializes them).
 int launch_xcd(const DevMatrix &m, const DevXcdSchedule &s, const DevWorkspace &ws,
                const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-               int64_t spin_limit, int64_t steal_ticks, void *stream);
+               int64_t spin_limit, int acquire, void *stream);
 // XCDs of the device when workgroup i runs on XCD i mod n (checked with a probe
 // kernel), else 1.
 int detect_xcds(int device);

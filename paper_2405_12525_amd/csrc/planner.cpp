@@ -346,9 +346,14 @@ static int64_t effective_chunk_nnz(const PlanShape &sh, const mpk_tune_t &tune,
 
 // XCD schedule: every level is split into n_xcd contiguous parts (by
 // nonzeros) and part x of every level belongs to XCD x, so a chunk's rows
-// mostly read rows of the same XCD one level up or down.  Chunks stay inside
-// one part and start on multiples of 16 rows where possible (one 128-byte
-// line of a single-RHS vector).  Dependencies are exact lists of chunks.
+// mostly read rows of the same XCD one level up or down (with sub-level
+// ordering, a part is a run of consecutive sub-levels).  Every chunk
+// boundary is a multiple of kLineRows rows: a level's span is taken from its
+// first row rounded up to the next multiple to the same for the next level,
+// so a chunk may hold up to kLineRows - 1 rows of a neighbouring level (the
+// dependency lists are exact, so this only moves work between XCDs).  The
+// schedule is then line-closed (see Schedule::line_closed).  Dependencies
+// are exact lists of chunks.
 static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
                                        int default_workgroups, Schedule &s, std::string &err) {
     const double t0 = now_ms();
@@ -363,9 +368,11 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
     s.n_queues = nx;
     s.n_groups = n_levels;
     s.chunk_ptr.assign(1, 0);
-    auto align_up = [](int64_t r) { return (r + 15) & ~(int64_t)15; };
+    auto align_up = [](int64_t r) { return (r + kLineRows - 1) & ~(int64_t)(kLineRows - 1); };
+    auto span = [&](int32_t l) { return l >= n_levels ? n : std::min<int64_t>(n, align_up(lp[l])); };
     for (int32_t l = 0; l < n_levels; ++l) {
-        const int64_t L0 = lp[l], L1 = lp[l + 1];
+        const int64_t L0 = span(l), L1 = span(l + 1);
+        if (L1 <= L0) continue;
         const int64_t rows = L1 - L0;
         const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(nx, rows / 16));
         int64_t a = L0;
@@ -389,8 +396,8 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
                             rp.begin() - 1;
                 e = std::min<int64_t>(e, r + 65536);
                 if (e < b) {
-                    // round to a multiple of 16 rows, at least one 16-row step past r
-                    int64_t ea = e & ~(int64_t)15;
+                    // round to a multiple of kLineRows rows, at least one step past r
+                    int64_t ea = e & ~(int64_t)(kLineRows - 1);
                     if (ea <= r) ea = align_up(r + 1);
                     e = std::min<int64_t>(ea, b);
                 }
@@ -402,6 +409,7 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
             a = b;
         }
     }
+    s.line_closed = true;
     const int32_t nc = s.n_chunks();
     std::vector<int32_t> chunk_of(n);
     for (int32_t c = 0; c < nc; ++c)

@@ -14,7 +14,13 @@ the loop admits them as stream slots and memory free up:
   M = p terms, psi as real and imaginary column pairs) batches only with
   steps of the same dt and M, since those fix the weights; each request
   takes its own columns of the stepped states;
-* batches for different matrices run concurrently on separate HIP streams;
+* batches for different matrices run concurrently on separate HIP streams,
+  at most max_inflight_per_matrix batches of one matrix at a time (by
+  default one), so that requests arriving for a busy matrix wait together
+  and leave as one larger batch instead of taking every stream;
+* each plan runs its batches through the level-blocked kernels or, where
+  the caller found them faster for that matrix (use_baseline), through the
+  p x SpMV kernels: the results are the same bit for bit;
 * a batch is admitted only while the device memory held by running batches
   (stacked inputs plus outputs) stays within the budget;
 * each batch's device status (mpk_run_status, copied into pinned host memory
@@ -107,9 +113,16 @@ class Server:
     """
 
     def __init__(self, plans: Sequence[Plan], n_streams: int = 4,
-                 mem_budget: Optional[int] = None, max_rhs: int = MAX_RHS):
+                 mem_budget: Optional[int] = None, max_rhs: int = MAX_RHS,
+                 max_inflight_per_matrix: int = 1,
+                 use_baseline: Optional[Sequence[bool]] = None):
         torch = _torch()
         self.plans = list(plans)
+        self.max_inflight_per_matrix = max(1, int(max_inflight_per_matrix))
+        self.use_baseline = [False] * len(self.plans) if use_baseline is None \
+            else [bool(b) for b in use_baseline]
+        if len(self.use_baseline) != len(self.plans):
+            raise ValueError("use_baseline needs one entry per plan")
         self.max_rhs = int(max_rhs)
         if not 1 <= self.max_rhs <= MAX_RHS:
             raise ValueError("max_rhs must be in [1, 16]")
@@ -164,12 +177,14 @@ class Server:
                 nvec = 1 if kind == "time_step" else p
                 Yo = self._scratch(self._out, si, nvec * P.n * R, dev)
                 Yo = Yo.view(P.n, R) if kind == "time_step" else Yo.view(p, P.n, R)
+            base = self.use_baseline[batch[0].matrix]
             if kind == "chebyshev":
-                Y = P.run_recur(X, *chebyshev_coefficients(p), Y=Yo, stream=stream)
+                run = P.run_baseline_recur if base else P.run_recur
+                Y = run(X, *chebyshev_coefficients(p), Y=Yo, stream=stream)
             elif kind == "time_step":
-                Y = P.cheb_time_step(X, batch[0].dt, p, out=Yo, stream=stream)
+                Y = P.cheb_time_step(X, batch[0].dt, p, out=Yo, stream=stream, baseline=base)
             else:
-                Y = P.run(X, p, Y=Yo, stream=stream)
+                Y = (P.run_baseline if base else P.run)(X, p, Y=Yo, stream=stream)
             # the batch's failure word, ready when the event below completes
             P.run_status(self._status[si], stream=stream)
             ev = torch.cuda.Event()
@@ -252,9 +267,12 @@ class Server:
                 else:
                     still.append(item)
             running = still
-            # dispatch: oldest waiting request first, while slots and memory allow
+            # dispatch: oldest waiting request first, while slots and memory
+            # allow, skipping matrices that already have their batches in flight
             while free_streams:
-                heads = [(q[0].arrival, m) for m, q in pending.items() if q]
+                busy = collections.Counter(item[2][0].matrix for item in running)
+                heads = [(q[0].arrival, m) for m, q in pending.items()
+                         if q and busy[m] < self.max_inflight_per_matrix]
                 if not heads:
                     break
                 _, m = min(heads)
@@ -308,7 +326,14 @@ def summarize(results: Sequence[Result], requests: Sequence[Request], plans: Seq
     first = min(r.arrival for r in results)
     last = max(r.done for r in results)
     span = max(last - first, 1e-9)
+    by_matrix = {}
+    for m in sorted({by_id[r.id].matrix for r in results}):
+        lm = np.array([r.latency for r in results if by_id[r.id].matrix == m])
+        by_matrix[m] = {"n": plans[m].n, "requests": int(lm.size),
+                        "p50_ms": float(np.percentile(lm, 50) * 1e3),
+                        "p99_ms": float(np.percentile(lm, 99) * 1e3)}
     return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
             "throughput_rps": len(results) / span, "gflops": fl / span / 1e9,
-            "mean_batch": float(np.mean([r.batch_size for r in results])), "span_s": span}
+            "mean_batch": float(np.mean([r.batch_size for r in results])), "span_s": span,
+            "by_matrix": by_matrix}

@@ -137,3 +137,51 @@ def test_unkept_outputs_equal_alone():
             assert np.array_equal(got[q.id], alone[q.id]), (realtime, q.id, q.kind)
     for P in plans:
         P.close()
+
+
+@pytest.mark.parametrize("inflight", [1, 3])
+def test_baseline_plans_and_inflight_limit(inflight):
+    """Plans served through the p x SpMV kernels (use_baseline) and the limit
+    on batches in flight per matrix change neither result nor order: every
+    output equals the request run alone through the level-blocked kernels, and
+    the per-matrix summary covers every matrix."""
+    torch.cuda.set_device(0)
+    mats = [w.stencil_2d5(40), w.stencil_3d27(14), w.anderson_3d(10)]
+    plans = [mpk.Plan(A) for A in mats]
+    plans[1].tune(schedule="xcd", chunk_nnz=2000)
+    specs = w.serving_requests(48, rate_per_s=4000.0, seed=123, pool_size=3, p_range=(1, 10),
+                               rhs_choices=(1, 2, 4, 8))
+    reqs = []
+    for i, s in enumerate(specs):
+        if i % 6 == 1 and s["R"] % 2 == 0:
+            kind, p, dt = "time_step", 10, 0.5
+        else:
+            kind, p, dt = ("chebyshev" if i % 4 == 0 else "powers"), s["p"], 0.0
+        reqs.append(serve.Request(id=s["id"], arrival=s["t"], matrix=s["matrix"], p=p,
+                                  x=device_x(mats[s["matrix"]].n, s["R"], s["x_seed"]),
+                                  kind=kind, dt=dt))
+    srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20,
+                       max_inflight_per_matrix=inflight, use_baseline=[True, False, True])
+    res = srv.serve(reqs, realtime=False)
+    assert [r.id for r in res] == [q.id for q in reqs]
+    assert all(r.error is None for r in res)
+    assert max(r.batch_size for r in res) > 1
+    for q, r in zip(reqs, res):
+        P = plans[q.matrix]
+        if q.kind == "chebyshev":
+            alone = P.run_recur(q.x, *mpk.chebyshev_coefficients(q.p))
+        elif q.kind == "time_step":
+            alone = P.cheb_time_step(q.x, q.dt, q.p)
+        else:
+            alone = P.run(q.x, q.p)
+        torch.cuda.synchronize()
+        assert r.Y.shape == alone.shape and torch.equal(r.Y, alone), (q.id, q.kind)
+    st = serve.summarize(res, reqs, plans)
+    assert sorted(st["by_matrix"]) == [0, 1, 2]
+    assert sum(v["requests"] for v in st["by_matrix"].values()) == len(reqs)
+    for m, v in st["by_matrix"].items():
+        assert v["n"] == mats[m].n and v["p99_ms"] >= v["p50_ms"] > 0
+    with pytest.raises(ValueError):
+        serve.Server(plans, use_baseline=[True])
+    for P in plans:
+        P.close()

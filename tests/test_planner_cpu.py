@@ -168,18 +168,23 @@ def test_schedules_are_topological(sched, reorder):
 
 
 def _check_xcd_schedule(A, P, s, p):
-    """XCD schedule: chunks inside one level, exact dependency lists, every
-    (chunk, power) once in its owner's queue, write-back flags exactly where a
-    consumer lives in another queue, and the queues drain with one worker each
-    (no cross-queue deadlock)."""
+    """XCD schedule: every chunk boundary on a multiple of 16 rows (line
+    closed) and each chunk inside the aligned span of one level (from its
+    first row rounded up to a multiple of 16 to the next level's), exact
+    dependency lists, every (chunk, power) once in its owner's queue,
+    write-back flags exactly where a consumer lives in another queue, and the
+    queues drain with one worker each (no cross-queue deadlock)."""
     cp, tasks, qp = s["chunk_ptr"], s["tasks"], s["qptr"]
     dp, di, cx, ro = s["dep_ptr"], s["dep_idx"], s["chunk_xcd"], s["remote_out"]
     nc, nq = len(cp) - 1, s["n_queues"]
     lp, perm = P.levels()
     assert cp[0] == 0 and cp[-1] == A.n and np.all(np.diff(cp) > 0)
-    level = np.searchsorted(lp, cp[:-1], side="right") - 1
+    assert np.all(cp[1:-1] % 16 == 0)
+    span = np.minimum(A.n, (lp + 15) // 16 * 16)
+    span[-1] = A.n
+    level = np.searchsorted(span, cp[:-1], side="right") - 1
     assert np.array_equal(level, s["chunk_group"])
-    assert np.all(cp[1:] <= lp[level + 1])
+    assert np.all(cp[1:] <= span[level + 1])
     # exact lists: the chunks the rows read, plus the chunk itself
     iperm = np.empty_like(perm)
     iperm[perm] = np.arange(A.n)
@@ -241,13 +246,12 @@ def test_xcd_schedule_lists_queues_and_progress(reorder):
 
 
 def test_xcd_chunks_start_on_16_row_boundaries():
-    A = w.stencil_3d27(24)
+    A = w.stencil_3d27(23)   # n = 12167: not a multiple of 16
     P = host_plan(A)
     P.tune(schedule="xcd", chunk_nnz=2000)
     s = P.schedule(4)
-    lp, _ = P.levels()
-    inner = set(s["chunk_ptr"].tolist()) - set(lp.tolist())
-    assert inner and all(r % 16 == 0 for r in inner)
+    cp = s["chunk_ptr"]
+    assert cp[-1] == A.n and all(r % 16 == 0 for r in cp[:-1].tolist())
 
 
 def test_xcd_schedule_with_few_workgroups_uses_one_queue():

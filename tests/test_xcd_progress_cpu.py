@@ -1,21 +1,19 @@
 """Host-side model of how the XCD schedule's workgroups make progress when
-two launches share the device (no GPU needed).
+other work shares the device (no GPU needed).
 
-Each launch of the XCD schedule has one task queue per XCD.  The model places
-workgroups on XCDs with a fixed number of slots each, the way a dispatcher
-fills the device when two kernels on different streams overlap, and lets
-every resident workgroup follow a pick rule step by step:
+Each launch of the XCD schedule has one task queue per XCD, and each of its
+workgroups takes the next ticket of the queue of the XCD it runs on and
+holds that task until its inputs are done.  The model places workgroups on
+XCDs with a fixed number of slots each and steps every resident workgroup.
 
-* "ticket" (the kernel's former rule): a workgroup takes the next ticket of
-  its own XCD's queue and holds that task until its inputs are done;
-* "claim" (the kernel's rule now): a workgroup claims only a queue head whose
-  inputs are done, its own XCD's queue first and every queue after a short
-  wait, and never holds a task while waiting.
-
-When the first launch holds every slot of XCDs 0-3 and the second every slot
-of XCDs 4-7, "ticket" deadlocks: each launch's tasks on the other half of the
-device are never taken, and its resident workgroups wait on them for ever.
-"claim" finishes both launches, in dependency order, whatever the placement.
+* Two launches that overlap can deadlock: when the first holds every slot of
+  XCDs 0-3 and the second every slot of XCDs 4-7, each launch's tasks on the
+  other half of the device are never taken and its resident workgroups wait
+  on them for ever.  This is why the library never lets two launches of the
+  XCD kernel run at the same time on one device.
+* One launch at a time finishes even when other work holds some XCDs for a
+  while: that work ends on its own, and the launch's waiting workgroups are
+  then placed on the freed XCDs.
 """
 import random
 
@@ -92,47 +90,16 @@ def step_ticket(g):
     return False
 
 
-def claim(L, j):
-    h = L.head[j]
-    if h >= L.qlen(j):
-        return -2
-    t = L.qptr[j] + h
-    if not L.ready(t):
-        return -1
-    L.head[j] += 1
-    return t
+class Other:
+    """A slot held by some other kernel that finishes after `steps` steps."""
+    def __init__(self, xcd, steps):
+        self.xcd, self.left, self.gone = xcd, steps, False
 
 
-def step_claim(g, steal_after=3):
-    """One step of the rule the kernel uses now."""
-    L, home = g.L, g.xcd % g.L.nq
-    t = claim(L, home)
-    if t < 0 and (t == -2 or g.waited >= steal_after):
-        left = t == -1
-        for i in range(1, L.nq):
-            u = claim(L, (home + i) % L.nq)
-            if u >= 0:
-                t = u
-                break
-            left |= u == -1
-        if t < 0 and not left:
-            g.gone = True
-            return True
-    elif t == -2:
-        g.gone = True
-        return True
-    if t >= 0:
-        L.run(t)
-        g.waited = 0
-        return True
-    g.waited += 1
-    return False
-
-
-def simulate(launches, resident, pending, rule, slots, max_idle=20, max_steps=200000):
-    """resident: {xcd: [WG, ...]}; pending: WGs waiting for a free slot on
-    their XCD, placed in order as slots free up.  Returns 'done' or 'deadlock'."""
-    step = step_ticket if rule == "ticket" else step_claim
+def simulate(launches, resident, pending, slots, max_idle=20, max_steps=200000):
+    """resident: {xcd: [WG or Other, ...]}; pending: WGs waiting for a free
+    slot on their XCD, placed in order as slots free up.  Returns 'done' or
+    'deadlock'."""
     idle = 0
     for _ in range(max_steps):
         if all(L.left == 0 for L in launches):
@@ -140,7 +107,12 @@ def simulate(launches, resident, pending, rule, slots, max_idle=20, max_steps=20
         changed = False
         for x in range(N_XCD):
             for g in list(resident[x]):
-                changed |= step(g)
+                if isinstance(g, Other):
+                    g.left -= 1
+                    g.gone = g.left <= 0
+                    changed = True
+                else:
+                    changed |= step_ticket(g)
                 if g.gone:
                     resident[x].remove(g)
                     for pg in list(pending):
@@ -174,47 +146,48 @@ def sched():
     return xcd_schedule(w.anderson_3d(10), p=5, chunk=120)
 
 
-def test_ticket_rule_deadlocks_when_launches_split_the_xcds(sched):
+def test_overlapping_launches_can_deadlock(sched):
     launches, resident, pending = split_placement(sched, slots=2, wgs_per_launch=16)
-    assert simulate(launches, resident, pending, "ticket", slots=2) == "deadlock"
+    assert simulate(launches, resident, pending, slots=2) == "deadlock"
     assert all(L.left > 0 for L in launches)
 
 
-def test_claim_rule_finishes_both_launches_split_across_xcds(sched):
-    launches, resident, pending = split_placement(sched, slots=2, wgs_per_launch=16)
-    assert simulate(launches, resident, pending, "claim", slots=2) == "done"
-    for L in launches:
-        assert len(L.seen) == len(L.tasks)
+def test_one_launch_finishes_with_every_xcd(sched):
+    L = Launch(sched)
+    resident = {x: [WG(L, x) for _ in range(2)] for x in range(N_XCD)}
+    assert simulate([L], resident, [], slots=2) == "done"
+    assert len(L.seen) == len(L.tasks)
+
+
+def test_one_launch_finishes_while_other_work_holds_xcds(sched):
+    # XCDs 2, 5 and 6 are full of other kernels' workgroups for a while; the
+    # launch's workgroups for them wait and are placed once those finish
+    L = Launch(sched)
+    resident = {x: [] for x in range(N_XCD)}
+    pending = []
+    for x in range(N_XCD):
+        if x in (2, 5, 6):
+            resident[x] = [Other(x, 40 + 10 * x), Other(x, 300)]
+            pending += [WG(L, x), WG(L, x)]
+        else:
+            resident[x] = [WG(L, x), WG(L, x)]
+    assert simulate([L], resident, pending, slots=2) == "done"
+    assert len(L.seen) == len(L.tasks)
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_claim_rule_finishes_under_random_placement(sched, seed):
+def test_one_launch_finishes_under_random_placement(sched, seed):
     rng = random.Random(seed)
     slots = rng.choice([1, 2, 3])
-    launches = [Launch(sched) for _ in range(rng.choice([1, 2, 3]))]
-    wgs = []
-    for L in launches:
-        wgs += [WG(L, rng.randrange(N_XCD)) for _ in range(rng.choice([4, 16, 64]))]
-    rng.shuffle(wgs)
+    L = Launch(sched)
     resident = {x: [] for x in range(N_XCD)}
     pending = []
+    for x in range(N_XCD):   # some slots start with other work of random length
+        for _ in range(rng.randrange(slots + 1)):
+            resident[x].append(Other(x, rng.randrange(1, 500)))
+    wgs = [WG(L, i % N_XCD) for i in range(rng.choice([8, 16, 64]))]
+    rng.shuffle(wgs)
     for g in wgs:
         (resident[g.xcd] if len(resident[g.xcd]) < slots else pending).append(g)
-    assert simulate(launches, resident, pending, "claim", slots=slots) == "done"
-    for L in launches:
-        assert len(L.seen) == len(L.tasks)
-
-
-def test_claim_rule_with_a_single_resident_workgroup(sched):
-    L = Launch(sched)
-    resident = {x: [] for x in range(N_XCD)}
-    resident[5] = [WG(L, 5)]
-    assert simulate([L], resident, [], "claim", slots=1) == "done"
-
-
-def test_ticket_rule_finishes_when_one_launch_has_every_xcd(sched):
-    # the former rule was sound for a lone launch with a workgroup on every XCD
-    L = Launch(sched)
-    resident = {x: [WG(L, x) for _ in range(2)] for x in range(N_XCD)}
-    assert simulate([L], resident, [], "ticket", slots=2) == "done"
+    assert simulate([L], resident, pending, slots=slots) == "done"
     assert len(L.seen) == len(L.tasks)
