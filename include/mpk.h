@@ -137,6 +137,13 @@ typedef struct {
                                 0 (default) = only where a cache line of an
                                 output could have been read before it was
                                 complete (see mpk_run)                          */
+    int dynamic_tickets;     /* WAVE, POWERS: 1 = workgroups take tasks from a
+                                shared counter; 0 (default) = workgroup b takes
+                                tasks b, b + W, b + 2W, ... (W workgroups) where
+                                the launch can hold the device alone: outside
+                                graph capture, without skip-ahead, with every
+                                workgroup resident; such launches (and XCD
+                                launches) wait for each other on a device     */
 } mpk_tune_t;
 
 typedef struct {
@@ -432,8 +439,10 @@ mpk_status_t mpk_run_status(mpk_plan_t plan, void *hip_stream, int32_t *status);
  * two segments, skip-ahead parking), keeps the fastest and sets it on the
  * plan.  Each candidate runs once untimed, then
  * `reps` timed runs on `stream` (mean).  Results are cached per (matrix
- * fingerprint, value precision, p, nrhs, recurrence): a later call with the
+ * fingerprint, value precision, p, nrhs, recur): a later call with the
  * same key applies the cached tuning without timing unless force != 0.
+ * recur: 0 = time mpk_run, 1 = mpk_run_recur, 2 = the weighted sums of
+ * mpk_run_poly (p >= 4; their kernels differ from the plain run's).
  * x: n*nrhs doubles, Y: p*n*nrhs doubles (device scratch; overwritten).
  * best / best_ms may be NULL.  The call synchronizes `stream`.
  * Errors: as mpk_run; MPK_ETIMEOUT if a candidate's waits hit their limit.
@@ -449,6 +458,9 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
  * workspace reserved for it.  Launches of one graph must not overlap (launch
  * it on one stream, or synchronize between streams); the graph must be
  * destroyed before its plan.  The capture itself runs on a private stream.
+ * A graph that holds a static-order or XCD-queue launch (mpk_tune_t
+ * dynamic_tickets) is ordered by mpk_graph_launch after every such launch
+ * issued before it on the device, like the eager runs.
  */
 typedef struct mpk_graph_s *mpk_graph_t;
 mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs,

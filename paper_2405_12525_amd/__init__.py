@@ -298,7 +298,9 @@ class Plan:
     def autotune(self, x, p: int, Y=None, reps: int = 3, force: bool = False, recur: bool = False,
                  stream=None) -> dict:
         """Time the candidate tunings for (p, nrhs) and keep the fastest
-        (mpk_plan_autotune).  Y is scratch.  Returns the tuning plus "ms"."""
+        (mpk_plan_autotune).  recur: False = the plain run, True = the
+        recurrence, 2 = the weighted sums of run_poly.  Y is scratch.  Returns
+        the tuning plus "ms"."""
         R, Y = self._prep(x, p, Y)
         t = _capi.Tune()
         ms = ctypes.c_double(0.0)

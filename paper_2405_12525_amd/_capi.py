@@ -47,7 +47,8 @@ class Tune(ctypes.Structure):
                 ("cache_safety", ctypes.c_double), ("chunk_nnz", ctypes.c_int),
                 ("lag", ctypes.c_int), ("workgroups", ctypes.c_int),
                 ("spin_limit_us", ctypes.c_int64), ("seg_powers", ctypes.c_int),
-                ("skip_ahead", ctypes.c_int), ("acquire_always", ctypes.c_int)]
+                ("skip_ahead", ctypes.c_int), ("acquire_always", ctypes.c_int),
+                ("dynamic_tickets", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -351,21 +351,28 @@ int32_t *status_word(mpk_plan_t plan, hipStream_t stream) {
     return plan->status_words.as<int32_t>() + slot;
 }
 
-// Per device: the event recorded after the latest launch of the XCD
-// schedule's kernel.  Its workgroups serve the queue of the XCD they run on,
-// so two overlapping launches could each fill the XCDs the other one's
-// queues need and wait for each other until their limits; every such launch
-// therefore waits for the previous one (other kernels may overlap it: they
-// finish on their own, after which its workgroups get every XCD).
-struct XcdGate {
+// Per device: the event recorded after the latest launch of a persistent
+// kernel whose progress needs workgroups resident: the XCD schedule's (its
+// workgroups serve the queue of the XCD they run on) and the static-order
+// level-blocked kernel (every workgroup's tasks are fixed in advance).  Two
+// overlapping launches could each hold compute units the other one's
+// waiting tasks need and wait for each other until their limits; every such
+// launch therefore waits for the previous one (other kernels may overlap
+// it: they finish on their own, after which its workgroups get the device).
+struct DeviceGate {
     std::mutex mu;
     hipEvent_t ev = nullptr;
     bool recorded = false;
 };
-XcdGate &xcd_gate(int device) {
-    static XcdGate gates[64];
+DeviceGate &device_gate(int device) {
+    static DeviceGate gates[64];
     return gates[device >= 0 && device < 64 ? device : 0];
 }
+
+// Set by mpk_graph_capture* around their capture: launches that need the
+// gate may be captured, and the flag it points to is raised when one is;
+// mpk_graph_launch then takes the gate around the whole graph.
+thread_local bool *t_capture_gated = nullptr;
 
 // The sliced layout of the plan's matrix, built on the device from its CSR
 // (plan row order), unless padding each slice to its longest row would add
@@ -397,7 +404,7 @@ mpk_status_t build_sell(mpk_plan_t plan) {
 // outside any capture): the zeroed failure words.
 mpk_status_t init_device_state(mpk_plan_t plan) {
     {
-        XcdGate &gate = xcd_gate(plan->device);
+        DeviceGate &gate = device_gate(plan->device);
         std::lock_guard<std::mutex> g(gate.mu);
         if (!gate.ev) {
             hipError_t e = hipEventCreateWithFlags(&gate.ev, hipEventDisableTiming);
@@ -411,6 +418,16 @@ mpk_status_t init_device_state(mpk_plan_t plan) {
     if (st) return st;
     hipError_t e = hipMemset(plan->status_words.ptr, 0, kStatusSlots * sizeof(int32_t));
     return e == hipSuccess ? MPK_OK : hip_fail(e, "hipMemset");
+}
+
+int resident_workgroups(mpk_plan_t plan, int R, bool acc) {
+    const long long key = -((long long)plan->value_bits * 1000 + R * 2 + (acc ? 1 : 0)) - 1;
+    auto it = plan->wg_cache.find(key);
+    if (it != plan->wg_cache.end()) return it->second;
+    const int wg = lb_resident_workgroups(plan->value_bits, R, plan->device,
+                                          plan->d_scol.ptr != nullptr, acc);
+    plan->wg_cache[key] = wg;
+    return wg;
 }
 
 int default_workgroups(mpk_plan_t plan, int R) {
@@ -647,32 +664,46 @@ mpk_status_t run_lb(mpk_plan_t plan, const double *x, int p, int nrhs, const dou
                                ((size_t)plan->n * nrhs) % kLineRows == 0 &&
                                reinterpret_cast<uintptr_t>(Y) % 128 == 0;
         const int acquire = (plan->tune.acquire_always || !lines_own) ? 1 : 0;
-        if (!se->host.qptr.empty()) {
+        const bool xcd = !se->host.qptr.empty();
+        // static task order: only where the launch can hold the device alone
+        // (not under capture, whose launches the gate cannot order; no
+        // skip-ahead; every workgroup resident at once)
+        const bool own_capture = capturing && t_capture_gated != nullptr;
+        const bool static_order = !xcd && (!capturing || own_capture) &&
+                                  !plan->tune.dynamic_tickets && plan->tune.skip_ahead == 0 &&
+                                  wg <= resident_workgroups(plan, nrhs, poly != nullptr);
+        // at most one gated launch in flight per device: wait for the
+        // previous one (any stream, any plan), then become the one to wait
+        // for; under the library's own capture the graph's launch takes the
+        // gate instead (another caller's capture is the caller's to order)
+        if ((xcd || static_order) && own_capture) *t_capture_gated = true;
+        const bool gated = (xcd || static_order) && !capturing;
+        DeviceGate &gate = device_gate(plan->device);
+        std::unique_lock<std::mutex> gl(gate.mu, std::defer_lock);
+        if (gated) {
+            gl.lock();
+            if (gate.ev && gate.recorded) {
+                e = hipStreamWaitEvent(stream, gate.ev, 0);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+            }
+        }
+        if (xcd) {
             DevXcdSchedule xs{ss->view(), ss->bound_sptr.as<int32_t>(), se->chunk_row.as<int32_t>(),
                               se->dep_ptr.as<int32_t>(),
                               se->dep_idx.as<int32_t>(),
                               se->tasks.as<int32_t>(), se->qptr.as<int32_t>(),
                               se->host.n_queues, se->host.n_chunks()};
-            // at most one launch of this kernel in flight per device: wait for
-            // the previous one (any stream, any plan), then become the one to
-            // wait for (not under capture: a captured graph's launches are
-            // the caller's to order)
-            XcdGate &gate = xcd_gate(plan->device);
-            std::lock_guard<std::mutex> gg(gate.mu);
-            if (!capturing && gate.ev && gate.recorded) {
-                e = hipStreamWaitEvent(stream, gate.ev, 0);
-                if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-            }
             rc = launch_xcd(m, xs, wv, a, &cf, acp, wg, spin_ticks, acquire, stream);
-            if (!rc && !capturing && gate.ev) {
-                e = hipEventRecord(gate.ev, stream);
-                if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-                gate.recorded = true;
-            }
         } else {
             rc = launch_lb(m, ds, wv, a, &cf, acp, wg, spin_ticks, plan->tune.skip_ahead,
-                           acquire, stream);
+                           acquire, static_order, stream);
         }
+        if (!rc && gated && gate.ev) {
+            e = hipEventRecord(gate.ev, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            gate.recorded = true;
+        }
+        if (gl.owns_lock()) gl.unlock();
         if (rc) return hip_fail((hipError_t)rc, "level-blocked kernel launch");
         if (na) continue;
         if (capturing) {
@@ -897,6 +928,7 @@ void mpk_tune_default(mpk_tune_t *t) {
     t->seg_powers = 0;
     t->skip_ahead = 0;
     t->acquire_always = 0;
+    t->dynamic_tickets = 0;
 }
 
 mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
@@ -1191,6 +1223,8 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
         return fail(MPK_EINVAL, "negative tuning value");
     if (t.acquire_always != 0 && t.acquire_always != 1)
         return fail(MPK_EINVAL, "acquire_always must be 0 or 1");
+    if (t.dynamic_tickets != 0 && t.dynamic_tickets != 1)
+        return fail(MPK_EINVAL, "dynamic_tickets must be 0 or 1");
     std::lock_guard<std::mutex> g(plan->mu);
     plan->tune = t;
     // schedules may still be read by queued kernels: keep them until destroy
@@ -1451,6 +1485,9 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     if (st) return st;
     if (reps < 1 || reps > 100) return fail(MPK_EINVAL, "reps must be in [1, 100]");
     if (plan->n == 0) return fail(MPK_EINVAL, "nothing to tune for an empty matrix");
+    if (recur < 0 || recur > 2) return fail(MPK_EINVAL, "recur must be 0, 1 or 2");
+    if (recur == 2 && p < 4)
+        return fail(MPK_EINVAL, "tuning the weighted sums needs p >= 4 (Y holds their scratch)");
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (stream) (void)hipStreamIsCapturing(stream, &cap);
@@ -1458,7 +1495,7 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     using Key = std::tuple<uint64_t, int, int, int, int>;
     static std::mutex cache_mu;
     static std::map<Key, std::pair<mpk_tune_t, double>> cache;
-    const Key key{plan->fingerprint, plan->value_bits, p, nrhs, recur ? 1 : 0};
+    const Key key{plan->fingerprint, plan->value_bits, p, nrhs, recur};
     mpk_tune_t base;
     {
         std::lock_guard<std::mutex> g(plan->mu);
@@ -1520,15 +1557,18 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     }
     if (cus > 0 && plan->d_scol.ptr) {
         // sliced layout: two or four workgroups per compute unit, and a
-        // wavefront slack of 2-5 times the running workgroups per power
+        // wavefront slack of 1-3 times the running workgroups per power
         // (the default is 8 times: no waits, but a window far beyond the
         // fast cache; smaller slack keeps the window smaller and the
-        // inputs cached, at the risk of waits that cascade)
+        // inputs cached, at the risk of waits that cascade); power order
+        // with up to eight workgroups per compute unit
         for (int wpc : {2, 4})
-            for (int m : {2, 3, 5})
+            for (int m2 : {2, 3, 4, 6})
                 for (int chunk : {8192, 16384})
-                    add(MPK_SCHED_WAVE, 64, chunk, std::max(1, m * wpc * cus / p), wpc * cus);
-        add(MPK_SCHED_POWERS, 64, 8192, 0, 2 * cus);
+                    add(MPK_SCHED_WAVE, 64, chunk, std::max(1, m2 * wpc * cus / (2 * p)),
+                        wpc * cus);
+        for (int wpc : {2, 4, 8})
+            for (int chunk : {8192, 16384}) add(MPK_SCHED_POWERS, 64, chunk, 0, wpc * cus);
     }
     if (p >= 4) add(MPK_SCHED_WAVE, 64, 32768, 0, 0, (p + 1) / 2);  // two segments
     add(MPK_SCHED_WAVE, 64, 16384, 0, 0, 0, 2);                     // park up to two tasks
@@ -1544,7 +1584,18 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
         (void)hipEventDestroy(e0);
         return hip_fail(e, "hipEventCreate");
     }
+    // weighted sums (recur == 2): Chebyshev time-step weights for dt = 1, the
+    // sums and the two-vector ring in Y (the values do not change the time)
+    const size_t vec = (size_t)plan->n * nrhs;
+    std::vector<double> tal(p), tbe(p), tga(p), twa(p + 1), twb(p + 1);
+    if (recur == 2 &&
+        (st = mpk_cheb_time_coefficients(p, 1.0, tal.data(), tbe.data(), tga.data(), twa.data(),
+                                          twb.data())))
+        return st;
     auto one = [&]() {
+        if (recur == 2)
+            return run_poly(plan, x, p, nrhs, tal.data(), tbe.data(), tga.data(), twa.data(),
+                            twb.data(), Y, Y + 2 * vec, stream_v, false);
         return recur ? run_lb(plan, x, p, nrhs, al.data(), be.data(), ga.data(), Y, stream_v)
                      : run_lb(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream_v);
     };
@@ -1605,6 +1656,8 @@ struct mpk_graph_s {
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int device = 0;
+    bool gated = false;  // holds a launch that needs the device gate
     ~mpk_graph_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1646,9 +1699,12 @@ mpk_status_t mpk_graph_capture(mpk_plan_t plan, const double *x, int p, int nrhs
             }
         }
     }
+    g->device = plan->device;
     e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    t_capture_gated = &g->gated;
     st = run_lb(plan, x, p, nrhs, alpha, beta, gamma, Y, g->stream);
+    t_capture_gated = nullptr;
     e = hipStreamEndCapture(g->stream, &g->graph);
     if (st) return st;
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -1718,10 +1774,13 @@ mpk_status_t mpk_graph_capture_time_step(mpk_plan_t plan, const double *psi, int
             }
         }
     }
+    g->device = plan->device;
     e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    t_capture_gated = &g->gated;
     st = run_poly(plan, psi, M, nrhs, al.data(), be.data(), ga.data(), wa.data(), wb.data(), acc,
                   work, g->stream, baseline != 0);
+    t_capture_gated = nullptr;
     if (!st && plan->n > 0) {
         const int rc = launch_combine_complex(acc, acc + (size_t)plan->n * nrhs, plan->n, nrhs,
                                               out, g->stream);
@@ -1736,10 +1795,26 @@ mpk_status_t mpk_graph_capture_time_step(mpk_plan_t plan, const double *psi, int
     return MPK_OK;
 }
 
-mpk_status_t mpk_graph_launch(mpk_graph_t graph, void *stream) {
+mpk_status_t mpk_graph_launch(mpk_graph_t graph, void *stream_v) {
     if (!graph) return fail(MPK_EINVAL, "graph is NULL");
-    hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    if (!graph->gated) {
+        hipError_t e = hipGraphLaunch(graph->exec, stream);
+        return e == hipSuccess ? MPK_OK : hip_fail(e, "hipGraphLaunch");
+    }
+    // the graph holds a launch that must not overlap another gated one
+    DeviceGate &gate = device_gate(graph->device);
+    std::lock_guard<std::mutex> gl(gate.mu);
+    hipError_t e = hipSuccess;
+    if (gate.ev && gate.recorded) e = hipStreamWaitEvent(stream, gate.ev, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    e = hipGraphLaunch(graph->exec, stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if (gate.ev) {
+        e = hipEventRecord(gate.ev, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        gate.recorded = true;
+    }
     return MPK_OK;
 }
 

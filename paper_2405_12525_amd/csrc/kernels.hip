@@ -578,6 +578,8 @@ struct LBParams {
     int64_t spin_limit;   // wall-clock ticks
     int32_t pending;      // skip-ahead slots (lbs_kernel)
     int32_t acquire;      // invalidate caches before a task reads its inputs
+    int32_t stride;       // > 0: workgroup b takes tasks b, b + stride, ...
+                          // (every workgroup resident); 0: a shared counter
 };
 
 // One non-blocking look at task t's inputs by wavefront 0 (all 64 lanes):
@@ -594,22 +596,31 @@ __device__ __forceinline__ bool inputs_ready(const LBParams &P, int32_t t) {
 }
 
 // Persistent kernel: workgroups take tasks (chunk c, power k) in schedule
-// order from a shared ticket counter.  Before computing, a task waits until
-// every chunk in [dep_lo[c], dep_hi[c]] has completed power k-1 and then
-// invalidates its caches (acquire) where needed; it computes with
-// write-through stores and publishes done[c] = k once they have completed.
-// Dependencies always carry smaller tickets and a workgroup holds one ticket
-// at a time, so the smallest unfinished ticket can always proceed; every
-// wait is also bounded by spin_limit, after which the run is flagged as
-// failed and all workgroups leave.
+// order, either from a shared ticket counter or, with P.stride = the number
+// of workgroups, statically: workgroup b takes tickets b, b + stride, ...
+// Before computing, a task waits until every chunk in [dep_lo[c], dep_hi[c]]
+// has completed power k-1 and then invalidates its caches (acquire) where
+// needed; it computes with write-through stores and publishes done[c] = k
+// once they have completed.  Dependencies always carry smaller tickets and a
+// workgroup takes its tickets in increasing order, one at a time, so the
+// holder of the smallest unfinished ticket can always proceed: with the
+// counter, tickets go only to running workgroups; with the static order,
+// only if every workgroup of the launch is resident, which the host ensures
+// (the grid fits the device and no other launch of a static or XCD-queue
+// kernel overlaps it).  The static order spares each task a round trip to a
+// counter that every workgroup of the device contends for, measured as the
+// larger part of a task's cost on matrices whose windows fit the caches.
+// Every wait is also bounded by spin_limit, after which the run is flagged
+// as failed and all workgroups leave.
 template <typename V, int RC, bool ACC, bool SELL>
 __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, const AccCoefs *ac) {
     __shared__ int32_t s_ticket;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
     if (tid == 0)
-        s_ticket = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+        s_ticket = P.stride ? (int32_t)blockIdx.x
+                            : __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     // All loop control below is made provably uniform (readfirstlane) and the
     // loop has a single exit: a loop whose exit the compiler considers
@@ -670,8 +681,9 @@ __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, cons
         __syncthreads();
         if (tid == 0) {
             __hip_atomic_store(P.ws.done + c, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_ticket = __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = P.stride ? t + P.stride
+                                : __hip_atomic_fetch_add(P.ws.ticket, 1, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_ticket);
@@ -1245,6 +1257,17 @@ int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr,
     return (int)hipGetLastError();
 }
 
+int lb_resident_workgroups(int value_bits, int R, int device, bool sell, bool acc) {
+    const void *fn = acc ? reinterpret_cast<const void *>(lb_acc_fn(value_bits, R, false, sell))
+                         : reinterpret_cast<const void *>(lb_fn(value_bits, R, false, sell));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess)
+        return 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
+    return per_cu * prop.multiProcessorCount;
+}
+
 int lb_max_workgroups(int value_bits, int R, int device, bool sell) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -1263,12 +1286,13 @@ int lb_max_workgroups(int value_bits, int R, int device, bool sell) {
 
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-              int64_t spin_limit, int pending, int acquire, void *stream) {
+              int64_t spin_limit, int pending, int acquire, bool static_order, void *stream) {
     if (a.R < 1 || a.R > 16) return (int)hipErrorInvalidValue;
     if (a.p < 1 || a.p > kMaxSegPowers || workgroups < 1) return (int)hipErrorInvalidValue;
     if (pending < 0 || pending > kMaxPending) return (int)hipErrorInvalidValue;
+    if (static_order && pending > 0) return (int)hipErrorInvalidValue;
     if (s.n_tasks == 0) return 0;
-    LBParams P{m, s, ws, a, spin_limit, pending, acquire ? 1 : 0};
+    LBParams P{m, s, ws, a, spin_limit, pending, acquire ? 1 : 0, static_order ? workgroups : 0};
     Coefs c{};
     if (cf) c = *cf;
     const bool sell = m.scol != nullptr;

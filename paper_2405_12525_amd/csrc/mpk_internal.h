@@ -80,6 +80,9 @@ int gpu_sample_cols(const int32_t *col, int64_t step, int64_t count, std::vector
 // r % 64, so that the 64 rows of a slice read slot j with one coalesced
 // access.  Slots past a row's length are padding and never read.
 constexpr int kSellRows = 64;
+// Row alignment of the persistent schedules' chunks: four slices, one pass
+// of a 256-thread workgroup over a chunk of one right-hand side.
+constexpr int kChunkRows = 4 * kSellRows;
 // gpu_sell_widths: width of every slice (host copy).  gpu_sell_fill: rlen[n]
 // and the slotted columns and values (value_bits 64 or 32, like val) into
 // buffers of `entries` = soff[n_slices] slots.
@@ -288,9 +291,13 @@ int launch_status_copy(int32_t *status_word, int32_t *out, void *stream);
 // acquire = 0: tasks read their inputs without invalidating caches first
 // (only valid for a line-closed schedule whose outputs are written in plan
 // order into 128-byte aligned vectors, see Schedule::line_closed).
+// static_order: workgroup b takes tasks b, b + workgroups, ... instead of
+// tickets from the shared counter; valid only if every workgroup of the
+// launch is resident (workgroups <= lb_resident_workgroups and no other
+// static-order or XCD-queue launch overlapping it); not with pending > 0.
 int launch_lb(const DevMatrix &m, const DevSchedule &s, const DevWorkspace &ws,
               const SegArgs &a, const Coefs *cf, const AccCoefs *acc, int workgroups,
-              int64_t spin_limit, int pending, int acquire, void *stream);
+              int64_t spin_limit, int pending, int acquire, bool static_order, void *stream);
 // One diagonal of the STEPS schedule: workgroup b runs task tasks[b] = (chunk, power).
 int launch_step(const DevMatrix &m, DevSlices sl, const int32_t *chunk_sptr,
                 const int32_t *chunk_row, const int32_t *tasks, int32_t n_tasks,
@@ -324,5 +331,8 @@ int detect_xcds(int device);
 // capped at two per compute unit for the LDS-staged routine and four for the
 // sliced layout (sell).
 int lb_max_workgroups(int value_bits, int R, int device, bool sell);
+// Workgroups of the level-blocked kernel (acc: the weighted-sum form) that
+// the device holds at once: occupancy per compute unit x compute units.
+int lb_resident_workgroups(int value_bits, int R, int device, bool sell, bool acc);
 
 }  // namespace mpk

@@ -578,11 +578,13 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
 
     // 2. chunks.  The persistent wavefront and power-order schedules track
     // dependencies per chunk and need no group structure: their chunks are
-    // cut at about chunk_nnz nonzeros on multiples of kSellRows rows (a chunk
-    // may span a group boundary; chunk_group is the group of its first row),
-    // so that each 128-byte line of an output vector belongs to one chunk
-    // (line_closed) and chunks hold whole slices of the sliced layout.  The
-    // diagonal schedules cut every group on its own.
+    // cut at about chunk_nnz nonzeros on multiples of kChunkRows rows (a
+    // chunk may span a group boundary; chunk_group is the group of its first
+    // row), so that each 128-byte line of an output vector belongs to one
+    // chunk (line_closed), chunks hold whole slices of the sliced layout, and
+    // a 256-thread workgroup runs a chunk of one right-hand side in full
+    // passes (a chunk of 320 rows would leave three of its four waves idle in
+    // the second pass).  The diagonal schedules cut every group on its own.
     s.chunk_ptr.push_back(0);
     const bool aligned = tune.schedule == MPK_SCHED_WAVE || tune.schedule == MPK_SCHED_POWERS;
     if (aligned) {
@@ -597,8 +599,8 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
             int64_t e = std::upper_bound(rp.begin() + r + 1, rp.begin() + n + 1, (int32_t)lim) -
                         rp.begin() - 1;
             e = std::min<int64_t>(e, r + 65536);
-            e -= e % kSellRows;
-            if (e <= r) e = r + kSellRows;  // at least one slice
+            e -= e % kChunkRows;
+            if (e <= r) e = r + kChunkRows;  // at least one full pass
             e = std::min<int64_t>(e, n);
             while (lev + 1 < n_levels && lp[lev + 1] <= r) ++lev;
             s.chunk_ptr.push_back((int32_t)e);

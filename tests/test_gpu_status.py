@@ -149,3 +149,78 @@ def test_concurrent_xcd_and_wave_runs_complete():
         assert np.array_equal(Y.cpu().numpy(), oracle.powers(A, x.cpu().numpy(), 5))
     for P in plans:
         P.close()
+
+
+def test_static_and_dynamic_task_orders_agree_and_overlap_safely():
+    """The static task order (every workgroup takes every W-th ticket) and
+    the shared counter give the same bits; static-order launches of several
+    plans on several streams, mixed with XCD, dynamic and per-diagonal
+    launches, all complete (the device gate orders the ones that need the
+    device alone) and match the oracle."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    mats = [w.stencil_3d27(18), w.anderson_3d(12), w.stencil_2d5(90), w.stencil_3d27(14)]
+    plans = [mpk.Plan(A) for A in mats]
+    plans[0].tune(schedule="powers", chunk_nnz=2000, workgroups=8 * cus)
+    plans[1].tune(schedule="wave", chunk_nnz=1500, workgroups=2 * cus, lag=40)
+    plans[2].tune(schedule="xcd", chunk_nnz=800)
+    plans[3].tune(schedule="wave", chunk_nnz=1200, dynamic_tickets=1)
+    # same bits with either order on one plan
+    x = dev_x(mats[0].n, 3, 77)
+    Ys = plans[0].run(x, 6)
+    plans[0].tune(dynamic_tickets=1)
+    Yd = plans[0].run(x, 6)
+    torch.cuda.synchronize()
+    plans[0].sync()
+    assert torch.equal(Ys, Yd)
+    plans[0].tune(dynamic_tickets=0)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    jobs = []
+    for rep in range(5):
+        for i, (A, P) in enumerate(zip(mats, plans)):
+            s = streams[(rep + i) % len(streams)]
+            x = dev_x(A.n, 1 + (rep % 4), 100 * rep + i)
+            Y = torch.empty((6, A.n, x.shape[1]), dtype=torch.float64, device="cuda")
+            with torch.cuda.stream(s):
+                P.run(x, 6, Y, stream=s)
+            jobs.append((A, P, x, Y, s))
+    torch.cuda.synchronize()
+    for P, s in {(P, s) for _, P, _, _, s in jobs}:
+        assert status_of(P, s) == 0
+    for P in plans:
+        P.sync()
+    for A, P, x, Y, _ in jobs:
+        assert np.array_equal(Y.cpu().numpy(), oracle.powers(A, x.cpu().numpy(), 6))
+    for P in plans:
+        P.close()
+
+
+def test_captured_static_order_runs_overlap_safely_with_eager_runs():
+    """Graphs captured with the static task order are gated at launch: two
+    graphs replayed on two streams next to eager static-order runs of
+    another plan all complete, every replay equal to the oracle."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    A, B = w.stencil_3d27(16), w.anderson_3d(11)
+    PA, PB = mpk.Plan(A), mpk.Plan(B)
+    PA.tune(schedule="wave", chunk_nnz=1500, workgroups=4 * cus, lag=30)
+    PB.tune(schedule="powers", chunk_nnz=1000, workgroups=8 * cus)
+    xa = [dev_x(A.n, 2, 500 + i) for i in range(2)]
+    Ya = [torch.empty((5, A.n, 2), dtype=torch.float64, device="cuda") for _ in range(2)]
+    graphs = [PA.capture(xa[i], 5, Ya[i]) for i in range(2)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    xb = dev_x(B.n, 3, 600)
+    refs_a = [oracle.powers(A, xa[i].cpu().numpy(), 5) for i in range(2)]
+    ref_b = oracle.powers(B, xb.cpu().numpy(), 7)
+    for rep in range(4):
+        for i, G in enumerate(graphs):
+            G.launch(stream=streams[i])
+        Yb = PB.run(xb, 7, stream=streams[2])
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert np.array_equal(Ya[i].cpu().numpy(), refs_a[i]), (rep, i)
+        assert np.array_equal(Yb.cpu().numpy(), ref_b), rep
+    PA.sync()
+    PB.sync()
+    for G in graphs:
+        G.close()
+    PA.close()
+    PB.close()
