@@ -29,6 +29,13 @@ Distributed-Memory Parallel Matrix Power Kernels", that it follows):
 * :func:`lp_diagonal_order` -- the LB-MPK traversal of the Lp diagram: the
   diagonals i + p = const in increasing order, each walked from bottom-right
   (largest level) to top-left (Fig. lp_basic).
+* :func:`sublevel_root` / :func:`sublevels` -- levels broken into
+  sub-levels (the paper's recursion stage s_m, Sec. "Experimental Setup",
+  breaks bulky levels down; it gives no construction, so this is a
+  reading): a second breadth-first distance d2 from a second root is taken
+  over the whole graph, and the sub-level of a vertex is the pair (its level,
+  d2).  Both coordinates change by at most one along any edge, so every edge
+  joins equal or adjacent sub-levels.
 """
 from __future__ import annotations
 
@@ -378,3 +385,49 @@ def permute_csr(A, perm):
         col[rowptr[new]:rowptr[new + 1]] = iperm[A.col[s:e]]
         val[rowptr[new]:rowptr[new + 1]] = A.val[s:e]
     return type(A)(n, rowptr.astype(np.int32), col, val, A.name + "_perm")
+
+
+def _distances(n: int, rowptr, col, root: int):
+    """d(v) = index of v's level in bfs_levels(root): the graph distance from
+    root inside root's component; later components continue the count."""
+    levels, _, _ = bfs_levels(n, rowptr, col, root)
+    d = np.empty(n, dtype=np.int64)
+    for i, L in enumerate(levels):
+        d[np.asarray(L, dtype=np.int64)] = i
+    return d
+
+
+def sublevel_root(n: int, rowptr, col, root: int = 0) -> int:
+    """Second root for the sub-levels of the levels rooted at `root`.
+
+    Reading (the paper gives none): take the widest level W of
+    bfs_levels(root) (the first one among equals), its smallest vertex w, and
+    return the vertex of W farthest from w in G(A) (ties to the smaller
+    index).  On a grid this puts the second root at the other end of the
+    widest level, so that the second distance runs across the levels.
+    """
+    if n == 0:
+        return 0
+    levels, _, _ = bfs_levels(n, rowptr, col, root)
+    W = max(levels, key=len)  # max returns the first widest
+    w = W[0]
+    d = _distances(n, rowptr, col, w)
+    return max(W, key=lambda v: (d[v], -v))
+
+
+def sublevels(n: int, rowptr, col, root: int = 0, root2=None):
+    """Sub-levels of the levels rooted at `root`.
+
+    d1(v) is v's level in bfs_levels(root), d2(v) its level in
+    bfs_levels(root2) (root2 = sublevel_root(root) when None).  Rows are
+    ordered by (d1, d2, original index): each level is a run of sub-levels.
+    Returns (d1, d2, perm, iperm) with perm[new] = old.
+    """
+    if root2 is None:
+        root2 = sublevel_root(n, rowptr, col, root)
+    d1 = _distances(n, rowptr, col, root)
+    d2 = _distances(n, rowptr, col, root2)
+    perm = np.array(sorted(range(n), key=lambda v: (d1[v], d2[v], v)), dtype=np.int64)
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[perm] = np.arange(n)
+    return d1, d2, perm, iperm

@@ -374,3 +374,106 @@ def test_peripheral_root_of_a_grid_is_a_corner():
     for start in (40, 13, 0):
         r = oracle.pseudo_peripheral_root(A.n, A.rowptr, A.col, start=start)
         assert r in (0, 8, 72, 80), (start, r)
+
+
+# ------------------------------------------------------------------ sub-levels
+# (levels broken into sub-levels by a second breadth-first distance; the
+# paper names the recursion stage s_m in Sec. "Experimental Setup" but gives
+# no construction, so these pin the reading the oracle states)
+
+def _coords(v, L):
+    return v % L, (v // L) % L, v // (L * L)
+
+
+@pytest.mark.parametrize("L", [5, 8])
+def test_sublevels_of_a_2d_grid_are_manhattan_coordinates(L):
+    # 5-point grid, root at the corner (0, 0): the levels are the
+    # anti-diagonals x + y, the widest is x + y = L - 1, its smallest vertex
+    # (L-1, 0) is farthest from (0, L-1); distances are Manhattan
+    A = w.stencil_2d5(L)
+    assert oracle.sublevel_root(A.n, A.rowptr, A.col, 0) == (L - 1) * L
+    d1, d2, perm, iperm = oracle.sublevels(A.n, A.rowptr, A.col, 0)
+    for v in range(A.n):
+        x, y, _ = _coords(v, L)
+        assert d1[v] == x + y and d2[v] == x + (L - 1 - y), v
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_sublevels_of_a_27_point_cube_are_chebyshev_shells(L):
+    # 27-point stencil: graph distance = Chebyshev distance; levels from the
+    # corner are the shells max(x, y, z); the widest is the outer shell,
+    # whose smallest vertex (L-1, 0, 0) is at distance L - 1 from
+    # (0, L-1, 0), the smallest vertex of the shell at that distance
+    A = w.stencil_3d27(L)
+    r2 = oracle.sublevel_root(A.n, A.rowptr, A.col, 0)
+    assert _coords(r2, L) == (0, L - 1, 0)
+    d1, d2, _, _ = oracle.sublevels(A.n, A.rowptr, A.col, 0)
+    for v in range(A.n):
+        x, y, z = _coords(v, L)
+        assert d1[v] == max(x, y, z) and d2[v] == max(x, L - 1 - y, z), v
+
+
+def _random_connected(n, deg, seed, symmetric=True):
+    g = np.random.default_rng(seed)
+    D = np.eye(n)
+    for v in range(1, n):              # a random spanning tree keeps it connected
+        D[v, g.integers(0, v)] = -1.0
+    for _ in range(n * deg):
+        a, b = g.integers(0, n, 2)
+        D[a, b] = -1.0
+    if symmetric:
+        D = np.minimum(D, D.T)
+    return w.from_dense(D, f"rand{seed}")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_sublevel_distances_match_graph_distances(seed, symmetric):
+    A = _random_connected(60, 2, seed, symmetric)
+    M = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n, A.n))
+    root = int(np.random.default_rng(seed).integers(0, A.n))
+    r2 = oracle.sublevel_root(A.n, A.rowptr, A.col, root)
+    d1, d2, _, _ = oracle.sublevels(A.n, A.rowptr, A.col, root)
+    # G(A) ignores edge direction (the pattern is symmetrised for levels)
+    assert np.array_equal(d1, csg.shortest_path(M, unweighted=True, directed=False, indices=root))
+    assert np.array_equal(d2, csg.shortest_path(M, unweighted=True, directed=False, indices=r2))
+    # the second root lies in the first widest level and is farthest there
+    # from that level's smallest vertex
+    widths = np.bincount(d1)
+    W = np.flatnonzero(d1 == int(np.argmax(widths)))
+    dw = csg.shortest_path(M, unweighted=True, directed=False, indices=int(W[0]))
+    far = W[dw[W] == dw[W].max()]
+    assert r2 == int(far.min())
+
+
+@pytest.mark.parametrize("which", ["paper20", "rand4", "rand5", "grid"])
+def test_every_edge_joins_equal_or_adjacent_sublevels(which):
+    if which == "paper20":
+        A = _golden_graph()
+    elif which == "grid":
+        A = w.stencil_3d27(5)
+    else:
+        A = _random_connected(80, 3, int(which[-1]), symmetric=False)
+    d1, d2, perm, iperm = oracle.sublevels(A.n, A.rowptr, A.col, 0)
+    for v in range(A.n):
+        for e in range(A.rowptr[v], A.rowptr[v + 1]):
+            u = A.col[e]
+            assert abs(d1[u] - d1[v]) <= 1 and abs(d2[u] - d2[v]) <= 1, (v, u)
+    # rows ordered by (level, sub-level, index): each level a run of sub-levels
+    assert sorted(perm.tolist()) == list(range(A.n))
+    keys = [(d1[v], d2[v], v) for v in perm]
+    assert keys == sorted(keys)
+    assert np.array_equal(iperm[perm], np.arange(A.n))
+
+
+def test_paper_stencil_sublevels_split_its_bulky_levels():
+    # the 20-vertex example of Fig. entire_stencil_figure: the sub-levels of
+    # every level are graph distances from the second root, and the widest
+    # level is split into more than one sub-level
+    A = _golden_graph()
+    d1, d2, _, _ = oracle.sublevels(A.n, A.rowptr, A.col, 0)
+    M = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n, A.n))
+    r2 = oracle.sublevel_root(A.n, A.rowptr, A.col, 0)
+    assert np.array_equal(d2, csg.shortest_path(M, unweighted=True, directed=False, indices=r2))
+    widest = int(np.argmax(np.bincount(d1)))
+    assert len(set(d2[d1 == widest].tolist())) > 1
