@@ -580,7 +580,7 @@ def main():
                     help="persistent workgroups with --schedule (0: the library's default)")
     ap.add_argument("--seg-powers", type=int, default=0,
                     help="powers per launch with --schedule (0: all)")
-    ap.add_argument("--reorder", default="bfs", choices=["bfs", "none"],
+    ap.add_argument("--reorder", default="bfs", choices=["bfs", "none", "sublevels"],
                     help="level construction with --schedule")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
                     help="headline workload (default: the 128^3 stencil; others for profiling)")
@@ -657,9 +657,10 @@ def main():
         P.close()
     best_base = min(base, key=lambda r: base[r]["median_ms"])
 
-    # level-blocked run: the autotuner's choice in each order, the faster one reported
+    # level-blocked run: the autotuner's choice in each order, the fastest one reported
     lb = None
-    for ro in (("bfs", "none") if args.schedule is None else (args.reorder,)):
+    by_order = {}
+    for ro in (("bfs", "none", "sublevels") if args.schedule is None else (args.reorder,)):
         t0 = time.perf_counter()
         Q = mpk.Plan(A, reorder=ro, value_bits=vb)
         if args.schedule is None:
@@ -673,6 +674,22 @@ def main():
         log(f"[bench] level-blocked reorder={ro}: autotuned in {time.perf_counter() - t0:.1f}s "
             f"-> {tq['schedule']} C={tq['cache_bytes'] >> 20} MiB chunk={tq['chunk_nnz']}: "
             f"{r['median_ms']:.3f} ms ({flop / r['median_ms'] / 1e6:.1f} Gflop/s)")
+        by_order[ro] = {"ms": round(r["median_ms"], 4), "schedule": tq["schedule"],
+                        "chunk_nnz": tq["chunk_nnz"], "workgroups": tq["workgroups"]}
+        if ro == "sublevels" and args.schedule is None:
+            # the XCD schedule on the sub-level order: each XCD's part of
+            # every level is a run of sub-levels
+            Q.tune(schedule="xcd", chunk_nnz=16384, lag=0, workgroups=0)
+            rx = time_calls(lambda: run_lb(Q, Y), args.steps, args.warmup, torch, stream)
+            Q.sync()
+            sx = Q.schedule(p)
+            inf = Q.info()
+            by_order["sublevels_xcd"] = {"ms": round(rx["median_ms"], 4), "schedule": "xcd",
+                                         "chunk_nnz": 16384, "lag": sx["lag"],
+                                         "window_bytes": int(sx["window_bytes"]),
+                                         "max_sublevels": inf["max_sublevels"]}
+            log(f"[bench] sub-level order, XCD schedule: {rx['median_ms']:.3f} ms")
+            Q.tune(**{k: v for k, v in tq.items() if k != "ms"})
         if lb is None or r["median_ms"] < lb["median_ms"]:
             if lb is not None:
                 P.close()
@@ -714,7 +731,7 @@ def main():
 
     Yh = None if args.no_cpu else Y.cpu().numpy()   # for the per-power check on the CPU leg
     extra = (p - 1) * 8 * A.n * R if cheb else 0  # y_{k-1} read again by the recurrence
-    lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "lb", A.n if reorder == "bfs" else 0)
+    lb_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "lb", A.n if reorder != "none" else 0)
     trad_bytes = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "trad",
                                    A.n if best_base == "bfs" else 0) + extra
     achieved = lb_bytes / (lb["mean_ms"] * 1e-3) / 1e9
@@ -759,6 +776,7 @@ def main():
                                                   / 1e9, 1),
                             "traffic": measured_traffic(args.workload, vb, "pxspmv:" + best_base)},
         "speedup_vs_pxspmv": round(bmed / lb["median_ms"], 3),
+        "level_blocked_by_order": by_order,
         "hip_graph": {"ms": round(gr["median_ms"], 4), "bit_identical": graph_same,
                       "launches_per_run": sched["n_steps"]},
         "bit_identical_to_pxspmv": same,

@@ -57,7 +57,14 @@ enum {
 /* Symmetric reordering applied by the planner. */
 enum {
     MPK_REORDER_BFS = 0,    /* BFS level order from the root (the paper's choice) */
-    MPK_REORDER_NONE = 1    /* keep the caller's order (levels derived from it)   */
+    MPK_REORDER_NONE = 1,   /* keep the caller's order (levels derived from it)   */
+    MPK_REORDER_SUBLEVELS = 2 /* BFS levels, each ordered by sub-level: the
+                               distance from a second root (opts.sublevel_root),
+                               so that every edge joins equal or adjacent
+                               sub-levels; an XCD's part of each level is then
+                               a run of sub-levels (a reading of the paper's
+                               recursion that breaks bulky levels, s_m in Sec.
+                               "Experimental Setup")                          */
 };
 
 /* Traversal order of the (chunk, power) tasks. */
@@ -107,7 +114,21 @@ typedef struct {
     int root;                /* BFS root row (default 0), or
                                 MPK_ROOT_PERIPHERAL                           */
     int device;              /* HIP device, MPK_DEVICE_CURRENT or MPK_DEVICE_NONE */
+    int64_t l2_bytes;        /* per-XCD L2 budget of the XCD schedule's window
+                                (0 = 4 MiB, the MI355X L2 per XCD)              */
+    int64_t mall_bytes;      /* the plan's initial blocking budget C
+                                (tune.cache_bytes; 0 = 64 MiB, the measured
+                                fast-read plateau of the Infinity Cache)        */
+    int min_group_rows;      /* level groups of the STEPS and DIAG schedules
+                                hold at least this many rows (0 = no minimum):
+                                enough rows per diagonal to fill the device     */
+    int sublevel_root;       /* MPK_REORDER_SUBLEVELS: the second root, or
+                                MPK_ROOT_AUTO (default): the vertex of the
+                                widest level farthest from that level's
+                                smallest vertex                                */
 } mpk_plan_opts_t;
+
+#define MPK_ROOT_AUTO (-1)
 
 /* Run-time tuning of a plan (mpk_plan_tune).  None of these changes a result
  * bit: every kernel sums each row sequentially in stored order. */
@@ -160,6 +181,12 @@ typedef struct {
                                 through LDS (chosen when padding every slice
                                 to its longest row would add more than 25%)  */
     int64_t sliced_entries;  /* stored slots of the sliced layout (0 if none)  */
+    int32_t sublevel_root;   /* MPK_REORDER_SUBLEVELS: the second root (plan's
+                                caller numbering), else -1                     */
+    int32_t max_sublevels;   /* MPK_REORDER_SUBLEVELS: most sub-levels in one
+                                level, else 0                                  */
+    int64_t l2_bytes, mall_bytes;
+    int32_t min_group_rows;
 } mpk_plan_info_t;
 
 typedef struct {
@@ -216,6 +243,12 @@ void mpk_plan_destroy(mpk_plan_t plan);
 /* Set the tuning used by later runs of this plan (NULL = defaults). */
 mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune);
 
+/*
+ * The plan's shape: the level structure of Sec. "RACE Applied to the Matrix
+ * Power Kernel" (the level equation's sets after the BFS reordering, or the
+ * order-derived levels), the stored matrix and the planner inputs.
+ * Errors: MPK_EINVAL (NULL).
+ */
 mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info);
 
 /* Copy out the level pointer (n_levels+1 entries) and the permutation
@@ -399,8 +432,13 @@ mpk_status_t mpk_combine_complex(mpk_plan_t plan, const double *acc, int nrhs, d
 
 /*
  * Convert nvec blocks of n*nrhs doubles between the caller's numbering and
- * the plan's: to_plan != 0 gives out[new] = in[perm[new]], else
- * out[perm[new]] = in[new].  Device pointers, must not overlap.
+ * the plan's, i.e. apply the symmetric BFS permutation of Sec. "RACE
+ * Applied to the Matrix Power Kernel" (rows sorted by level) or its inverse
+ * to vectors: to_plan != 0 gives out[new] = in[perm[new]], else
+ * out[perm[new]] = in[new].  The paper permutes once and runs many times;
+ * with MPK_ORDER_PLAN this call is that one permutation.  Device pointers,
+ * must not overlap.  Asynchronous on hip_stream.
+ * Errors: MPK_EINVAL (NULL, overlap, nvec < 0, bad nrhs), MPK_ENODEVICE.
  */
 mpk_status_t mpk_permute(mpk_plan_t plan, int to_plan, const double *in, double *out, int nvec,
                          int nrhs, void *hip_stream);

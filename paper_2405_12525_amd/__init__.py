@@ -17,11 +17,11 @@ import numpy as np
 
 from . import _capi
 from ._capi import (MPK_DEVICE_CURRENT, MPK_DEVICE_NONE, MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN,
-                    MPK_REORDER_BFS, MPK_REORDER_NONE, MPK_SCHED_DIAG, MPK_SCHED_POWERS,
+                    MPK_REORDER_BFS, MPK_REORDER_NONE, MPK_REORDER_SUBLEVELS, MPK_ROOT_AUTO, MPK_SCHED_DIAG, MPK_SCHED_POWERS,
                     MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPK_SCHED_XCD, MPKError, check)
 
 __all__ = ["Plan", "MPKError", "version", "MPK_ORDER_ORIGINAL", "MPK_ORDER_PLAN",
-           "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
+           "MPK_REORDER_BFS", "MPK_REORDER_NONE", "MPK_REORDER_SUBLEVELS", "MPK_ROOT_AUTO", "MPK_SCHED_STEPS", "MPK_SCHED_WAVE", "MPK_SCHED_DIAG",
            "MPK_SCHED_POWERS", "MPK_SCHED_XCD", "use_torch_allocator", "MPK_DEVICE_NONE", "MPK_DEVICE_CURRENT", "chebyshev_coefficients",
            "cheb_time_coefficients",
            "flops", "lib", "probe_load", "probe_load_xcd"]
@@ -167,7 +167,12 @@ class Plan:
     """
 
     def __init__(self, A, value_bits: int = 64, reorder: str = "bfs", order: str = "original",
-                 root=0, device=MPK_DEVICE_CURRENT):
+                 root=0, device=MPK_DEVICE_CURRENT, l2_bytes: int = 0, mall_bytes: int = 0,
+                 min_group_rows: int = 0, sublevel_root: int = MPK_ROOT_AUTO):
+        """reorder: "bfs" (levels from `root`, or root="peripheral"), "none"
+        (the caller's order) or "sublevels" (BFS levels, each ordered by the
+        distance from `sublevel_root`, -1 = automatic).  l2_bytes /
+        mall_bytes / min_group_rows: planner budgets (0 = defaults)."""
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
@@ -192,9 +197,14 @@ class Plan:
         opts = _capi.PlanOpts()
         L.mpk_plan_opts_default(ctypes.byref(opts))
         opts.value_bits = int(value_bits)
-        opts.reorder = {"bfs": MPK_REORDER_BFS, "none": MPK_REORDER_NONE}[reorder]
+        opts.reorder = {"bfs": MPK_REORDER_BFS, "none": MPK_REORDER_NONE,
+                        "sublevels": MPK_REORDER_SUBLEVELS}[reorder]
         opts.order = {"original": MPK_ORDER_ORIGINAL, "plan": MPK_ORDER_PLAN}[order]
         opts.root = -1 if root == "peripheral" else int(root)   # MPK_ROOT_PERIPHERAL
+        opts.l2_bytes = int(l2_bytes)
+        opts.mall_bytes = int(mall_bytes)
+        opts.min_group_rows = int(min_group_rows)
+        opts.sublevel_root = int(sublevel_root)
         if device is None or device == "none":
             device = MPK_DEVICE_NONE
         opts.device = int(device)
@@ -205,6 +215,7 @@ class Plan:
         self.order = order
         self.host_only = opts.device == MPK_DEVICE_NONE
         self._tune = self.default_tune()
+        self._tune["cache_bytes"] = self.info()["mall_bytes"]   # the plan's budget C
 
     # ------------------------------------------------------------ lifetime
     def close(self):

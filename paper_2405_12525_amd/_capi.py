@@ -12,7 +12,8 @@ MPK_OK, MPK_EINVAL, MPK_EBADCSR, MPK_ENOMEM, MPK_EHIP, MPK_EUNSUPPORTED, MPK_ETI
 STATUS_NAMES = {0: "MPK_OK", 1: "MPK_EINVAL", 2: "MPK_EBADCSR", 3: "MPK_ENOMEM", 4: "MPK_EHIP",
                 5: "MPK_EUNSUPPORTED", 6: "MPK_ETIMEOUT", 7: "MPK_ENODEVICE"}
 MPK_ORDER_ORIGINAL, MPK_ORDER_PLAN = 0, 1
-MPK_REORDER_BFS, MPK_REORDER_NONE = 0, 1
+MPK_REORDER_BFS, MPK_REORDER_NONE, MPK_REORDER_SUBLEVELS = 0, 1, 2
+MPK_ROOT_AUTO = -1
 MPK_SCHED_STEPS, MPK_SCHED_WAVE, MPK_SCHED_DIAG, MPK_SCHED_POWERS, MPK_SCHED_XCD = 0, 1, 2, 3, 4
 MPK_DEVICE_CURRENT, MPK_DEVICE_NONE = -1, -2
 MPK_MAX_RHS = 16
@@ -39,7 +40,9 @@ class CSRStruct(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("value_bits", ctypes.c_int), ("reorder", ctypes.c_int), ("order", ctypes.c_int),
-                ("root", ctypes.c_int), ("device", ctypes.c_int)]
+                ("root", ctypes.c_int), ("device", ctypes.c_int), ("l2_bytes", ctypes.c_int64),
+                ("mall_bytes", ctypes.c_int64), ("min_group_rows", ctypes.c_int),
+                ("sublevel_root", ctypes.c_int)]
 
 
 class Tune(ctypes.Structure):
@@ -57,7 +60,10 @@ class PlanInfo(ctypes.Structure):
                 ("reorder", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("matrix_bytes", ctypes.c_int64),
                 ("plan_ms", ctypes.c_double), ("device", ctypes.c_int32),
-                ("sliced_layout", ctypes.c_int32), ("sliced_entries", ctypes.c_int64)]
+                ("sliced_layout", ctypes.c_int32), ("sliced_entries", ctypes.c_int64),
+                ("sublevel_root", ctypes.c_int32), ("max_sublevels", ctypes.c_int32),
+                ("l2_bytes", ctypes.c_int64), ("mall_bytes", ctypes.c_int64),
+                ("min_group_rows", ctypes.c_int32)]
 
 
 class SchedInfo(ctypes.Structure):

@@ -158,6 +158,9 @@ struct mpk_plan_s {
     int pattern_sym = -1;        // structurally symmetric pattern (-1: not checked yet)
     int n_xcd = 8;               // XCDs found on the device (host-only plans: 8)
     bool xcd_bound = true;       // a workgroup can tell which XCD it runs on
+    int64_t l2_bytes = 4 << 20, mall_bytes = 64 << 20;  // planner budgets
+    int32_t min_group_rows = 0;
+    int32_t sublevel_root = -1, max_sublevels = 0;     // MPK_REORDER_SUBLEVELS
     // device data
     DevBuf d_rowptr, d_col, d_val, d_outrow, d_perm;
     DevBuf d_soff, d_rlen, d_scol, d_sval;   // sliced layout (empty if not built)
@@ -284,7 +287,7 @@ mpk_status_t get_schedule(mpk_plan_t plan, int p, SchedEntry **out, int default_
     }
     PlanShape sh{plan->n, plan->nnz, plan->value_bits / 8, &plan->lv.level_ptr, &plan->rowptr,
                  &plan->row_lo, &plan->row_hi, pcol, n_xcd,
-                 plan->xcd_bound && n_xcd > 1};
+                 plan->xcd_bound && n_xcd > 1, plan->l2_bytes, plan->min_group_rows};
     std::string err;
     mpk_status_t st = build_schedule(sh, p, plan->tune, default_wg, e->host, err);
     if (st) return fail(st, err);
@@ -807,6 +810,9 @@ uint64_t fingerprint(int64_t n, int64_t nnz, const mpk_plan_opts_t &o, const int
     mix((uint64_t)n);
     mix((uint64_t)nnz);
     mix((uint64_t)o.reorder * 1000 + o.order * 100 + (uint64_t)o.root);
+    // the planner inputs that change schedules or the row order
+    mix((uint64_t)o.l2_bytes);
+    mix((uint64_t)o.min_group_rows * 2 + (uint64_t)(uint32_t)o.sublevel_root * 4096);
     constexpr int kPieces = 64;
     uint64_t piece[kPieces];
     const int64_t len = n + 1;
@@ -914,6 +920,10 @@ void mpk_plan_opts_default(mpk_plan_opts_t *o) {
     o->order = MPK_ORDER_ORIGINAL;
     o->root = 0;
     o->device = MPK_DEVICE_CURRENT;
+    o->l2_bytes = (int64_t)4 << 20;
+    o->mall_bytes = (int64_t)64 << 20;
+    o->min_group_rows = 0;
+    o->sublevel_root = MPK_ROOT_AUTO;
 }
 
 void mpk_tune_default(mpk_tune_t *t) {
@@ -940,21 +950,38 @@ mpk_status_t mpk_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn
     return MPK_OK;
 }
 
+// Options shared by mpk_plan and mpk_plan_device; zero budgets take the defaults.
+static mpk_status_t check_opts(mpk_plan_opts_t &o) {
+    if (o.value_bits != 64 && o.value_bits != 32) return fail(MPK_EINVAL, "value_bits must be 32 or 64");
+    if (o.reorder != MPK_REORDER_BFS && o.reorder != MPK_REORDER_NONE &&
+        o.reorder != MPK_REORDER_SUBLEVELS)
+        return fail(MPK_EINVAL, "bad reorder");
+    if (o.order != MPK_ORDER_ORIGINAL && o.order != MPK_ORDER_PLAN) return fail(MPK_EINVAL, "bad order");
+    if (o.l2_bytes < 0 || o.mall_bytes < 0 || o.min_group_rows < 0)
+        return fail(MPK_EINVAL, "l2_bytes, mall_bytes and min_group_rows must be >= 0");
+    if (o.l2_bytes == 0) o.l2_bytes = (int64_t)4 << 20;
+    if (o.mall_bytes == 0) o.mall_bytes = (int64_t)64 << 20;
+    if (o.l2_bytes < 65536 || o.mall_bytes < 65536)
+        return fail(MPK_EINVAL, "l2_bytes and mall_bytes must be at least 64 KiB");
+    if (o.sublevel_root < MPK_ROOT_AUTO) return fail(MPK_EINVAL, "bad sublevel_root");
+    return MPK_OK;
+}
+
 mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_t *out) {
     if (!out) return fail(MPK_EINVAL, "out is NULL");
     *out = nullptr;
     mpk_plan_opts_t o;
     mpk_plan_opts_default(&o);
     if (opts) o = *opts;
-    if (o.value_bits != 64 && o.value_bits != 32) return fail(MPK_EINVAL, "value_bits must be 32 or 64");
-    if (o.reorder != MPK_REORDER_BFS && o.reorder != MPK_REORDER_NONE) return fail(MPK_EINVAL, "bad reorder");
-    if (o.order != MPK_ORDER_ORIGINAL && o.order != MPK_ORDER_PLAN) return fail(MPK_EINVAL, "bad order");
+    mpk_status_t st0 = check_opts(o);
+    if (st0) return st0;
     const bool host_only = o.device == MPK_DEVICE_NONE;
     std::string err;
     mpk_status_t st = validate_csr(A, !host_only, err);
     if (st) return fail(st, err);
     if (A->n > 0 && o.root != MPK_ROOT_PERIPHERAL && (o.root < 0 || o.root >= A->n))
         return fail(MPK_EINVAL, "root out of range");
+    if (A->n > 0 && o.sublevel_root >= A->n) return fail(MPK_EINVAL, "sublevel_root out of range");
 
     const double t0 = now_ms();
     std::unique_ptr<mpk_plan_s> plan;
@@ -967,6 +994,10 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
         plan->order = o.order;
         plan->host_only = host_only;
         mpk_tune_default(&plan->tune);
+        plan->l2_bytes = o.l2_bytes;
+        plan->mall_bytes = o.mall_bytes;
+        plan->min_group_rows = o.min_group_rows;
+        plan->tune.cache_bytes = o.mall_bytes;
         const bool plan_cols = o.order == MPK_ORDER_PLAN;
         plan->plan_cols = plan_cols;
         const size_t nnz = (size_t)A->nnz;
@@ -1019,8 +1050,14 @@ mpk_status_t mpk_plan(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mpk_plan_
             }
         }
         if (!gpu_levels) {
-            plan->lv = o.reorder == MPK_REORDER_BFS ? bfs_levels(A->n, A->rowptr, A->col, o.root)
-                                                    : order_levels(A->n, A->rowptr, A->col);
+            if (o.reorder == MPK_REORDER_NONE) {
+                plan->lv = order_levels(A->n, A->rowptr, A->col);
+            } else {
+                plan->lv = bfs_levels(A->n, A->rowptr, A->col, o.root);
+                if (o.reorder == MPK_REORDER_SUBLEVELS)
+                    plan->lv = sublevel_order(A->n, A->rowptr, A->col, plan->lv, o.sublevel_root,
+                                              &plan->sublevel_root, &plan->max_sublevels);
+            }
             permute_csr(A->n, A->rowptr, A->col, host_only ? nullptr : A->val, plan->lv,
                         plan_cols, pc);
             plan->rowptr = pc.rowptr;
@@ -1083,15 +1120,15 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
     mpk_plan_opts_default(&o);
     if (opts) o = *opts;
     if (o.device == MPK_DEVICE_NONE) return fail(MPK_EINVAL, "a device CSR needs a device plan");
-    if (o.value_bits != 64 && o.value_bits != 32) return fail(MPK_EINVAL, "value_bits must be 32 or 64");
-    if (o.reorder != MPK_REORDER_BFS && o.reorder != MPK_REORDER_NONE) return fail(MPK_EINVAL, "bad reorder");
-    if (o.order != MPK_ORDER_ORIGINAL && o.order != MPK_ORDER_PLAN) return fail(MPK_EINVAL, "bad order");
+    mpk_status_t st0 = check_opts(o);
+    if (st0) return st0;
     if (A->n < 0 || A->nnz < 0) return fail(MPK_EBADCSR, "negative n or nnz");
     if (A->n >= (int64_t)INT32_MAX) return fail(MPK_EUNSUPPORTED, "n >= 2^31 is not supported");
     if (A->nnz >= (int64_t)INT32_MAX) return fail(MPK_EUNSUPPORTED, "nnz >= 2^31 is not supported");
     if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val))) return fail(MPK_EINVAL, "NULL array");
     if (A->n > 0 && o.root != MPK_ROOT_PERIPHERAL && (o.root < 0 || o.root >= A->n))
         return fail(MPK_EINVAL, "root out of range");
+    if (A->n > 0 && o.sublevel_root >= A->n) return fail(MPK_EINVAL, "sublevel_root out of range");
     const double t0 = now_ms();
     int dev = o.device;
     if (dev == MPK_DEVICE_CURRENT) {
@@ -1111,8 +1148,8 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
     if ((int64_t)ends[1] != nnz) return fail(MPK_EBADCSR, "rowptr[n] != nnz");
     if (bad_cols) return fail(MPK_EBADCSR, "column index out of range");
     const bool plan_cols = o.order == MPK_ORDER_PLAN;
-    // the pseudo-peripheral root, and graphs beyond the device level search,
-    // are planned from a host copy
+    // the pseudo-peripheral root, the sub-level order and graphs beyond the
+    // device level search are planned from a host copy
     auto via_host = [&]() -> mpk_status_t {
         std::vector<int32_t> rp((size_t)n + 1), cl((size_t)nnz);
         std::vector<double> vl((size_t)nnz);
@@ -1127,7 +1164,9 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
         o2.device = dev;
         return mpk_plan(&H, &o2, out);
     };
-    if (o.reorder == MPK_REORDER_BFS && o.root == MPK_ROOT_PERIPHERAL) return via_host();
+    if ((o.reorder == MPK_REORDER_BFS && o.root == MPK_ROOT_PERIPHERAL) ||
+        o.reorder == MPK_REORDER_SUBLEVELS)
+        return via_host();
     std::unique_ptr<mpk_plan_s> plan;
     try {
         plan.reset(new mpk_plan_s());
@@ -1139,6 +1178,10 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
         plan->host_only = false;
         plan->plan_cols = plan_cols;
         mpk_tune_default(&plan->tune);
+        plan->l2_bytes = o.l2_bytes;
+        plan->mall_bytes = o.mall_bytes;
+        plan->min_group_rows = o.min_group_rows;
+        plan->tune.cache_bytes = o.mall_bytes;
         plan->device = dev;
         plan->n_xcd = detect_xcds(dev);
         plan->xcd_bound = plan->n_xcd > 1;
@@ -1212,6 +1255,7 @@ mpk_status_t mpk_plan_tune(mpk_plan_t plan, const mpk_tune_t *tune) {
     if (!plan) return fail(MPK_EINVAL, "plan is NULL");
     mpk_tune_t t;
     mpk_tune_default(&t);
+    t.cache_bytes = plan->mall_bytes;  // the plan's budget C
     if (tune) t = *tune;
     if (t.schedule < MPK_SCHED_STEPS || t.schedule > MPK_SCHED_XCD) return fail(MPK_EINVAL, "bad schedule");
     if (t.cache_bytes <= 0 || !(t.cache_safety > 0.0) || t.cache_safety > 1.0)
@@ -1250,6 +1294,11 @@ mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info) {
     info->device = plan->device;
     info->sliced_layout = plan->d_scol.ptr ? 1 : 0;
     info->sliced_entries = plan->sell_entries;
+    info->sublevel_root = plan->sublevel_root;
+    info->max_sublevels = plan->max_sublevels;
+    info->l2_bytes = plan->l2_bytes;
+    info->mall_bytes = plan->mall_bytes;
+    info->min_group_rows = plan->min_group_rows;
     return MPK_OK;
 }
 
@@ -1527,7 +1576,7 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     // persistent workgroups, segments of p and skip-ahead parking
     std::vector<mpk_tune_t> cands;
     auto add = [&](int sched, int64_t cache_mib, int chunk, int lag, int wg = 0, int seg = 0,
-                   int skip = 0) {
+                   int skip = 0, int dyn = 0) {
         mpk_tune_t t = base;
         t.schedule = sched;
         t.cache_bytes = cache_mib << 20;
@@ -1537,6 +1586,7 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
         t.workgroups = wg;
         t.seg_powers = seg;
         t.skip_ahead = skip;
+        t.dynamic_tickets = dyn;
         cands.push_back(t);
     };
     for (int64_t c : {32, 64, 128})
@@ -1569,6 +1619,14 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
                         wpc * cus);
         for (int wpc : {2, 4, 8})
             for (int chunk : {8192, 16384}) add(MPK_SCHED_POWERS, 64, chunk, 0, wpc * cus);
+        // the shared counter as well: where a task's inputs come from many
+        // chunks (random columns within wide bands) the fixed order can
+        // leave workgroups waiting that the counter would have given other
+        // tasks; the timing decides
+        for (int wpc : {2, 4}) {
+            add(MPK_SCHED_POWERS, 64, 8192, 0, wpc * cus, 0, 0, 1);
+            add(MPK_SCHED_WAVE, 64, 16384, std::max(1, 2 * wpc * cus / p), wpc * cus, 0, 0, 1);
+        }
     }
     if (p >= 4) add(MPK_SCHED_WAVE, 64, 32768, 0, 0, (p + 1) / 2);  // two segments
     add(MPK_SCHED_WAVE, 64, 16384, 0, 0, 0, 2);                     // park up to two tasks

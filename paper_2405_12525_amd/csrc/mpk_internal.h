@@ -26,6 +26,17 @@ mpk_status_t validate_csr(const mpk_csr_t *A, bool need_values, std::string &err
 // row when the frontier empties.
 Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t root);
 
+// Levels broken into sub-levels: rows of each level of `lv` (BFS levels,
+// ascending original index inside a level) reordered by (d2, original index)
+// with d2 the BFS distance from root2 (the same level construction from
+// another root); root2 < 0: the vertex of the widest level (the first among
+// equals) farthest from that level's smallest vertex, ties to the smaller
+// index.  Both distances change by at most one along any edge, so every
+// edge joins equal or adjacent sub-levels.  Returns root2 through *root_out
+// and the most sub-levels of one level through *max_sub.
+Levels sublevel_order(int64_t n, const int32_t *rowptr, const int32_t *col, const Levels &lv,
+                      int32_t root2, int32_t *root_out, int32_t *max_sub);
+
 // Identity permutation with levels derived from the given order: level j+1
 // ends just past the farthest neighbour of level j, so every row's
 // neighbours lie in its own or an adjacent level.
@@ -131,6 +142,8 @@ struct PlanShape {
     const std::vector<int32_t> *pcol;    // plan-numbered columns (XCD schedule)
     int n_xcd;                           // XCDs that own parts of each level (>= 1)
     bool xcd_local;                      // tasks of one queue run on one XCD only
+    int64_t l2_bytes = 4 << 20;          // per-XCD window budget (XCD schedule)
+    int32_t min_group_rows = 0;          // smallest level group (STEPS, DIAG)
 };
 
 mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,

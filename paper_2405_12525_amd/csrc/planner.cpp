@@ -127,6 +127,53 @@ static int32_t pseudo_peripheral(int64_t n, const int32_t *rowptr, const int32_t
     }
 }
 
+// Level index of every row: d[perm[r]] = level of plan row r.
+static std::vector<int32_t> level_of(int64_t n, const Levels &lv) {
+    std::vector<int32_t> d(n);
+    for (size_t l = 0; l + 1 < lv.level_ptr.size(); ++l)
+        for (int32_t r = lv.level_ptr[l]; r < lv.level_ptr[l + 1]; ++r) d[lv.perm[r]] = (int32_t)l;
+    return d;
+}
+
+Levels sublevel_order(int64_t n, const int32_t *rowptr, const int32_t *col, const Levels &lv,
+                      int32_t root2, int32_t *root_out, int32_t *max_sub) {
+    Levels out;
+    out.level_ptr = lv.level_ptr;
+    if (root_out) *root_out = -1;
+    if (max_sub) *max_sub = 0;
+    if (n == 0) return out;
+    if (root2 < 0 || root2 >= n) {
+        // the widest level (first among equals) and its smallest vertex w
+        size_t wl = 0;
+        for (size_t l = 0; l + 1 < lv.level_ptr.size(); ++l)
+            if (lv.level_ptr[l + 1] - lv.level_ptr[l] > lv.level_ptr[wl + 1] - lv.level_ptr[wl])
+                wl = l;
+        const int32_t w = lv.perm[lv.level_ptr[wl]];  // a level lists ascending indices
+        const std::vector<int32_t> dw = level_of(n, bfs_levels(n, rowptr, col, w));
+        root2 = w;
+        for (int32_t r = lv.level_ptr[wl]; r < lv.level_ptr[wl + 1]; ++r) {
+            const int32_t v = lv.perm[r];  // ascending: a tie keeps the smaller index
+            if (dw[v] > dw[root2]) root2 = v;
+        }
+    }
+    const std::vector<int32_t> d2 = level_of(n, bfs_levels(n, rowptr, col, root2));
+    out.perm = lv.perm;
+    int32_t most = 0;
+    for (size_t l = 0; l + 1 < lv.level_ptr.size(); ++l) {
+        auto b = out.perm.begin() + lv.level_ptr[l], e = out.perm.begin() + lv.level_ptr[l + 1];
+        std::stable_sort(b, e, [&](int32_t a, int32_t c) { return d2[a] < d2[c]; });
+        int32_t subs = 0;
+        for (auto it = b; it != e; ++it)
+            if (it == b || d2[*it] != d2[*(it - 1)]) ++subs;
+        most = std::max(most, subs);
+    }
+    out.iperm.assign(n, 0);
+    for (int64_t r = 0; r < n; ++r) out.iperm[out.perm[r]] = (int32_t)r;
+    if (root_out) *root_out = root2;
+    if (max_sub) *max_sub = most;
+    return out;
+}
+
 Levels bfs_levels(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t root) {
     Levels lv;
     lv.perm.reserve(n);
@@ -363,8 +410,11 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
     const auto &pcol = *sh.pcol;
     const int nx = std::max(1, std::min(sh.n_xcd, kMaxQueues));
     const int32_t n_levels = (int32_t)lp.size() - 1;
-    const int64_t chunk_nnz = effective_chunk_nnz(sh, tune, default_workgroups);
     const double row_bytes = 4.0, nz_bytes = 4.0 + sh.value_bytes;
+    // p + 1 consecutive chunks of one queue fit its XCD's L2 budget
+    const int64_t l2_cap = std::max<int64_t>(
+        1024, (int64_t)((double)sh.l2_bytes * tune.cache_safety / ((p + 1) * nz_bytes)));
+    const int64_t chunk_nnz = std::min(effective_chunk_nnz(sh, tune, default_workgroups), l2_cap);
     s.n_queues = nx;
     s.n_groups = n_levels;
     s.chunk_ptr.assign(1, 0);
@@ -450,7 +500,12 @@ static mpk_status_t build_xcd_schedule(const PlanShape &sh, int p, const mpk_tun
     const double avg_reach = reach_sum / std::max(1, nc);
     int64_t D = tune.lag;
     if (D <= 0) {
-        const double fit = budget / ((double)p * avg_chunk_bytes) - avg_reach;
+        // window of the whole device within C, and of one queue (a 1/nx
+        // share of the positions) within its XCD's L2 budget
+        const double fit = std::min(budget / ((double)p * avg_chunk_bytes),
+                                    (double)sh.l2_bytes * tune.cache_safety * nx /
+                                        ((double)p * avg_chunk_bytes)) -
+                           avg_reach;
         // Slack so that a task's inputs lie about 8x the running workgroups
         // back in ticket order (p tasks share each position): with less, the
         // producer of an input is often still running when its consumer
@@ -562,15 +617,18 @@ mpk_status_t build_schedule(const PlanShape &sh, int p, const mpk_tune_t &tune,
     std::vector<int32_t> group_ptr(1, 0);  // in levels
     {
         double acc = 0.0;
+        int64_t grows = 0;  // rows in the open group
         for (int32_t l = 0; l < n_levels; ++l) {
             const int64_t rows = lp[l + 1] - lp[l];
             const int64_t nz = (int64_t)rp[lp[l + 1]] - rp[lp[l]];
             const double b = rows * row_bytes + nz * nz_bytes;
-            if (acc > 0.0 && acc + b > gmax) {
+            if (acc > 0.0 && acc + b > gmax && grows >= sh.min_group_rows) {
                 group_ptr.push_back(l);
                 acc = 0.0;
+                grows = 0;
             }
             acc += b;
+            grows += rows;
         }
         group_ptr.push_back(n_levels);
     }

@@ -389,3 +389,90 @@ def test_empty_and_tiny_plans():
     B = w.identity(1)
     s = host_plan(B).schedule(4)
     assert s["n_chunks"] == 1 and s["tasks"].tolist() == [[0, 1], [0, 2], [0, 3], [0, 4]]
+
+
+# ------------------------------------------------------------------ sub-levels and budgets
+
+@pytest.mark.parametrize("which", ["paper20", "grid2d", "cube", "rand", "rand_nonsym"])
+def test_sublevel_order_matches_oracle(which):
+    A = {"paper20": _golden_graph, "grid2d": lambda: w.stencil_2d5(17),
+         "cube": lambda: w.stencil_3d27(9), "rand": lambda: w.random_sparse(300, 0.01, 4),
+         "rand_nonsym": lambda: w.random_sparse(300, 0.01, 5, symmetric_pattern=False)}[which]()
+    P = host_plan(A, reorder="sublevels")
+    lp, perm = P.levels()
+    d1, d2, operm, _ = oracle.sublevels(A.n, A.rowptr, A.col, 0)
+    assert np.array_equal(perm, operm)
+    assert [int(v) for v in lp] == [0] + np.cumsum(np.bincount(d1)).tolist()
+    info = P.info()
+    assert info["sublevel_root"] == oracle.sublevel_root(A.n, A.rowptr, A.col, 0)
+    assert info["max_sublevels"] == max(len(set(d2[d1 == i].tolist())) for i in range(d1.max() + 1))
+    # the same levels as the plain BFS order, only reordered inside each level
+    lpb, permb = host_plan(A).levels()
+    assert np.array_equal(lp, lpb)
+    for i in range(len(lp) - 1):
+        assert sorted(perm[lp[i]:lp[i + 1]].tolist()) == permb[lp[i]:lp[i + 1]].tolist()
+
+
+def test_sublevel_order_with_given_second_root():
+    A = w.stencil_2d5(12)
+    P = host_plan(A, reorder="sublevels", sublevel_root=5)
+    _, perm = P.levels()
+    assert np.array_equal(perm, oracle.sublevels(A.n, A.rowptr, A.col, 0, root2=5)[2])
+    assert P.info()["sublevel_root"] == 5
+    with pytest.raises(mpk.MPKError):
+        host_plan(A, reorder="sublevels", sublevel_root=A.n)
+
+
+@pytest.mark.parametrize("sched", ["steps", "wave", "diag", "powers"])
+def test_schedules_on_sublevel_order_are_topological(sched):
+    for A in (w.stencil_3d27(10), w.random_sparse(300, 0.01, 3)):
+        P = host_plan(A, reorder="sublevels")
+        P.tune(schedule=sched, chunk_nnz=200, cache_bytes=40000, lag=0)
+        for p in (1, 4):
+            s = P.schedule(p)
+            _check_schedule(A, s, p)
+            _deps_cover_reads(A, P, s)
+
+
+def test_xcd_schedule_on_sublevel_order():
+    for A in (w.stencil_3d27(12), w.anderson_3d(8)):
+        P = host_plan(A, reorder="sublevels")
+        P.tune(schedule="xcd", chunk_nnz=300, lag=0)
+        for p in (2, 5):
+            s = P.schedule(p)
+            _check_xcd_schedule(A, P, s, p)
+
+
+def test_planner_budget_options():
+    A = w.stencil_3d27(14)
+    d = host_plan(A).info()
+    assert d["l2_bytes"] == 4 << 20 and d["mall_bytes"] == 64 << 20 and d["min_group_rows"] == 0
+    P = host_plan(A, l2_bytes=1 << 20, mall_bytes=8 << 20, min_group_rows=600)
+    i = P.info()
+    assert (i["l2_bytes"], i["mall_bytes"], i["min_group_rows"]) == (1 << 20, 8 << 20, 600)
+    assert P.tuning["cache_bytes"] == 8 << 20          # the plan's budget C
+    # every level group but the last holds at least min_group_rows rows
+    P.tune(schedule="steps", cache_bytes=20000, chunk_nnz=1 << 20)
+    lp, _ = P.levels()
+    s = P.schedule(3)
+    cp = np.asarray(s["chunk_ptr"])
+    grp = np.asarray(s["chunk_group"])
+    rows = np.bincount(grp, weights=np.diff(cp))
+    assert rows[:-1].min() >= 600
+    Q = host_plan(A)
+    Q.tune(schedule="steps", cache_bytes=20000, chunk_nnz=1 << 20)
+    assert Q.schedule(3)["n_groups"] > s["n_groups"]
+    # the L2 budget bounds the XCD schedule's chunks: p + 1 of them fit it
+    for l2 in (1 << 20, 64 << 10):
+        R = host_plan(A, l2_bytes=l2)
+        R.tune(schedule="xcd", chunk_nnz=1 << 20)
+        sx = R.schedule(4)
+        cp = np.asarray(sx["chunk_ptr"])
+        _, perm = R.levels()
+        prp = np.concatenate([[0], np.cumsum(np.diff(A.rowptr)[perm])])  # plan-order rowptr
+        nz = prp[cp[1:]] - prp[cp[:-1]]
+        # a chunk ends on the row that reaches the cap, rounded to 16 rows
+        assert nz.max() <= max(1024, l2 // (5 * 12)) + 27 * 16
+    for bad in (dict(l2_bytes=-1), dict(mall_bytes=1000), dict(min_group_rows=-3)):
+        with pytest.raises(mpk.MPKError):
+            host_plan(A, **bad)
