@@ -169,6 +169,9 @@ def serving(torch, mpk, w, rates, n_requests=512):
                                          "p99_ms": round(v["p99_ms"], 3)}
                               for m, v in st["by_matrix"].items()}}
 
+    # one stream per matrix (at most one batch of a matrix in flight); a
+    # fixed stream per matrix by size (Server.size_lanes) was measured no
+    # better: its shared stream made the small matrices wait longer
     srv = serve.Server(plans, n_streams=len(plans), use_baseline=use_base)
     warm = requests(1000.0)[:24]
     srv.serve(warm, realtime=False, keep=False)
@@ -190,7 +193,8 @@ def serving(torch, mpk, w, rates, n_requests=512):
     out = {"requests": n_requests, "rate_rule": "fixed (--serve-rate)", **runs[0],
            "kernels": {names[m]: "p x SpMV" if b else "level-blocked"
                        for m, b in enumerate(use_base)},
-           "streams": len(plans), "max_inflight_per_matrix": 1,
+           "streams": len(plans),
+           "max_inflight_per_matrix": 1,
            "saturated_rps": round(sat["throughput_rps"], 1),
            "saturated_gflops": round(sat["gflops"], 1),
            "saturated_mean_batch": round(sat["mean_batch"], 2)}
@@ -559,6 +563,60 @@ def reduce_counters(d):
     return out
 
 
+def counters_markdown(d, summary):
+    """Markdown summary of one reduced profile: the commands that made it,
+    the --stats table and the per-run traffic of the two kernels."""
+    import csv
+    import glob
+    cmd = summary.get("command") or "python3 bench.py ..."
+    rel = "gpurun_out/prof"
+    lines = [f"# Kernel trace and L2-egress traffic: {summary.get('workload', '')}", "",
+             "Commands (from the repository root on one MI355X, after "
+             "`cd /tmp && export TMPDIR=/tmp`; `bench.py` by its full path):", "", "```"]
+    for sub, opt in (("trace", "--kernel-trace --stats"), ("fetch", "--pmc FETCH_SIZE --kernel-trace"),
+                     ("write", "--pmc WRITE_SIZE --kernel-trace"),
+                     ("tcc", "--pmc TCC_HIT_sum TCC_MISS_sum --kernel-trace")):
+        lines.append(f"rocprofv3 {opt} -d {rel}/{sub} -o run --output-format csv -- {cmd}")
+    for sub, c in (("cfetch", "FETCH_SIZE"), ("cwrite", "WRITE_SIZE")):
+        lines.append(f"rocprofv3 --pmc {c} --kernel-trace -d {rel}/{sub} -o copy --output-format csv "
+                     f"-- python3 bench.py --copy-calibration")
+    lines += [f"python3 bench.py --reduce-counters {rel} > summary.json",
+              f"python3 bench.py --reduce-counters {rel} --markdown > summary.md", "```", "",
+              f"kernels.hip SHA-256: `{summary.get('kernels_sha256')}`", "",
+              "## --stats summary (kernel_stats.csv, the 12 longest in total)", "",
+              "| Kernel | Calls | Average µs | Total ms |", "|---|---|---|---|"]
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "trace", "**", "*kernel_stats.csv"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[:12]:
+        lines.append(f"| `{_kernel_key(r['Name'])}` | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['TotalDurationNs']) / 1e6:.2f} |")
+    lines += ["", "## Traffic per run", "",
+              f"Scope: {summary.get('traffic_scope')}.  Calibration: {summary.get('calibration')}; "
+              f"FETCH_SIZE scale {summary.get('fetch_scale')}, WRITE_SIZE scale "
+              f"{summary.get('write_scale')}.", "",
+              "| Run | Kernel | Launches/run | Avg launch µs | L2-egress bytes/run | L2 hit rate |",
+              "|---|---|---|---|---|---|"]
+    for key, e in summary.get("runs", {}).items():
+        lines.append(f"| `{key}` | `{e['kernel']}` | {e['launches_per_run']} | {e['avg_launch_us']} | "
+                     f"{e['l2_egress_bytes_per_run']:,} | {e.get('l2_hit_rate')} |")
+    return "\n".join(lines) + "\n"
+
+
+def sweep_markdown(sweep):
+    """Markdown table of a --bandwidth-sweep result."""
+    lines = ["| Working set | global GB/s | xcd_local GB/s |", "|---|---|---|"]
+    by = {}
+    for r in sweep["points"]:
+        by.setdefault(r["bytes"], {})[r["mode"]] = r["GBs"]
+    for b in sorted(by):
+        size = f"{b >> 20} MiB" if b < (1 << 30) else f"{b >> 30} GiB"
+        lines.append(f"| {size} | {by[b].get('global', '')} | {by[b].get('xcd_local', '')} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -593,6 +651,10 @@ def main():
     ap.add_argument("--reduce-counters", metavar="DIR", default=None,
                     help="reduce the rocprofv3 output of a profiled configuration (DIR/trace, "
                          "fetch, write, tcc, cfetch, cwrite) to JSON on stdout and stop")
+    ap.add_argument("--markdown", action="store_true",
+                    help="with --reduce-counters: print the markdown summary instead of JSON")
+    ap.add_argument("--sweep-markdown", metavar="JSON", default=None,
+                    help="print a --bandwidth-sweep result file as a markdown table and stop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
@@ -602,7 +664,15 @@ def main():
         sys.exit(2)
 
     if args.reduce_counters:
-        print(json.dumps(reduce_counters(args.reduce_counters), indent=1), flush=True)
+        red = reduce_counters(args.reduce_counters)
+        if args.markdown:
+            print(counters_markdown(args.reduce_counters, red), end="", flush=True)
+        else:
+            print(json.dumps(red, indent=1), flush=True)
+        return
+    if args.sweep_markdown:
+        with open(args.sweep_markdown) as f:
+            print(sweep_markdown(json.load(f)), end="", flush=True)
         return
 
     import torch

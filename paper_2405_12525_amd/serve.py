@@ -17,7 +17,10 @@ the loop admits them as stream slots and memory free up:
 * batches for different matrices run concurrently on separate HIP streams,
   at most max_inflight_per_matrix batches of one matrix at a time (by
   default one), so that requests arriving for a busy matrix wait together
-  and leave as one larger batch instead of taking every stream;
+  and leave as one larger batch instead of taking every stream; with lanes,
+  each matrix runs on a fixed stream (Server.size_lanes gives the largest
+  matrices a stream each and lets the small ones share one, so that their
+  short batches do not wait behind long ones);
 * each plan runs its batches through the level-blocked kernels or, where
   the caller found them faster for that matrix (use_baseline), through the
   p x SpMV kernels: the results are the same bit for bit;
@@ -115,9 +118,14 @@ class Server:
     def __init__(self, plans: Sequence[Plan], n_streams: int = 4,
                  mem_budget: Optional[int] = None, max_rhs: int = MAX_RHS,
                  max_inflight_per_matrix: int = 1,
-                 use_baseline: Optional[Sequence[bool]] = None):
+                 use_baseline: Optional[Sequence[bool]] = None,
+                 lanes: Optional[Sequence[int]] = None):
         torch = _torch()
         self.plans = list(plans)
+        self.lanes = None if lanes is None else [int(v) for v in lanes]
+        if self.lanes is not None and (len(self.lanes) != len(self.plans) or
+                                       not all(0 <= v < max(1, int(n_streams)) for v in self.lanes)):
+            raise ValueError("lanes needs one stream index in [0, n_streams) per plan")
         self.max_inflight_per_matrix = max(1, int(max_inflight_per_matrix))
         self.use_baseline = [False] * len(self.plans) if use_baseline is None \
             else [bool(b) for b in use_baseline]
@@ -138,6 +146,20 @@ class Server:
         # per-stream buffers reused by serve(keep=False): stacked inputs, outputs
         self._stage = [None] * len(self.streams)
         self._out = [None] * len(self.streams)
+
+    @staticmethod
+    def size_lanes(plans: Sequence[Plan], n_streams: int) -> List[int]:
+        """Stream per matrix: the n_streams - 1 largest matrices (by stored
+        entries) get a stream each and the others share the last one, so a
+        small matrix's short batches never queue behind a large matrix's
+        long ones on a stream (nor on the hardware queue it maps to, when
+        n_streams does not exceed the device's hardware queues)."""
+        n_streams = max(1, int(n_streams))
+        order = sorted(range(len(plans)), key=lambda m: -plans[m].nnz)
+        lanes = [n_streams - 1] * len(plans)
+        for rank, m in enumerate(order[:n_streams - 1]):
+            lanes[m] = rank
+        return lanes
 
     def _scratch(self, store: list, si: int, numel: int, device):
         """Stream si's reusable buffer of at least numel doubles.  Only the
@@ -272,7 +294,8 @@ class Server:
             while free_streams:
                 busy = collections.Counter(item[2][0].matrix for item in running)
                 heads = [(q[0].arrival, m) for m, q in pending.items()
-                         if q and busy[m] < self.max_inflight_per_matrix]
+                         if q and busy[m] < self.max_inflight_per_matrix and
+                         (self.lanes is None or self.lanes[m] in free_streams)]
                 if not heads:
                     break
                 _, m = min(heads)
@@ -284,7 +307,11 @@ class Server:
                     for r in reversed(batch):
                         q.appendleft(r)
                     break
-                si = free_streams.pop()
+                if self.lanes is None:
+                    si = free_streams.pop()
+                else:
+                    si = self.lanes[m]
+                    free_streams.remove(si)
                 start = time.perf_counter() - t0
                 Y, ev, p = self._launch(batch, si, keep)
                 in_use += nbytes

@@ -139,7 +139,7 @@ def test_unkept_outputs_equal_alone():
         P.close()
 
 
-@pytest.mark.parametrize("inflight", [1, 3])
+@pytest.mark.parametrize("inflight", [1, 3, "lanes"])
 def test_baseline_plans_and_inflight_limit(inflight):
     """Plans served through the p x SpMV kernels (use_baseline) and the limit
     on batches in flight per matrix change neither result nor order: every
@@ -160,8 +160,12 @@ def test_baseline_plans_and_inflight_limit(inflight):
         reqs.append(serve.Request(id=s["id"], arrival=s["t"], matrix=s["matrix"], p=p,
                                   x=device_x(mats[s["matrix"]].n, s["R"], s["x_seed"]),
                                   kind=kind, dt=dt))
-    srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20,
-                       max_inflight_per_matrix=inflight, use_baseline=[True, False, True])
+    if inflight == "lanes":
+        srv = serve.Server(plans, n_streams=2, mem_budget=64 << 20, use_baseline=[True, False, True],
+                           lanes=serve.Server.size_lanes(plans, 2))
+    else:
+        srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20,
+                           max_inflight_per_matrix=inflight, use_baseline=[True, False, True])
     res = srv.serve(reqs, realtime=False)
     assert [r.id for r in res] == [q.id for q in reqs]
     assert all(r.error is None for r in res)

@@ -59,3 +59,12 @@ def test_time_steps_batch_only_with_equal_dt_and_order():
 def test_time_step_batch_bytes():
     # x, the stepped states, two sums and the two-vector ring
     assert serve.batch_bytes(1000, 16, 4, "time_step") == 8 * 1000 * 4 * 6
+
+
+def test_size_lanes_give_large_matrices_their_own_stream():
+    import types
+    plans = [types.SimpleNamespace(nnz=v) for v in (10, 5000, 300, 90000, 20, 7000)]
+    lanes = serve.Server.size_lanes(plans, 4)
+    assert lanes == [3, 2, 3, 0, 3, 1]
+    assert serve.Server.size_lanes(plans, 1) == [0] * 6
+    assert sorted(set(serve.Server.size_lanes(plans, 8))) == list(range(6))
