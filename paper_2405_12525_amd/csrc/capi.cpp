@@ -1627,6 +1627,7 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
             add(MPK_SCHED_POWERS, 64, 8192, 0, wpc * cus, 0, 0, 1);
             add(MPK_SCHED_WAVE, 64, 16384, std::max(1, 2 * wpc * cus / p), wpc * cus, 0, 0, 1);
         }
+        add(MPK_SCHED_POWERS, 64, 4096, 0, 8 * cus, 0, 0, 1);
     }
     if (p >= 4) add(MPK_SCHED_WAVE, 64, 32768, 0, 0, (p + 1) / 2);  // two segments
     add(MPK_SCHED_WAVE, 64, 16384, 0, 0, 0, 2);                     // park up to two tasks

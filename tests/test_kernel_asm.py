@@ -158,9 +158,11 @@ def _instructions_with_loop_flag(lines):
 
 def _publish_ok(lines):
     """Every flag store inside the task loop (a dword store at agent scope)
-    follows a barrier that is entered only through an s_waitcnt vmcnt(0)
-    (the line just before the barrier, with no label in between), and no
-    vector memory instruction lies between that barrier and the store."""
+    follows a barrier that is entered only through an s_waitcnt vmcnt(0):
+    between that wait and the barrier lie neither labels nor global, buffer,
+    flat or scratch memory instructions (scalar and vector arithmetic and LDS
+    may), and no vector memory instruction lies between that barrier and the
+    store."""
     ins = _instructions_with_loop_flag(lines)
     flags = [t for t, loop in ins if loop and re.match(r"global_store_dword .* sc1", t)]
     assert flags
@@ -170,7 +172,12 @@ def _publish_ok(lines):
         if not (re.match(r"global_store_dword .* sc1", line) and line in flags):
             continue
         b = max(j for j in range(f) if raw[j].startswith("s_barrier"))
-        assert re.match(r"s_waitcnt .*vmcnt\(0\)", raw[b - 1]), raw[b - 3:b + 1]
+        w = b - 1
+        while not re.match(r"s_waitcnt .*vmcnt\(0\)", raw[w]):
+            assert not raw[w].startswith(("global_", "buffer_", "flat_", "scratch_")), raw[w:b + 1]
+            assert not re.match(r"^\.LBB", raw[w]) and not raw[w].endswith(":"), raw[w:b + 1]
+            w -= 1
+            assert w > 0, raw[b - 3:b + 1]
         between = [l for l in raw[b + 1:f] if l.startswith(("global_", "buffer_", "flat_"))
                    or re.match(r"^\.LBB", l)]
         assert not between, between
