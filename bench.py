@@ -853,6 +853,7 @@ def main():
         "plan": {"host_ms": round(info["plan_ms"], 1), "levels": info["n_levels"],
                  "chunks": sched["n_chunks"], "launches_per_run": sched["n_steps"],
                  "window_bytes": int(sched["window_bytes"]), "max_reach": sched["max_reach"],
+                 "window_within_budget_C": bool(sched["window_bytes"] <= tune["cache_bytes"]),
                  "sliced_layout": bool(info["sliced_layout"]),
                  "spmv_equivalents": round(info["plan_ms"] / (bmed / p), 1),
                  "from_device_csr_ms": dev_ms,
