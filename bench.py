@@ -288,14 +288,15 @@ def flush_bytes(wts, V):
     return V if n_flush == 0 else V + 2 * V * (n_flush - 1)
 
 
-def time_step(torch, mpk, w, steps, warmup, stream, with_oracle=True):
+def time_step(torch, mpk, w, steps, warmup, stream, with_oracle=True, tuning=None):
     """One Chebyshev time step exp(-i dt H) psi on the Anderson lattice (160^3,
     FP32 values, 4 complex states as 8 real columns, M = 16, dt = 1): the
     weighted sums accumulated in the kernels over a two-vector ring, level-
     blocked and as p x SpMV, against the recurrence that writes all M vectors
     (without even summing them).  The result is checked bit for bit against
     the oracle's sums with the same weights when the CPU leg is on
-    (with_oracle)."""
+    (with_oracle).  tuning: a fixed level-blocked tuning instead of the
+    autotuner's (profiling)."""
     import numpy as np
     A, x, _, _ = w.config("anderson160_cheb16_r8")
     M, dt = 16, 1.0
@@ -305,7 +306,10 @@ def time_step(torch, mpk, w, steps, warmup, stream, with_oracle=True):
     # the lattice's own order: faster than BFS order for both forms here
     P = mpk.Plan(A, value_bits=32, reorder="none")
     Y = torch.empty((M, n, R), dtype=torch.float64, device="cuda")
-    tq = P.autotune(xd, M, Y, reps=3, recur=2, stream=stream)   # the weighted-sum kernels
+    if tuning is None:
+        tq = P.autotune(xd, M, Y, reps=3, recur=2, stream=stream)   # the weighted-sum kernels
+    else:
+        tq = P.tune(**tuning)
     out = torch.empty_like(xd)
     acc = torch.empty((2, n, R), dtype=torch.float64, device="cuda")
     work = torch.empty((2, n, R), dtype=torch.float64, device="cuda")
@@ -536,7 +540,8 @@ def reduce_counters(d):
         with open(KERNEL_SRC, "rb") as fh:
             out["kernels_sha256"] = hashlib.sha256(fh.read()).hexdigest()
         out["command"] = line.get("command")
-        out["workload"] = line["config"]["workload"]
+        out["workload"] = line.get("config", {}).get("workload", line.get("workload", ""))
+    if line is not None and "roofline" in line:
         p = line["config"]["p"]
 
         def run_entry(pred, launches):
@@ -602,6 +607,15 @@ def counters_markdown(d, summary):
     for key, e in summary.get("runs", {}).items():
         lines.append(f"| `{key}` | `{e['kernel']}` | {e['launches_per_run']} | {e['avg_launch_us']} | "
                      f"{e['l2_egress_bytes_per_run']:,} | {e.get('l2_hit_rate')} |")
+    lines += ["", "## Traffic per launch of the MPK kernels", "",
+              "| Kernel | Launches | Avg µs | L2-egress bytes/launch | L2 hit rate |",
+              "|---|---|---|---|---|"]
+    hot = ("lb_", "spmv_", "step_", "xcd_", "combine_")
+    for k, e in sorted(summary.get("kernels", {}).items(), key=lambda kv: -kv[1]["avg_us"] *
+                       kv[1]["launches"]):
+        if k.split("::")[-1].startswith(hot) and "l2_egress_bytes_per_launch" in e:
+            lines.append(f"| `{k}` | {e['launches']} | {e['avg_us']} | "
+                         f"{e['l2_egress_bytes_per_launch']:,} | {e.get('l2_hit_rate')} |")
     return "\n".join(lines) + "\n"
 
 
@@ -693,8 +707,16 @@ def main():
         print(json.dumps(bandwidth_sweep(torch, mpk, stream)), flush=True)
         return
     if args.time_step_only:
-        print(json.dumps(time_step(torch, mpk, w, args.steps, args.warmup, stream,
-                                   not args.no_cpu)), flush=True)
+        fixed = None
+        if args.schedule is not None:
+            fixed = dict(schedule=args.schedule, chunk_nnz=args.chunk, lag=args.lag,
+                         workgroups=args.workgroups, seg_powers=args.seg_powers,
+                         cache_bytes=args.cache_mib << 20)
+        ts = time_step(torch, mpk, w, args.steps, args.warmup, stream, not args.no_cpu, fixed)
+        ts["command"] = "python3 bench.py " + " ".join(sys.argv[1:])
+        ts["workload"] = ("Chebyshev time step, Anderson 160^3 periodic, FP32 values, 4 complex "
+                          "states, M = 16, dt = 1")
+        print(json.dumps(ts), flush=True)
         return
     t0 = time.perf_counter()
     A, x, p, kind = w.config(args.workload)
