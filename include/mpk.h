@@ -109,7 +109,8 @@ typedef struct {
 typedef struct {
     int value_bits;          /* 64 (default) or 32: values stored as float,
                                 promoted to double before each product        */
-    int reorder;             /* MPK_REORDER_BFS (default) or MPK_REORDER_NONE   */
+    int reorder;             /* MPK_REORDER_BFS (default), MPK_REORDER_NONE or
+                                MPK_REORDER_SUBLEVELS                           */
     int order;               /* MPK_ORDER_ORIGINAL (default) or MPK_ORDER_PLAN  */
     int root;                /* BFS root row (default 0), or
                                 MPK_ROOT_PERIPHERAL                           */
@@ -142,10 +143,13 @@ typedef struct {
     int chunk_nnz;           /* target nonzeros per chunk = per workgroup task
                                 (default 32768; capped at nnz / (2 x running
                                 workgroups), at least 1024, so that small
-                                matrices still fill the device)                 */
-    int lag;                 /* WAVE, XCD: slack in chunks; 0 = from the budget  */
-    int workgroups;          /* persistent schedules: workgroups; 0 = two per
-                                compute unit (where they fit)                   */
+                                matrices still fill the device; WAVE and POWERS
+                                cut chunks on multiples of 256 rows)            */
+    int lag;                 /* WAVE, XCD: slack in chunks; 0 = from the budget
+                                and the running workgroups                      */
+    int workgroups;          /* persistent schedules: workgroups; 0 = as many as
+                                fit, at most two per compute unit (four with the
+                                sliced layout)                                  */
     int64_t spin_limit_us;   /* dependency-wait limit in microseconds, 0 = 2 s  */
     int seg_powers;          /* powers blocked together per launch (1..64);
                                 p is run as ceil(p / seg_powers) segments that
