@@ -364,6 +364,8 @@ def time_step(torch, mpk, w, steps, warmup, stream, with_oracle=True, tuning=Non
     lb_b = Ab + V + 2 * V + 2 * V + 3 * V
     res = {"n": n, "nnz": A.nnz, "M": M, "dt": dt, "states": R // 2, "real_columns": R,
            "values": "fp32", "schedule": tq["schedule"], "gflops_flop_count": flop,
+           "tuning": {k: tq[k] for k in ("schedule", "chunk_nnz", "lag", "workgroups",
+                                         "seg_powers", "dynamic_tickets")},
            "lb_fused_ms": round(lb, 4), "lb_fused_gflops": round(flop / lb / 1e6, 1),
            "pxspmv_fused_ms": round(tr, 4), "pxspmv_fused_gflops": round(flop / tr / 1e6, 1),
            "hip_graph_ms": graphs,

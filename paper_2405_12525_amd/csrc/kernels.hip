@@ -304,15 +304,25 @@ __device__ void run_rows(const DevMatrix &m, const PowerIO &io, int R_rt, int32_
 // slot past the row end reloads the row's last entry and adds nothing).  The
 // 64 rows of a slice read each slot with one coalesced access, and the R
 // threads of a row share it.  No LDS, no barrier: idle lanes (R not dividing
-// the block) just skip.  U = 4: more waves in flight won over fewer round
-// trips per row (8 and 16 were measured slower, also for 4 to 16
-// right-hand sides).
+// the block) just skip.  U slots per group: fewer loads in flight per thread
+// queue less in the memory system, more save round trips; the best width
+// differs between the kernels (measured on 27-point rows and on 7-point rows
+// with 8 right-hand sides; 6, 8 and 16 were slower everywhere):
+// * the persistent level-blocked kernels, whose tasks wait on each other:
+//   U = 4;
+// * the one-launch-per-power baseline: U = 2 for one right-hand side (3.4%
+//   faster than 4 on the 27-point stencil), U = 4 for more (2 and 3 were
+//   13% and 6% slower with 8 right-hand sides).
 template <int RC>
 struct SellU {
     static constexpr int value = 4;
 };
+template <int RC>
+struct SpmvSellU {
+    static constexpr int value = RC == 1 ? 2 : 4;
+};
 constexpr int64_t kSpmvSellGrid = 4096;   // baseline workgroups per power (sliced layout)
-template <typename V, int RC, bool WT, bool ACC>
+template <typename V, int RC, bool WT, bool ACC, int U>
 __device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, int R_rt,
                                          int32_t r0, int32_t r1) {
     const int R = RC ? RC : R_rt;
@@ -321,7 +331,6 @@ __device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, 
     const int li = tid / R;
     const int rr = tid - li * R;
     if (li >= rows_per_step) return;
-    constexpr int U = SellU<RC>::value;
     const V *sval = static_cast<const V *>(m.sval);
     for (int32_t row = r0 + li; row < r1; row += rows_per_step) {
         const int32_t L = m.rlen[row];
@@ -498,7 +507,7 @@ template <typename V, int RC, bool ACC>
 __global__ __launch_bounds__(kBlock) void spmv_sell_kernel(DevMatrix m, PowerIO io, int32_t R) {
     const int32_t step = kBlock / (RC ? RC : R);
     for (int32_t r0 = blockIdx.x * step; r0 < m.n; r0 += gridDim.x * step)
-        run_sell<V, RC, false, ACC>(m, io, R, r0, min(m.n, r0 + step));
+        run_sell<V, RC, false, ACC, SpmvSellU<RC>::value>(m, io, R, r0, min(m.n, r0 + step));
 }
 
 // ------------------------------------------------------------------ level-blocked
@@ -513,7 +522,7 @@ __device__ __forceinline__ void run_chunk(const DevMatrix &m, const PowerIO &io,
                                           DevSlices sl, const int32_t *chunk_sptr,
                                           const int32_t *chunk_row, int32_t c) {
     if constexpr (SELL) {
-        run_sell<V, RC, WT, ACC>(m, io, R, chunk_row[c], chunk_row[c + 1]);
+        run_sell<V, RC, WT, ACC, SellU<RC>::value>(m, io, R, chunk_row[c], chunk_row[c + 1]);
     } else {
         __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
         run_slices<V, RC, Staging<RC, kTaskKP>::value, WT, ACC>(m, io, R, sl, chunk_sptr[c],
