@@ -168,7 +168,10 @@ typedef struct {
                                 the launch can hold the device alone: outside
                                 graph capture, without skip-ahead, with every
                                 workgroup resident; such launches (and XCD
-                                launches) wait for each other on a device     */
+                                launches) of this process wait for each other
+                                on a device (another process's persistent
+                                kernels are not ordered: a wait they block
+                                ends at spin_limit_us with MPK_ETIMEOUT)       */
 } mpk_tune_t;
 
 typedef struct {

@@ -423,6 +423,8 @@ mpk_status_t init_device_state(mpk_plan_t plan) {
     return e == hipSuccess ? MPK_OK : hip_fail(e, "hipMemset");
 }
 
+// Workgroups of the level-blocked kernel the device holds at once (cached in
+// wg_cache under negative keys, apart from default_workgroups' entries).
 int resident_workgroups(mpk_plan_t plan, int R, bool acc) {
     const long long key = -((long long)plan->value_bits * 1000 + R * 2 + (acc ? 1 : 0)) - 1;
     auto it = plan->wg_cache.find(key);
