@@ -162,7 +162,12 @@ def serving(torch, mpk, w, rates, n_requests=512):
 
     def paced(st, rate):
         return {"rate_rps": round(rate, 1), "p50_ms": round(st["p50_ms"], 3),
-                "p99_ms": round(st["p99_ms"], 3), "throughput_rps": round(st["throughput_rps"], 1),
+                "p99_ms": round(st["p99_ms"], 3),
+                "queue_p50_ms": round(st["queue_p50_ms"], 3),
+                "queue_p99_ms": round(st["queue_p99_ms"], 3),
+                "device_p50_ms": round(st["device_p50_ms"], 3),
+                "device_p99_ms": round(st["device_p99_ms"], 3),
+                "throughput_rps": round(st["throughput_rps"], 1),
                 "gflops": round(st["gflops"], 1), "mean_batch": round(st["mean_batch"], 2),
                 "by_matrix": {names[m]: {"n": v["n"], "requests": v["requests"],
                                          "p50_ms": round(v["p50_ms"], 3),

@@ -359,8 +359,16 @@ def summarize(results: Sequence[Result], requests: Sequence[Request], plans: Seq
         by_matrix[m] = {"n": plans[m].n, "requests": int(lm.size),
                         "p50_ms": float(np.percentile(lm, 50) * 1e3),
                         "p99_ms": float(np.percentile(lm, 99) * 1e3)}
+    # where the latency goes: waiting for a stream and memory (arrival to
+    # launch) and the batch's time from launch to observed completion
+    wait = np.array([r.start - r.arrival for r in results])
+    run = np.array([r.done - r.start for r in results])
     return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "queue_p50_ms": float(np.percentile(wait, 50) * 1e3),
+            "queue_p99_ms": float(np.percentile(wait, 99) * 1e3),
+            "device_p50_ms": float(np.percentile(run, 50) * 1e3),
+            "device_p99_ms": float(np.percentile(run, 99) * 1e3),
             "throughput_rps": len(results) / span, "gflops": fl / span / 1e9,
             "mean_batch": float(np.mean([r.batch_size for r in results])), "span_s": span,
             "by_matrix": by_matrix}

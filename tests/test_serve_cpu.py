@@ -68,3 +68,23 @@ def test_size_lanes_give_large_matrices_their_own_stream():
     assert lanes == [3, 2, 3, 0, 3, 1]
     assert serve.Server.size_lanes(plans, 1) == [0] * 6
     assert sorted(set(serve.Server.size_lanes(plans, 8))) == list(range(6))
+
+
+def test_summarize_splits_queue_and_device_time():
+    import types
+    plans = [types.SimpleNamespace(n=100, nnz=500), types.SimpleNamespace(n=1000, nnz=9000)]
+    reqs = [serve.Request(id=i, arrival=0.01 * i, matrix=i % 2, p=4, x=FakeX(2)) for i in range(4)]
+    # request i waits i ms for its launch and runs 10 ms
+    res = [serve.Result(id=i, Y=None, arrival=0.01 * i, start=0.01 * i + 0.001 * i,
+                        done=0.01 * i + 0.001 * i + 0.010, batch_size=1) for i in range(4)]
+    st = serve.summarize(res, reqs, plans)
+    assert st["requests"] == 4
+    assert abs(st["device_p50_ms"] - 10.0) < 1e-9 and abs(st["device_p99_ms"] - 10.0) < 1e-9
+    assert abs(st["queue_p50_ms"] - 1.5) < 1e-9
+    assert abs(st["p50_ms"] - 11.5) < 1e-9
+    assert sorted(st["by_matrix"]) == [0, 1]
+    assert st["by_matrix"][1]["n"] == 1000 and st["by_matrix"][1]["requests"] == 2
+    # failed results are left out
+    res[0] = serve.Result(id=0, Y=None, arrival=0.0, start=0.0, done=1.0, batch_size=1,
+                          error="a dependency wait hit its limit")
+    assert serve.summarize(res, reqs, plans)["requests"] == 3
