@@ -659,6 +659,8 @@ def main():
                     help="persistent workgroups with --schedule (0: the library's default)")
     ap.add_argument("--seg-powers", type=int, default=0,
                     help="powers per launch with --schedule (0: all)")
+    ap.add_argument("--dynamic-tickets", type=int, default=0, choices=[0, 1],
+                    help="with --schedule: 1 = tasks from a shared counter, 0 = static order")
     ap.add_argument("--reorder", default="bfs", choices=["bfs", "none", "sublevels"],
                     help="level construction with --schedule")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
@@ -718,7 +720,7 @@ def main():
         if args.schedule is not None:
             fixed = dict(schedule=args.schedule, chunk_nnz=args.chunk, lag=args.lag,
                          workgroups=args.workgroups, seg_powers=args.seg_powers,
-                         cache_bytes=args.cache_mib << 20)
+                         cache_bytes=args.cache_mib << 20, dynamic_tickets=args.dynamic_tickets)
         ts = time_step(torch, mpk, w, args.steps, args.warmup, stream, not args.no_cpu, fixed)
         ts["command"] = "python3 bench.py " + " ".join(sys.argv[1:])
         ts["workload"] = ("Chebyshev time step, Anderson 160^3 periodic, FP32 values, 4 complex "
@@ -767,7 +769,8 @@ def main():
         else:
             tq = Q.tune(schedule=args.schedule, chunk_nnz=args.chunk,
                         cache_bytes=args.cache_mib << 20, lag=args.lag,
-                        workgroups=args.workgroups, seg_powers=args.seg_powers)
+                        workgroups=args.workgroups, seg_powers=args.seg_powers,
+                        dynamic_tickets=args.dynamic_tickets)
         r = time_calls(lambda: run_lb(Q, Y), args.steps, args.warmup, torch, stream)
         Q.sync()
         log(f"[bench] level-blocked reorder={ro}: autotuned in {time.perf_counter() - t0:.1f}s "
