@@ -171,7 +171,13 @@ typedef struct {
                                 launches) of this process wait for each other
                                 on a device (another process's persistent
                                 kernels are not ordered: a wait they block
-                                ends at spin_limit_us with MPK_ETIMEOUT)       */
+                                ends at spin_limit_us with MPK_ETIMEOUT).
+                                Other kernels running at the same time hold
+                                compute units that the fixed order waits
+                                for, so runs made beside other work (several
+                                streams, serving) should set 1: with the
+                                counter a task waits only on tasks that
+                                running workgroups hold                         */
 } mpk_tune_t;
 
 typedef struct {
@@ -483,9 +489,12 @@ mpk_status_t mpk_run_status(mpk_plan_t plan, void *hip_stream, int32_t *status);
  * persistent schedules one or two workgroups per compute unit, p split into
  * two segments, skip-ahead parking), keeps the fastest and sets it on the
  * plan.  Each candidate runs once untimed, then
- * `reps` timed runs on `stream` (mean).  Results are cached per (matrix
- * fingerprint, value precision, p, nrhs, recur): a later call with the
- * same key applies the cached tuning without timing unless force != 0.
+ * `reps` timed runs on `stream` (mean).  A plan whose tuning has
+ * dynamic_tickets = 1 when the call starts keeps the shared counter in every
+ * candidate.  Results are cached per (matrix fingerprint, value precision,
+ * p, nrhs, recur, that dynamic_tickets): a later call with the same key
+ * applies the cached tuning (the plan's spin_limit_us kept) without timing
+ * unless force != 0.
  * recur: 0 = time mpk_run, 1 = mpk_run_recur, 2 = the weighted sums of
  * mpk_run_poly (p >= 4; their kernels differ from the plain run's).
  * x: n*nrhs doubles, Y: p*n*nrhs doubles (device scratch; overwritten).

@@ -1543,15 +1543,18 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (stream) (void)hipStreamIsCapturing(stream, &cap);
     if (cap != hipStreamCaptureStatusNone) return fail(MPK_EINVAL, "cannot autotune while capturing");
-    using Key = std::tuple<uint64_t, int, int, int, int>;
-    static std::mutex cache_mu;
-    static std::map<Key, std::pair<mpk_tune_t, double>> cache;
-    const Key key{plan->fingerprint, plan->value_bits, p, nrhs, recur};
     mpk_tune_t base;
     {
         std::lock_guard<std::mutex> g(plan->mu);
         base = plan->tune;
     }
+    // a plan set to the shared counter (for runs beside other kernels) keeps
+    // it in every candidate
+    const int keep_dyn = base.dynamic_tickets;
+    using Key = std::tuple<uint64_t, int, int, int, int, int>;
+    static std::mutex cache_mu;
+    static std::map<Key, std::pair<mpk_tune_t, double>> cache;
+    const Key key{plan->fingerprint, plan->value_bits, p, nrhs, recur, keep_dyn};
     if (!force) {
         std::pair<mpk_tune_t, double> hit;
         bool found = false;
@@ -1565,7 +1568,6 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
         }
         if (found) {
             mpk_tune_t t = hit.first;
-            t.workgroups = base.workgroups;
             t.spin_limit_us = base.spin_limit_us;
             if ((st = mpk_plan_tune(plan, &t))) return st;
             if (best) *best = t;
@@ -1588,7 +1590,13 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
         t.workgroups = wg;
         t.seg_powers = seg;
         t.skip_ahead = skip;
-        t.dynamic_tickets = dyn;
+        t.dynamic_tickets = dyn | keep_dyn;
+        for (const mpk_tune_t &c : cands)
+            if (c.schedule == t.schedule && c.cache_bytes == t.cache_bytes &&
+                c.chunk_nnz == t.chunk_nnz && c.lag == t.lag && c.workgroups == t.workgroups &&
+                c.seg_powers == t.seg_powers && c.skip_ahead == t.skip_ahead &&
+                c.dynamic_tickets == t.dynamic_tickets)
+                return;  // the same candidate once more
         cands.push_back(t);
     };
     for (int64_t c : {32, 64, 128})

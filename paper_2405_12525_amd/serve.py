@@ -23,7 +23,12 @@ the loop admits them as stream slots and memory free up:
   short batches do not wait behind long ones);
 * each plan runs its batches through the level-blocked kernels or, where
   the caller found them faster for that matrix (use_baseline), through the
-  p x SpMV kernels: the results are the same bit for bit;
+  p x SpMV kernels: the results are the same bit for bit.  Plans served
+  through the level-blocked kernels are set to take tasks from the shared
+  counter (tune dynamic_tickets = 1): their runs share the device with other
+  batches, and the fixed task order needs every workgroup of a launch
+  resident, which other kernels delay, while with the counter a task waits
+  only on tasks that running workgroups hold;
 * a batch is admitted only while the device memory held by running batches
   (stacked inputs plus outputs) stays within the budget;
 * each batch's device status (mpk_run_status, copied into pinned host memory
@@ -110,7 +115,18 @@ def form_batch(queue: collections.deque, max_rhs: int = MAX_RHS) -> List[Request
 class Server:
     """Holds plans on the device and serves request streams.
 
-    plans: one Plan per matrix (device plans, already tuned as wished).
+    Streams that share a hardware queue run in that queue's order, so a
+    short batch waits for a long one queued before it on another stream.
+    HIP maps a process's streams onto GPU_MAX_HW_QUEUES queues (4 unless set
+    in the environment before HIP starts), the default stream included: give
+    the process more queues than n_streams.  A level-blocked batch holds its
+    persistent workgroups for its whole run; two long ones can fill the
+    device, and batches on other streams then wait for them.
+
+    plans: one Plan per matrix (device plans, already tuned as wished; a
+        plan served through the level-blocked kernels is set to
+        dynamic_tickets = 1 here, so tune it with that set, e.g.
+        P.tune(dynamic_tickets=1) before P.autotune, which then keeps it).
     n_streams: batches that may run at once.
     mem_budget: bytes of batch memory (inputs plus outputs) in flight.
     """
@@ -131,6 +147,9 @@ class Server:
             else [bool(b) for b in use_baseline]
         if len(self.use_baseline) != len(self.plans):
             raise ValueError("use_baseline needs one entry per plan")
+        for P, base in zip(self.plans, self.use_baseline):
+            if not base and P.n > 0 and not P.tuning["dynamic_tickets"]:
+                P.tune(dynamic_tickets=1)
         self.max_rhs = int(max_rhs)
         if not 1 <= self.max_rhs <= MAX_RHS:
             raise ValueError("max_rhs must be in [1, 16]")
@@ -146,6 +165,16 @@ class Server:
         # per-stream buffers reused by serve(keep=False): stacked inputs, outputs
         self._stage = [None] * len(self.streams)
         self._out = [None] * len(self.streams)
+
+    def prepare(self, max_p: int, rhs=range(1, MAX_RHS + 1)) -> None:
+        """Build ahead of time what batches of up to max_p powers and any
+        stacked right-hand-side count in rhs fetch on first use (schedules,
+        slice tables, workspaces; mpk_plan_prepare).  Otherwise the first
+        batch of each new shape plans and uploads on the host while the loop
+        waits, and every batch in flight is observed late."""
+        for P, base in zip(self.plans, self.use_baseline):
+            if P.n > 0:
+                P.prepare([1] if base else range(1, int(max_p) + 1), rhs)
 
     @staticmethod
     def size_lanes(plans: Sequence[Plan], n_streams: int) -> List[int]:
@@ -353,16 +382,21 @@ def summarize(results: Sequence[Result], requests: Sequence[Request], plans: Seq
     first = min(r.arrival for r in results)
     last = max(r.done for r in results)
     span = max(last - first, 1e-9)
-    by_matrix = {}
-    for m in sorted({by_id[r.id].matrix for r in results}):
-        lm = np.array([r.latency for r in results if by_id[r.id].matrix == m])
-        by_matrix[m] = {"n": plans[m].n, "requests": int(lm.size),
-                        "p50_ms": float(np.percentile(lm, 50) * 1e3),
-                        "p99_ms": float(np.percentile(lm, 99) * 1e3)}
     # where the latency goes: waiting for a stream and memory (arrival to
     # launch) and the batch's time from launch to observed completion
     wait = np.array([r.start - r.arrival for r in results])
     run = np.array([r.done - r.start for r in results])
+    mat = np.array([by_id[r.id].matrix for r in results])
+    by_matrix = {}
+    for m in sorted(set(mat.tolist())):
+        sel = mat == m
+        lm = lat[sel]
+        by_matrix[m] = {"n": plans[m].n, "requests": int(lm.size),
+                        "p50_ms": float(np.percentile(lm, 50) * 1e3),
+                        "p99_ms": float(np.percentile(lm, 99) * 1e3),
+                        "queue_p99_ms": float(np.percentile(wait[sel], 99) * 1e3),
+                        "device_p50_ms": float(np.percentile(run[sel], 50) * 1e3),
+                        "device_p99_ms": float(np.percentile(run[sel], 99) * 1e3)}
     return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
             "queue_p50_ms": float(np.percentile(wait, 50) * 1e3),

@@ -111,10 +111,24 @@ def test_autotune_choice_is_exact_and_cached():
     t0 = time.perf_counter()
     t2 = Q.autotune(xd, 5)
     assert time.perf_counter() - t0 < 0.5
-    assert {k: t2[k] for k in ("schedule", "cache_bytes", "chunk_nnz")} == \
-        {k: t[k] for k in ("schedule", "cache_bytes", "chunk_nnz")}
+    tuned = ("schedule", "cache_bytes", "chunk_nnz", "lag", "workgroups", "seg_powers",
+             "skip_ahead", "dynamic_tickets")
+    assert {k: t2[k] for k in tuned} == {k: t[k] for k in tuned}
+    # a plan set to the shared counter keeps it in every candidate, and its
+    # choice is cached apart from the fixed-order one
+    Q.tune(dynamic_tickets=1)
+    t3 = Q.autotune(xd, 5, reps=1, force=True)
+    assert t3["dynamic_tickets"] == 1 and Q.tuning["dynamic_tickets"] == 1
+    Y3 = Q.run(xd, 5)
+    Q.sync()
+    assert np.array_equal(host(Y3), oracle.powers(A, x, 5))
+    R = mpk.Plan(A)
+    R.tune(dynamic_tickets=1)
+    t4 = R.autotune(xd, 5)
+    assert {k: t4[k] for k in tuned} == {k: t3[k] for k in tuned}
     P.close()
     Q.close()
+    R.close()
 
 
 def test_autotune_recurrence_fp32():

@@ -35,6 +35,9 @@ def test_mix_equals_alone(realtime):
                                   x=device_x(mats[s["matrix"]].n, s["R"], s["x_seed"]),
                                   kind=kind))
     srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20)
+    # level-blocked plans run beside other batches: tasks from the shared counter
+    assert all(P.tuning["dynamic_tickets"] == 1 for P in plans)
+    assert plans[2].tuning["schedule"] == "xcd" and plans[1].tuning["chunk_nnz"] == 3000
     res = srv.serve(reqs, realtime=realtime)
     assert [r.id for r in res] == [q.id for q in reqs]
     assert max(r.batch_size for r in res) > 1          # batching happened
@@ -166,6 +169,9 @@ def test_baseline_plans_and_inflight_limit(inflight):
     else:
         srv = serve.Server(plans, n_streams=3, mem_budget=64 << 20,
                            max_inflight_per_matrix=inflight, use_baseline=[True, False, True])
+    # only the plan served through the level-blocked kernels is switched
+    assert [P.tuning["dynamic_tickets"] for P in plans] == [0, 1, 0]
+    srv.prepare(10)   # every shape these requests can form, built ahead
     res = srv.serve(reqs, realtime=False)
     assert [r.id for r in res] == [q.id for q in reqs]
     assert all(r.error is None for r in res)
@@ -185,6 +191,7 @@ def test_baseline_plans_and_inflight_limit(inflight):
     assert sum(v["requests"] for v in st["by_matrix"].values()) == len(reqs)
     for m, v in st["by_matrix"].items():
         assert v["n"] == mats[m].n and v["p99_ms"] >= v["p50_ms"] > 0
+        assert v["device_p99_ms"] >= v["device_p50_ms"] > 0 and v["queue_p99_ms"] >= 0
     with pytest.raises(ValueError):
         serve.Server(plans, use_baseline=[True])
     for P in plans:
