@@ -489,7 +489,8 @@ mpk_status_t mpk_run_status(mpk_plan_t plan, void *hip_stream, int32_t *status);
  * persistent schedules one or two workgroups per compute unit, p split into
  * two segments, skip-ahead parking), keeps the fastest and sets it on the
  * plan.  Each candidate runs once untimed, then
- * `reps` timed runs on `stream` (mean).  A plan whose tuning has
+ * `reps` timed runs on `stream` (mean); the three fastest then run as many
+ * times again and are compared on the mean of all their timed runs.  A plan whose tuning has
  * dynamic_tickets = 1 when the call starts keeps the shared counter in every
  * candidate.  Results are cached per (matrix fingerprint, value precision,
  * p, nrhs, recur, that dynamic_tickets): a later call with the same key

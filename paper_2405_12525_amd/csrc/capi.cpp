@@ -1668,17 +1668,18 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
         return recur ? run_lb(plan, x, p, nrhs, al.data(), be.data(), ga.data(), Y, stream_v)
                      : run_lb(plan, x, p, nrhs, nullptr, nullptr, nullptr, Y, stream_v);
     };
-    double best_t = 0.0;
-    int best_i = -1;
+    // `reps` timed runs of candidate i after one untimed run (which builds
+    // its schedule and slices on the first call); appends to sum / count.
+    // Returns false when a wait hit its limit (not a candidate) or on an
+    // error (st set).
     bool timed_out = false;
-    for (size_t i = 0; i < cands.size() && st == MPK_OK; ++i) {
-        if ((st = mpk_plan_tune(plan, &cands[i]))) break;
-        if ((st = one())) break;  // untimed: builds the schedule and slices
+    auto time_cand = [&](size_t i, double &sum, int &count) {
+        if ((st = mpk_plan_tune(plan, &cands[i]))) return false;
+        if ((st = one())) return false;
         if (mpk_plan_sync(plan) != MPK_OK) {
-            timed_out = true;  // a wait hit its limit: not a candidate
-            continue;
+            timed_out = true;
+            return false;
         }
-        std::vector<double> ms;
         for (int r = 0; r < reps && st == MPK_OK; ++r) {
             e = hipEventRecord(e0, stream);
             if (e == hipSuccess) st = one();
@@ -1687,20 +1688,35 @@ mpk_status_t mpk_plan_autotune(mpk_plan_t plan, const double *x, int p, int nrhs
             float f = 0.f;
             if (e == hipSuccess && st == MPK_OK) e = hipEventElapsedTime(&f, e0, e1);
             if (e != hipSuccess && st == MPK_OK) st = hip_fail(e, "timing a candidate");
-            ms.push_back(f);
+            sum += f;
+            ++count;
         }
-        if (st) break;
+        if (st) return false;
         if (mpk_plan_sync(plan) != MPK_OK) {
             timed_out = true;
-            continue;
+            return false;
         }
-        // the mean, not the median: a schedule whose run time is bimodal
-        // (waits that cascade only sometimes) must not win on a lucky draw
-        double mean = 0.0;
-        for (double v : ms) mean += v;
-        mean /= (double)ms.size();
-        if (best_i < 0 || mean < best_t) {
-            best_t = mean;
+        return true;
+    };
+    // the mean, not the median: a schedule whose run time is bimodal (waits
+    // that cascade only sometimes) must not win on a lucky draw; for the
+    // same reason the three fastest are timed once more, after all the
+    // others, and compared on all their runs
+    std::vector<double> sum(cands.size(), 0.0);
+    std::vector<int> count(cands.size(), 0);
+    std::vector<size_t> ok;
+    for (size_t i = 0; i < cands.size() && st == MPK_OK; ++i)
+        if (time_cand(i, sum[i], count[i])) ok.push_back(i);
+    auto mean = [&](size_t i) { return sum[i] / (double)count[i]; };
+    std::sort(ok.begin(), ok.end(), [&](size_t a, size_t b) { return mean(a) < mean(b); });
+    if (ok.size() > 3) ok.resize(3);
+    double best_t = 0.0;
+    int best_i = -1;
+    for (size_t j = 0; j < ok.size() && st == MPK_OK; ++j) {
+        const size_t i = ok[j];
+        if (ok.size() > 1 && !time_cand(i, sum[i], count[i])) continue;
+        if (best_i < 0 || mean(i) < best_t) {
+            best_t = mean(i);
             best_i = (int)i;
         }
     }
