@@ -63,7 +63,7 @@ class PlanInfo(ctypes.Structure):
                 ("sliced_layout", ctypes.c_int32), ("sliced_entries", ctypes.c_int64),
                 ("sublevel_root", ctypes.c_int32), ("max_sublevels", ctypes.c_int32),
                 ("l2_bytes", ctypes.c_int64), ("mall_bytes", ctypes.c_int64),
-                ("min_group_rows", ctypes.c_int32)]
+                ("min_group_rows", ctypes.c_int32), ("sliced_col_bits", ctypes.c_int32)]
 
 
 class SchedInfo(ctypes.Structure):

@@ -475,7 +475,7 @@ __global__ void sell_width_kernel(const int32_t *rowptr, int64_t n, int32_t *wid
 template <typename V>
 __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, const V *val,
                                  int64_t n, const int64_t *soff, int32_t *rlen, int32_t *scol,
-                                 V *sval) {
+                                 int16_t *sdel, V *sval) {
     __shared__ int32_t rp[kSellRows + 1];
     const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
     for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
@@ -494,12 +494,40 @@ __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, cons
             }
             const int64_t dst = base + (int64_t)(e - rp[lo]) * kSellRows + lo;
             scol[dst] = col[e];
+            if (sdel) sdel[dst] = (int16_t)(col[e] - (int32_t)(r0 + lo));
             sval[dst] = val[e];
         }
     }
 }
 
+// out = max over the entries of |col - row| (out preset to 0)
+__global__ void max_col_offset_kernel(const int32_t *rowptr, const int32_t *col, int64_t n,
+                                      int32_t *out) {
+    int32_t m = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            const int64_t d = (int64_t)col[e] - r;
+            m = (int32_t)std::max<int64_t>(m, d < 0 ? -d : d);
+        }
+    if (m > 0) atomicMax(out, m);
+}
+
 }  // namespace
+
+int gpu_max_col_offset(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t *out) {
+    *out = 0;
+    if (n == 0) return 0;
+    Scratch s;
+    int32_t *d;
+    MPK_TRY(s.get(&d, 1));
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, 0, d, (int64_t)1, 0);
+    hipLaunchKernelGGL(max_col_offset_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr,
+                       col, n, d);
+    MPK_TRY(hipGetLastError());
+    MPK_TRY(hipMemcpy(out, d, 4, hipMemcpyDeviceToHost));
+    return 0;
+}
 
 int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width) {
     const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
@@ -516,7 +544,7 @@ int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &widt
 
 int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                   int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
-                  int32_t *scol, void *sval) {
+                  int32_t *scol, int16_t *sdel, void *sval) {
     (void)entries;
     if (n == 0) return 0;
     const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
@@ -524,11 +552,11 @@ int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const vo
     if (value_bits == 32)
         hipLaunchKernelGGL(sell_fill_kernel<float>, grid, dim3(kThreads), 0, 0,
                            rowptr, col, static_cast<const float *>(val), n, soff, rlen, scol,
-                           static_cast<float *>(sval));
+                           sdel, static_cast<float *>(sval));
     else
         hipLaunchKernelGGL(sell_fill_kernel<double>, grid, dim3(kThreads), 0, 0,
                            rowptr, col, static_cast<const double *>(val), n, soff, rlen, scol,
-                           static_cast<double *>(sval));
+                           sdel, static_cast<double *>(sval));
     MPK_TRY(hipGetLastError());
     return (int)hipDeviceSynchronize();
 }

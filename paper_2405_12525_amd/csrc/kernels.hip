@@ -322,9 +322,10 @@ struct SpmvSellU {
     static constexpr int value = RC == 1 ? 2 : 4;
 };
 constexpr int64_t kSpmvSellGrid = 4096;   // baseline workgroups per power (sliced layout)
-template <typename V, int RC, bool WT, bool ACC, int U>
-__device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, int R_rt,
-                                         int32_t r0, int32_t r1) {
+// DEL: the columns come from the 16-bit offsets (col = row + offset).
+template <typename V, int RC, bool WT, bool ACC, int U, bool DEL>
+__device__ __forceinline__ void run_sell_cols(const DevMatrix &m, const PowerIO &io, int R_rt,
+                                              int32_t r0, int32_t r1) {
     const int R = RC ? RC : R_rt;
     const int rows_per_step = kBlock / R;
     const int tid = threadIdx.x;
@@ -342,7 +343,10 @@ __device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t q = base + (int64_t)min(j + u, L - 1) * kSellRows;
-                c[u] = m.scol[q];
+                if constexpr (DEL)
+                    c[u] = row + (int32_t)m.sdel[q];
+                else
+                    c[u] = m.scol[q];
                 a[u] = static_cast<double>(sval[q]);
             }
 #pragma unroll
@@ -354,6 +358,14 @@ __device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, 
         const int32_t o = m.out_row ? m.out_row[row] : row;
         finish<WT, ACC>(io, s, (size_t)o * R + rr);
     }
+}
+template <typename V, int RC, bool WT, bool ACC, int U>
+__device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, int R_rt,
+                                         int32_t r0, int32_t r1) {
+    if (m.sdel)  // uniform: the plan's layout
+        run_sell_cols<V, RC, WT, ACC, U, true>(m, io, R_rt, r0, r1);
+    else
+        run_sell_cols<V, RC, WT, ACC, U, false>(m, io, R_rt, r0, r1);
 }
 
 // Products staged per thread and buffer: the slice path for R < 4 (R = 0 is

@@ -96,11 +96,15 @@ constexpr int kSellRows = 64;
 constexpr int kChunkRows = 4 * kSellRows;
 // gpu_sell_widths: width of every slice (host copy).  gpu_sell_fill: rlen[n]
 // and the slotted columns and values (value_bits 64 or 32, like val) into
-// buffers of `entries` = soff[n_slices] slots.
+// buffers of `entries` = soff[n_slices] slots, and when sdel is not null the
+// slotted column offsets col - row as 16-bit integers (the caller has checked
+// with gpu_max_col_offset that they fit).  gpu_max_col_offset: max over the
+// entries of |col - row| (host copy in *out).
 int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width);
 int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                   int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
-                  int32_t *scol, void *sval);
+                  int32_t *scol, int16_t *sdel, void *sval);
+int gpu_max_col_offset(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t *out);
 // Levels from far[] (order_levels' rule): level 0 = row 0, level j+1 ends
 // just past the farthest neighbour of level j.
 Levels levels_from_far(int64_t n, const std::vector<int32_t> &far);
@@ -166,6 +170,8 @@ struct DevMatrix {
     const int64_t *soff;      // n_slices + 1 slot offsets
     const int32_t *rlen;      // n row lengths
     const int32_t *scol;      // slotted columns
+    const int16_t *sdel;      // slotted column offsets col - row where they all
+                              // fit 16 bits (the kernels then read these), or null
     const void *sval;         // slotted values (double or float)
 };
 

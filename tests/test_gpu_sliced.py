@@ -113,3 +113,59 @@ def test_sliced_rows_time_step_sums():
         got = acc.cpu().numpy()
         assert np.array_equal(got[0], ra) and np.array_equal(got[1], rb), baseline
     P.close()
+
+
+def with_far_entries(A, far, every, seed):
+    """A copy of A where every `every`-th row gets one more entry at column
+    row + far (or row - far where that falls outside), value N(0,1)."""
+    g = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(A.n):
+        c = list(A.col[A.rowptr[i]:A.rowptr[i + 1]])
+        v = list(A.val[A.rowptr[i]:A.rowptr[i + 1]])
+        if i % every == 3:
+            j = i + far if i + far < A.n else i - far
+            if 0 <= j < A.n and j not in c:
+                c.append(j)
+                v.append(float(g.standard_normal()))
+        rows.append(len(c))
+        cols += c
+        vals += v
+    rp = np.zeros(A.n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(rows)
+    return w.CSR(A.n, rp, np.array(cols, dtype=np.int32), np.array(vals), f"far{far}")
+
+
+@pytest.mark.parametrize("far, bits", [(32767, 16), (32768, 32), (39000, 32)])
+def test_column_offsets_16_and_32_bits(far, bits):
+    """The sliced layout stores columns as 16-bit offsets from the row when
+    every entry lies within 32767 of its row, else as columns; both give the
+    oracle's bits.  A 34^3 stencil (n = 39304) with a few entries exactly at
+    the limit or beyond it."""
+    A = with_far_entries(w.stencil_3d27(34), far, 499, far)
+    assert max(abs(int(c) - i) for i in range(A.n)
+               for c in A.col[A.rowptr[i]:A.rowptr[i + 1]]) == far
+    for R in (1, 3):
+        x = dev_x(A.n, R, 7 + R)
+        ref = oracle.powers(A, x.cpu().numpy(), 4)
+        P = mpk.Plan(A, reorder="none")
+        info = P.info()
+        assert info["sliced_layout"] == 1 and info["sliced_col_bits"] == bits
+        for sched in ("wave", "powers", "steps"):
+            P.tune(schedule=sched, chunk_nnz=4000, lag=4)
+            Y = P.run(x, 4)
+            B = P.run_baseline(x, 4)
+            P.sync()
+            assert torch.equal(Y, B), (far, R, sched)
+            assert np.array_equal(Y.cpu().numpy(), ref), (far, R, sched)
+        P.close()
+
+
+def test_stencils_read_16_bit_offsets():
+    for A in (w.stencil_3d27(16), w.stencil_2d5(50), ragged_stencil()):
+        P = mpk.Plan(A, reorder="none")
+        assert P.info()["sliced_col_bits"] == 16, A.name
+        P.close()
+    P = mpk.Plan(w.banded_random(1 << 14, half_width=300), reorder="none")
+    assert P.info()["sliced_col_bits"] == 0     # no sliced layout
+    P.close()
