@@ -201,8 +201,9 @@ typedef struct {
     int64_t l2_bytes, mall_bytes;
     int32_t min_group_rows;
     int32_t sliced_col_bits; /* columns as the sliced layout's kernels read
-                                them: 16 = offsets col - row (every entry
-                                within 32767 of its row), 32 = columns, 0 = no
+                                them: 16 = offsets col - row taken modulo n
+                                into [-n/2, n/2) (every entry within 32767 of
+                                its row that way), 32 = columns, 0 = no
                                 sliced layout                                  */
 } mpk_plan_info_t;
 

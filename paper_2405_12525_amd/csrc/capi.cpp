@@ -382,9 +382,10 @@ thread_local bool *t_capture_gated = nullptr;
 // (plan row order), unless padding each slice to its longest row would add
 // more than a quarter to the stored entries (rows of uneven length: there
 // the LDS-staged slices of the CSR were measured faster).  Where every
-// column lies within 32767 of its row (banded orders: a 27-point stencil's
-// natural order reaches one plane), the kernels read 16-bit column offsets
-// instead of the 32-bit columns: 10 bytes per FP64 entry instead of 12.
+// column lies within 32767 of its row, modulo n (banded orders: a 27-point
+// stencil's natural order reaches one plane; periodic lattices wrap), the
+// kernels read 16-bit column offsets instead of the 32-bit columns: 10 bytes
+// per FP64 entry instead of 12.
 mpk_status_t build_sell(mpk_plan_t plan) {
     if (plan->n == 0 || plan->nnz == 0) return MPK_OK;
     std::vector<int32_t> width;

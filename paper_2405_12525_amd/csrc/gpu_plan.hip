@@ -467,6 +467,17 @@ __global__ void sell_width_kernel(const int32_t *rowptr, int64_t n, int32_t *wid
     }
 }
 
+// The offset of column c from row r taken modulo n into [-n/2, n/2): the
+// kernels recover c as r + offset, wrapped into [0, n).  Periodic lattices
+// whose wrap-around neighbours lie far away in index then still have small
+// offsets.
+__device__ __forceinline__ int64_t col_offset(int64_t c, int64_t r, int64_t n) {
+    int64_t d = c - r;
+    if (2 * d >= n) d -= n;
+    else if (2 * d < -n) d += n;
+    return d;
+}
+
 // Entry j of row r goes to soff[r / 64] + j * 64 + r % 64; rlen[r] = length.
 // One block per 64-row slice: the slice's nonzeros are contiguous in the CSR,
 // so the block reads them coalesced and finds each one's row by a binary
@@ -494,23 +505,23 @@ __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, cons
             }
             const int64_t dst = base + (int64_t)(e - rp[lo]) * kSellRows + lo;
             scol[dst] = col[e];
-            if (sdel) sdel[dst] = (int16_t)(col[e] - (int32_t)(r0 + lo));
+            if (sdel) sdel[dst] = (int16_t)col_offset(col[e], r0 + lo, n);
             sval[dst] = val[e];
         }
     }
 }
 
-// out = max over the entries of |col - row| (out preset to 0)
+// out = max over the entries of |col_offset| (out preset to 0)
 __global__ void max_col_offset_kernel(const int32_t *rowptr, const int32_t *col, int64_t n,
                                       int32_t *out) {
-    int32_t m = 0;
+    int64_t m = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * blockDim.x)
         for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-            const int64_t d = (int64_t)col[e] - r;
-            m = (int32_t)std::max<int64_t>(m, d < 0 ? -d : d);
+            const int64_t d = col_offset(col[e], r, n);
+            m = std::max<int64_t>(m, d < 0 ? -d : d);
         }
-    if (m > 0) atomicMax(out, m);
+    if (m > 0) atomicMax(out, (int32_t)m);
 }
 
 }  // namespace

@@ -322,7 +322,8 @@ struct SpmvSellU {
     static constexpr int value = RC == 1 ? 2 : 4;
 };
 constexpr int64_t kSpmvSellGrid = 4096;   // baseline workgroups per power (sliced layout)
-// DEL: the columns come from the 16-bit offsets (col = row + offset).
+// DEL: the columns come from the 16-bit offsets (col = row + offset, wrapped
+// into [0, n)).
 template <typename V, int RC, bool WT, bool ACC, int U, bool DEL>
 __device__ __forceinline__ void run_sell_cols(const DevMatrix &m, const PowerIO &io, int R_rt,
                                               int32_t r0, int32_t r1) {
@@ -343,9 +344,11 @@ __device__ __forceinline__ void run_sell_cols(const DevMatrix &m, const PowerIO 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t q = base + (int64_t)min(j + u, L - 1) * kSellRows;
-                if constexpr (DEL)
-                    c[u] = row + (int32_t)m.sdel[q];
-                else
+                if constexpr (DEL) {  // row + offset, wrapped into [0, n)
+                    int32_t cc = row + (int32_t)m.sdel[q];
+                    cc += cc < 0 ? m.n : 0;
+                    c[u] = cc >= m.n ? cc - m.n : cc;
+                } else
                     c[u] = m.scol[q];
                 a[u] = static_cast<double>(sval[q]);
             }

@@ -97,9 +97,10 @@ constexpr int kChunkRows = 4 * kSellRows;
 // gpu_sell_widths: width of every slice (host copy).  gpu_sell_fill: rlen[n]
 // and the slotted columns and values (value_bits 64 or 32, like val) into
 // buffers of `entries` = soff[n_slices] slots, and when sdel is not null the
-// slotted column offsets col - row as 16-bit integers (the caller has checked
-// with gpu_max_col_offset that they fit).  gpu_max_col_offset: max over the
-// entries of |col - row| (host copy in *out).
+// slotted column offsets as 16-bit integers: col - row taken modulo n into
+// [-n/2, n/2) (the caller has checked with gpu_max_col_offset that they fit).
+// gpu_max_col_offset: max over the entries of |that offset| (host copy in
+// *out).
 int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width);
 int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                   int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
@@ -170,8 +171,9 @@ struct DevMatrix {
     const int64_t *soff;      // n_slices + 1 slot offsets
     const int32_t *rlen;      // n row lengths
     const int32_t *scol;      // slotted columns
-    const int16_t *sdel;      // slotted column offsets col - row where they all
-                              // fit 16 bits (the kernels then read these), or null
+    const int16_t *sdel;      // slotted column offsets (col - row modulo n, in
+                              // [-n/2, n/2)) where they all fit 16 bits (the
+                              // kernels then read these), or null
     const void *sval;         // slotted values (double or float)
 };
 

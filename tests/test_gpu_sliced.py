@@ -138,11 +138,12 @@ def with_far_entries(A, far, every, seed):
 
 @pytest.mark.parametrize("far, bits", [(32767, 16), (32768, 32), (39000, 32)])
 def test_column_offsets_16_and_32_bits(far, bits):
-    """The sliced layout stores columns as 16-bit offsets from the row when
-    every entry lies within 32767 of its row, else as columns; both give the
-    oracle's bits.  A 34^3 stencil (n = 39304) with a few entries exactly at
-    the limit or beyond it."""
-    A = with_far_entries(w.stencil_3d27(34), far, 499, far)
+    """The sliced layout stores columns as 16-bit offsets from the row
+    (modulo n, into [-n/2, n/2)) when every entry lies within 32767 of its
+    row that way, else as columns; both give the oracle's bits.  A 42^3
+    stencil (n = 74088) with a few entries exactly at the limit or beyond it
+    (39000 is 35088 the other way round)."""
+    A = with_far_entries(w.stencil_3d27(42), far, 499, far)
     assert max(abs(int(c) - i) for i in range(A.n)
                for c in A.col[A.rowptr[i]:A.rowptr[i + 1]]) == far
     for R in (1, 3):
@@ -165,6 +166,27 @@ def test_stencils_read_16_bit_offsets():
     for A in (w.stencil_3d27(16), w.stencil_2d5(50), ragged_stencil()):
         P = mpk.Plan(A, reorder="none")
         assert P.info()["sliced_col_bits"] == 16, A.name
+        P.close()
+    # a periodic lattice: the wrap-around neighbours lie n - 1600 away in
+    # index, 1600 modulo n
+    A = w.anderson_3d(40)
+    assert max(abs(int(c) - i) for i in range(A.n)
+               for c in A.col[A.rowptr[i]:A.rowptr[i + 1]]) > 32767
+    x = dev_x(A.n, 2, 5)
+    ref = oracle.powers(A, x.cpu().numpy(), 5)
+    for vb in (64, 32):
+        P = mpk.Plan(A, reorder="none", value_bits=vb)
+        assert P.info()["sliced_col_bits"] == 16
+        P.tune(schedule="wave", chunk_nnz=3000, lag=3)
+        Y = P.run(x, 5)
+        B = P.run_baseline(x, 5)
+        P.sync()
+        assert torch.equal(Y, B)
+        if vb == 64:
+            assert np.array_equal(Y.cpu().numpy(), ref)
+        else:
+            assert np.array_equal(Y.cpu().numpy(),
+                                  oracle.powers(A, x.cpu().numpy(), 5, value_bits=32))
         P.close()
     P = mpk.Plan(w.banded_random(1 << 14, half_width=300), reorder="none")
     assert P.info()["sliced_col_bits"] == 0     # no sliced layout
