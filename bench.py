@@ -481,7 +481,22 @@ def _kernel_key(name):
     return name.split("(")[0].strip()
 
 
-def reduce_counters(d):
+def reduce_counter_dirs(dirs):
+    """reduce_counters of the first directory, with the per-run traffic of
+    the others (the same workload profiled at other tunings, without their
+    own copy calibration) added to its runs."""
+    red = reduce_counters(dirs[0])
+    red["dirs"] = [dirs[0]]
+    red["commands"] = [red.get("command")]
+    for d in dirs[1:]:
+        e = reduce_counters(d, (red["fetch_scale"], red["write_scale"]))
+        red.setdefault("runs", {}).update(e.get("runs", {}))
+        red["dirs"].append(d)
+        red["commands"].append(e.get("command"))
+    return red
+
+
+def reduce_counters(d, scales=None):
     """Reduce the rocprofv3 output of one profiled bench configuration:
     d/trace (--kernel-trace --stats), d/fetch (--pmc FETCH_SIZE), d/write
     (--pmc WRITE_SIZE), d/tcc (--pmc TCC_HIT_sum TCC_MISS_sum) and the
@@ -489,7 +504,8 @@ def reduce_counters(d):
     the counters convert to bytes).  Per kernel: launches, mean duration,
     FETCH/WRITE KiB per launch, the bytes they stand for at L2 egress (reads
     into the L2 from the Infinity Cache or HBM, and writes out of it) and
-    the L2 hit rate."""
+    the L2 hit rate.  scales: (FETCH_SIZE, WRITE_SIZE) factors taken from
+    another directory's calibration instead."""
     import csv
     import glob
     from collections import defaultdict
@@ -519,6 +535,8 @@ def reduce_counters(d):
     cw = per_launch("cwrite").get("__amd_rocclr_copyBuffer", {}).get("WRITE_SIZE")
     fetch_scale = round(gib_kib / cf, 4) if cf else None
     write_scale = round(gib_kib / cw, 4) if cw else None
+    if scales is not None:
+        fetch_scale, write_scale = scales
     stats = {}
     for r in rows("trace", "*kernel_stats.csv"):
         stats[_kernel_key(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3)
@@ -584,25 +602,30 @@ def reduce_counters(d):
     return out
 
 
-def counters_markdown(d, summary):
-    """Markdown summary of one reduced profile: the commands that made it,
-    the --stats table and the per-run traffic of the two kernels."""
+def counters_markdown(dirs, summary):
+    """Markdown summary of a reduced profile: the commands that made it,
+    the --stats table (first directory) and the per-run traffic of the two
+    kernels (every directory)."""
     import csv
     import glob
-    cmd = summary.get("command") or "python3 bench.py ..."
-    rel = "gpurun_out/prof"
+    d = dirs[0]
+    cmds = summary.get("commands") or [summary.get("command")]
     lines = [f"# Kernel trace and L2-egress traffic: {summary.get('workload', '')}", "",
              "Commands (from the repository root on one MI355X, after "
              "`cd /tmp && export TMPDIR=/tmp`; `bench.py` by its full path):", "", "```"]
-    for sub, opt in (("trace", "--kernel-trace --stats"), ("fetch", "--pmc FETCH_SIZE --kernel-trace"),
-                     ("write", "--pmc WRITE_SIZE --kernel-trace"),
-                     ("tcc", "--pmc TCC_HIT_sum TCC_MISS_sum --kernel-trace")):
-        lines.append(f"rocprofv3 {opt} -d {rel}/{sub} -o run --output-format csv -- {cmd}")
+    for rel, cmd in zip(dirs, cmds):
+        cmd = cmd or "python3 bench.py ..."
+        for sub, opt in (("trace", "--kernel-trace --stats"),
+                         ("fetch", "--pmc FETCH_SIZE --kernel-trace"),
+                         ("write", "--pmc WRITE_SIZE --kernel-trace"),
+                         ("tcc", "--pmc TCC_HIT_sum TCC_MISS_sum --kernel-trace")):
+            lines.append(f"rocprofv3 {opt} -d {rel}/{sub} -o run --output-format csv -- {cmd}")
     for sub, c in (("cfetch", "FETCH_SIZE"), ("cwrite", "WRITE_SIZE")):
-        lines.append(f"rocprofv3 --pmc {c} --kernel-trace -d {rel}/{sub} -o copy --output-format csv "
+        lines.append(f"rocprofv3 --pmc {c} --kernel-trace -d {d}/{sub} -o copy --output-format csv "
                      f"-- python3 bench.py --copy-calibration")
-    lines += [f"python3 bench.py --reduce-counters {rel} > summary.json",
-              f"python3 bench.py --reduce-counters {rel} --markdown > summary.md", "```", "",
+    lines += [f"python3 bench.py --reduce-counters {' '.join(dirs)} > summary.json",
+              f"python3 bench.py --reduce-counters {' '.join(dirs)} --markdown > summary.md",
+              "```", "",
               f"kernels.hip SHA-256: `{summary.get('kernels_sha256')}`", "",
               "## --stats summary (kernel_stats.csv, the 12 longest in total)", "",
               "| Kernel | Calls | Average µs | Total ms |", "|---|---|---|---|"]
@@ -680,7 +703,7 @@ def main():
                     help="print only the Chebyshev time-step measurement (for profiling)")
     ap.add_argument("--bandwidth-sweep", action="store_true",
                     help="only run the load-bandwidth probe over 1 MiB .. 4 GiB working sets")
-    ap.add_argument("--reduce-counters", metavar="DIR", default=None,
+    ap.add_argument("--reduce-counters", metavar="DIR", nargs="+", default=None,
                     help="reduce the rocprofv3 output of a profiled configuration (DIR/trace, "
                          "fetch, write, tcc, cfetch, cwrite) to JSON on stdout and stop")
     ap.add_argument("--markdown", action="store_true",
@@ -696,7 +719,7 @@ def main():
         sys.exit(2)
 
     if args.reduce_counters:
-        red = reduce_counters(args.reduce_counters)
+        red = reduce_counter_dirs(args.reduce_counters)
         if args.markdown:
             print(counters_markdown(args.reduce_counters, red), end="", flush=True)
         else:

@@ -511,17 +511,36 @@ __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, cons
     }
 }
 
-// out = max over the entries of |col_offset| (out preset to 0)
+// out = max over the entries of |col_offset| (out preset to 0).  Blocks
+// walk 64-row slices as sell_fill_kernel does: coalesced reads of the
+// slice's entries, each one's row found in the slice's row pointers (LDS).
 __global__ void max_col_offset_kernel(const int32_t *rowptr, const int32_t *col, int64_t n,
                                       int32_t *out) {
+    __shared__ int32_t rp[kSellRows + 1];
+    __shared__ int32_t bmax;
+    if (threadIdx.x == 0) bmax = 0;
     int64_t m = 0;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x)
-        for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-            const int64_t d = col_offset(col[e], r, n);
+    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
+    for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
+        const int64_t r0 = s * kSellRows;
+        const int nr = (int)std::min<int64_t>(kSellRows, n - r0);
+        __syncthreads();
+        for (int i = threadIdx.x; i <= nr; i += blockDim.x) rp[i] = rowptr[r0 + i];
+        __syncthreads();
+        for (int32_t e = rp[0] + (int32_t)threadIdx.x; e < rp[nr]; e += blockDim.x) {
+            int lo = 0, hi = nr - 1;   // last row i with rp[i] <= e
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const int64_t d = col_offset(col[e], r0 + lo, n);
             m = std::max<int64_t>(m, d < 0 ? -d : d);
         }
-    if (m > 0) atomicMax(out, (int32_t)m);
+    }
+    __syncthreads();
+    if (m > 0) atomicMax(&bmax, (int32_t)m);
+    __syncthreads();
+    if (threadIdx.x == 0 && bmax > 0) atomicMax(out, bmax);
 }
 
 }  // namespace
@@ -533,8 +552,9 @@ int gpu_max_col_offset(int64_t n, const int32_t *rowptr, const int32_t *col, int
     int32_t *d;
     MPK_TRY(s.get(&d, 1));
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, 0, d, (int64_t)1, 0);
-    hipLaunchKernelGGL(max_col_offset_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, rowptr,
-                       col, n, d);
+    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
+    hipLaunchKernelGGL(max_col_offset_kernel, dim3((unsigned)std::min<int64_t>(n_sl, 65536)),
+                       dim3(kThreads), 0, 0, rowptr, col, n, d);
     MPK_TRY(hipGetLastError());
     MPK_TRY(hipMemcpy(out, d, 4, hipMemcpyDeviceToHost));
     return 0;
