@@ -68,33 +68,69 @@ __global__ void transpose_kernel(const int32_t *rowptr, const int32_t *col, int6
 
 // One BFS level: every unvisited neighbour v of the frontier gets level L
 // (claimed by compare-and-swap, so once) and is appended to `next`.  One
-// wavefront per frontier vertex: its lanes check the out- and in-neighbours
-// together, and the wave appends all its claims with one atomic add.
-__global__ void expand_kernel(const int32_t *rowptr, const int32_t *col, const int32_t *tptr,
-                              const int32_t *tcol, const int32_t *front, int32_t nf,
-                              int32_t *lev, int32_t L, int32_t *next, int32_t *cnt) {
+// wavefront per frontier vertex: its lanes check up to 64 out- and
+// in-neighbours together per round.  A block's claims of a round gather in
+// an LDS list, and one thread reserves their place in `next` with a single
+// atomic add: the level's counter is the one address every block updates,
+// and one update per wave made it the level's bottleneck.
+constexpr int kExpandThreads = 1024;
+constexpr int kExpandGrid = 1024;   // blocks per level launch (grid-stride beyond)
+constexpr int32_t kLevelBatch = 16;  // level launches per read-back of their counts
+// The frontier's size is read from the device (*nfp, the previous level's
+// counter), so that the host can launch several levels before it reads any
+// count back.
+__global__ __launch_bounds__(kExpandThreads) void expand_kernel(
+        const int32_t *rowptr, const int32_t *col, const int32_t *tptr, const int32_t *tcol,
+        const int32_t *front, const int32_t *nfp, int32_t *lev, int32_t L, int32_t *next,
+        int32_t *cnt) {
+    __shared__ int32_t list[kExpandThreads];
+    __shared__ int32_t s_n, s_take, s_base;
+    const int32_t nf = *nfp;
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < nf; f += nwaves) {
-        const int32_t u = front[f];
-        const int32_t a0 = rowptr[u], na = rowptr[u + 1] - a0;
-        const int32_t b0 = tptr[u], total = na + (tptr[u + 1] - b0);
-        for (int32_t base = 0; base < total; base += 64) {  // uniform over the wave
-            const int32_t k = base + lane;
-            int32_t v = 0;
-            bool claim = false;
-            if (k < total) {
-                v = k < na ? col[a0 + k] : tcol[b0 + (k - na)];
-                claim = lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int wpb = (int)(blockDim.x >> 6);
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    // block-uniform: the block's waves take frontier vertices f0 + wave
+    for (int64_t f0 = (int64_t)blockIdx.x * wpb; f0 < nf; f0 += (int64_t)gridDim.x * wpb) {
+        const int64_t f = f0 + wave;
+        int32_t a0 = 0, na = 0, b0 = 0, total = 0;
+        if (f < nf) {
+            const int32_t u = front[f];
+            a0 = rowptr[u];
+            na = rowptr[u + 1] - a0;
+            b0 = tptr[u];
+            total = na + (tptr[u + 1] - b0);
+        }
+        bool more = true;
+        for (int32_t base = 0; more; base += 64) {   // rounds, uniform over the block
+            if (base < total) {                        // uniform over the wave
+                const int32_t k = base + lane;
+                int32_t v = 0;
+                bool claim = false;
+                if (k < total) {
+                    v = k < na ? col[a0 + k] : tcol[b0 + (k - na)];
+                    claim = lev[v] < 0 && atomicCAS(&lev[v], -1, L) == -1;
+                }
+                const unsigned long long m = __ballot(claim);
+                if (m) {
+                    const int first = __ffsll((long long)m) - 1;
+                    int32_t pos = 0;
+                    if (lane == first) pos = atomicAdd(&s_n, (int32_t)__popcll(m));
+                    pos = __shfl(pos, first);
+                    if (claim) list[pos + (int32_t)__popcll(m & ((1ull << lane) - 1ull))] = v;
+                }
             }
-            const unsigned long long m = __ballot(claim);
-            if (m) {
-                const int first = __ffsll((long long)m) - 1;
-                int32_t pos = 0;
-                if (lane == first) pos = atomicAdd(cnt, (int32_t)__popcll(m));
-                pos = __shfl(pos, first);
-                if (claim) next[pos + (int32_t)__popcll(m & ((1ull << lane) - 1ull))] = v;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_take = s_n;
+                s_base = s_n > 0 ? atomicAdd(cnt, s_n) : 0;
+                s_n = 0;
             }
+            __syncthreads();
+            for (int i = (int)threadIdx.x; i < s_take; i += (int)blockDim.x)
+                next[s_base + i] = list[i];
+            more = __syncthreads_or(base + 64 < total);
         }
     }
 }
@@ -285,43 +321,58 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
                        fill, tcol);
     MPK_TRY(hipGetLastError());
 
-    // 2. levels, one launch per level; a restart at the lowest unvisited row
-    //    when the frontier empties
+    // 2. levels: expand launches in batches of kLevelBatch (each reads its
+    //    frontier's size from the previous level's counter), then one read-back
+    //    of the batch's counts; a level that came out empty while rows remain
+    //    starts a new component at the lowest unvisited row
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0, lev, n, -1);
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(kMaxDeviceLevels + 2)), dim3(kThreads), 0, 0,
                        cnt, (int64_t)kMaxDeviceLevels + 2, 0);
-    int64_t visited = 0;
-    int32_t L = 0;
-    int32_t nf = 0;
-    int restarts = 0;
+    int32_t *buf[2] = {front, next};   // level l's rows are in buf[l & 1]
+    auto place_root = [&](int32_t v, int32_t lvl) -> hipError_t {  // v alone on level lvl
+        const int32_t one = 1;
+        hipError_t e = hipMemcpy(lev + v, &lvl, 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(buf[lvl & 1], &v, 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(cnt + lvl, &one, 4, hipMemcpyHostToDevice);
+        return e;
+    };
     int32_t first = (root >= 0 && root < n) ? root : 0;
+    MPK_TRY(place_root(first, 0));
+    int64_t visited = 1;
+    int32_t top = 0;   // the highest level holding rows
+    int restarts = 0;
+    std::vector<int32_t> got(kLevelBatch);
     while (visited < n) {
-        // each level costs a launch and a round trip: graphs with very many
-        // levels or components are left to the host planner
-        if (L > kMaxDeviceLevels || restarts > kMaxDeviceRestarts) return kTooManyLevels;
-        if (nf == 0) {
-            if (visited > 0) {
-                ++restarts;
-                const int32_t nn = (int32_t)n;
-                MPK_TRY(hipMemcpy(start, &nn, 4, hipMemcpyHostToDevice));
-                hipLaunchKernelGGL(first_unvisited_kernel, dim3(grid_for(n)), dim3(kThreads), 0,
-                                   0, lev, n, start);
-                MPK_TRY(hipMemcpy(&first, start, 4, hipMemcpyDeviceToHost));
-                if (first < 0 || first >= n) return (int)hipErrorUnknown;
-            }
-            MPK_TRY(hipMemcpy(lev + first, &L, 4, hipMemcpyHostToDevice));
-            MPK_TRY(hipMemcpy(front, &first, 4, hipMemcpyHostToDevice));
-            nf = 1;
-        }
-        visited += nf;
-        ++L;
-        hipLaunchKernelGGL(expand_kernel, dim3(grid_for((int64_t)nf * 64)), dim3(kThreads), 0, 0,
-                           rowptr, col, tptr, tcol, front, nf, lev, L, next, cnt + L);
+        // each level costs a launch: graphs with very many levels or
+        // components are left to the host planner
+        if (top + 1 > kMaxDeviceLevels) return kTooManyLevels;
+        const int32_t l0 = top + 1, l1 = std::min(l0 + kLevelBatch, kMaxDeviceLevels + 1);
+        for (int32_t l = l0; l < l1; ++l)
+            hipLaunchKernelGGL(expand_kernel, dim3(kExpandGrid), dim3(kExpandThreads), 0, 0,
+                               rowptr, col, tptr, tcol, buf[(l - 1) & 1], cnt + (l - 1), lev, l,
+                               buf[l & 1], cnt + l);
         MPK_TRY(hipGetLastError());
-        MPK_TRY(hipMemcpy(&nf, cnt + L, 4, hipMemcpyDeviceToHost));
-        if (nf < 0 || visited + nf > n) return (int)hipErrorUnknown;
-        std::swap(front, next);
+        MPK_TRY(hipMemcpy(got.data(), cnt + l0, (size_t)(l1 - l0) * 4, hipMemcpyDeviceToHost));
+        int32_t l = l0;
+        for (; l < l1 && got[l - l0] > 0; ++l) {
+            if (visited + got[l - l0] > n) return (int)hipErrorUnknown;
+            visited += got[l - l0];
+            top = l;
+        }
+        if (l < l1 && visited < n) {   // level l came out empty: a new component
+            if (++restarts > kMaxDeviceRestarts || l > kMaxDeviceLevels) return kTooManyLevels;
+            const int32_t nn = (int32_t)n;
+            MPK_TRY(hipMemcpy(start, &nn, 4, hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(first_unvisited_kernel, dim3(grid_for(n)), dim3(kThreads), 0, 0,
+                               lev, n, start);
+            MPK_TRY(hipMemcpy(&first, start, 4, hipMemcpyDeviceToHost));
+            if (first < 0 || first >= n) return (int)hipErrorUnknown;
+            MPK_TRY(place_root(first, l));
+            visited += 1;
+            top = l;
+        }
     }
+    const int32_t L = top + 1;   // levels 0 .. top
     const int32_t n_levels = L;
 
     // 3. rows by level, ascending original index inside a level (the radix

@@ -390,8 +390,21 @@ def _host_levels(A, **kw):
     return mpk.Plan(A, device=mpk.MPK_DEVICE_NONE, **kw).levels()
 
 
+def _with_dense_rows(n, seed):
+    """A sparse random pattern where rows 0, 7 and n/2 (and their columns)
+    are dense: frontier vertices with hundreds of neighbours, which the
+    device BFS checks 64 at a time over several rounds."""
+    g = np.random.default_rng(seed)
+    m = g.random((n, n)) < 0.001
+    for r in (0, 7, n // 2):
+        m[r, g.random(n) < 0.3] = True
+    m = m | m.T
+    np.fill_diagonal(m, True)
+    return w.from_dense(np.where(m, g.standard_normal((n, n)), 0.0), "dense_rows")
+
+
 @pytest.mark.parametrize("case", ["stencil", "random_sym", "random_nonsym", "disconnected",
-                                  "empty_rows", "anderson"])
+                                  "empty_rows", "anderson", "dense_rows"])
 @pytest.mark.parametrize("order", ["original", "plan"])
 def test_device_levels_equal_host_levels(case, order):
     # BFS levels and the permutation computed on the GPU are the host
@@ -403,7 +416,8 @@ def test_device_levels_equal_host_levels(case, order):
          "disconnected": lambda: w.random_sparse(2500, 0.0004, 43, symmetric_pattern=True),
          "empty_rows": lambda: w.CSR(6, np.array([0, 0, 2, 2, 3, 3, 3], np.int32),
                                      np.array([4, 1, 2], np.int32), np.array([1.0, 2.0, 3.0])),
-         "anderson": lambda: w.anderson_3d(12)}[case]()
+         "anderson": lambda: w.anderson_3d(12),
+         "dense_rows": lambda: _with_dense_rows(3000, 45)}[case]()
     for root in (0, A.n // 2):
         P = mpk.Plan(A, order=order, root=root)
         lp, perm = P.levels()
