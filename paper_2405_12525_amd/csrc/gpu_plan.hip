@@ -255,15 +255,38 @@ __global__ void gather_kernel(const int32_t *col, int64_t step, int64_t count, i
 }
 
 // Device scratch freed on every exit path.
+// Device scratch of one planning call, freed when it ends.  reserve() takes
+// one block that later get()s are carved from (256-byte aligned); requests
+// beyond it get allocations of their own.  (Each hipFree costs ~0.3 ms: the
+// level construction's eighteen buffers freed one by one took ~5 ms.)
 struct Scratch {
     std::vector<void *> ptrs;
+    char *arena = nullptr;
+    size_t cap = 0, used = 0;
     ~Scratch() {
         for (void *p : ptrs) (void)hipFree(p);
     }
+    static size_t round_up(size_t b) { return (b + 255) & ~(size_t)255; }
+    hipError_t reserve(size_t bytes) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) return e;
+        ptrs.push_back(q);
+        arena = static_cast<char *>(q);
+        cap = bytes;
+        used = 0;
+        return hipSuccess;
+    }
     template <typename T>
     hipError_t get(T **p, size_t count) {
+        const size_t b = round_up(std::max<size_t>(count, 1) * sizeof(T));
+        if (arena && used + b <= cap) {
+            *p = reinterpret_cast<T *>(arena + used);
+            used += b;
+            return hipSuccess;
+        }
         void *q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+        hipError_t e = hipMalloc(&q, b);
         if (e != hipSuccess) return e;
         ptrs.push_back(q);
         *p = static_cast<T *>(q);
@@ -288,6 +311,11 @@ int gpu_levels_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int3
     Scratch s;
     int32_t *tptr, *fill, *tcol, *lev, *front, *next, *cnt, *perm_in, *perm, *keys, *iperm,
         *len, *level_ptr, *lo, *hi, *start;
+    // the arrays below, the level pointers and room for the scans' and the
+    // sort's temporary storage, in one block
+    MPK_TRY(s.reserve(Scratch::round_up((size_t)(n + 1) * 4) * 3 +
+                      Scratch::round_up((size_t)nnz * 4) + Scratch::round_up((size_t)n * 4) * 10 +
+                      Scratch::round_up(((size_t)kMaxDeviceLevels + 2) * 4) * 2 + (64u << 20)));
     MPK_TRY(s.get(&tptr, n + 1));
     MPK_TRY(s.get(&fill, n + 1));
     MPK_TRY(s.get(&tcol, nnz));
