@@ -930,6 +930,7 @@ def main():
                  "window_bytes": int(sched["window_bytes"]), "max_reach": sched["max_reach"],
                  "window_within_budget_C": bool(sched["window_bytes"] <= tune["cache_bytes"]),
                  "sliced_layout": bool(info["sliced_layout"]),
+                 "sliced_col_bits": info["sliced_col_bits"],
                  "spmv_equivalents": round(info["plan_ms"] / (bmed / p), 1),
                  "from_device_csr_ms": dev_ms,
                  "from_device_csr_spmv_equivalents": {k: round(v / (bmed / p), 1)
