@@ -205,6 +205,12 @@ typedef struct {
                                 into [-n/2, n/2) (every entry within 32767 of
                                 its row that way), 32 = columns, 0 = no
                                 sliced layout                                  */
+    uint64_t fingerprint;    /* hash of the shape, the ordering and blocking
+                                options, the row pointers and a sample of the
+                                columns: the matrix part of the autotuner's
+                                cache key (values and their precision are not
+                                in it); equal for plans of the same matrix
+                                from host or device arrays                      */
 } mpk_plan_info_t;
 
 typedef struct {

@@ -63,7 +63,8 @@ class PlanInfo(ctypes.Structure):
                 ("sliced_layout", ctypes.c_int32), ("sliced_entries", ctypes.c_int64),
                 ("sublevel_root", ctypes.c_int32), ("max_sublevels", ctypes.c_int32),
                 ("l2_bytes", ctypes.c_int64), ("mall_bytes", ctypes.c_int64),
-                ("min_group_rows", ctypes.c_int32), ("sliced_col_bits", ctypes.c_int32)]
+                ("min_group_rows", ctypes.c_int32), ("sliced_col_bits", ctypes.c_int32),
+                ("fingerprint", ctypes.c_uint64)]
 
 
 class SchedInfo(ctypes.Structure):

@@ -1247,10 +1247,14 @@ mpk_status_t mpk_plan_device(const mpk_csr_t *A, const mpk_plan_opts_t *opts, mp
         std::vector<int32_t> sample, rp0;
         if ((rc = gpu_sample_cols(A->col, step, nnz ? (nnz + step - 1) / step : 0, sample)))
             return hip_fail((hipError_t)rc, "hipMemcpy (column sample)");
-        rp0.resize((size_t)n + 1);
-        e = hipMemcpy(rp0.data(), A->rowptr, rp0.size() * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy (row pointer)");
-        plan->fingerprint = fingerprint(n, nnz, o, rp0.data(), sample);
+        const int32_t *rph = plan->rowptr.data();   // the caller's, in its own order
+        if (o.reorder == MPK_REORDER_BFS) {               // the plan's is permuted
+            rp0.resize((size_t)n + 1);
+            e = hipMemcpy(rp0.data(), A->rowptr, rp0.size() * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy (row pointer)");
+            rph = rp0.data();
+        }
+        plan->fingerprint = fingerprint(n, nnz, o, rph, sample);
         mpk_status_t st2 = build_sell(plan.get());
         if (st2) return st2;
     } catch (const std::bad_alloc &) {
@@ -1309,6 +1313,7 @@ mpk_status_t mpk_plan_info(mpk_plan_t plan, mpk_plan_info_t *info) {
     info->sliced_layout = plan->d_scol.ptr ? 1 : 0;
     info->sliced_entries = plan->sell_entries;
     info->sliced_col_bits = plan->d_sdel.ptr ? 16 : (plan->d_scol.ptr ? 32 : 0);
+    info->fingerprint = plan->fingerprint;
     info->sublevel_root = plan->sublevel_root;
     info->max_sublevels = plan->max_sublevels;
     info->l2_bytes = plan->l2_bytes;

@@ -476,8 +476,9 @@ def test_plan_from_device_csr_equals_host_plan(reorder, order, vb, case):
     lq, permq = Q.levels()
     assert np.array_equal(lp, lq) and np.array_equal(perm, permq)
     ip, iq = P.info(), Q.info()
-    assert {k: ip[k] for k in ("n", "nnz", "n_levels", "max_level_rows", "matrix_bytes")} == \
-        {k: iq[k] for k in ("n", "nnz", "n_levels", "max_level_rows", "matrix_bytes")}
+    same = ("n", "nnz", "n_levels", "max_level_rows", "matrix_bytes", "fingerprint",
+            "sliced_layout", "sliced_col_bits")
+    assert {k: ip[k] for k in same} == {k: iq[k] for k in same}
     x = w.uniform_vectors(A.n, 2, 9)
     xs = x[perm] if order == "plan" else x
     Y, B = run_both(P, xs, 4)

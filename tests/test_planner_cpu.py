@@ -476,3 +476,18 @@ def test_planner_budget_options():
     for bad in (dict(l2_bytes=-1), dict(mall_bytes=1000), dict(min_group_rows=-3)):
         with pytest.raises(mpk.MPKError):
             host_plan(A, **bad)
+
+
+def test_fingerprint_keys_pattern_and_options():
+    """The matrix part of the autotuner's cache key: equal for the same
+    pattern and ordering options (values do not change the tuning; the value
+    precision is a key field of its own), different for another pattern, row
+    order or root."""
+    A = w.stencil_3d27(8)
+    B = w.CSR(A.n, A.rowptr, A.col, A.val * 2.0 + 1.0, "scaled")
+    C = w.anderson_3d(8)
+    fp = lambda M, **kw: mpk.Plan(M, device=mpk.MPK_DEVICE_NONE, **kw).info()["fingerprint"]
+    assert fp(A) == fp(A) == fp(B) == fp(A, value_bits=32)
+    assert fp(A) != fp(C)
+    assert fp(A) != fp(A, reorder="none")
+    assert fp(A) != fp(A, root=5)
