@@ -254,8 +254,7 @@ __global__ void gather_kernel(const int32_t *col, int64_t step, int64_t count, i
         out[k] = col[k * step];
 }
 
-// Device scratch freed on every exit path.
-// Device scratch of one planning call, freed when it ends.  reserve() takes
+// Device scratch of one planning call, freed on every exit path.  reserve() takes
 // one block that later get()s are carved from (256-byte aligned); requests
 // beyond it get allocations of their own.  (Each hipFree costs ~0.3 ms: the
 // level construction's eighteen buffers freed one by one took ~5 ms.)
