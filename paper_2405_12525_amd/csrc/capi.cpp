@@ -400,17 +400,15 @@ mpk_status_t build_sell(mpk_plan_t plan) {
     if ((st = plan->d_rlen.alloc((size_t)plan->n * 4))) return st;
     if ((st = plan->d_scol.alloc((size_t)entries * 4))) return st;
     if ((st = plan->d_sval.alloc((size_t)entries * (plan->value_bits / 8)))) return st;
-    plan->d_sdel.release();
+    // the offsets are filled in the same pass and dropped if one does not fit
+    if ((st = plan->d_sdel.alloc((size_t)entries * 2))) return st;
     int32_t reach = 0;
-    rc = gpu_max_col_offset(plan->n, plan->d_rowptr.as<int32_t>(), plan->d_col.as<int32_t>(),
-                            &reach);
-    if (rc) return hip_fail((hipError_t)rc, "column offsets");
-    if (reach <= 32767 && (st = plan->d_sdel.alloc((size_t)entries * 2))) return st;
     rc = gpu_sell_fill(plan->n, plan->d_rowptr.as<int32_t>(), plan->d_col.as<int32_t>(),
                        plan->d_val.ptr, plan->value_bits, plan->d_soff.as<const int64_t>(), entries,
                        plan->d_rlen.as<int32_t>(), plan->d_scol.as<int32_t>(),
-                       plan->d_sdel.as<int16_t>(), plan->d_sval.ptr);
+                       plan->d_sdel.as<int16_t>(), plan->d_sval.ptr, &reach);
     if (rc) return hip_fail((hipError_t)rc, "sliced layout");
+    if (reach > 32767) plan->d_sdel.release();
     plan->sell_entries = entries;
     return MPK_OK;
 }

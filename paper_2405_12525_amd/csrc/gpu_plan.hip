@@ -564,8 +564,11 @@ __device__ __forceinline__ int64_t col_offset(int64_t c, int64_t r, int64_t n) {
 template <typename V>
 __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, const V *val,
                                  int64_t n, const int64_t *soff, int32_t *rlen, int32_t *scol,
-                                 int16_t *sdel, V *sval) {
+                                 int16_t *sdel, V *sval, int32_t *max_off) {
     __shared__ int32_t rp[kSellRows + 1];
+    __shared__ int32_t bmax;
+    if (threadIdx.x == 0) bmax = 0;
+    int64_t m = 0;
     const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
     for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
         const int64_t r0 = s * kSellRows;
@@ -582,61 +585,25 @@ __global__ void sell_fill_kernel(const int32_t *rowptr, const int32_t *col, cons
                 if (rp[mid] <= e) lo = mid; else hi = mid - 1;
             }
             const int64_t dst = base + (int64_t)(e - rp[lo]) * kSellRows + lo;
-            scol[dst] = col[e];
-            if (sdel) sdel[dst] = (int16_t)col_offset(col[e], r0 + lo, n);
+            const int32_t c = col[e];
+            scol[dst] = c;
+            if (sdel) {   // kept only if every offset fits 16 bits (max_off)
+                const int64_t d = col_offset(c, r0 + lo, n);
+                sdel[dst] = (int16_t)d;
+                m = std::max<int64_t>(m, d < 0 ? -d : d);
+            }
             sval[dst] = val[e];
         }
     }
-}
-
-// out = max over the entries of |col_offset| (out preset to 0).  Blocks
-// walk 64-row slices as sell_fill_kernel does: coalesced reads of the
-// slice's entries, each one's row found in the slice's row pointers (LDS).
-__global__ void max_col_offset_kernel(const int32_t *rowptr, const int32_t *col, int64_t n,
-                                      int32_t *out) {
-    __shared__ int32_t rp[kSellRows + 1];
-    __shared__ int32_t bmax;
-    if (threadIdx.x == 0) bmax = 0;
-    int64_t m = 0;
-    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
-    for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
-        const int64_t r0 = s * kSellRows;
-        const int nr = (int)std::min<int64_t>(kSellRows, n - r0);
+    if (sdel) {   // uniform
         __syncthreads();
-        for (int i = threadIdx.x; i <= nr; i += blockDim.x) rp[i] = rowptr[r0 + i];
+        if (m > 0) atomicMax(&bmax, (int32_t)m);
         __syncthreads();
-        for (int32_t e = rp[0] + (int32_t)threadIdx.x; e < rp[nr]; e += blockDim.x) {
-            int lo = 0, hi = nr - 1;   // last row i with rp[i] <= e
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rp[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            const int64_t d = col_offset(col[e], r0 + lo, n);
-            m = std::max<int64_t>(m, d < 0 ? -d : d);
-        }
+        if (threadIdx.x == 0 && bmax > 0) atomicMax(max_off, bmax);
     }
-    __syncthreads();
-    if (m > 0) atomicMax(&bmax, (int32_t)m);
-    __syncthreads();
-    if (threadIdx.x == 0 && bmax > 0) atomicMax(out, bmax);
 }
 
 }  // namespace
-
-int gpu_max_col_offset(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t *out) {
-    *out = 0;
-    if (n == 0) return 0;
-    Scratch s;
-    int32_t *d;
-    MPK_TRY(s.get(&d, 1));
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, 0, d, (int64_t)1, 0);
-    const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
-    hipLaunchKernelGGL(max_col_offset_kernel, dim3((unsigned)std::min<int64_t>(n_sl, 65536)),
-                       dim3(kThreads), 0, 0, rowptr, col, n, d);
-    MPK_TRY(hipGetLastError());
-    MPK_TRY(hipMemcpy(out, d, 4, hipMemcpyDeviceToHost));
-    return 0;
-}
 
 int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width) {
     const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
@@ -653,21 +620,27 @@ int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &widt
 
 int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                   int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
-                  int32_t *scol, int16_t *sdel, void *sval) {
+                  int32_t *scol, int16_t *sdel, void *sval, int32_t *max_offset) {
     (void)entries;
+    *max_offset = 0;
     if (n == 0) return 0;
     const int64_t n_sl = (n + kSellRows - 1) / kSellRows;
     const dim3 grid((unsigned)std::min<int64_t>(n_sl, 65536));
+    Scratch s;
+    int32_t *d_max;
+    MPK_TRY(s.get(&d_max, 1));
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, 0, d_max, (int64_t)1, 0);
     if (value_bits == 32)
         hipLaunchKernelGGL(sell_fill_kernel<float>, grid, dim3(kThreads), 0, 0,
                            rowptr, col, static_cast<const float *>(val), n, soff, rlen, scol,
-                           sdel, static_cast<float *>(sval));
+                           sdel, static_cast<float *>(sval), d_max);
     else
         hipLaunchKernelGGL(sell_fill_kernel<double>, grid, dim3(kThreads), 0, 0,
                            rowptr, col, static_cast<const double *>(val), n, soff, rlen, scol,
-                           sdel, static_cast<double *>(sval));
+                           sdel, static_cast<double *>(sval), d_max);
     MPK_TRY(hipGetLastError());
-    return (int)hipDeviceSynchronize();
+    MPK_TRY(hipMemcpy(max_offset, d_max, 4, hipMemcpyDeviceToHost));
+    return 0;
 }
 
 }  // namespace mpk

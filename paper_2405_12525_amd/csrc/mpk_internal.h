@@ -97,15 +97,13 @@ constexpr int kChunkRows = 4 * kSellRows;
 // gpu_sell_widths: width of every slice (host copy).  gpu_sell_fill: rlen[n]
 // and the slotted columns and values (value_bits 64 or 32, like val) into
 // buffers of `entries` = soff[n_slices] slots, and when sdel is not null the
-// slotted column offsets as 16-bit integers: col - row taken modulo n into
-// [-n/2, n/2) (the caller has checked with gpu_max_col_offset that they fit).
-// gpu_max_col_offset: max over the entries of |that offset| (host copy in
-// *out).
+// slotted column offsets as 16-bit integers (col - row taken modulo n into
+// [-n/2, n/2)) with the largest |offset| in *max_offset: the offsets are
+// valid only if it is at most 32767.
 int gpu_sell_widths(int64_t n, const int32_t *rowptr, std::vector<int32_t> &width);
 int gpu_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const void *val,
                   int value_bits, const int64_t *soff, int64_t entries, int32_t *rlen,
-                  int32_t *scol, int16_t *sdel, void *sval);
-int gpu_max_col_offset(int64_t n, const int32_t *rowptr, const int32_t *col, int32_t *out);
+                  int32_t *scol, int16_t *sdel, void *sval, int32_t *max_offset);
 // Levels from far[] (order_levels' rule): level 0 = row 0, level j+1 ends
 // just past the farthest neighbour of level j.
 Levels levels_from_far(int64_t n, const std::vector<int32_t> &far);
