@@ -256,9 +256,11 @@ def other_configs(torch, mpk, w, steps, warmup, stream, with_oracle):
                 if ref is not None:
                     rel = per_power_rel_err(Y.cpu().numpy(), ref)
                     best["rel"] = [max(a, b) for a, b in zip(best.get("rel", rel), rel)]
+                tuning = {k: tq[k] for k in ("schedule", "chunk_nnz", "lag", "workgroups",
+                                             "seg_powers", "skip_ahead", "dynamic_tickets")}
                 for key, ms in (("trad", tr), ("lb", lb)):
                     if key not in best or ms < best[key][0]:
-                        best[key] = (ms, ro, tq["schedule"] if key == "lb" else None)
+                        best[key] = (ms, ro, tq["schedule"] if key == "lb" else None, tuning)
                 P.close()
             tag = f"{name}_fp{vb}"
             vbytes = 8 * A.n * R
@@ -266,7 +268,7 @@ def other_configs(torch, mpk, w, steps, warmup, stream, with_oracle):
             lb_b = algorithmic_bytes(A.n, A.nnz, p, R, vb // 8, "lb")
             out[tag] = {"n": A.n, "nnz": A.nnz, "p": p, "nrhs": R, "kind": kind,
                         "lb_ms": round(best["lb"][0], 4), "lb_reorder": best["lb"][1],
-                        "lb_schedule": best["lb"][2],
+                        "lb_schedule": best["lb"][2], "lb_tuning": best["lb"][3],
                         "lb_gflops": round(flop / best["lb"][0] / 1e6, 1),
                         "pxspmv_ms": round(best["trad"][0], 4), "pxspmv_reorder": best["trad"][1],
                         "pxspmv_gflops": round(flop / best["trad"][0] / 1e6, 1),
