@@ -323,8 +323,20 @@ struct SpmvSellU {
 };
 constexpr int64_t kSpmvSellGrid = 4096;   // baseline workgroups per power (sliced layout)
 // DEL: the columns come from the 16-bit offsets (col = row + offset, wrapped
-// into [0, n)).
-template <typename V, int RC, bool WT, bool ACC, int U, bool DEL>
+// into [0, n)).  NT: the matrix is loaded non-temporally (the one-launch-per-
+// power baseline with one right-hand side, which reads each line once per
+// launch: 1.5% faster on the 27-point stencil.  With 8 or 16 right-hand sides
+// the rows of neighbouring waves share the lines, and the hint made it 5-28%
+// slower; in the level-blocked run, whose reuse is the matrix kept in the
+// caches between powers, 28% slower.)
+template <bool NT, typename T>
+__device__ __forceinline__ T load_matrix(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <typename V, int RC, bool WT, bool ACC, int U, bool DEL, bool NT>
 __device__ __forceinline__ void run_sell_cols(const DevMatrix &m, const PowerIO &io, int R_rt,
                                               int32_t r0, int32_t r1) {
     const int R = RC ? RC : R_rt;
@@ -345,12 +357,12 @@ __device__ __forceinline__ void run_sell_cols(const DevMatrix &m, const PowerIO 
             for (int u = 0; u < U; ++u) {
                 const int64_t q = base + (int64_t)min(j + u, L - 1) * kSellRows;
                 if constexpr (DEL) {  // row + offset, wrapped into [0, n)
-                    int32_t cc = row + (int32_t)m.sdel[q];
+                    int32_t cc = row + (int32_t)load_matrix<NT>(m.sdel + q);
                     cc += cc < 0 ? m.n : 0;
                     c[u] = cc >= m.n ? cc - m.n : cc;
                 } else
-                    c[u] = m.scol[q];
-                a[u] = static_cast<double>(sval[q]);
+                    c[u] = load_matrix<NT>(m.scol + q);
+                a[u] = static_cast<double>(load_matrix<NT>(sval + q));
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) xv[u] = io.in[(size_t)c[u] * R + rr];
@@ -362,13 +374,13 @@ __device__ __forceinline__ void run_sell_cols(const DevMatrix &m, const PowerIO 
         finish<WT, ACC>(io, s, (size_t)o * R + rr);
     }
 }
-template <typename V, int RC, bool WT, bool ACC, int U>
+template <typename V, int RC, bool WT, bool ACC, int U, bool NT = false>
 __device__ __forceinline__ void run_sell(const DevMatrix &m, const PowerIO &io, int R_rt,
                                          int32_t r0, int32_t r1) {
     if (m.sdel)  // uniform: the plan's layout
-        run_sell_cols<V, RC, WT, ACC, U, true>(m, io, R_rt, r0, r1);
+        run_sell_cols<V, RC, WT, ACC, U, true, NT>(m, io, R_rt, r0, r1);
     else
-        run_sell_cols<V, RC, WT, ACC, U, false>(m, io, R_rt, r0, r1);
+        run_sell_cols<V, RC, WT, ACC, U, false, NT>(m, io, R_rt, r0, r1);
 }
 
 // Products staged per thread and buffer: the slice path for R < 4 (R = 0 is
@@ -522,7 +534,8 @@ template <typename V, int RC, bool ACC>
 __global__ __launch_bounds__(kBlock) void spmv_sell_kernel(DevMatrix m, PowerIO io, int32_t R) {
     const int32_t step = kBlock / (RC ? RC : R);
     for (int32_t r0 = blockIdx.x * step; r0 < m.n; r0 += gridDim.x * step)
-        run_sell<V, RC, false, ACC, SpmvSellU<RC>::value>(m, io, R, r0, min(m.n, r0 + step));
+        run_sell<V, RC, false, ACC, SpmvSellU<RC>::value, RC == 1>(m, io, R, r0,
+                                                                   min(m.n, r0 + step));
 }
 
 // ------------------------------------------------------------------ level-blocked
