@@ -323,12 +323,13 @@ struct SpmvSellU {
 };
 constexpr int64_t kSpmvSellGrid = 4096;   // baseline workgroups per power (sliced layout)
 // DEL: the columns come from the 16-bit offsets (col = row + offset, wrapped
-// into [0, n)).  NT: the matrix is loaded non-temporally (the one-launch-per-
-// power baseline with one right-hand side, which reads each line once per
-// launch: 1.5% faster on the 27-point stencil.  With 8 or 16 right-hand sides
+// into [0, n)).  NT: the matrix is loaded non-temporally: by the one-launch-
+// per-power baseline with one right-hand side, which reads each line once per
+// launch (1.5% faster on the 27-point stencil; with 8 or 16 right-hand sides
 // the rows of neighbouring waves share the lines, and the hint made it 5-28%
-// slower; in the level-blocked run, whose reuse is the matrix kept in the
-// caches between powers, 28% slower.)
+// slower), and by the level-blocked tasks of a segment's last power only
+// (their reuse is the matrix kept in the caches between powers: the hint on
+// every power made them 28% slower).
 template <bool NT, typename T>
 __device__ __forceinline__ T load_matrix(const T *p) {
     if constexpr (NT)
@@ -545,12 +546,20 @@ __global__ __launch_bounds__(kBlock) void spmv_sell_kernel(DevMatrix m, PowerIO 
 // diagonals' results are visible because they ran in earlier launches.
 // Chunk c of one power: its slices staged through LDS, or (SELL) its rows in
 // the sliced layout.  WT: write-through result stores.
+// last: the segment's last power, whose matrix reads are the chunk's last use
+// in this launch (sliced layout: loaded non-temporally, so that the caches
+// keep the rows still to be reused: 1.4% faster on the 27-point stencil).
 template <typename V, int RC, bool WT, bool ACC, bool SELL>
 __device__ __forceinline__ void run_chunk(const DevMatrix &m, const PowerIO &io, int R,
                                           DevSlices sl, const int32_t *chunk_sptr,
-                                          const int32_t *chunk_row, int32_t c) {
+                                          const int32_t *chunk_row, int32_t c,
+                                          bool last = false) {
     if constexpr (SELL) {
-        run_sell<V, RC, WT, ACC, SellU<RC>::value>(m, io, R, chunk_row[c], chunk_row[c + 1]);
+        if (last)   // uniform: the task's power
+            run_sell<V, RC, WT, ACC, SellU<RC>::value, true>(m, io, R, chunk_row[c],
+                                                             chunk_row[c + 1]);
+        else
+            run_sell<V, RC, WT, ACC, SellU<RC>::value>(m, io, R, chunk_row[c], chunk_row[c + 1]);
     } else {
         __shared__ RowSmem<Staging<RC, kTaskKP>::value> sm;
         run_slices<V, RC, Staging<RC, kTaskKP>::value, WT, ACC>(m, io, R, sl, chunk_sptr[c],
@@ -706,7 +715,7 @@ __device__ __forceinline__ void lb_body(const LBParams &P, const Coefs &cf, cons
         }
         if (!ok) break;  // uniform: a wait hit its limit, the run is abandoned
         run_chunk<V, RC, true, ACC, SELL>(P.m, power_io<ACC>(P.a, cf, ac, k, P.m.n), P.a.R,
-                                          P.s.sl, P.s.chunk_sptr, P.s.chunk_row, c);
+                                          P.s.sl, P.s.chunk_sptr, P.s.chunk_row, c, k == P.a.p);
         // The results were stored write-through; every wave waits until its
         // stores have completed (vmcnt = 0) before the barrier, so the chunk
         // is visible device-wide when the flag below is published and the
