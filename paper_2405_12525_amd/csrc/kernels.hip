@@ -547,17 +547,19 @@ __global__ __launch_bounds__(kBlock) void spmv_sell_kernel(DevMatrix m, PowerIO 
 // Chunk c of one power: its slices staged through LDS, or (SELL) its rows in
 // the sliced layout.  WT: write-through result stores.
 // last: the segment's last power, whose matrix reads are the chunk's last use
-// in this launch (sliced layout: loaded non-temporally, so that the caches
-// keep the rows still to be reused: 1.4% faster on the 27-point stencil).
+// in this launch (sliced layout, one right-hand side: loaded non-temporally,
+// so that the caches keep the rows still to be reused: 1.4% faster on the
+// 27-point stencil; with 16 right-hand sides, whose rows share lines across
+// waves, 2-3% slower, so not there).
 template <typename V, int RC, bool WT, bool ACC, bool SELL>
 __device__ __forceinline__ void run_chunk(const DevMatrix &m, const PowerIO &io, int R,
                                           DevSlices sl, const int32_t *chunk_sptr,
                                           const int32_t *chunk_row, int32_t c,
                                           bool last = false) {
     if constexpr (SELL) {
-        if (last)   // uniform: the task's power
-            run_sell<V, RC, WT, ACC, SellU<RC>::value, true>(m, io, R, chunk_row[c],
-                                                             chunk_row[c + 1]);
+        if (RC == 1 && last)   // uniform: the task's power
+            run_sell<V, RC, WT, ACC, SellU<RC>::value, RC == 1>(m, io, R, chunk_row[c],
+                                                                chunk_row[c + 1]);
         else
             run_sell<V, RC, WT, ACC, SellU<RC>::value>(m, io, R, chunk_row[c], chunk_row[c + 1]);
     } else {
